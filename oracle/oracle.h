@@ -1,0 +1,103 @@
+/*
+ * CPU oracle for the coupled displacement / phase-field operator.
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow FP64 reference used by the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark. The
+ * product path (the HIP library) never links, loads or calls it, and it shares
+ * no code, header or table with that library.
+ *
+ * Method: finite-strain Hencky material with a Peric-Dettmer inelastic block
+ * (Hooke branch, or one Prandtl branch with linear hardening and an overstress
+ * factor) in series with a phase-field fracture element (Sections 2-3 of the
+ * paper), discretised with tensor-product hexahedra and Gauss quadrature
+ * (Section 4). Element operators use dense element matrices built from the 1-D
+ * Lagrange basis (no sum factorisation).
+ *
+ * Conventions (shared interface, see inputs.py): nodes lexicographic x-fastest,
+ * z = SoA [4][n_nodes] (u_x,u_y,u_z,phi), qp = e*Q^3 + qx + Q*(qy + Q*qz),
+ * state = SoA [8][n_q] (D xx,yy,zz,yz,xz,xy = Cin^-1 - I; ebar_p; H_n),
+ * phase = uint8[n_q]. Units mm, MPa, s, N/mm.
+ */
+#ifndef PF_ORACLE_H
+#define PF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { int p, q, nx, ny, nz; double lx, ly, lz; } or_mesh;
+typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; } or_phase;
+typedef struct { double l0, eta, zeta, dt, s_phi; int at; } or_frac;
+
+/* Every pointwise quantity the tests look at. */
+typedef struct {
+  double P[9];        /* first Piola stress P = tau_degr F^-T, row-major P[i*3+J] */
+  double f0;          /* s_phi * L */
+  double f1[3];       /* s_phi * (2 Gc l0 / c0) * grad_X phi */
+  double tau[6];      /* degraded Kirchhoff stress, Voigt xx,yy,zz,yz,xz,xy */
+  double beta[3];     /* eigenvalues of b_tr - I, ascending */
+  double eps[3];      /* principal trial log strains */
+  double theta;       /* trace of the log strain */
+  double q;           /* undegraded trial von Mises stress */
+  double dgamma;      /* plastic multiplier increment */
+  double c;           /* radial-return factor on the deviatoric strain */
+  double psi_plus;    /* tensile energy psi^+ */
+  double H;           /* max(H_n, psi^+) */
+  double L;           /* local phase-field residual */
+  double g;           /* degradation g(phi) */
+  int plastic_active; /* 1 if the (degraded) yield check failed */
+  int nonphysical;    /* 1 if 1+beta_i <= 0 or det F <= 0 */
+} or_qp_out;
+
+/* 1-D rules. Gauss-Legendre points/weights and GLL points on [-1,1]. */
+void or_gauss(int n, double* x, double* w);
+void or_gll(int n, double* x);
+
+/* Pointwise residual integrand (steps R1-R12). G = grad_X u row-major. */
+void or_qf_residual(const or_phase* ph, const or_frac* fr, const double G[9],
+                    double phi, const double gphi[3], double phi_n,
+                    const double st[8], or_qp_out* out);
+
+/* Pointwise directional derivative (steps J1-J12): (dG, dphi, dgphi) -> (dP, df0, df1). */
+void or_qf_jacobian(const or_phase* ph, const or_frac* fr, const double G[9],
+                    double phi, const double gphi[3], double phi_n,
+                    const double st[8], const double dG[9], double dphi,
+                    const double dgphi[3], double dP[9], double* df0, double df1[3]);
+
+/* Pointwise partial derivatives of (P, f0, f1) with respect to the phase's
+ * (Gc, sigma0, visc): dP[k*9+..], df0[k], df1[k*3+..] for k = 0,1,2. */
+void or_qf_param_partials(const or_phase* ph, const or_frac* fr, const double G[9],
+                          double phi, const double gphi[3], double phi_n,
+                          const double st[8], double dP[27], double df0[3], double df1[9]);
+
+/* Global applies. elems = list of element ids to include (NULL = all).
+ * Output vectors are zeroed first and hold the sum over the listed elements.
+ * Return 0 on success, 1 if any quadrature point was non-physical, -1 on bad args. */
+int or_residual(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
+                const uint8_t* phase, const double* state, const double* phi_n,
+                const double* z, double* r, const int32_t* elems, int64_t n_elems);
+int or_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
+                const uint8_t* phase, const double* state, const double* phi_n,
+                const double* z, const double* dz, double* y,
+                const int32_t* elems, int64_t n_elems);
+/* gz = J^T v (built from the explicit transpose of each point's tangent matrix);
+ * gparams[nph*3] = v^T dR/d(Gc, sigma0, visc) summed per phase. */
+int or_adjoint(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
+               const uint8_t* phase, const double* state, const double* phi_n,
+               const double* z, const double* v, double* gz, double* gparams,
+               const int32_t* elems, int64_t n_elems);
+
+/* Dense element Jacobian (4*P^3 x 4*P^3, row-major, dof = field*P^3 + local node)
+ * of element e. */
+int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
+                        const uint8_t* phase, const double* state, const double* phi_n,
+                        const double* z, int64_t e, double* Ke);
+
+/* Number of OpenMP threads the applies use (1 when built without OpenMP). */
+int or_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
