@@ -1,0 +1,500 @@
+// Pointwise (quadrature-point) functions of the coupled operator, device side.
+//
+// Material model (Sections 2-3 of the paper): finite-strain Hencky material,
+// Peric-Dettmer block with a Hooke branch or one Prandtl branch (Box 1, Box 2)
+// whose yield stress carries linear hardening and an overstress factor
+// (1 + a dgamma), a = visc/dt, in series with the phase-field fracture element
+// (degradation g = (1-phi)^2 + eta, Amor split, Miehe history, AT1/AT2 crack
+// density, damage viscosity). The Prandtl update uses the degraded trial stress
+// g*q_tr and g*mu (eq:degraded-trial-stress, eq:degraded-yield-condition).
+//
+// Everything is formulated in the principal frame of b_tr (Appendix A): the
+// stress update acts on eigenvalues, and the tangent (Appendices B-C) acts on
+// the rotated perturbation N^T db N, whose off-diagonal part is scaled by the
+// divided difference (tau_i - tau_j)/(b_i - b_j) = g mu c (ln b_i - ln b_j)/(b_i - b_j),
+// the form of the eigenvector-derivative term that stays finite for equal
+// eigenvalues. The inelastic state is carried as D = Cin^-1 - I so that
+// A = b_tr - I = G + G^T + G G^T + F D F^T is formed without cancellation.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pfmf {
+
+template <typename T> struct MatParams {
+  T mu, kappa, Gc, sigma0, H, a;  // a = visc / dt
+  int plastic;
+};
+
+template <typename T> struct FracParams {
+  T l0, eta, zeta, inv_dt, s_phi, c0, inv_c0l0, kf;  // kf = s_phi * 2 l0 / c0 (times Gc at use)
+  int at;
+};
+
+__device__ inline double pf_rsqrt(double x) { return rsqrt(x); }
+__device__ inline float pf_rsqrt(float x) { return rsqrtf(x); }
+__device__ inline double pf_sqrt(double x) { return sqrt(x); }
+__device__ inline float pf_sqrt(float x) { return sqrtf(x); }
+__device__ inline double pf_log1p(double x) { return log1p(x); }
+__device__ inline float pf_log1p(float x) { return log1pf(x); }
+__device__ inline double pf_abs(double x) { return fabs(x); }
+__device__ inline float pf_abs(float x) { return fabsf(x); }
+
+template <typename T> struct Eps;
+template <> struct Eps<double> {
+  static constexpr double conv = 1e-34;    // squared relative off-diagonal threshold
+  static constexpr double series = 1e-3;   // |x| below which log1p(x)/x uses its series
+  static constexpr int max_sweeps = 8;
+};
+template <> struct Eps<float> {
+  static constexpr float conv = 1e-15f;
+  static constexpr float series = 3e-2f;
+  static constexpr int max_sweeps = 6;
+};
+
+// Symmetric 3x3 stored as s[6] = {xx, yy, zz, yz, xz, xy}.
+// General 3x3 stored row-major m[9].
+
+// Cyclic Jacobi on a symmetric 3x3: a (overwritten, diagonal on exit holds the
+// eigenvalues) and eigenvector matrix V (columns). Uniform sweep count with an
+// early exit when the off-diagonal part is negligible.
+template <typename T>
+__device__ inline void jacobi_rotate(T& app, T& aqq, T& apq, T& arp, T& arq, T* V, int p, int q) {
+  const T o = apq;
+  const T d = aqq - app;
+  // t = tan(angle) of the smaller rotation; t = 0 when o == 0
+  T th = d / (T(2) * o);
+  T t = T(1) / (pf_abs(th) + pf_sqrt(th * th + T(1)));
+  t = (th < T(0)) ? -t : t;
+  t = (o == T(0)) ? T(0) : t;
+  const T c = pf_rsqrt(t * t + T(1));
+  const T s = t * c;
+  app -= t * o;
+  aqq += t * o;
+  apq = T(0);
+  const T rp = c * arp - s * arq;
+  const T rq = s * arp + c * arq;
+  arp = rp;
+  arq = rq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T vp = V[3 * k + p], vq = V[3 * k + q];
+    V[3 * k + p] = c * vp - s * vq;
+    V[3 * k + q] = s * vp + c * vq;
+  }
+}
+
+template <typename T>
+__device__ inline void eig_sym3(const T* A, T* lam, T* V) {
+  T a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? T(1) : T(0);
+  for (int sweep = 0; sweep < Eps<T>::max_sweeps; ++sweep) {
+    const T off = a01 * a01 + a02 * a02 + a12 * a12;
+    const T dia = a00 * a00 + a11 * a11 + a22 * a22;
+    if (off <= Eps<T>::conv * dia) break;
+    jacobi_rotate(a00, a11, a01, a02, a12, V, 0, 1);  // (p,q)=(0,1), r=2: arp=a20, arq=a21
+    jacobi_rotate(a00, a22, a02, a01, a12, V, 0, 2);  // (0,2), r=1: a10, a12
+    jacobi_rotate(a11, a22, a12, a01, a02, V, 1, 2);  // (1,2), r=0: a01, a02
+  }
+  lam[0] = a00;
+  lam[1] = a11;
+  lam[2] = a22;
+}
+
+// (ln b_i - ln b_j) / (b_i - b_j) for b = 1 + beta, finite at b_i == b_j.
+// eps_i = 0.5 ln b_i are already available; below the series threshold the
+// quotient uses log1p(x)/x = 1 - x/2 + x^2/3 - ... with x = b_i/b_j - 1.
+template <typename T>
+__device__ inline T log_divdiff(T beta_i, T beta_j, T eps_i, T eps_j) {
+  const T bj = T(1) + beta_j;
+  const T x = (beta_i - beta_j) / bj;
+  if (pf_abs(x) < Eps<T>::series) {
+    T s = T(1) / T(7);
+    s = T(1) / T(6) - x * s;
+    s = T(1) / T(5) - x * s;
+    s = T(1) / T(4) - x * s;
+    s = T(1) / T(3) - x * s;
+    s = T(1) / T(2) - x * s;
+    s = T(1) - x * s;
+    return s / bj;
+  }
+  return T(2) * (eps_i - eps_j) / (beta_i - beta_j);
+}
+
+// Everything the tangent needs at one point (residual pass output).
+template <typename T> struct QPState {
+  T Fi[9];      // F^-1
+  T b[6];       // b_tr = I + A
+  T N[9];       // eigenvectors of b_tr (columns)
+  T hinv[3];    // 1 / (2 b_i)
+  T e[3];       // deviatoric principal trial log strain
+  T theta;      // tr eps
+  T g, gp;      // degradation and its derivative
+  T c;          // radial-return factor
+  T kq, kphi;   // plastic tangent: d(c e)_i = c de_i + e_i (kq e.de + kphi dphi)
+  T taub[3];    // block principal Kirchhoff stress (undegraded)
+  T taud[3];    // degraded principal Kirchhoff stress
+  T coef[3];    // off-diagonal tangent factors for pairs (1,2), (0,2), (0,1)
+  T tau[6];     // degraded Kirchhoff stress tau_degr
+  T psi, H, L;  // psi^+, max(H_n, psi^+), local phase-field residual
+  T dLcoef;     // dL / dphi at fixed history
+  T ddg_s0, ddg_visc;  // d dgamma / d sigma0, d dgamma / d visc (0 when elastic)
+  bool tension, hactive, plastic, bad;
+};
+
+// Residual state at one point: steps of Box 1 / Box 2 and Section 3.
+//   G: grad_X u (row-major), phi: phase field at the point, phin: previous phi,
+//   st: D[6] (Voigt), ebar_p, H_n.
+template <typename T>
+__device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, const T* G, T phi,
+                                T phin, const T* st, QPState<T>& s) {
+  // F = I + G and its inverse
+  T F[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? T(1) : T(0));
+  const T c00 = F[4] * F[8] - F[5] * F[7];
+  const T c01 = F[5] * F[6] - F[3] * F[8];
+  const T c02 = F[3] * F[7] - F[4] * F[6];
+  const T det = F[0] * c00 + F[1] * c01 + F[2] * c02;
+  const T idet = T(1) / det;
+  s.Fi[0] = c00 * idet;
+  s.Fi[3] = c01 * idet;
+  s.Fi[6] = c02 * idet;
+  s.Fi[1] = (F[2] * F[7] - F[1] * F[8]) * idet;
+  s.Fi[4] = (F[0] * F[8] - F[2] * F[6]) * idet;
+  s.Fi[7] = (F[1] * F[6] - F[0] * F[7]) * idet;
+  s.Fi[2] = (F[1] * F[5] - F[2] * F[4]) * idet;
+  s.Fi[5] = (F[2] * F[3] - F[0] * F[5]) * idet;
+  s.Fi[8] = (F[0] * F[4] - F[1] * F[3]) * idet;
+
+  // A = b_tr - I = G + G^T + G G^T + F D F^T  (eq:inelasticity-be-update, Cin^-1 = I + D)
+  T A[6];
+  const int ri[6] = {0, 1, 2, 1, 0, 0}, ci[6] = {0, 1, 2, 2, 2, 1};
+  T FD[9];
+  {
+    const T D00 = st[0], D11 = st[1], D22 = st[2], D12 = st[3], D02 = st[4], D01 = st[5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T f0 = F[3 * i], f1 = F[3 * i + 1], f2 = F[3 * i + 2];
+      FD[3 * i + 0] = f0 * D00 + f1 * D01 + f2 * D02;
+      FD[3 * i + 1] = f0 * D01 + f1 * D11 + f2 * D12;
+      FD[3 * i + 2] = f0 * D02 + f1 * D12 + f2 * D22;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = ri[k], j = ci[k];
+    T v = G[3 * i + j] + G[3 * j + i];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) v += G[3 * i + l] * G[3 * j + l] + FD[3 * i + l] * F[3 * j + l];
+    A[k] = v;
+    s.b[k] = v + ((k < 3) ? T(1) : T(0));
+  }
+  // principal values and frame (eq:inelasticity-spectral-decomposition)
+  T beta[3];
+  eig_sym3(A, beta, s.N);
+  s.bad = !(det > T(0)) || !(beta[0] > T(-1)) || !(beta[1] > T(-1)) || !(beta[2] > T(-1));
+  // principal trial log strains with log1p (eq:inelasticity-log-strain-principal)
+  T eps[3];
+  s.theta = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    eps[i] = T(0.5) * pf_log1p(beta[i]);
+    s.hinv[i] = T(0.5) / (T(1) + beta[i]);
+    s.theta += eps[i];
+  }
+  const T th3 = s.theta * (T(1) / T(3));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s.e[i] = eps[i] - th3;
+  // degradation (eq:degr-funct)
+  const T omp = T(1) - phi;
+  s.g = omp * omp + fr.eta;
+  s.gp = T(-2) * omp;
+  // Prandtl branch with the degraded trial stress (Box 2, eq:degraded-yield-condition)
+  const T ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
+  const T q = T(2) * m.mu * pf_sqrt(T(1.5) * ee);
+  const T sn = m.sigma0 + m.H * st[6];
+  const T f = s.g * q - sn;
+  s.plastic = m.plastic && (f > T(0));
+  s.c = T(1);
+  s.kq = T(0);
+  s.kphi = T(0);
+  s.ddg_s0 = T(0);
+  s.ddg_visc = T(0);
+  if (s.plastic) {
+    const T B = T(3) * s.g * m.mu + m.H + m.a * sn;
+    const T dg = T(2) * f / (B + pf_sqrt(B * B + T(4) * m.a * m.H * f));
+    const T iq = T(1) / q;
+    s.c = T(1) - T(3) * m.mu * dg * iq;
+    const T sy = sn + m.H * dg;
+    const T den = T(3) * s.g * m.mu + m.H * (T(1) + m.a * dg) + m.a * sy;
+    const T iden = T(1) / den;
+    const T w = T(3) * m.mu * iq;
+    s.kq = -w * (s.g * iden - dg * iq) * (T(6) * m.mu * m.mu * iq);
+    s.kphi = -w * s.gp * (q - T(3) * m.mu * dg) * iden;
+    s.ddg_s0 = -(T(1) + m.a * dg) * iden;
+    s.ddg_visc = -sy * dg * fr.inv_dt * iden;
+  }
+  // block stress, Amor split, psi^+ (eq:principal-stress-update-eigenvalues,
+  // eq:linear-degraded-stress, principal psi^+ of Appendix A)
+  s.tension = s.theta >= T(0);
+  const T kt = m.kappa * s.theta;
+  const T tmu = T(2) * m.mu * s.c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.taub[i] = tmu * s.e[i] + kt;
+    s.taud[i] = s.tension ? s.g * s.taub[i] : s.g * (tmu * s.e[i]) + kt;
+  }
+  s.psi = m.mu * s.c * s.c * ee + (s.tension ? T(0.5) * kt * s.theta : T(0));
+  // history (Miehe): strict switch
+  s.hactive = s.psi > st[7];
+  s.H = s.hactive ? s.psi : st[7];
+  // local phase-field residual (eq:L-viscous) and its phi-derivative (eq:linearized-local-damage-residual)
+  const T alpha_p = (fr.at == 2) ? T(2) * phi : T(1);
+  const T alpha_pp = (fr.at == 2) ? T(2) : T(0);
+  s.L = s.gp * s.H + m.Gc * fr.inv_c0l0 * alpha_p + fr.zeta * (phi - phin) * fr.inv_dt;
+  s.dLcoef = T(2) * s.H + m.Gc * fr.inv_c0l0 * alpha_pp + fr.zeta * fr.inv_dt;
+  // degraded Kirchhoff stress in the global frame
+  const T* N = s.N;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = ri[k], j = ci[k];
+    s.tau[k] = s.taud[0] * N[3 * i] * N[3 * j] + s.taud[1] * N[3 * i + 1] * N[3 * j + 1] +
+               s.taud[2] * N[3 * i + 2] * N[3 * j + 2];
+  }
+  // off-diagonal tangent factors g mu c (ln b_i - ln b_j)/(b_i - b_j)
+  const T gmc = s.g * m.mu * s.c;
+  s.coef[0] = gmc * log_divdiff(beta[1], beta[2], eps[1], eps[2]);
+  s.coef[1] = gmc * log_divdiff(beta[0], beta[2], eps[0], eps[2]);
+  s.coef[2] = gmc * log_divdiff(beta[0], beta[1], eps[0], eps[1]);
+}
+
+// First Piola stress P = tau_degr F^-T (eq:mechanical-gradient-transformation).
+template <typename T>
+__device__ inline void piola(const QPState<T>& s, T* P) {
+  const T* t = s.tau;
+  const T tm[9] = {t[0], t[5], t[4], t[5], t[1], t[3], t[4], t[3], t[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      P[3 * i + J] = tm[3 * i] * s.Fi[3 * J] + tm[3 * i + 1] * s.Fi[3 * J + 1] + tm[3 * i + 2] * s.Fi[3 * J + 2];
+}
+
+// Directional derivative (Appendices B-C): (dG, dphi) -> (dP, dL).
+// The phase-field gradient term is linear and handled by the caller.
+template <typename T>
+__device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
+                                  T* dP, T& dL) {
+  // dl = dG F^-1
+  T dl[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      dl[3 * i + j] = dG[3 * i] * s.Fi[j] + dG[3 * i + 1] * s.Fi[3 + j] + dG[3 * i + 2] * s.Fi[6 + j];
+  // db_tr = dl b + b dl^T  (symmetric)
+  const T* b = s.b;
+  const T bm[9] = {b[0], b[5], b[4], b[5], b[1], b[3], b[4], b[3], b[2]};
+  T M[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = dl[3 * i] * bm[j] + dl[3 * i + 1] * bm[3 + j] + dl[3 * i + 2] * bm[6 + j];
+  const T dA[9] = {2 * M[0],    M[1] + M[3], M[2] + M[6], M[1] + M[3], 2 * M[4],
+                   M[5] + M[7], M[2] + M[6], M[5] + M[7], 2 * M[8]};
+  // rotate into the eigenframe: W = dA N, dbt = N^T W
+  const T* N = s.N;
+  T W[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      W[3 * i + j] = dA[3 * i] * N[j] + dA[3 * i + 1] * N[3 + j] + dA[3 * i + 2] * N[6 + j];
+  T dbd[3], dbo[3];  // diagonal, and off-diagonal pairs (1,2),(0,2),(0,1)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dbd[i] = N[i] * W[i] + N[3 + i] * W[3 + i] + N[6 + i] * W[6 + i];
+  dbo[0] = N[1] * W[2] + N[4] * W[5] + N[7] * W[8];
+  dbo[1] = N[0] * W[2] + N[3] * W[5] + N[6] * W[8];
+  dbo[2] = N[0] * W[1] + N[3] * W[4] + N[6] * W[7];
+  // principal strain increments
+  T deps[3];
+  T dth = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    deps[i] = dbd[i] * s.hinv[i];
+    dth += deps[i];
+  }
+  const T dth3 = dth * (T(1) / T(3));
+  T de[3], dce[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) de[i] = deps[i] - dth3;
+  // linearised radial return (Box A1 generalised)
+  const T kk = s.kq * (s.e[0] * de[0] + s.e[1] * de[1] + s.e[2] * de[2]) + s.kphi * dphi;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dce[i] = s.c * de[i] + s.e[i] * kk;
+  // degraded principal stress increments (eq:linear-degraded-stress-linearization)
+  const T kdt = m.kappa * dth;
+  const T tm2 = T(2) * m.mu;
+  T X[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (s.tension)
+      X[i] = s.g * (tm2 * dce[i] + kdt) + s.gp * dphi * s.taub[i];
+    else
+      X[i] = s.g * (tm2 * dce[i]) + kdt + s.gp * dphi * (s.taub[i] - m.kappa * s.theta);
+  }
+  const T o12 = dbo[0] * s.coef[0], o02 = dbo[1] * s.coef[1], o01 = dbo[2] * s.coef[2];
+  // dtau = N Xfull N^T, Xfull = [[X0,o01,o02],[o01,X1,o12],[o02,o12,X2]]
+  T Y[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T n0 = N[3 * i], n1 = N[3 * i + 1], n2 = N[3 * i + 2];
+    Y[3 * i + 0] = n0 * X[0] + n1 * o01 + n2 * o02;
+    Y[3 * i + 1] = n0 * o01 + n1 * X[1] + n2 * o12;
+    Y[3 * i + 2] = n0 * o02 + n1 * o12 + n2 * X[2];
+  }
+  // Mm = dtau - tau dl^T ; dP = Mm F^-T
+  const T* t = s.tau;
+  const T tm[9] = {t[0], t[5], t[4], t[5], t[1], t[3], t[4], t[3], t[2]};
+  T Mm[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Mm[3 * i + j] = (Y[3 * i] * N[3 * j] + Y[3 * i + 1] * N[3 * j + 1] + Y[3 * i + 2] * N[3 * j + 2]) -
+                      (tm[3 * i] * dl[3 * j] + tm[3 * i + 1] * dl[3 * j + 1] + tm[3 * i + 2] * dl[3 * j + 2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      dP[3 * i + J] = Mm[3 * i] * s.Fi[3 * J] + Mm[3 * i + 1] * s.Fi[3 * J + 1] + Mm[3 * i + 2] * s.Fi[3 * J + 2];
+  // history and local phase-field residual (eq:history-field-linearization,
+  // eq:energy-displacement-linearization, eq:linearized-local-damage-residual)
+  T dH = T(0);
+  if (s.hactive) {
+    dH = tm2 * s.c * (s.e[0] * dce[0] + s.e[1] * dce[1] + s.e[2] * dce[2]);
+    if (s.tension) dH += m.kappa * s.theta * dth;
+  }
+  dL = s.dLcoef * dphi + s.gp * dH;
+}
+
+// Reverse (transpose) of qp_tangent: cotangents (Pb = dP-bar, Lb = dL-bar) ->
+// (Gb = dG-bar, phib = dphi-bar). Also returns the diagonal of the rotated stress
+// cotangent Xd_i = [N^T (Pb F^-1) N]_ii used by the parameter partials.
+template <typename T>
+__device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, const T* Pb, T Lb, T* Gb,
+                                    T& phib, T* Xd) {
+  const T* N = s.N;
+  const T tm2 = T(2) * m.mu;
+  // dL = dLcoef dphi + gp dH
+  phib = s.dLcoef * Lb;
+  const T Hb = s.gp * Lb;
+  // Mmb = Pb F^-1   (dP = Mm F^-T)
+  T Mmb[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      Mmb[3 * i + k] = Pb[3 * i] * s.Fi[k] + Pb[3 * i + 1] * s.Fi[3 + k] + Pb[3 * i + 2] * s.Fi[6 + k];
+  // dl-bar from -tau dl^T:  dlb = -Mmb^T tau
+  const T* t = s.tau;
+  const T tm[9] = {t[0], t[5], t[4], t[5], t[1], t[3], t[4], t[3], t[2]};
+  T dlb[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dlb[3 * j + k] = -(Mmb[j] * tm[k] + Mmb[3 + j] * tm[3 + k] + Mmb[6 + j] * tm[6 + k]);
+  // Xb = N^T Mmb N
+  T Z[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Z[3 * i + j] = Mmb[3 * i] * N[j] + Mmb[3 * i + 1] * N[3 + j] + Mmb[3 * i + 2] * N[6 + j];
+  T Xb[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Xb[3 * i + j] = N[i] * Z[j] + N[3 + i] * Z[3 + j] + N[6 + i] * Z[6 + j];
+  Xd[0] = Xb[0];
+  Xd[1] = Xb[4];
+  Xd[2] = Xb[8];
+  // off-diagonal: X_ij = dbt_ij coef_ij (both (i,j) and (j,i))
+  T dbtb[9];
+  dbtb[5] = dbtb[7] = (Xb[5] + Xb[7]) * s.coef[0];  // (1,2)
+  dbtb[2] = dbtb[6] = (Xb[2] + Xb[6]) * s.coef[1];  // (0,2)
+  dbtb[1] = dbtb[3] = (Xb[1] + Xb[3]) * s.coef[2];  // (0,1)
+  // each off-diagonal dbt entry of the symmetric forward matrix appears in both
+  // positions of the full product, so its cotangent is shared equally
+  dbtb[5] *= T(0.5); dbtb[7] *= T(0.5);
+  dbtb[2] *= T(0.5); dbtb[6] *= T(0.5);
+  dbtb[1] *= T(0.5); dbtb[3] *= T(0.5);
+  // diagonal stress increments
+  T dceb[3] = {T(0), T(0), T(0)};
+  T dthb = T(0);
+  const T kapth = m.kappa * s.theta;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T xb = Xb[4 * i];
+    if (s.tension) {
+      dceb[i] += s.g * tm2 * xb;
+      dthb += s.g * m.kappa * xb;
+      phib += s.gp * s.taub[i] * xb;
+    } else {
+      dceb[i] += s.g * tm2 * xb;
+      dthb += m.kappa * xb;
+      phib += s.gp * (s.taub[i] - kapth) * xb;
+    }
+  }
+  // history: dH = hactive (2 mu c e.dce + tension kappa theta dth)
+  if (s.hactive) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dceb[i] += tm2 * s.c * s.e[i] * Hb;
+    if (s.tension) dthb += kapth * Hb;
+  }
+  // dce_i = c de_i + e_i (kq e.de + kphi dphi)
+  const T sdot = s.e[0] * dceb[0] + s.e[1] * dceb[1] + s.e[2] * dceb[2];
+  T deb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) deb[i] = s.c * dceb[i] + s.kq * sdot * s.e[i];
+  phib += s.kphi * sdot;
+  // de_i = deps_i - dth/3, dth = sum deps
+  const T mdeb = (deb[0] + deb[1] + deb[2]) * (T(1) / T(3));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) dbtb[4 * i] = (deb[i] - mdeb + dthb) * s.hinv[i];
+  // dbt = N^T dA N  ->  dAb = N dbtb N^T
+  T R[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      R[3 * i + j] = N[3 * i] * dbtb[j] + N[3 * i + 1] * dbtb[3 + j] + N[3 * i + 2] * dbtb[6 + j];
+  T dAb[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dAb[3 * i + j] = R[3 * i] * N[3 * j] + R[3 * i + 1] * N[3 * j + 1] + R[3 * i + 2] * N[3 * j + 2];
+  // dA = M + M^T, M = dl b  ->  Mb = dAb + dAb^T ; dlb += Mb b
+  const T* b = s.b;
+  const T bm[9] = {b[0], b[5], b[4], b[5], b[1], b[3], b[4], b[3], b[2]};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      T acc = T(0);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) acc += (dAb[3 * i + j] + dAb[3 * j + i]) * bm[3 * k + j];
+      dlb[3 * i + k] += acc;
+    }
+  // dl = dG F^-1  ->  Gb = dlb F^-T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J)
+      Gb[3 * i + J] = dlb[3 * i] * s.Fi[3 * J] + dlb[3 * i + 1] * s.Fi[3 * J + 1] + dlb[3 * i + 2] * s.Fi[3 * J + 2];
+}
+
+}  // namespace pfmf

@@ -1,0 +1,398 @@
+// libpfmf: host side of the C ABI declared in include/pfmf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pfmf.h"
+#include "pf_ops.hpp"
+#include "pf_mg.hpp"
+#include "pf_tables.hpp"
+
+using namespace pfmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+pf_status fail(pf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(PF_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct pf_ctx {
+  int device = 0;
+  pf_mesh_desc mesh{};
+  int P = 0, Q = 0;
+  int nx1 = 0, ny1 = 0, nz1 = 0;
+  int64_t n_nodes = 0, n_q = 0;
+  int nbx = 0, nby = 0, nbz = 0, n_bricks = 0;
+  int colour_base[9] = {0};
+  std::vector<pf_phase> phases;
+  pf_fracture fr{};
+  const uint8_t* qp_phase = nullptr;
+  const double* qp_state = nullptr;
+  const double* phi_n = nullptr;
+  // device buffers
+  DevTables* d_tab = nullptr;
+  DevTablesF* d_tabf = nullptr;
+  MatParams<double>* d_mats = nullptr;
+  MatParams<float>* d_matsf = nullptr;
+  double* d_gpart = nullptr;
+  int* d_flag = nullptr;
+  hipStream_t last_stream = nullptr;
+  MGState mg;
+};
+
+namespace {
+
+MeshDev mesh_dev(const pf_ctx* c) {
+  MeshDev m;
+  m.nx = c->mesh.nx;
+  m.ny = c->mesh.ny;
+  m.nz = c->mesh.nz;
+  m.nbx = c->nbx;
+  m.nby = c->nby;
+  m.nbz = c->nbz;
+  m.hx = c->mesh.lx / c->mesh.nx;
+  m.hy = c->mesh.ly / c->mesh.ny;
+  m.hz = c->mesh.lz / c->mesh.nz;
+  return m;
+}
+
+template <typename T>
+FracParams<T> frac_params(const pf_fracture& f) {
+  FracParams<T> r;
+  const double c0 = (f.at == 2) ? 2.0 : 8.0 / 3.0;
+  r.l0 = (T)f.l0;
+  r.eta = (T)f.eta;
+  r.zeta = (T)f.zeta;
+  r.inv_dt = (T)(1.0 / f.dt);
+  r.s_phi = (T)f.s_phi;
+  r.c0 = (T)c0;
+  r.inv_c0l0 = (T)(1.0 / (c0 * f.l0));
+  r.kf = (T)(f.s_phi * 2.0 * f.l0 / c0);
+  r.at = f.at;
+  return r;
+}
+
+template <typename T>
+MatParams<T> mat_params(const pf_phase& p, const pf_fracture& f) {
+  MatParams<T> m;
+  m.mu = (T)(p.E / (2.0 * (1.0 + p.nu)));
+  m.kappa = (T)(p.E / (3.0 * (1.0 - 2.0 * p.nu)));
+  m.Gc = (T)p.Gc;
+  m.sigma0 = (T)p.sigma0;
+  m.H = (T)p.H;
+  m.a = (T)(p.visc / f.dt);
+  m.plastic = p.plastic ? 1 : 0;
+  return m;
+}
+
+pf_status upload_mats(pf_ctx* c) {
+  std::vector<MatParams<double>> md;
+  std::vector<MatParams<float>> mf;
+  for (auto& p : c->phases) {
+    md.push_back(mat_params<double>(p, c->fr));
+    mf.push_back(mat_params<float>(p, c->fr));
+  }
+  HIPCHK(hipMemcpy(c->d_mats, md.data(), md.size() * sizeof(md[0]), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_matsf, mf.data(), mf.size() * sizeof(mf[0]), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+pf_status build_tables(pf_ctx* c) {
+  auto* t = new DevTables;
+  auto* tf = new DevTablesF;
+  std::memset(t, 0, sizeof *t);
+  std::memset(tf, 0, sizeof *tf);
+  for (int P = 2; P <= 5; ++P) {
+    std::vector<double> xn;
+    gauss_lobatto(P, xn);
+    for (int Q = 2; Q <= 5; ++Q) {
+      std::vector<double> xq, wq, B, D;
+      gauss_legendre(Q, xq, wq);
+      lagrange_tables(xn, xq, B, D);
+      for (int q = 0; q < Q; ++q) {
+        t->w[Q][q] = wq[q];
+        tf->w[Q][q] = (float)wq[q];
+        for (int i = 0; i < P; ++i) {
+          t->B[P][Q][q][i] = B[q * P + i];
+          t->D[P][Q][q][i] = D[q * P + i];
+          tf->B[P][Q][q][i] = (float)B[q * P + i];
+          tf->D[P][Q][q][i] = (float)D[q * P + i];
+        }
+      }
+    }
+  }
+  hipError_t e1 = hipMalloc(&c->d_tab, sizeof(DevTables));
+  hipError_t e2 = hipMalloc(&c->d_tabf, sizeof(DevTablesF));
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    delete t;
+    delete tf;
+    return fail(PF_ENOMEM, "table allocation failed");
+  }
+  hipError_t e3 = hipMemcpy(c->d_tab, t, sizeof(DevTables), hipMemcpyHostToDevice);
+  hipError_t e4 = hipMemcpy(c->d_tabf, tf, sizeof(DevTablesF), hipMemcpyHostToDevice);
+  delete t;
+  delete tf;
+  if (e3 != hipSuccess || e4 != hipSuccess) return fail(PF_EHIP, "table upload failed");
+  return PF_OK;
+}
+
+pf_status check_ctx(pf_ctx* c) {
+  if (!c) return fail(PF_EINVAL, "null context");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device) return fail(PF_EINVAL, "context belongs to device %d, current device is %d", c->device, dev);
+  return PF_OK;
+}
+
+template <int MODE, int P, int Q>
+pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
+  using S = OpShape<P, Q>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_op64<MODE, P, Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)S::lds_bytes));
+    attr_set = true;
+  }
+  for (int col = 0; col < 8; ++col) {
+    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    a.brick_base = c->colour_base[col];
+    hipLaunchKernelGGL((k_op64<MODE, P, Q>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int MODE>
+pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
+  switch (c->mesh.p) {
+    case 1: return launch_op64<MODE, 2, 2>(c, a, s);
+    case 2: return launch_op64<MODE, 3, 3>(c, a, s);
+    case 3: return launch_op64<MODE, 4, 4>(c, a, s);
+    case 4: return launch_op64<MODE, 5, 5>(c, a, s);
+    default: return fail(PF_EUNSUPPORTED, "order p=%d not built", c->mesh.p);
+  }
+}
+
+OpArgs op_args(pf_ctx* c) {
+  OpArgs a;
+  a.m = mesh_dev(c);
+  a.nx1 = c->nx1;
+  a.ny1 = c->ny1;
+  a.n_nodes = c->n_nodes;
+  a.n_q = c->n_q;
+  a.z = nullptr;
+  a.w = nullptr;
+  a.phin = c->phi_n;
+  a.state = c->qp_state;
+  a.phase = c->qp_phase;
+  a.mats = c->d_mats;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<double>(c->fr);
+  a.out = nullptr;
+  a.gpart = c->d_gpart;
+  a.brick_base = 0;
+  a.flag = c->d_flag;
+  return a;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+
+pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_phases, const pf_fracture* fr,
+                        const uint8_t* qp_phase, const double* qp_state, const double* phi_n, void* stream,
+                        pf_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(PF_EINVAL, "out is null");
+  *out = nullptr;
+  if (!mesh || !phases || !fr || !qp_phase || !qp_state || !phi_n) return fail(PF_EINVAL, "null argument");
+  if (mesh->p < 1 || mesh->p > 4) return fail(PF_EUNSUPPORTED, "order p=%d outside 1..4", mesh->p);
+  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(PF_EINVAL, "empty mesh");
+  if (!(mesh->lx > 0 && mesh->ly > 0 && mesh->lz > 0)) return fail(PF_EINVAL, "box lengths must be positive");
+  if (n_phases < 1 || n_phases > 255) return fail(PF_EINVAL, "n_phases=%d outside 1..255", n_phases);
+  if (!(fr->l0 > 0 && fr->dt > 0 && fr->eta >= 0 && fr->s_phi > 0) || (fr->at != 1 && fr->at != 2))
+    return fail(PF_EINVAL, "bad fracture parameters");
+  const int64_t nx1 = (int64_t)mesh->p * mesh->nx + 1, ny1 = (int64_t)mesh->p * mesh->ny + 1,
+                nz1 = (int64_t)mesh->p * mesh->nz + 1;
+  if (nx1 * ny1 * nz1 >= (int64_t)1 << 31) return fail(PF_EINVAL, "mesh too large for 32-bit node ids");
+  for (int i = 0; i < n_phases; ++i) {
+    const pf_phase& p = phases[i];
+    if (!(p.E > 0 && p.nu > -1 && p.nu < 0.5 && p.Gc >= 0 && p.sigma0 >= 0 && p.H >= 0 && p.visc >= 0))
+      return fail(PF_EINVAL, "bad parameters for phase %d", i);
+    if (p.plastic && !(p.sigma0 > 0)) return fail(PF_EINVAL, "plastic phase %d needs sigma0 > 0", i);
+  }
+  auto* c = new pf_ctx;
+  (void)hipGetDevice(&c->device);
+  c->mesh = *mesh;
+  c->P = mesh->p + 1;
+  c->Q = mesh->p + 1;
+  c->nx1 = (int)nx1;
+  c->ny1 = (int)ny1;
+  c->nz1 = (int)nz1;
+  c->n_nodes = nx1 * ny1 * nz1;
+  c->n_q = (int64_t)mesh->nx * mesh->ny * mesh->nz * c->Q * c->Q * c->Q;
+  c->nbx = (mesh->nx + 1) / 2;
+  c->nby = (mesh->ny + 1) / 2;
+  c->nbz = (mesh->nz + 1) / 2;
+  c->n_bricks = c->nbx * c->nby * c->nbz;
+  c->colour_base[0] = 0;
+  for (int col = 0; col < 8; ++col)
+    c->colour_base[col + 1] = c->colour_base[col] + bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+  c->phases.assign(phases, phases + n_phases);
+  c->fr = *fr;
+  c->qp_phase = qp_phase;
+  c->qp_state = qp_state;
+  c->phi_n = phi_n;
+  c->last_stream = (hipStream_t)stream;
+  pf_status st = build_tables(c);
+  if (st != PF_OK) { pf_destroy(c); return st; }
+  if (hipMalloc(&c->d_mats, n_phases * sizeof(MatParams<double>)) != hipSuccess ||
+      hipMalloc(&c->d_matsf, n_phases * sizeof(MatParams<float>)) != hipSuccess ||
+      hipMalloc(&c->d_gpart, (size_t)c->n_bricks * n_phases * 3 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
+    pf_destroy(c);
+    return fail(PF_ENOMEM, "context allocation failed");
+  }
+  if (hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess) { pf_destroy(c); return fail(PF_EHIP, "memset failed"); }
+  st = upload_mats(c);
+  if (st != PF_OK) { pf_destroy(c); return st; }
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf_sizes(const pf_ctx* c, int64_t* n_nodes, int64_t* n_q, int64_t* n_dof) {
+  if (!c) return fail(PF_EINVAL, "null context");
+  if (n_nodes) *n_nodes = c->n_nodes;
+  if (n_q) *n_q = c->n_q;
+  if (n_dof) *n_dof = 4 * c->n_nodes;
+  return PF_OK;
+}
+
+pf_status pf_set_params(pf_ctx* c, const double* params) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!params) return fail(PF_EINVAL, "null params");
+  for (size_t i = 0; i < c->phases.size(); ++i) {
+    const double gc = params[3 * i], s0 = params[3 * i + 1], vi = params[3 * i + 2];
+    if (!(gc >= 0 && s0 >= 0 && vi >= 0)) return fail(PF_EINVAL, "bad parameters for phase %zu", i);
+    if (c->phases[i].plastic && !(s0 > 0)) return fail(PF_EINVAL, "plastic phase %zu needs sigma0 > 0", i);
+  }
+  for (size_t i = 0; i < c->phases.size(); ++i) {
+    c->phases[i].Gc = params[3 * i];
+    c->phases[i].sigma0 = params[3 * i + 1];
+    c->phases[i].visc = params[3 * i + 2];
+  }
+  // stream-ordered with respect to the default stream only; the caller
+  // synchronises its own stream before changing parameters
+  HIPCHK(hipDeviceSynchronize());
+  return upload_mats(c);
+}
+
+pf_status pf_apply_residual(pf_ctx* c, const double* z, double* r, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!z || !r) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->n_nodes * sizeof(double);
+  if (overlaps(z, nb, r, nb)) return fail(PF_EINVAL, "r aliases z");
+  OpArgs a = op_args(c);
+  a.z = z;
+  a.out = r;
+  c->last_stream = (hipStream_t)stream;
+  return dispatch_op64<M_RES>(c, a, (hipStream_t)stream);
+}
+
+pf_status pf_apply_jacobian(pf_ctx* c, const double* z, const double* dz, double* y, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!z || !dz || !y) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->n_nodes * sizeof(double);
+  if (overlaps(z, nb, y, nb) || overlaps(dz, nb, y, nb)) return fail(PF_EINVAL, "y aliases an input");
+  OpArgs a = op_args(c);
+  a.z = z;
+  a.w = dz;
+  a.out = y;
+  c->last_stream = (hipStream_t)stream;
+  return dispatch_op64<M_JAC>(c, a, (hipStream_t)stream);
+}
+
+pf_status pf_apply_adjoint(pf_ctx* c, const double* z, const double* v, double* gz, double* gparams, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!z || !v || !gz || !gparams) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->n_nodes * sizeof(double);
+  const size_t np = c->phases.size() * 3 * sizeof(double);
+  if (overlaps(z, nb, gz, nb) || overlaps(v, nb, gz, nb) || overlaps(gparams, np, gz, nb) ||
+      overlaps(gparams, np, z, nb) || overlaps(gparams, np, v, nb))
+    return fail(PF_EINVAL, "an output aliases an input");
+  OpArgs a = op_args(c);
+  a.z = z;
+  a.w = v;
+  a.out = gz;
+  c->last_stream = (hipStream_t)stream;
+  st = dispatch_op64<M_ADJ>(c, a, (hipStream_t)stream);
+  if (st) return st;
+  hipLaunchKernelGGL(k_sum_params, dim3((int)c->phases.size() * 3), dim3(NT), 0, (hipStream_t)stream, c->d_gpart,
+                     c->n_bricks, (int)c->phases.size(), gparams);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status pf_check(pf_ctx* c) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(c->last_stream));
+  int flag = 0;
+  HIPCHK(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIPCHK(hipMemset(c->d_flag, 0, sizeof(int)));
+    return fail(PF_ENONPHYSICAL, "a quadrature point left the physical domain (det F <= 0 or b_i <= 0)");
+  }
+  return PF_OK;
+}
+
+void pf_destroy(pf_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  mg_free(c->mg);
+  (void)hipFree(c->d_tab);
+  (void)hipFree(c->d_tabf);
+  (void)hipFree(c->d_mats);
+  (void)hipFree(c->d_matsf);
+  (void)hipFree(c->d_gpart);
+  (void)hipFree(c->d_flag);
+  delete c;
+}
+
+}  // extern "C"
+
+#include "pf_mg_host.hpp"

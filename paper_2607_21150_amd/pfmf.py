@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libpfmf.so (the C ABI in include/pfmf.h).
+
+Argument marshalling only: every step of the operator runs in the library's HIP
+kernels. Torch provides device memory and the current stream. Importing this
+module does not load the library; the first call does, and it raises if the
+library is missing (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfmf.so")
+
+PF_OK, PF_EINVAL, PF_EHIP, PF_ENOMEM, PF_EUNSUPPORTED, PF_ENONPHYSICAL = 0, -1, -2, -3, -4, -5
+
+EXPORTED = [
+    "pf_setup_mesh", "pf_sizes", "pf_set_params", "pf_apply_residual", "pf_apply_jacobian",
+    "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
+    "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
+]
+
+
+class PfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pfmf error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("p", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double)]
+
+
+class PhaseDesc(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("Gc", C.c_double), ("sigma0", C.c_double),
+                ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int)]
+
+
+class FractureDesc(C.Structure):
+    _fields_ = [("l0", C.c_double), ("eta", C.c_double), ("zeta", C.c_double), ("dt", C.c_double),
+                ("s_phi", C.c_double), ("at", C.c_int)]
+
+
+class PmgOpts(C.Structure):
+    _fields_ = [("cheb_degree", C.c_int), ("coarse_p", C.c_int), ("coarse_sweeps", C.c_int),
+                ("reserved", C.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpfmf.so and declare its signatures (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python -m paper_2607_21150_amd.build")
+    L = C.CDLL(LIB_PATH)
+    vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+    L.pf_setup_mesh.argtypes = [C.POINTER(MeshDesc), C.POINTER(PhaseDesc), C.c_int, C.POINTER(FractureDesc),
+                                vp, vp, vp, vp, C.POINTER(vp)]
+    L.pf_sizes.argtypes = [vp, i64p, i64p, i64p]
+    L.pf_set_params.argtypes = [vp, vp]
+    L.pf_apply_residual.argtypes = [vp, vp, vp, vp]
+    L.pf_apply_jacobian.argtypes = [vp, vp, vp, vp, vp]
+    L.pf_apply_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pf_linearize.argtypes = [vp, vp, vp]
+    L.pf_level_info.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p]
+    L.pf_apply_jacobian_f32.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.pf_prolong.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.pf_restrict.argtypes = [vp, C.c_int, vp, vp, vp]
+    L.pf_level_diagonal.argtypes = [vp, C.c_int, vp, vp]
+    L.pf_pmg_vcycle.argtypes = [vp, vp, vp, C.POINTER(PmgOpts), vp]
+    L.pf_check.argtypes = [vp]
+    L.pf_destroy.argtypes = [vp]
+    L.pf_destroy.restype = None
+    L.pf_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("pf_destroy", "pf_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != PF_OK:
+        msg = load().pf_last_error().decode()
+        raise PfError(code, msg)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _req(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise PfError(PF_EINVAL, f"{name} must be a device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise PfError(PF_EINVAL, f"{name}: expected contiguous {dtype} {tuple(shape)}, "
+                                 f"got {t.dtype} {tuple(t.shape)}")
+    return t
+
+
+class Context:
+    """One operator context (pf_ctx). Holds references to the device state tensors."""
+
+    def __init__(self, mesh, phases, fracture, qp_phase, qp_state, phi_n, stream=None):
+        L = load()
+        self._phases = list(phases)
+        md = MeshDesc(mesh.p, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz)
+        arr = (PhaseDesc * len(phases))(*[PhaseDesc(p.E, p.nu, p.Gc, p.sigma0, p.H, p.visc, int(p.plastic))
+                                          for p in phases])
+        fd = FractureDesc(fracture.l0, fracture.eta, fracture.zeta, fracture.dt, fracture.s_phi, int(fracture.at))
+        self.n_nodes = mesh.n_nodes
+        self.n_q = mesh.n_q
+        self.mesh = mesh
+        self.qp_phase = _req(qp_phase, torch.uint8, (mesh.n_q,), "qp_phase")
+        self.qp_state = _req(qp_state, torch.float64, (8, mesh.n_q), "qp_state")
+        self.phi_n = _req(phi_n, torch.float64, (mesh.n_nodes,), "phi_n")
+        h = C.c_void_p()
+        _check(L.pf_setup_mesh(C.byref(md), arr, len(phases), C.byref(fd), _ptr(self.qp_phase),
+                               _ptr(self.qp_state), _ptr(self.phi_n), _stream(stream), C.byref(h)))
+        self._h = h
+        self.n_phases = len(phases)
+
+    @classmethod
+    def from_inputs(cls, d, device="cuda"):
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        return cls(d["mesh"], d["phases"], d["fracture"], t(d["phase"], torch.uint8),
+                   t(d["state"], torch.float64), t(d["phi_n"], torch.float64))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- C ABI calls (same names)
+    def sizes(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(load().pf_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.n_phases, 3))
+        _check(load().pf_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+
+    def apply_residual(self, z, r=None, stream=None):
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        r = torch.empty_like(z) if r is None else _req(r, torch.float64, (4, self.n_nodes), "r")
+        _check(load().pf_apply_residual(self._h, _ptr(z), _ptr(r), _stream(stream)))
+        return r
+
+    def apply_jacobian(self, z, dz, y=None, stream=None):
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        _req(dz, torch.float64, (4, self.n_nodes), "dz")
+        y = torch.empty_like(z) if y is None else _req(y, torch.float64, (4, self.n_nodes), "y")
+        _check(load().pf_apply_jacobian(self._h, _ptr(z), _ptr(dz), _ptr(y), _stream(stream)))
+        return y
+
+    def apply_adjoint(self, z, v, gz=None, gparams=None, stream=None):
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        _req(v, torch.float64, (4, self.n_nodes), "v")
+        gz = torch.empty_like(z) if gz is None else _req(gz, torch.float64, (4, self.n_nodes), "gz")
+        if gparams is None:
+            gparams = torch.empty((self.n_phases, 3), dtype=torch.float64, device=z.device)
+        _req(gparams, torch.float64, (self.n_phases, 3), "gparams")
+        _check(load().pf_apply_adjoint(self._h, _ptr(z), _ptr(v), _ptr(gz), _ptr(gparams), _stream(stream)))
+        return gz, gparams
+
+    def linearize(self, z, stream=None):
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        _check(load().pf_linearize(self._h, _ptr(z), _stream(stream)))
+
+    def level_info(self, level):
+        p, n = C.c_int(), C.c_int64()
+        _check(load().pf_level_info(self._h, int(level), C.byref(p), C.byref(n)))
+        return p.value, n.value
+
+    def apply_jacobian_f32(self, level, dz, y=None, stream=None):
+        _, n = self.level_info(level)
+        _req(dz, torch.float32, (4, n), "dz")
+        y = torch.empty_like(dz) if y is None else _req(y, torch.float32, (4, n), "y")
+        _check(load().pf_apply_jacobian_f32(self._h, int(level), _ptr(dz), _ptr(y), _stream(stream)))
+        return y
+
+    def prolong(self, level, xc, xf=None, stream=None):
+        _, nf = self.level_info(level)
+        _, nc = self.level_info(level + 1)
+        _req(xc, torch.float32, (4, nc), "xc")
+        xf = torch.empty((4, nf), dtype=torch.float32, device=xc.device) if xf is None else xf
+        _check(load().pf_prolong(self._h, int(level), _ptr(xc), _ptr(xf), _stream(stream)))
+        return xf
+
+    def restrict(self, level, rf, rc=None, stream=None):
+        _, nf = self.level_info(level)
+        _, nc = self.level_info(level + 1)
+        _req(rf, torch.float32, (4, nf), "rf")
+        rc = torch.empty((4, nc), dtype=torch.float32, device=rf.device) if rc is None else rc
+        _check(load().pf_restrict(self._h, int(level), _ptr(rf), _ptr(rc), _stream(stream)))
+        return rc
+
+    def level_diagonal(self, level, stream=None):
+        _, n = self.level_info(level)
+        d = torch.empty((4, n), dtype=torch.float32, device="cuda")
+        _check(load().pf_level_diagonal(self._h, int(level), _ptr(d), _stream(stream)))
+        return d
+
+    def pmg_vcycle(self, b, x=None, cheb_degree=3, coarse_p=1, coarse_sweeps=4, stream=None):
+        _req(b, torch.float32, (4, self.n_nodes), "b")
+        x = torch.empty_like(b) if x is None else _req(x, torch.float32, (4, self.n_nodes), "x")
+        o = PmgOpts(cheb_degree, coarse_p, coarse_sweeps, 0)
+        _check(load().pf_pmg_vcycle(self._h, _ptr(b), _ptr(x), C.byref(o), _stream(stream)))
+        return x
+
+    def check(self):
+        _check(load().pf_check(self._h))
