@@ -1,13 +1,537 @@
-// FP32 p-multigrid state (device buffers owned by the context).
+// FP32 p-multigrid: linearisation record, level operators at the fine
+// quadrature, point-Jacobi diagonals, level transfers and Chebyshev vector ops.
+//
+// Levels are orders p, p-1, ..., coarse_p on the same mesh. Every level is
+// evaluated at the fine Gauss points with the fine linearisation record, so a
+// coarse operator is the Galerkin product P^T A P of the fine one (the coarse
+// space is a subspace of the fine space). Kinematics (F, eigenframe, log strains)
+// are recomputed in FP32 from FP32 mirrors of u and D at every apply; the yield,
+// split and history decisions and the return-mapping scalars come from the
+// record taken in FP64 by the linearisation.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "pf_brick.hpp"
+#include "pf_ops.hpp"
+#include "pf_qf.hpp"
+
 namespace pfmf {
+
+struct RecordSoA {
+  float* rec;      // [6][n_q]: c, kq, kphi, g, gp, dL
+  uint8_t* flags;  // [n_q]
+  float* D32;      // [6][n_q]
+};
+
+struct LevelDev {
+  int P;           // nodes per direction of this level's elements
+  int nx1, ny1;
+  int64_t n_nodes;
+};
+
+struct MGLevel {
+  int p = 0, P = 0;
+  int nx1 = 0, ny1 = 0, nz1 = 0;
+  int64_t n_nodes = 0;
+  float *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *b = nullptr;
+  float *diag = nullptr, *dinv = nullptr;
+  double lmax = 0.0;
+  // transfer to the next coarser level: per direction, prolongation rows
+  // (fine index -> coarse base + Pc weights) and restriction rows
+  // (coarse index -> fine base + (2 pf + 1) weights)
+  int* pbase[3] = {nullptr, nullptr, nullptr};
+  float* pw[3] = {nullptr, nullptr, nullptr};
+  int* rbase[3] = {nullptr, nullptr, nullptr};
+  float* rw[3] = {nullptr, nullptr, nullptr};
+};
 
 struct MGState {
   int n_levels = 0;
+  MGLevel lv[5];
+  float* z32 = nullptr;  // FP32 mirror of u on the fine level [3][n_nodes]
+  RecordSoA rec{nullptr, nullptr, nullptr};
+  float* tmpA = nullptr;
+  float* tmpB = nullptr;
+  double* red = nullptr;  // reduction scratch
+  bool linearized = false;
 };
 
-inline void mg_free(MGState& mg) { mg.n_levels = 0; }
+inline void mg_free_level(MGLevel& L) {
+  float* fs[] = {L.x, L.r, L.d, L.t, L.b, L.diag, L.dinv};
+  for (float* f : fs) (void)hipFree(f);
+  for (int k = 0; k < 3; ++k) {
+    (void)hipFree(L.pbase[k]);
+    (void)hipFree(L.pw[k]);
+    (void)hipFree(L.rbase[k]);
+    (void)hipFree(L.rw[k]);
+  }
+  L = MGLevel();
+}
+
+inline void mg_free(MGState& mg) {
+  for (int l = 0; l < 5; ++l) mg_free_level(mg.lv[l]);
+  (void)hipFree(mg.z32);
+  (void)hipFree(mg.rec.rec);
+  (void)hipFree(mg.rec.flags);
+  (void)hipFree(mg.rec.D32);
+  (void)hipFree(mg.tmpA);
+  (void)hipFree(mg.tmpB);
+  (void)hipFree(mg.red);
+  mg = MGState();
+}
+
+// ---------------------------------------------------------------------------
+// Linearisation: FP64 decisions -> FP32 record (one launch over all bricks).
+// ---------------------------------------------------------------------------
+
+struct LinArgs {
+  MeshDev m;
+  int nx1, ny1;
+  int64_t n_nodes, n_q;
+  const double* z;
+  const double* phin;
+  const double* state;
+  const uint8_t* phase;
+  const MatParams<double>* mats;
+  int nph;
+  FracParams<double> fr;
+  RecordSoA rec;
+  int* flag;
+};
+
+template <int P, int Q>
+__global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTables* __restrict__ tabs) {
+  using S = OpShape<P, Q>;
+  constexpr int NB3 = S::NB3, Q3 = S::Q3, ER = S::ER;
+  extern __shared__ double lds[];
+  double* zb = lds;
+  double* tmp = zb + 4 * NB3;
+  double* tab = tmp + S::TMP;
+  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  for (int t = threadIdx.x; t < Q * P; t += NT) {
+    tab[t] = tabs->B[P][Q][t / P][t % P];
+    tab[Q * P + t] = tabs->D[P][Q][t / P][t % P];
+  }
+  stage_brick<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, zb);
+  __syncthreads();
+  const TabRef<double> tb{tab, tab + Q * P};
+  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
+  double* xb = tmp;
+  double* xd = xb + ER * P * P * Q;
+  double* ybb = xd + ER * P * P * Q;
+  double* ydb = ybb + ER * P * Q * Q;
+  double* ybd = ydb + ER * P * Q * Q;
+  const int t = threadIdx.x;
+  const int el = t / Q3, ql = t % Q3;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  bool any_bad = false;
+  for (int r = 0; r < S::ROUNDS; ++r) {
+    const int slot0 = r * ER, slot = slot0 + el;
+    const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+    const bool active = (t < ER * Q3) && (slot < 8) && sx < g.nex && sy < g.ney && sz < g.nez;
+    double G[9], phi = 0.0;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      fwd_xy<double, P, Q, ER>(zb + f * NB3, slot0, g, tb, f < 3, xb, xd, ybb, ydb, ybd);
+      if (t < ER * Q3) {
+        double v, d[3];
+        fwd_z<double, P, Q>(ybb, ydb, ybd, el, qx, qy, qz, tb, f < 3, v, d);
+        if (f < 3) {
+#pragma unroll
+          for (int J = 0; J < 3; ++J) G[3 * f + J] = d[J] * ih[J];
+        } else {
+          phi = v;
+        }
+      }
+      __syncthreads();
+    }
+    if (active) {
+      const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+      const int64_t gq = e * Q3 + ql;
+      double st[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];
+      const int pid = a.phase[gq];
+      const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+      QPState<double> s;
+      qp_state<double>(mp, a.fr, G, phi, 0.0, st, s);
+      any_bad |= s.bad;
+      LinRecord rc;
+      record_from_state<double>(s, rc);
+      a.rec.rec[0 * a.n_q + gq] = rc.c;
+      a.rec.rec[1 * a.n_q + gq] = rc.kq;
+      a.rec.rec[2 * a.n_q + gq] = rc.kphi;
+      a.rec.rec[3 * a.n_q + gq] = rc.g;
+      a.rec.rec[4 * a.n_q + gq] = rc.gp;
+      a.rec.rec[5 * a.n_q + gq] = rc.dL;
+      a.rec.flags[gq] = rc.flags;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a.rec.D32[k * a.n_q + gq] = (float)st[k];
+    }
+  }
+  if (any_bad) a.flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 level apply (MODE 0) and point-Jacobi diagonal (MODE 1).
+// PF: fine nodes per direction (kinematics), PC: this level's nodes per direction.
+// ---------------------------------------------------------------------------
+
+struct A32Args {
+  MeshDev m;
+  LevelDev fine, lev;
+  int64_t n_q;
+  const float* z32;      // fine u mirror [3][n_fine]
+  const float* dz;       // level vector [4][n_lev]
+  RecordSoA rec;
+  const uint8_t* phase;
+  const MatParams<float>* mats;
+  int nph;
+  FracParams<float> fr;
+  float* out;
+};
+
+template <int PF, int PC, int Q> struct A32Shape {
+  static constexpr int PM = PF > PC ? PF : PC;
+  static constexpr int NBF = 2 * PF - 1, NBF3 = NBF * NBF * NBF;
+  static constexpr int NBC = 2 * PC - 1, NBC3 = NBC * NBC * NBC;
+  static constexpr int PC3 = PC * PC * PC, Q3 = Q * Q * Q;
+  static constexpr int ER = (NT / Q3) < 8 ? (NT / Q3) : 8;
+  static constexpr int ROUNDS = (8 + ER - 1) / ER;
+  static constexpr int FWD = 2 * ER * PM * PM * Q + 3 * ER * PM * Q * Q;
+  static constexpr int BWD = 4 * ER * Q3 + 3 * ER * PM * Q * Q + 2 * ER * PM * PM * Q;
+  static constexpr int DIAG = 22 * ER * Q3;
+  static constexpr int TMP0 = FWD > BWD ? FWD : BWD;
+  static constexpr int TMP = TMP0 > DIAG ? TMP0 : DIAG;
+  static constexpr int EV = 8 * 4 * PC3;
+  static constexpr int TAB = 2 * Q * PF + 2 * Q * PC + Q;
+  static constexpr size_t lds_floats = (size_t)3 * NBF3 + 4 * NBC3 + EV + TMP + TAB;
+  static constexpr size_t lds_bytes = lds_floats * sizeof(float);
+};
+
+template <int MODE, int PF, int PC, int Q>
+__global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTablesF* __restrict__ tabs) {
+  using S = A32Shape<PF, PC, Q>;
+  constexpr int NBF3 = S::NBF3, NBC3 = S::NBC3, PC3 = S::PC3, Q3 = S::Q3, ER = S::ER, PM = S::PM;
+  extern __shared__ float ldsf[];
+  float* ub = ldsf;                 // [3][NBF3] fine u
+  float* wb = ub + 3 * NBF3;        // [4][NBC3] level direction
+  float* ev = wb + 4 * NBC3;        // [8][4][PC3]
+  float* tmp = ev + S::EV;
+  float* tab = tmp + S::TMP;        // Bf, Df (Q x PF), Bc, Dc (Q x PC), w (Q)
+  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  for (int t = threadIdx.x; t < Q * PF; t += NT) {
+    tab[t] = tabs->B[PF][Q][t / PF][t % PF];
+    tab[Q * PF + t] = tabs->D[PF][Q][t / PF][t % PF];
+  }
+  for (int t = threadIdx.x; t < Q * PC; t += NT) {
+    tab[2 * Q * PF + t] = tabs->B[PC][Q][t / PC][t % PC];
+    tab[2 * Q * PF + Q * PC + t] = tabs->D[PC][Q][t / PC][t % PC];
+  }
+  if (threadIdx.x < Q) tab[2 * Q * PF + 2 * Q * PC + threadIdx.x] = tabs->w[Q][threadIdx.x];
+  stage_brick<float, float, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, ub);
+  if (MODE == 0) stage_brick<float, float, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, wb);
+  __syncthreads();
+  const TabRef<float> tf{tab, tab + Q * PF};
+  const TabRef<float> tc{tab + 2 * Q * PF, tab + 2 * Q * PF + Q * PC};
+  const float* wq = tab + 2 * Q * PF + 2 * Q * PC;
+  const float ih[3] = {(float)(2.0 / a.m.hx), (float)(2.0 / a.m.hy), (float)(2.0 / a.m.hz)};
+  const float jdet = (float)(a.m.hx * a.m.hy * a.m.hz * 0.125);
+  float* xb = tmp;
+  float* xd = xb + ER * PM * PM * Q;
+  float* ybb = xd + ER * PM * PM * Q;
+  float* ydb = ybb + ER * PM * Q * Q;
+  float* ybd = ydb + ER * PM * Q * Q;
+  float* q0 = tmp;
+  float* z0 = q0 + 4 * ER * Q3;
+  float* zx = z0 + ER * PM * Q * Q;
+  float* zy = zx + ER * PM * Q * Q;
+  float* y0 = zy + ER * PM * Q * Q;
+  float* yx = y0 + ER * PM * PM * Q;
+  const int t = threadIdx.x;
+  const int el = t / Q3, ql = t % Q3;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  for (int r = 0; r < S::ROUNDS; ++r) {
+    const int slot0 = r * ER, slot = slot0 + el;
+    const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+    const bool active = (t < ER * Q3) && (slot < 8) && sx < g.nex && sy < g.ney && sz < g.nez;
+    float G[9], W[9], wphi = 0.f, gw[3] = {0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int f = 0; f < 3; ++f) {
+      fwd_xy<float, PF, Q, ER>(ub + f * NBF3, slot0, g, tf, true, xb, xd, ybb, ydb, ybd);
+      if (t < ER * Q3) {
+        float v, d[3];
+        fwd_z<float, PF, Q>(ybb, ydb, ybd, el, qx, qy, qz, tf, true, v, d);
+#pragma unroll
+        for (int J = 0; J < 3; ++J) G[3 * f + J] = d[J] * ih[J];
+      }
+      __syncthreads();
+    }
+    if (MODE == 0) {
+#pragma unroll 1
+      for (int f = 0; f < 4; ++f) {
+        fwd_xy<float, PC, Q, ER>(wb + f * NBC3, slot0, g, tc, true, xb, xd, ybb, ydb, ybd);
+        if (t < ER * Q3) {
+          float v, d[3];
+          fwd_z<float, PC, Q>(ybb, ydb, ybd, el, qx, qy, qz, tc, true, v, d);
+          if (f < 3) {
+#pragma unroll
+            for (int J = 0; J < 3; ++J) W[3 * f + J] = d[J] * ih[J];
+          } else {
+            wphi = v;
+#pragma unroll
+            for (int J = 0; J < 3; ++J) gw[J] = d[J] * ih[J];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    float Fu[9], f0 = 0.f, f1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fu[k] = 0.f;
+    QPState<float> s;
+    MatParams<float> mp;
+    float wdet = 0.f;
+    if (active) {
+      const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+      const int64_t gq = e * Q3 + ql;
+      LinRecord rc;
+      rc.c = a.rec.rec[0 * a.n_q + gq];
+      rc.kq = a.rec.rec[1 * a.n_q + gq];
+      rc.kphi = a.rec.rec[2 * a.n_q + gq];
+      rc.g = a.rec.rec[3 * a.n_q + gq];
+      rc.gp = a.rec.rec[4 * a.n_q + gq];
+      rc.dL = a.rec.rec[5 * a.n_q + gq];
+      rc.flags = a.rec.flags[gq];
+      float D[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) D[k] = a.rec.D32[k * a.n_q + gq];
+      const int pid = a.phase[gq];
+      mp = a.mats[pid < a.nph ? pid : 0];
+      qp_state_lin<float>(mp, G, D, rc, s);
+      wdet = wq[qx] * wq[qy] * wq[qz] * jdet;
+      if (MODE == 0) {
+        float dL;
+        qp_tangent<float>(mp, s, W, wphi, Fu, dL);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+        f0 = wdet * a.fr.s_phi * dL;
+        const float kfg = a.fr.kf * mp.Gc;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gw[J];
+      }
+    }
+    if (MODE == 0) {
+#pragma unroll 1
+      for (int f = 0; f < 4; ++f) {
+        if (t < ER * Q3) {
+          if (f < 3) {
+            q0[t] = 0.f;
+            q0[ER * Q3 + t] = Fu[3 * f + 0] * ih[0];
+            q0[2 * ER * Q3 + t] = Fu[3 * f + 1] * ih[1];
+            q0[3 * ER * Q3 + t] = Fu[3 * f + 2] * ih[2];
+          } else {
+            q0[t] = f0;
+            q0[ER * Q3 + t] = f1[0] * ih[0];
+            q0[2 * ER * Q3 + t] = f1[1] * ih[1];
+            q0[3 * ER * Q3 + t] = f1[2] * ih[2];
+          }
+        }
+        __syncthreads();
+        bwd_field<float, PC, Q, ER>(q0, q0 + ER * Q3, q0 + 2 * ER * Q3, q0 + 3 * ER * Q3, f == 3, slot0, ER, tc,
+                                    z0, zx, zy, y0, yx, ev, 4, f);
+      }
+    } else {
+      // diagonal: quadratic-form coefficients per point in reference coordinates,
+      // then every (element, node) pair sums over the points with the 1-D tables
+      float* cf = tmp;  // [22][ER*Q3]
+      if (t < ER * Q3) {
+        float c22[22];
+#pragma unroll
+        for (int k = 0; k < 22; ++k) c22[k] = 0.f;
+        if (active) {
+#pragma unroll 1
+          for (int i = 0; i < 3; ++i) {
+            float C[3][3];
+#pragma unroll 1
+            for (int K = 0; K < 3; ++K) {
+              float dG[9], dP[9], dL;
+#pragma unroll
+              for (int k = 0; k < 9; ++k) dG[k] = 0.f;
+              dG[3 * i + K] = 1.f;
+              qp_tangent<float>(mp, s, dG, 0.f, dP, dL);
+#pragma unroll
+              for (int J = 0; J < 3; ++J) C[J][K] = dP[3 * i + J];
+            }
+            // xx, yy, zz, xy, xz, yz
+            c22[6 * i + 0] = wdet * ih[0] * ih[0] * C[0][0];
+            c22[6 * i + 1] = wdet * ih[1] * ih[1] * C[1][1];
+            c22[6 * i + 2] = wdet * ih[2] * ih[2] * C[2][2];
+            c22[6 * i + 3] = wdet * ih[0] * ih[1] * (C[0][1] + C[1][0]);
+            c22[6 * i + 4] = wdet * ih[0] * ih[2] * (C[0][2] + C[2][0]);
+            c22[6 * i + 5] = wdet * ih[1] * ih[2] * (C[1][2] + C[2][1]);
+          }
+          float dG[9], dP[9], dL;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) dG[k] = 0.f;
+          qp_tangent<float>(mp, s, dG, 1.f, dP, dL);
+          c22[18] = wdet * a.fr.s_phi * dL;
+          const float kfg = wdet * a.fr.kf * mp.Gc;
+          c22[19] = kfg * ih[0] * ih[0];
+          c22[20] = kfg * ih[1] * ih[1];
+          c22[21] = kfg * ih[2] * ih[2];
+        }
+#pragma unroll
+        for (int k = 0; k < 22; ++k) cf[k * ER * Q3 + t] = c22[k];
+      }
+      __syncthreads();
+      for (int o = t; o < ER * PC3; o += NT) {
+        const int e2 = o / PC3, a2 = o % PC3;
+        const int ax = a2 % PC, ay = (a2 / PC) % PC, az = a2 / (PC * PC);
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < Q3; ++q) {
+          const int px = q % Q, py = (q / Q) % Q, pz = q / (Q * Q);
+          const float bx = tc.B[px * PC + ax], dx = tc.D[px * PC + ax];
+          const float by = tc.B[py * PC + ay], dy = tc.D[py * PC + ay];
+          const float bz = tc.B[pz * PC + az], dz = tc.D[pz * PC + az];
+          const float gx = dx * by * bz, gy = bx * dy * bz, gz = bx * by * dz, nn = bx * by * bz;
+          const float* cq = cf + e2 * Q3 + q;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            acc[i] += gx * gx * cq[(6 * i + 0) * ER * Q3] + gy * gy * cq[(6 * i + 1) * ER * Q3] +
+                      gz * gz * cq[(6 * i + 2) * ER * Q3] + gx * gy * cq[(6 * i + 3) * ER * Q3] +
+                      gx * gz * cq[(6 * i + 4) * ER * Q3] + gy * gz * cq[(6 * i + 5) * ER * Q3];
+          }
+          acc[3] += nn * nn * cq[18 * ER * Q3] + gx * gx * cq[19 * ER * Q3] + gy * gy * cq[20 * ER * Q3] +
+                    gz * gz * cq[21 * ER * Q3];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ev[((slot0 + e2) * 4 + f) * PC3 + a2] = acc[f];
+      }
+      __syncthreads();
+    }
+  }
+  scatter_brick<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+}
+
+// ---------------------------------------------------------------------------
+// Level transfers (one direction per launch) and vector kernels.
+// ---------------------------------------------------------------------------
+
+// out[f][i2][i1][i0] = sum_k w[c*nw + k] in[f][...][base[c] + k][...] along `axis`,
+// where c is the output coordinate along axis. in dims: (n0i, n1i, n2i).
+__global__ void k_transfer_1d(const float* __restrict__ in, float* __restrict__ out, int n0o, int n1o, int n2o,
+                              int n0i, int n1i, int n2i, int axis, const int* __restrict__ base,
+                              const float* __restrict__ w, int nw) {
+  const int64_t no = (int64_t)n0o * n1o * n2o;
+  const int64_t ni = (int64_t)n0i * n1i * n2i;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < no; o += (int64_t)gridDim.x * blockDim.x) {
+    const int i0 = (int)(o % n0o);
+    const int i1 = (int)((o / n0o) % n1o);
+    const int i2 = (int)(o / ((int64_t)n0o * n1o));
+    const int c = axis == 0 ? i0 : (axis == 1 ? i1 : i2);
+    const int nin = axis == 0 ? n0i : (axis == 1 ? n1i : n2i);
+    const int b0 = base[c];
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nw; ++k) {
+      const int src = b0 + k;
+      const float wk = w[(int64_t)c * nw + k];
+      if (src < 0 || src >= nin || wk == 0.f) continue;
+      int j0 = i0, j1 = i1, j2 = i2;
+      if (axis == 0) j0 = src; else if (axis == 1) j1 = src; else j2 = src;
+      const int64_t ii = j0 + (int64_t)n0i * (j1 + (int64_t)n1i * j2);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[f] += wk * in[f * ni + ii];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) out[f * no + o] = acc[f];
+  }
+}
+
+__global__ void k_vec_zero(float* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.f;
+}
+
+__global__ void k_vec_copy(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+// y += x
+__global__ void k_vec_add(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += x[i];
+}
+
+// r = b - t
+__global__ void k_vec_sub(const float* __restrict__ b, const float* __restrict__ t, float* __restrict__ r, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - t[i];
+}
+
+// Chebyshev start: d = s * dinv * r ; x = (x_zero ? 0 : x) + d
+__global__ void k_cheb_first(const float* __restrict__ r, const float* __restrict__ dinv, float* __restrict__ d,
+                             float* __restrict__ x, float s, int x_zero, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float di = s * dinv[i] * r[i];
+    d[i] = di;
+    x[i] = (x_zero ? 0.f : x[i]) + di;
+  }
+}
+
+// Chebyshev step: r -= t ; d = a d + b dinv r ; x += d
+__global__ void k_cheb_step(float* __restrict__ r, const float* __restrict__ t, const float* __restrict__ dinv,
+                            float* __restrict__ d, float* __restrict__ x, float a, float b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float ri = r[i] - t[i];
+    r[i] = ri;
+    const float di = a * d[i] + b * dinv[i] * ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+// dinv = 1 / diag (0 where the diagonal vanishes)
+__global__ void k_vec_inv(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i] != 0.f ? 1.f / a[i] : 0.f;
+}
+
+// x = dinv * x
+__global__ void k_vec_scale(const float* __restrict__ dinv, float* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= dinv[i];
+}
+
+// double-precision sum of squares, per-block partials (deterministic)
+__global__ void k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double red[NT];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// b = a / ||a|| given the squared norm on the host
+__global__ void k_vec_axs(const float* __restrict__ a, float* __restrict__ b, float s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = s * a[i];
+}
+
+// FP64 -> FP32 mirror of the displacement rows of z
+__global__ void k_mirror_u(const double* __restrict__ z, float* __restrict__ z32, int64_t n_nodes) {
+  const int64_t n = 3 * n_nodes;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    z32[i] = (float)z[i];
+}
 
 }  // namespace pfmf

@@ -1,43 +1,431 @@
-// Host side of the FP32 p-multigrid entry points.
+// Host side of the FP32 p-multigrid entry points (included at the end of pfmf.hip).
 #pragma once
+#include <random>
+
+namespace {
+
+constexpr int VEC_BLOCKS = 2048;
+
+inline int vec_grid(int64_t n) {
+  const int64_t b = (n + NT - 1) / NT;
+  return (int)(b < VEC_BLOCKS ? (b > 0 ? b : 1) : VEC_BLOCKS);
+}
+
+// 1-D transfer rows between orders pf (fine) and pc (coarse) on N elements.
+void transfer_rows_1d(int pf, int pc, int N, std::vector<int>& pbase, std::vector<float>& pw,
+                      std::vector<int>& rbase, std::vector<float>& rw) {
+  std::vector<double> xf, xc, B, D;
+  gauss_lobatto(pf + 1, xf);
+  gauss_lobatto(pc + 1, xc);
+  lagrange_tables(xc, xf, B, D);  // B[il][j] = coarse basis j at fine node il
+  const int Pc = pc + 1;
+  const int nf = pf * N + 1, nc = pc * N + 1;
+  pbase.assign(nf, 0);
+  pw.assign((size_t)nf * Pc, 0.f);
+  for (int i = 0; i < nf; ++i) {
+    const int e = std::min(i / pf, N - 1);
+    const int il = i - pf * e;
+    pbase[i] = pc * e;
+    for (int j = 0; j < Pc; ++j) pw[(size_t)i * Pc + j] = (float)B[il * Pc + j];
+  }
+  const int nw = 2 * pf + 1;
+  rbase.assign(nc, 0);
+  rw.assign((size_t)nc * nw, 0.f);
+  for (int J = 0; J < nc; ++J) {
+    int elo, ehi;
+    if (J % pc != 0) {
+      elo = ehi = J / pc;
+    } else {
+      elo = J / pc - 1 < 0 ? 0 : J / pc - 1;
+      ehi = J / pc < N ? J / pc : N - 1;
+    }
+    rbase[J] = pf * elo;
+    for (int k = 0; k < nw; ++k) {
+      const int i = rbase[J] + k;
+      if (i > pf * (ehi + 1) || i >= nf) continue;
+      const int e = (i <= pf * (elo + 1)) ? elo : ehi;
+      const int il = i - pf * e, j = J - pc * e;
+      if (j < 0 || j > pc) continue;
+      rw[(size_t)J * nw + k] = (float)B[il * Pc + j];
+    }
+  }
+}
+
+template <typename T>
+pf_status upload(T** dst, const std::vector<T>& v) {
+  if (hipMalloc(dst, v.size() * sizeof(T)) != hipSuccess) return fail(PF_ENOMEM, "multigrid allocation failed");
+  HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+pf_status mg_alloc(pf_ctx* c) {
+  MGState& mg = c->mg;
+  if (mg.n_levels > 0) return PF_OK;
+  const int p = c->mesh.p;
+  const int coarse = 1;
+  mg.n_levels = p - coarse + 1;
+  const int N[3] = {c->mesh.nx, c->mesh.ny, c->mesh.nz};
+  for (int l = 0; l < mg.n_levels; ++l) {
+    MGLevel& L = mg.lv[l];
+    L.p = p - l;
+    L.P = L.p + 1;
+    L.nx1 = L.p * N[0] + 1;
+    L.ny1 = L.p * N[1] + 1;
+    L.nz1 = L.p * N[2] + 1;
+    L.n_nodes = (int64_t)L.nx1 * L.ny1 * L.nz1;
+    const size_t nb = 4 * L.n_nodes * sizeof(float);
+    float** bufs[] = {&L.x, &L.r, &L.d, &L.t, &L.b, &L.diag, &L.dinv};
+    for (float** b : bufs)
+      if (hipMalloc(b, nb) != hipSuccess) return fail(PF_ENOMEM, "multigrid level allocation failed");
+    if (l + 1 < mg.n_levels) {
+      for (int k = 0; k < 3; ++k) {
+        std::vector<int> pb, rb;
+        std::vector<float> pw, rw;
+        transfer_rows_1d(L.p, L.p - 1, N[k], pb, pw, rb, rw);
+        pf_status st;
+        if ((st = upload(&L.pbase[k], pb)) || (st = upload(&L.pw[k], pw)) || (st = upload(&L.rbase[k], rb)) ||
+            (st = upload(&L.rw[k], rw)))
+          return st;
+      }
+    }
+  }
+  const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
+  if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
+      hipMalloc(&mg.rec.rec, 6 * c->n_q * sizeof(float)) != hipSuccess ||
+      hipMalloc(&mg.rec.flags, c->n_q) != hipSuccess ||
+      hipMalloc(&mg.rec.D32, 6 * c->n_q * sizeof(float)) != hipSuccess ||
+      hipMalloc(&mg.tmpA, nfine) != hipSuccess || hipMalloc(&mg.tmpB, nfine) != hipSuccess ||
+      hipMalloc(&mg.red, VEC_BLOCKS * sizeof(double)) != hipSuccess)
+    return fail(PF_ENOMEM, "multigrid allocation failed");
+  return PF_OK;
+}
+
+A32Args a32_args(pf_ctx* c, int level, const float* dz, float* out) {
+  A32Args a;
+  a.m = mesh_dev(c);
+  const MGLevel& F = c->mg.lv[0];
+  const MGLevel& L = c->mg.lv[level];
+  a.fine = LevelDev{F.P, F.nx1, F.ny1, F.n_nodes};
+  a.lev = LevelDev{L.P, L.nx1, L.ny1, L.n_nodes};
+  a.n_q = c->n_q;
+  a.z32 = c->mg.z32;
+  a.dz = dz;
+  a.rec = c->mg.rec;
+  a.phase = c->qp_phase;
+  a.mats = c->d_matsf;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<float>(c->fr);
+  a.out = out;
+  return a;
+}
+
+template <int MODE, int PF, int PC>
+pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
+  using S = A32Shape<PF, PC, PF>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_level32<MODE, PF, PC, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)S::lds_bytes));
+    attr_set = true;
+  }
+  for (int col = 0; col < 8; ++col) {
+    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int MODE, int PF>
+pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
+  switch (PC) {
+    case 2: return launch_level32<MODE, PF, 2>(c, a, s);
+    case 3: if constexpr (PF >= 3) return launch_level32<MODE, PF, 3>(c, a, s); break;
+    case 4: if constexpr (PF >= 4) return launch_level32<MODE, PF, 4>(c, a, s); break;
+    case 5: if constexpr (PF >= 5) return launch_level32<MODE, PF, 5>(c, a, s); break;
+    default: break;
+  }
+  return fail(PF_EUNSUPPORTED, "level order not built");
+}
+
+template <int MODE>
+pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
+  const A32Args a = a32_args(c, level, dz, out);
+  const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
+  switch (PF) {
+    case 2: return dispatch_pc<MODE, 2>(c, PC, a, s);
+    case 3: return dispatch_pc<MODE, 3>(c, PC, a, s);
+    case 4: return dispatch_pc<MODE, 4>(c, PC, a, s);
+    case 5: return dispatch_pc<MODE, 5>(c, PC, a, s);
+    default: return fail(PF_EUNSUPPORTED, "order not built");
+  }
+}
+
+template <int P>
+pf_status launch_linearize(pf_ctx* c, const LinArgs& a, hipStream_t s) {
+  using S = OpShape<P, P>;
+  const size_t lds = (4 * S::NB3 + S::TMP + S::TAB) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIPCHK(hipFuncSetAttribute((const void*)k_linearize<P, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = true;
+  }
+  for (int col = 0; col < 8; ++col) {
+    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    hipLaunchKernelGGL((k_linearize<P, P>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+pf_status sumsq(pf_ctx* c, const float* x, int64_t n, hipStream_t s, double* out) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(NT), 0, s, x, n, c->mg.red);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h(g);
+  HIPCHK(hipMemcpyAsync(h.data(), c->mg.red, g * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (double v : h) acc += v;
+  *out = acc;
+  return PF_OK;
+}
+
+// y = P x (coarse level l+1 -> level l), separable passes x, y, z.
+pf_status prolong(pf_ctx* c, int l, const float* xc, float* xf, hipStream_t s) {
+  const MGLevel& F = c->mg.lv[l];
+  const MGLevel& C = c->mg.lv[l + 1];
+  float* A = c->mg.tmpA;
+  float* B = c->mg.tmpB;
+  int64_t n;
+  n = (int64_t)F.nx1 * C.ny1 * C.nz1;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, xc, A, F.nx1, C.ny1, C.nz1, C.nx1, C.ny1,
+                     C.nz1, 0, F.pbase[0], F.pw[0], C.P);
+  n = (int64_t)F.nx1 * F.ny1 * C.nz1;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, A, B, F.nx1, F.ny1, C.nz1, F.nx1, C.ny1,
+                     C.nz1, 1, F.pbase[1], F.pw[1], C.P);
+  n = F.n_nodes;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, B, xf, F.nx1, F.ny1, F.nz1, F.nx1, F.ny1,
+                     C.nz1, 2, F.pbase[2], F.pw[2], C.P);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+// rc = P^T rf (level l -> coarse level l+1).
+pf_status restrict_(pf_ctx* c, int l, const float* rf, float* rc, hipStream_t s) {
+  const MGLevel& F = c->mg.lv[l];
+  const MGLevel& C = c->mg.lv[l + 1];
+  float* A = c->mg.tmpA;
+  float* B = c->mg.tmpB;
+  const int nw = 2 * F.p + 1;
+  int64_t n;
+  n = (int64_t)C.nx1 * F.ny1 * F.nz1;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, rf, A, C.nx1, F.ny1, F.nz1, F.nx1, F.ny1,
+                     F.nz1, 0, F.rbase[0], F.rw[0], nw);
+  n = (int64_t)C.nx1 * C.ny1 * F.nz1;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, A, B, C.nx1, C.ny1, F.nz1, C.nx1, F.ny1,
+                     F.nz1, 1, F.rbase[1], F.rw[1], nw);
+  n = C.n_nodes;
+  hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, B, rc, C.nx1, C.ny1, C.nz1, C.nx1, C.ny1,
+                     F.nz1, 2, F.rbase[2], F.rw[2], nw);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+// Chebyshev(k) with point Jacobi on level l for A x = b, bounds [0.1, 1.1] * lmax.
+pf_status chebyshev(pf_ctx* c, int l, const float* b, float* x, int k, bool x_zero, hipStream_t s) {
+  MGLevel& L = c->mg.lv[l];
+  const int64_t n = 4 * L.n_nodes;
+  const int g = vec_grid(n);
+  const double lmax = L.lmax, lmin = 0.1 * L.lmax, lhi = 1.1 * L.lmax;
+  const double theta = 0.5 * (lhi + lmin), delta = 0.5 * (lhi - lmin), sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  (void)lmax;
+  pf_status st;
+  if (x_zero) {
+    hipLaunchKernelGGL(k_vec_copy, dim3(g), dim3(NT), 0, s, b, L.r, n);
+  } else {
+    if ((st = level_op<0>(c, l, x, L.t, s))) return st;
+    hipLaunchKernelGGL(k_vec_sub, dim3(g), dim3(NT), 0, s, b, L.t, L.r, n);
+  }
+  hipLaunchKernelGGL(k_cheb_first, dim3(g), dim3(NT), 0, s, L.r, L.dinv, L.d, x, (float)(1.0 / theta),
+                     x_zero ? 1 : 0, n);
+  for (int it = 1; it < k; ++it) {
+    if ((st = level_op<0>(c, l, L.d, L.t, s))) return st;
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    hipLaunchKernelGGL(k_cheb_step, dim3(g), dim3(NT), 0, s, L.r, L.t, L.dinv, L.d, x, (float)(rn * rho),
+                       (float)(2.0 * rn / delta), n);
+    rho = rn;
+  }
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status vcycle(pf_ctx* c, int l, const float* b, float* x, const pf_pmg_opts& o, hipStream_t s) {
+  MGState& mg = c->mg;
+  MGLevel& L = mg.lv[l];
+  const int64_t n = 4 * L.n_nodes;
+  const int g = vec_grid(n);
+  pf_status st;
+  if (l == mg.n_levels - 1) {
+    for (int sw = 0; sw < o.coarse_sweeps; ++sw)
+      if ((st = chebyshev(c, l, b, x, o.cheb_degree, sw == 0, s))) return st;
+    return PF_OK;
+  }
+  if ((st = chebyshev(c, l, b, x, o.cheb_degree, true, s))) return st;
+  if ((st = level_op<0>(c, l, x, L.t, s))) return st;
+  hipLaunchKernelGGL(k_vec_sub, dim3(g), dim3(NT), 0, s, b, L.t, L.r, n);
+  MGLevel& C = mg.lv[l + 1];
+  if ((st = restrict_(c, l, L.r, C.b, s))) return st;
+  if ((st = vcycle(c, l + 1, C.b, C.x, o, s))) return st;
+  if ((st = prolong(c, l, C.x, L.t, s))) return st;
+  hipLaunchKernelGGL(k_vec_add, dim3(g), dim3(NT), 0, s, L.t, x, n);
+  HIPCHK(hipGetLastError());
+  return chebyshev(c, l, b, x, o.cheb_degree, false, s);
+}
+
+pf_status need_lin(pf_ctx* c, int level) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!c->mg.linearized) return fail(PF_EINVAL, "call pf_linearize first");
+  if (level < 0 || level >= c->mg.n_levels) return fail(PF_EINVAL, "level %d outside 0..%d", level, c->mg.n_levels - 1);
+  return PF_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
-  (void)z; (void)stream;
   pf_status st = check_ctx(c);
   if (st) return st;
-  return fail(PF_EUNSUPPORTED, "pf_linearize not built");
+  if (!z) return fail(PF_EINVAL, "null z");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  if ((st = mg_alloc(c))) return st;
+  MGState& mg = c->mg;
+  hipLaunchKernelGGL(k_mirror_u, dim3(vec_grid(3 * c->n_nodes)), dim3(NT), 0, s, z, mg.z32, c->n_nodes);
+  HIPCHK(hipGetLastError());
+  LinArgs a;
+  a.m = mesh_dev(c);
+  a.nx1 = c->nx1;
+  a.ny1 = c->ny1;
+  a.n_nodes = c->n_nodes;
+  a.n_q = c->n_q;
+  a.z = z;
+  a.phin = c->phi_n;
+  a.state = c->qp_state;
+  a.phase = c->qp_phase;
+  a.mats = c->d_mats;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<double>(c->fr);
+  a.rec = mg.rec;
+  a.flag = c->d_flag;
+  switch (c->mesh.p) {
+    case 1: st = launch_linearize<2>(c, a, s); break;
+    case 2: st = launch_linearize<3>(c, a, s); break;
+    case 3: st = launch_linearize<4>(c, a, s); break;
+    case 4: st = launch_linearize<5>(c, a, s); break;
+    default: st = fail(PF_EUNSUPPORTED, "order not built");
+  }
+  if (st) return st;
+  mg.linearized = true;
+  std::mt19937_64 rng(21150);
+  std::uniform_real_distribution<float> U(-1.f, 1.f);
+  for (int l = 0; l < mg.n_levels; ++l) {
+    MGLevel& L = mg.lv[l];
+    const int64_t n = 4 * L.n_nodes;
+    const int g = vec_grid(n);
+    if ((st = level_op<1>(c, l, nullptr, L.diag, s))) return st;
+    hipLaunchKernelGGL(k_vec_inv, dim3(g), dim3(NT), 0, s, L.diag, L.dinv, n);
+    // lambda_max(D^-1 A) by power iteration
+    std::vector<float> h(n);
+    for (auto& v : h) v = U(rng);
+    HIPCHK(hipMemcpyAsync(L.d, h.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+    double nrm2;
+    if ((st = sumsq(c, L.d, n, s, &nrm2))) return st;
+    hipLaunchKernelGGL(k_vec_axs, dim3(g), dim3(NT), 0, s, L.d, L.d, (float)(1.0 / std::sqrt(nrm2)), n);
+    double lam = 0.0;
+    for (int it = 0; it < 15; ++it) {
+      if ((st = level_op<0>(c, l, L.d, L.t, s))) return st;
+      hipLaunchKernelGGL(k_vec_scale, dim3(g), dim3(NT), 0, s, L.dinv, L.t, n);
+      if ((st = sumsq(c, L.t, n, s, &nrm2))) return st;
+      lam = std::sqrt(nrm2);
+      if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PF_ENONPHYSICAL, "eigenvalue estimate failed on level %d", l);
+      hipLaunchKernelGGL(k_vec_axs, dim3(g), dim3(NT), 0, s, L.t, L.d, (float)(1.0 / lam), n);
+    }
+    L.lmax = lam;
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return PF_OK;
 }
 
 pf_status pf_level_info(const pf_ctx* c, int level, int* p, int64_t* n_nodes) {
-  (void)c; (void)level; (void)p; (void)n_nodes;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  if (!c) return fail(PF_EINVAL, "null context");
+  if (!c->mg.linearized) return fail(PF_EINVAL, "call pf_linearize first");
+  if (level < 0 || level >= c->mg.n_levels) return fail(PF_EINVAL, "level %d outside 0..%d", level, c->mg.n_levels - 1);
+  if (p) *p = c->mg.lv[level].p;
+  if (n_nodes) *n_nodes = c->mg.lv[level].n_nodes;
+  return PF_OK;
 }
 
 pf_status pf_apply_jacobian_f32(pf_ctx* c, int level, const float* dz, float* y, void* stream) {
-  (void)c; (void)level; (void)dz; (void)y; (void)stream;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  pf_status st = need_lin(c, level);
+  if (st) return st;
+  if (!dz || !y) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->mg.lv[level].n_nodes * sizeof(float);
+  if (overlaps(dz, nb, y, nb)) return fail(PF_EINVAL, "y aliases dz");
+  c->last_stream = (hipStream_t)stream;
+  return level_op<0>(c, level, dz, y, (hipStream_t)stream);
 }
 
 pf_status pf_prolong(pf_ctx* c, int level, const float* xc, float* xf, void* stream) {
-  (void)c; (void)level; (void)xc; (void)xf; (void)stream;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  pf_status st = need_lin(c, level);
+  if (st) return st;
+  if (level + 1 >= c->mg.n_levels) return fail(PF_EINVAL, "no coarser level below %d", level);
+  if (!xc || !xf) return fail(PF_EINVAL, "null vector");
+  c->last_stream = (hipStream_t)stream;
+  return prolong(c, level, xc, xf, (hipStream_t)stream);
 }
 
 pf_status pf_restrict(pf_ctx* c, int level, const float* rf, float* rc, void* stream) {
-  (void)c; (void)level; (void)rf; (void)rc; (void)stream;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  pf_status st = need_lin(c, level);
+  if (st) return st;
+  if (level + 1 >= c->mg.n_levels) return fail(PF_EINVAL, "no coarser level below %d", level);
+  if (!rf || !rc) return fail(PF_EINVAL, "null vector");
+  c->last_stream = (hipStream_t)stream;
+  return restrict_(c, level, rf, rc, (hipStream_t)stream);
 }
 
 pf_status pf_level_diagonal(pf_ctx* c, int level, float* diag, void* stream) {
-  (void)c; (void)level; (void)diag; (void)stream;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  pf_status st = need_lin(c, level);
+  if (st) return st;
+  if (!diag) return fail(PF_EINVAL, "null vector");
+  const int64_t n = 4 * c->mg.lv[level].n_nodes;
+  hipLaunchKernelGGL(k_vec_copy, dim3(vec_grid(n)), dim3(NT), 0, (hipStream_t)stream, c->mg.lv[level].diag, diag, n);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
 }
 
 pf_status pf_pmg_vcycle(pf_ctx* c, const float* b, float* x, const pf_pmg_opts* o, void* stream) {
-  (void)c; (void)b; (void)x; (void)o; (void)stream;
-  return fail(PF_EUNSUPPORTED, "multigrid not built");
+  pf_status st = need_lin(c, 0);
+  if (st) return st;
+  if (!b || !x) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->n_nodes * sizeof(float);
+  if (overlaps(b, nb, x, nb)) return fail(PF_EINVAL, "x aliases b");
+  pf_pmg_opts opt{3, 1, 4, 0};
+  if (o) {
+    if (o->cheb_degree > 0) opt.cheb_degree = o->cheb_degree;
+    if (o->coarse_p > 0) opt.coarse_p = o->coarse_p;
+    if (o->coarse_sweeps > 0) opt.coarse_sweeps = o->coarse_sweeps;
+  }
+  if (opt.cheb_degree > 32 || opt.coarse_sweeps > 64) return fail(PF_EINVAL, "smoother degree too large");
+  if (opt.coarse_p != 1) return fail(PF_EUNSUPPORTED, "only coarse_p = 1 is built");
+  c->last_stream = (hipStream_t)stream;
+  return vcycle(c, 0, b, x, opt, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -142,12 +142,11 @@ template <typename T> struct QPState {
   bool tension, hactive, plastic, bad;
 };
 
-// Residual state at one point: steps of Box 1 / Box 2 and Section 3.
-//   G: grad_X u (row-major), phi: phase field at the point, phin: previous phi,
-//   st: D[6] (Voigt), ebar_p, H_n.
+// Kinematics at one point (Box 1 step 1, Appendix A): F^-1, b_tr, principal frame,
+// principal log strains. G: grad_X u (row-major), st: D[6] (Voigt).
+// Returns beta_i and eps_i for the divided differences.
 template <typename T>
-__device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, const T* G, T phi,
-                                T phin, const T* st, QPState<T>& s) {
+__device__ inline void qp_kin(const T* G, const T* st, QPState<T>& s, T* beta, T* eps) {
   // F = I + G and its inverse
   T F[9];
 #pragma unroll
@@ -191,11 +190,9 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
     s.b[k] = v + ((k < 3) ? T(1) : T(0));
   }
   // principal values and frame (eq:inelasticity-spectral-decomposition)
-  T beta[3];
   eig_sym3(A, beta, s.N);
   s.bad = !(det > T(0)) || !(beta[0] > T(-1)) || !(beta[1] > T(-1)) || !(beta[2] > T(-1));
   // principal trial log strains with log1p (eq:inelasticity-log-strain-principal)
-  T eps[3];
   s.theta = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -206,6 +203,34 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   const T th3 = s.theta * (T(1) / T(3));
 #pragma unroll
   for (int i = 0; i < 3; ++i) s.e[i] = eps[i] - th3;
+}
+
+// Degraded Kirchhoff stress in the global frame and the off-diagonal tangent
+// factors g mu c (ln b_i - ln b_j)/(b_i - b_j), from the principal quantities.
+template <typename T>
+__device__ inline void qp_frame_stress(const MatParams<T>& m, const T* beta, const T* eps, QPState<T>& s) {
+  const int ri[6] = {0, 1, 2, 1, 0, 0}, ci[6] = {0, 1, 2, 2, 2, 1};
+  const T* N = s.N;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = ri[k], j = ci[k];
+    s.tau[k] = s.taud[0] * N[3 * i] * N[3 * j] + s.taud[1] * N[3 * i + 1] * N[3 * j + 1] +
+               s.taud[2] * N[3 * i + 2] * N[3 * j + 2];
+  }
+  const T gmc = s.g * m.mu * s.c;
+  s.coef[0] = gmc * log_divdiff(beta[1], beta[2], eps[1], eps[2]);
+  s.coef[1] = gmc * log_divdiff(beta[0], beta[2], eps[0], eps[2]);
+  s.coef[2] = gmc * log_divdiff(beta[0], beta[1], eps[0], eps[1]);
+}
+
+// Residual state at one point: steps of Box 1 / Box 2 and Section 3.
+//   G: grad_X u (row-major), phi: phase field at the point, phin: previous phi,
+//   st: D[6] (Voigt), ebar_p, H_n.
+template <typename T>
+__device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, const T* G, T phi,
+                                T phin, const T* st, QPState<T>& s) {
+  T beta[3], eps[3];
+  qp_kin<T>(G, st, s, beta, eps);
   // degradation (eq:degr-funct)
   const T omp = T(1) - phi;
   s.g = omp * omp + fr.eta;
@@ -254,19 +279,52 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   const T alpha_pp = (fr.at == 2) ? T(2) : T(0);
   s.L = s.gp * s.H + m.Gc * fr.inv_c0l0 * alpha_p + fr.zeta * (phi - phin) * fr.inv_dt;
   s.dLcoef = T(2) * s.H + m.Gc * fr.inv_c0l0 * alpha_pp + fr.zeta * fr.inv_dt;
-  // degraded Kirchhoff stress in the global frame
-  const T* N = s.N;
+  qp_frame_stress<T>(m, beta, eps, s);
+}
+
+// Linearisation record of one point, taken in FP64 once per linearisation and
+// stored in FP32: the return-mapping factor and its tangent coefficients, the
+// degradation and the local phase-field coefficient, and the switch decisions.
+struct LinRecord {
+  float c, kq, kphi, g, gp, dL;  // dL = dL/dphi at fixed history
+  uint8_t flags;                  // bit0 tension, bit1 history active, bit2 plastic
+};
+
+template <typename T>
+__device__ inline void record_from_state(const QPState<T>& s, LinRecord& r) {
+  r.c = (float)s.c;
+  r.kq = (float)s.kq;
+  r.kphi = (float)s.kphi;
+  r.g = (float)s.g;
+  r.gp = (float)s.gp;
+  r.dL = (float)s.dLcoef;
+  r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0);
+}
+
+// State for the linearised FP32 apply: kinematics recomputed from the FP32
+// mirrors, every decision and coefficient taken from the record.
+template <typename T>
+__device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const T* D, const LinRecord& r,
+                                    QPState<T>& s) {
+  T beta[3], eps[3];
+  qp_kin<T>(G, D, s, beta, eps);
+  s.c = (T)r.c;
+  s.kq = (T)r.kq;
+  s.kphi = (T)r.kphi;
+  s.g = (T)r.g;
+  s.gp = (T)r.gp;
+  s.dLcoef = (T)r.dL;
+  s.tension = r.flags & 1;
+  s.hactive = (r.flags >> 1) & 1;
+  s.plastic = (r.flags >> 2) & 1;
+  const T kt = m.kappa * s.theta;
+  const T tmu = T(2) * m.mu * s.c;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int i = ri[k], j = ci[k];
-    s.tau[k] = s.taud[0] * N[3 * i] * N[3 * j] + s.taud[1] * N[3 * i + 1] * N[3 * j + 1] +
-               s.taud[2] * N[3 * i + 2] * N[3 * j + 2];
+  for (int i = 0; i < 3; ++i) {
+    s.taub[i] = tmu * s.e[i] + kt;
+    s.taud[i] = s.tension ? s.g * s.taub[i] : s.g * (tmu * s.e[i]) + kt;
   }
-  // off-diagonal tangent factors g mu c (ln b_i - ln b_j)/(b_i - b_j)
-  const T gmc = s.g * m.mu * s.c;
-  s.coef[0] = gmc * log_divdiff(beta[1], beta[2], eps[1], eps[2]);
-  s.coef[1] = gmc * log_divdiff(beta[0], beta[2], eps[0], eps[2]);
-  s.coef[2] = gmc * log_divdiff(beta[0], beta[1], eps[0], eps[1]);
+  qp_frame_stress<T>(m, beta, eps, s);
 }
 
 // First Piola stress P = tau_degr F^-T (eq:mechanical-gradient-transformation).

@@ -1,6 +1,7 @@
 // libpfmf: host side of the C ABI declared in include/pfmf.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
