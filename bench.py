@@ -106,10 +106,20 @@ def main():
     gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    dz32 = dz.float()
+    y32 = torch.empty_like(dz32)
+    b32 = torch.empty_like(dz32)
+    x32 = torch.empty_like(dz32)
+    ctx.linearize(z)
+    ctx.apply_jacobian_f32(0, dz32, b32)
+
     ops = {
         "residual": lambda: ctx.apply_residual(z, r),
         "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
         "adjoint": lambda: ctx.apply_adjoint(z, v, gz, gp),
+        "linearize": lambda: ctx.linearize(z),
+        "fp32_apply": lambda: ctx.apply_jacobian_f32(0, dz32, y32),
+        "vcycle": lambda: ctx.pmg_vcycle(b32, x32),
     }
     for _ in range(args.warmup):
         for f in ops.values():
@@ -146,6 +156,8 @@ def main():
         errs["residual"] = sampled_rel_err(orc, mesh, rr, lambda e: orc.residual(d["z"], elems=e), rng)
         errs["jacobian"] = sampled_rel_err(orc, mesh, yy, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
         errs["adjoint"] = sampled_rel_err(orc, mesh, gg, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
+        y32h = y32.double().cpu().numpy()
+        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32h, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
     except Exception as exc:  # the oracle is a checker; its absence does not stop the benchmark
         errs["error"] = str(exc)
 
@@ -188,8 +200,10 @@ def main():
         "cpu_baseline": cpu,
         "ms": ms,
         "ms_min": ms_min,
-        "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ms},
-        "gbs_alg": {k: alg_bytes(mesh, k) / (ms[k] * 1e-3) / 1e9 for k in ms},
+        "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("residual", "jacobian", "adjoint", "fp32_apply")},
+        "gbs_alg": {k: alg_bytes(mesh, k) / (ms[k] * 1e-3) / 1e9 for k in ("residual", "jacobian", "adjoint",
+                                                                              "fp32_apply")},
+        "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
     print(json.dumps(out), flush=True)

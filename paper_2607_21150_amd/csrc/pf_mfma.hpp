@@ -1,0 +1,347 @@
+// Sum factorisation on the matrix cores for elements with at most 4 nodes and
+// exactly 4 Gauss points per direction (Q3 fine level and the FP32 levels of a
+// Q3 multigrid).
+//
+// One wavefront owns one element: lane l = a + 4 b + 16 c. v_mfma_f64_4x4x4f64
+// (4 blocks) reads its A operand A[blk][i][k] at lane i + 4 blk + 16 k, its B
+// operand B[blk][k][j] at lane j + 4 blk + 16 k and writes D[blk][i][j] at lane
+// j + 4 blk + 16 i. With the element's data in A, one instruction contracts lane
+// bits 4-5 and moves bits 0-1 there; with the data in B it contracts bits 4-5 in
+// place. Bits 2-3 (the block) are brought to bits 4-5 by one lane permutation.
+//
+// Nodal layout: (x, y, z) = (bits 0-1, 2-3, 4-5).
+// Point layout after the forward pass: (qx, qz, qy) = (bits 0-1, 2-3, 4-5).
+// Forward: contract z (data in A), contract x (data in A), permute, contract y
+// (data in B). Backward: contract qy (B), permute, contract qz (A), contract qx (A).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pf_brick.hpp"
+#include "pf_mg.hpp"
+#include "pf_ops.hpp"
+#include "pf_qf.hpp"
+
+namespace pfmf {
+
+__device__ inline double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+// swap lane bits 2-3 with 4-5
+__device__ inline double swap_blocks(double v) {
+  const int l = threadIdx.x & 63;
+  const int src = (l & 3) | ((l >> 4) << 2) | (((l >> 2) & 3) << 4);
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int rlo = __builtin_amdgcn_ds_bpermute(src << 2, lo);
+  const int rhi = __builtin_amdgcn_ds_bpermute(src << 2, hi);
+  return __hiloint2double(rhi, rlo);
+}
+
+// Per-lane basis operands of one (P, Q = 4) pair, zero-padded beyond P nodes.
+//   fB = B[l%4][l/16] (B[q][node]), fD likewise; bB = B[l/16][l%4], bD likewise.
+struct Basis4 {
+  double fB, fD, bB, bD;
+};
+
+template <int P>
+__device__ inline Basis4 load_basis4(const DevTables* __restrict__ t) {
+  const int l = threadIdx.x & 63;
+  const int a = l & 3, c = l >> 4;
+  Basis4 b;
+  b.fB = (c < P) ? t->B[P][4][a][c] : 0.0;
+  b.fD = (c < P) ? t->D[P][4][a][c] : 0.0;
+  b.bB = (a < P) ? t->B[P][4][c][a] : 0.0;
+  b.bD = (a < P) ? t->D[P][4][c][a] : 0.0;
+  return b;
+}
+
+// Forward for NF fields in lockstep (independent chains interleaved): nodal
+// values u[f] (layout x,y,z) -> value v[f] and reference gradient d[f][0..2] at
+// the lane's point (layout qx,qz,qy). grad_mask / val_mask select the outputs.
+template <int NF>
+__device__ inline void sf4_fwd_n(const double* u, const Basis4& b, unsigned val_mask, unsigned grad_mask,
+                                 double* v, double (*d)[3]) {
+  double T[NF], Tz[NF], V2[NF], DX[NF], DZ[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    T[f] = mfma4(u[f], b.fB, 0.0);
+    if ((grad_mask >> f) & 1) Tz[f] = mfma4(u[f], b.fD, 0.0);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    V2[f] = mfma4(T[f], b.fB, 0.0);
+    if ((grad_mask >> f) & 1) {
+      DX[f] = mfma4(T[f], b.fD, 0.0);
+      DZ[f] = mfma4(Tz[f], b.fB, 0.0);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    V2[f] = swap_blocks(V2[f]);
+    if ((grad_mask >> f) & 1) {
+      DX[f] = swap_blocks(DX[f]);
+      DZ[f] = swap_blocks(DZ[f]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    if ((val_mask >> f) & 1) v[f] = mfma4(b.fB, V2[f], 0.0);
+    if ((grad_mask >> f) & 1) {
+      d[f][0] = mfma4(b.fB, DX[f], 0.0);
+      d[f][1] = mfma4(b.fD, V2[f], 0.0);
+      d[f][2] = mfma4(b.fB, DZ[f], 0.0);
+    }
+  }
+}
+
+// Backward for NF fields in lockstep: point coefficients f0[f] (value test, used
+// where f0_mask is set) and f1[f][0..2] (reference-gradient tests) -> nodal
+// contribution out[f] (layout x,y,z).
+template <int NF>
+__device__ inline void sf4_bwd_n(const double* f0, const double (*f1)[3], unsigned f0_mask, const Basis4& b,
+                                 double* out) {
+  double Z0[NF], Zx[NF], Zz[NF], Y0[NF], Yx[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Z0[f] = mfma4(b.bD, f1[f][1], 0.0);
+    Zx[f] = mfma4(b.bB, f1[f][0], 0.0);
+    Zz[f] = mfma4(b.bB, f1[f][2], 0.0);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    if ((f0_mask >> f) & 1) Z0[f] = mfma4(b.bB, f0[f], Z0[f]);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Z0[f] = swap_blocks(Z0[f]);
+    Zx[f] = swap_blocks(Zx[f]);
+    Zz[f] = swap_blocks(Zz[f]);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Y0[f] = mfma4(Zz[f], b.bD, 0.0);
+    Yx[f] = mfma4(Zx[f], b.bB, 0.0);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Y0[f] = mfma4(Z0[f], b.bB, Y0[f]);
+    out[f] = mfma4(Yx[f], b.bD, 0.0);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) out[f] = mfma4(Y0[f], b.bB, out[f]);
+}
+
+// Sum the element vectors ev[slot][f][64] (lane-indexed nodes a = i + 4 j + 16 k)
+// into the brick nodes and write them with the colour rule.
+template <typename T, int P, int NF>
+__device__ inline void scatter_brick4(const T* ev, const MeshDev& m, int nx1, int ny1, int64_t n_nodes,
+                                      const BrickGeom& g, T* __restrict__ dst) {
+  constexpr int p = P - 1, NB = 2 * P - 1, NB3 = NB * NB * NB;
+  const int mx = g.nex * p + 1, my = g.ney * p + 1, mz = g.nez * p + 1;
+  const int px = g.bx & 1, py = g.by & 1, pz = g.bz & 1;
+  for (int t = threadIdx.x; t < NB3; t += NT) {
+    const int lx = t % NB, ly = (t / NB) % NB, lz = t / (NB * NB);
+    if (!(lx < mx && ly < my && lz < mz)) continue;
+    T acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = T(0);
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz) {
+      const int k = lz - sz * p;
+      if (k < 0 || k > p || sz >= g.nez) continue;
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy) {
+        const int j = ly - sy * p;
+        if (j < 0 || j > p || sy >= g.ney) continue;
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const int i = lx - sx * p;
+          if (i < 0 || i > p || sx >= g.nex) continue;
+          const int slot = sx + 2 * sy + 4 * sz;
+          const int a = i + 4 * j + 16 * k;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f] += ev[(slot * NF + f) * 64 + a];
+        }
+      }
+    }
+    const bool shx = (lx == 0 && g.bx > 0) || (lx == mx - 1 && !g.last_x);
+    const bool shy = (ly == 0 && g.by > 0) || (ly == my - 1 && !g.last_y);
+    const bool shz = (lz == 0 && g.bz > 0) || (lz == mz - 1 && !g.last_z);
+    const bool store = !((shx && px) || (shy && py) || (shz && pz));
+    const int64_t gi = (int64_t)(g.ex0 * p + lx) + (int64_t)nx1 * ((g.ey0 * p + ly) + (int64_t)ny1 * (g.ez0 * p + lz));
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T* d = dst + f * n_nodes + gi;
+      if (store) *d = acc[f];
+      else *d += acc[f];
+    }
+  }
+}
+
+// Global node of lane (x, y, z) of element slot (sx, sy, sz) of the brick; -1 if
+// the lane is outside the element's P^3 nodes.
+template <int P>
+__device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, int nx1, int ny1) {
+  const int l = threadIdx.x & 63;
+  const int x = l & 3, y = (l >> 2) & 3, z = l >> 4;
+  if (x >= P || y >= P || z >= P) return -1;
+  constexpr int p = P - 1;
+  return (int64_t)((g.ex0 + sx) * p + x) + (int64_t)nx1 * (((g.ey0 + sy) * p + y) + (int64_t)ny1 * ((g.ez0 + sz) * p + z));
+}
+
+// FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ double ev[8 * 4 * 64];
+  __shared__ double red[NT];
+  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const Basis4 bs = load_basis4<4>(tabs);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
+  const int ql = qx + 4 * qy + 16 * qz;
+  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
+  const double wdet = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * (a.m.hx * a.m.hy * a.m.hz * 0.125);
+  int pids[2] = {-1, -1};
+  double gpar[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  bool any_bad = false;
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    const int slot = wv + 4 * half;
+    const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+    if (!(sx < g.nex && sy < g.ney && sz < g.nez)) continue;  // uniform per wave
+    const int64_t gn = lane_node<4>(g, sx, sy, sz, a.nx1, a.ny1);
+    // gather the element's nodal values (lane = node)
+    double zu[4], wu[4], pn = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) zu[f] = a.z[f * a.n_nodes + gn];
+    if (MODE != M_RES) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) wu[f] = a.w[f * a.n_nodes + gn];
+    } else {
+      pn = a.phin[gn];
+    }
+    // per-point state, issued early
+    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+    const int64_t gq = e * 64 + ql;
+    double st[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];
+    const int pid = a.phase[gq];
+    // forward sum factorisation
+    double G[9], phi = 0.0, gphi[3] = {0.0, 0.0, 0.0}, phin = 0.0;
+    {
+      double v[4], d[4][3];
+      sf4_fwd_n<4>(zu, bs, 0x8u, MODE == M_JAC ? 0x7u : 0xFu, v, d);
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) G[3 * f + J] = d[f][J] * ih[J];
+      phi = v[3];
+      if (MODE != M_JAC) {
+#pragma unroll
+        for (int J = 0; J < 3; ++J) gphi[J] = d[3][J] * ih[J];
+      }
+    }
+    if (MODE == M_RES) {
+      double v[1], d[1][3];
+      sf4_fwd_n<1>(&pn, bs, 0x1u, 0x0u, v, d);
+      phin = v[0];
+    }
+    double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
+    if (MODE != M_RES) {
+      double v[4], d[4][3];
+      sf4_fwd_n<4>(wu, bs, 0x8u, 0xFu, v, d);
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) W[3 * f + J] = d[f][J] * ih[J];
+      wphi = v[3];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) gw[J] = d[3][J] * ih[J];
+    }
+    // pointwise function
+    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<double> s;
+    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+    any_bad |= s.bad;
+    const double kfg = a.fr.kf * mp.Gc;
+    double Fu[9], f0, f1[3];
+    if (MODE == M_RES) {
+      piola<double>(s, Fu);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+      f0 = wdet * a.fr.s_phi * s.L;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
+    } else if (MODE == M_JAC) {
+      double dL;
+      qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+      f0 = wdet * a.fr.s_phi * dL;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gw[J];
+    } else {
+      double Pb[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
+      const double f0b = wdet * wphi;
+      const double Lb = a.fr.s_phi * f0b;
+      double phib, Xd[3];
+      qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
+      f0 = phib;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
+      double gsum[3] = {0.0, 0.0, 0.0};
+      const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
+      gsum[0] += alpha_p * a.fr.inv_c0l0 * Lb + a.fr.kf * wdet * (gphi[0] * gw[0] + gphi[1] * gw[1] + gphi[2] * gw[2]);
+      if (s.plastic) {
+        const double ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
+        const double q = 2.0 * mp.mu * sqrt(1.5 * ee);
+        const double w3q = 3.0 * mp.mu / q;
+        const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
+        const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        gsum[1] += -w3q * s.ddg_s0 * base;
+        gsum[2] += -w3q * s.ddg_visc * base;
+      }
+      pids[half] = pid;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gpar[half][k] = gsum[k];
+    }
+    // backward into the element vector
+    {
+      double b0[4], b1[4][3], r[4];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        b0[f] = 0.0;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) b1[f][J] = Fu[3 * f + J] * ih[J];
+      }
+      b0[3] = f0;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1[3][J] = f1[J] * ih[J];
+      sf4_bwd_n<4>(b0, b1, 0x8u, bs, r);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];
+    }
+  }
+  if (MODE == M_ADJ) {
+    // deterministic per-phase block reduction of the parameter partials
+    for (int ph = 0; ph < a.nph; ++ph) {
+      for (int k = 0; k < 3; ++k) {
+        red[threadIdx.x] = (pids[0] == ph ? gpar[0][k] : 0.0) + (pids[1] == ph ? gpar[1][k] : 0.0);
+        __syncthreads();
+        for (int st = NT / 2; st > 0; st >>= 1) {
+          if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+          __syncthreads();
+        }
+        if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + blockIdx.x) * a.nph + ph) * 3 + k] = red[0];
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  if (any_bad) a.flag[0] = 1;
+}
+
+}  // namespace pfmf

@@ -39,17 +39,64 @@ __device__ inline float pf_log1p(float x) { return log1pf(x); }
 __device__ inline double pf_abs(double x) { return fabs(x); }
 __device__ inline float pf_abs(float x) { return fabsf(x); }
 
+// Reciprocal and reciprocal square root from the hardware estimate refined by
+// two Newton steps (FP64) or used as is (FP32, about 1 ulp). Arguments here are
+// finite and positive (or nonzero for the reciprocal) by construction.
+__device__ inline double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double frsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double t = fma(-h * y, y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-h * y, y, 0.5);
+  return fma(y, t, y);
+}
+__device__ inline float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
 template <typename T> struct Eps;
 template <> struct Eps<double> {
-  static constexpr double conv = 1e-34;    // squared relative off-diagonal threshold
-  static constexpr double series = 1e-3;   // |x| below which log1p(x)/x uses its series
+  static constexpr double conv = 1e-30;    // squared relative off-diagonal threshold
+  static constexpr double tiny = 1e-280;   // below this the 2x2 block is left unrotated
+  static constexpr double series = 0.25;   // |x| up to which log1p uses the atanh series
+  static constexpr int nterms = 11;        // atanh series terms (relative error < 1e-17)
   static constexpr int max_sweeps = 8;
 };
 template <> struct Eps<float> {
-  static constexpr float conv = 1e-15f;
-  static constexpr float series = 3e-2f;
+  static constexpr float conv = 1e-13f;
+  static constexpr float tiny = 1e-30f;
+  static constexpr float series = 0.25f;
+  static constexpr int nterms = 5;
   static constexpr int max_sweeps = 6;
 };
+
+// 1 + s^2/3 + s^4/5 + ... (atanh(s)/s), Horner in s^2
+template <typename T>
+__device__ inline T atanh_ratio(T s2) {
+  T r = T(1) / T(2 * Eps<T>::nterms - 1);
+#pragma unroll
+  for (int k = Eps<T>::nterms - 2; k >= 0; --k) r = fma(r, s2, T(1) / T(2 * k + 1));
+  return r;
+}
+
+// 0.5 log1p(x) = atanh(x / (2 + x)); series for |x| <= 0.25, library beyond.
+template <typename T>
+__device__ inline T half_log1p(T x) {
+  T r;
+  if (pf_abs(x) <= Eps<T>::series) {
+    const T sv = x * frcp(T(2) + x);
+    r = sv * atanh_ratio(sv * sv);
+  } else {
+    r = T(0.5) * pf_log1p(x);
+  }
+  return r;
+}
 
 // Symmetric 3x3 stored as s[6] = {xx, yy, zz, yz, xz, xy}.
 // General 3x3 stored row-major m[9].
@@ -59,27 +106,32 @@ template <> struct Eps<float> {
 // early exit when the off-diagonal part is negligible.
 template <typename T>
 __device__ inline void jacobi_rotate(T& app, T& aqq, T& apq, T& arp, T& arq, T* V, int p, int q) {
-  const T o = apq;
+  // rotation angle phi with tan(2 phi) = 2 apq / (aqq - app), |phi| <= pi/4, from
+  // cos(2 phi) = |d|/r, sin(2 phi) = sgn(d) 2 apq / r and the half-angle formulas
   const T d = aqq - app;
-  // t = tan(angle) of the smaller rotation; t = 0 when o == 0
-  T th = d / (T(2) * o);
-  T t = T(1) / (pf_abs(th) + pf_sqrt(th * th + T(1)));
-  t = (th < T(0)) ? -t : t;
-  t = (o == T(0)) ? T(0) : t;
-  const T c = pf_rsqrt(t * t + T(1));
-  const T s = t * c;
+  const T o = apq;
+  const T r2 = d * d + T(4) * o * o;
+  const bool flat = !(r2 > Eps<T>::tiny);
+  const T ir = frsqrt(flat ? T(1) : r2);
+  const T cos2 = flat ? T(1) : pf_abs(d) * ir;
+  const T sin2 = flat ? T(0) : ((d < T(0)) ? T(-2) : T(2)) * o * ir;
+  const T h = T(0.5) + T(0.5) * cos2;
+  const T ic = frsqrt(h);  // 1 / cos(phi)
+  const T c = h * ic;
+  const T sn = T(0.5) * sin2 * ic;
+  const T t = sn * ic;     // tan(phi)
   app -= t * o;
   aqq += t * o;
   apq = T(0);
-  const T rp = c * arp - s * arq;
-  const T rq = s * arp + c * arq;
+  const T rp = c * arp - sn * arq;
+  const T rq = sn * arp + c * arq;
   arp = rp;
   arq = rq;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const T vp = V[3 * k + p], vq = V[3 * k + q];
-    V[3 * k + p] = c * vp - s * vq;
-    V[3 * k + q] = s * vp + c * vq;
+    V[3 * k + p] = c * vp - sn * vq;
+    V[3 * k + q] = sn * vp + c * vq;
   }
 }
 
@@ -102,23 +154,21 @@ __device__ inline void eig_sym3(const T* A, T* lam, T* V) {
 }
 
 // (ln b_i - ln b_j) / (b_i - b_j) for b = 1 + beta, finite at b_i == b_j.
-// eps_i = 0.5 ln b_i are already available; below the series threshold the
-// quotient uses log1p(x)/x = 1 - x/2 + x^2/3 - ... with x = b_i/b_j - 1.
+// With x = b_i / b_j - 1 and z = x / (2 + x): ln(b_i/b_j) = 2 atanh(z), so the
+// quotient is 2/(2 + x) atanh(z)/z / b_j (series for |x| <= 0.25); beyond that the
+// logarithms are far enough apart for the plain difference quotient.
 template <typename T>
-__device__ inline T log_divdiff(T beta_i, T beta_j, T eps_i, T eps_j) {
-  const T bj = T(1) + beta_j;
-  const T x = (beta_i - beta_j) / bj;
-  if (pf_abs(x) < Eps<T>::series) {
-    T s = T(1) / T(7);
-    s = T(1) / T(6) - x * s;
-    s = T(1) / T(5) - x * s;
-    s = T(1) / T(4) - x * s;
-    s = T(1) / T(3) - x * s;
-    s = T(1) / T(2) - x * s;
-    s = T(1) - x * s;
-    return s / bj;
+__device__ inline T log_divdiff(T beta_i, T beta_j, T eps_i, T eps_j, T ib_j) {
+  const T x = (beta_i - beta_j) * ib_j;
+  T r;
+  if (pf_abs(x) <= Eps<T>::series) {
+    const T w = frcp(T(2) + x);
+    const T zz = x * w;
+    r = T(2) * w * atanh_ratio(zz * zz) * ib_j;
+  } else {
+    r = T(2) * (eps_i - eps_j) * frcp(beta_i - beta_j);
   }
-  return T(2) * (eps_i - eps_j) / (beta_i - beta_j);
+  return r;
 }
 
 // Everything the tangent needs at one point (residual pass output).
@@ -155,7 +205,7 @@ __device__ inline void qp_kin(const T* G, const T* st, QPState<T>& s, T* beta, T
   const T c01 = F[5] * F[6] - F[3] * F[8];
   const T c02 = F[3] * F[7] - F[4] * F[6];
   const T det = F[0] * c00 + F[1] * c01 + F[2] * c02;
-  const T idet = T(1) / det;
+  const T idet = frcp(det);
   s.Fi[0] = c00 * idet;
   s.Fi[3] = c01 * idet;
   s.Fi[6] = c02 * idet;
@@ -196,8 +246,8 @@ __device__ inline void qp_kin(const T* G, const T* st, QPState<T>& s, T* beta, T
   s.theta = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    eps[i] = T(0.5) * pf_log1p(beta[i]);
-    s.hinv[i] = T(0.5) / (T(1) + beta[i]);
+    eps[i] = half_log1p(beta[i]);
+    s.hinv[i] = T(0.5) * frcp(T(1) + beta[i]);
     s.theta += eps[i];
   }
   const T th3 = s.theta * (T(1) / T(3));
@@ -218,9 +268,9 @@ __device__ inline void qp_frame_stress(const MatParams<T>& m, const T* beta, con
                s.taud[2] * N[3 * i + 2] * N[3 * j + 2];
   }
   const T gmc = s.g * m.mu * s.c;
-  s.coef[0] = gmc * log_divdiff(beta[1], beta[2], eps[1], eps[2]);
-  s.coef[1] = gmc * log_divdiff(beta[0], beta[2], eps[0], eps[2]);
-  s.coef[2] = gmc * log_divdiff(beta[0], beta[1], eps[0], eps[1]);
+  s.coef[0] = gmc * log_divdiff(beta[1], beta[2], eps[1], eps[2], T(2) * s.hinv[2]);
+  s.coef[1] = gmc * log_divdiff(beta[0], beta[2], eps[0], eps[2], T(2) * s.hinv[2]);
+  s.coef[2] = gmc * log_divdiff(beta[0], beta[1], eps[0], eps[1], T(2) * s.hinv[1]);
 }
 
 // Residual state at one point: steps of Box 1 / Box 2 and Section 3.
@@ -237,7 +287,8 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   s.gp = T(-2) * omp;
   // Prandtl branch with the degraded trial stress (Box 2, eq:degraded-yield-condition)
   const T ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
-  const T q = T(2) * m.mu * pf_sqrt(T(1.5) * ee);
+  const T u15 = T(1.5) * ee;
+  const T q = (u15 > T(0)) ? T(2) * m.mu * u15 * frsqrt(u15) : T(0);
   const T sn = m.sigma0 + m.H * st[6];
   const T f = s.g * q - sn;
   s.plastic = m.plastic && (f > T(0));
@@ -248,12 +299,13 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   s.ddg_visc = T(0);
   if (s.plastic) {
     const T B = T(3) * s.g * m.mu + m.H + m.a * sn;
-    const T dg = T(2) * f / (B + pf_sqrt(B * B + T(4) * m.a * m.H * f));
-    const T iq = T(1) / q;
+    const T disc = B * B + T(4) * m.a * m.H * f;
+    const T dg = T(2) * f * frcp(B + disc * frsqrt(disc));
+    const T iq = frcp(q);
     s.c = T(1) - T(3) * m.mu * dg * iq;
     const T sy = sn + m.H * dg;
     const T den = T(3) * s.g * m.mu + m.H * (T(1) + m.a * dg) + m.a * sy;
-    const T iden = T(1) / den;
+    const T iden = frcp(den);
     const T w = T(3) * m.mu * iq;
     s.kq = -w * (s.g * iden - dg * iq) * (T(6) * m.mu * m.mu * iq);
     s.kphi = -w * s.gp * (q - T(3) * m.mu * dg) * iden;

@@ -12,6 +12,7 @@
 #include "pfmf.h"
 #include "pf_ops.hpp"
 #include "pf_mg.hpp"
+#include "pf_mfma.hpp"
 #include "pf_tables.hpp"
 
 using namespace pfmf;
@@ -186,11 +187,23 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
 }
 
 template <int MODE>
+pf_status launch_op64_q3(pf_ctx* c, OpArgs a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    a.brick_base = c->colour_base[col];
+    hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int MODE>
 pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   switch (c->mesh.p) {
     case 1: return launch_op64<MODE, 2, 2>(c, a, s);
     case 2: return launch_op64<MODE, 3, 3>(c, a, s);
-    case 3: return launch_op64<MODE, 4, 4>(c, a, s);
+    case 3: return launch_op64_q3<MODE>(c, a, s);
     case 4: return launch_op64<MODE, 5, 5>(c, a, s);
     default: return fail(PF_EUNSUPPORTED, "order p=%d not built", c->mesh.p);
   }
