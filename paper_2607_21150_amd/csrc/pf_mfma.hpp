@@ -190,7 +190,7 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
 
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
 template <int MODE>
-__global__ __launch_bounds__(NT) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+__global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
   const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
@@ -342,6 +342,94 @@ __global__ __launch_bounds__(NT) void k_op64_q3(OpArgs a, int colour, DevTables*
   __syncthreads();
   scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
+}
+
+}  // namespace pfmf
+
+namespace pfmf {
+
+// FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
+// level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
+// contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).
+template <int PC>
+__global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ float ev[8 * 4 * 64];
+  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const Basis4 bf = load_basis4<4>(tabs);
+  const Basis4 bc = load_basis4<PC>(tabs);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
+  const int ql = qx + 4 * qy + 16 * qz;
+  const float ih[3] = {(float)(2.0 / a.m.hx), (float)(2.0 / a.m.hy), (float)(2.0 / a.m.hz)};
+  const float wdet = (float)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * (a.m.hx * a.m.hy * a.m.hz * 0.125));
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    const int slot = wv + 4 * half;
+    const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+    if (!(sx < g.nex && sy < g.ney && sz < g.nez)) continue;  // uniform per wave
+    const int64_t gf = lane_node<4>(g, sx, sy, sz, a.fine.nx1, a.fine.ny1);
+    const int64_t gc = lane_node<PC>(g, sx, sy, sz, a.lev.nx1, a.lev.ny1);
+    double zu[3], wu[4];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) zu[f] = (double)a.z32[f * a.fine.n_nodes + gf];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) wu[f] = gc >= 0 ? (double)a.dz[f * a.lev.n_nodes + gc] : 0.0;
+    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+    const int64_t gq = e * 64 + ql;
+    LinRecord rc;
+    rc.c = a.rec.rec[0 * a.n_q + gq];
+    rc.kq = a.rec.rec[1 * a.n_q + gq];
+    rc.kphi = a.rec.rec[2 * a.n_q + gq];
+    rc.g = a.rec.rec[3 * a.n_q + gq];
+    rc.gp = a.rec.rec[4 * a.n_q + gq];
+    rc.dL = a.rec.rec[5 * a.n_q + gq];
+    rc.flags = a.rec.flags[gq];
+    float D[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) D[k] = a.rec.D32[k * a.n_q + gq];
+    const int pid = a.phase[gq];
+    float G[9], W[9], wphi, gw[3];
+    {
+      double v[3], d[3][3];
+      sf4_fwd_n<3>(zu, bf, 0x0u, 0x7u, v, d);
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) G[3 * f + J] = (float)d[f][J] * ih[J];
+    }
+    {
+      double v[4], d[4][3];
+      sf4_fwd_n<4>(wu, bc, 0x8u, 0xFu, v, d);
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) W[3 * f + J] = (float)d[f][J] * ih[J];
+      wphi = (float)v[3];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) gw[J] = (float)d[3][J] * ih[J];
+    }
+    const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<float> s;
+    qp_state_lin<float>(mp, G, D, rc, s);
+    float Fu[9], dL;
+    qp_tangent<float>(mp, s, W, wphi, Fu, dL);
+    const float kfg = a.fr.kf * mp.Gc;
+    double b0[4], b1[4][3], r[4];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      b0[f] = 0.0;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+    }
+    b0[3] = (double)(wdet * a.fr.s_phi * dL);
+#pragma unroll
+    for (int J = 0; J < 3; ++J) b1[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
+    sf4_bwd_n<4>(b0, b1, 0x8u, bc, r);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (float)r[f];
+  }
+  __syncthreads();
+  scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }
 
 }  // namespace pfmf

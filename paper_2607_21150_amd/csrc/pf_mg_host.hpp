@@ -149,10 +149,29 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
   return fail(PF_EUNSUPPORTED, "level order not built");
 }
 
+template <int PC>
+pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    hipLaunchKernelGGL((k_a32_q3<PC>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
 template <int MODE>
 pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
   const A32Args a = a32_args(c, level, dz, out);
   const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
+  if (MODE == 0 && PF == 4) {
+    switch (PC) {
+      case 4: return launch_a32_q3<4>(c, a, s);
+      case 3: return launch_a32_q3<3>(c, a, s);
+      case 2: return launch_a32_q3<2>(c, a, s);
+      default: break;
+    }
+  }
   switch (PF) {
     case 2: return dispatch_pc<MODE, 2>(c, PC, a, s);
     case 3: return dispatch_pc<MODE, 3>(c, PC, a, s);

@@ -135,22 +135,98 @@ __device__ inline void jacobi_rotate(T& app, T& aqq, T& apq, T& arp, T& arq, T* 
   }
 }
 
+__device__ inline float seed_cos_third(float r) { return cosf(acosf(r) * (1.0f / 3.0f)); }
+
+// Symmetric 3x3 eigen-decomposition A = V diag(lam) V^T (eigenvectors in the
+// columns of V). Closed-form eigenvalues of the deviator (cos(acos(r)/3), seeded
+// in FP32 and refined by one Newton step on 4 c^3 - 3 c = r), the null vector of
+// A - lam I for the most isolated eigenvalue by cross products, any orthonormal
+// completion of it, and one cyclic Jacobi sweep on V^T A V. The sweep removes the
+// error of the closed form (second order after one sweep) and diagonalises a
+// nearly repeated pair exactly, where the closed form alone is inaccurate.
 template <typename T>
 __device__ inline void eig_sym3(const T* A, T* lam, T* V) {
-  T a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+  const T a00 = A[0], a11 = A[1], a22 = A[2], a12 = A[3], a02 = A[4], a01 = A[5];
+  const T m = (a00 + a11 + a22) * (T(1) / T(3));
+  const T s00 = a00 - m, s11 = a11 - m, s22 = a22 - m;
+  const T J2 = T(0.5) * (s00 * s00 + s11 * s11 + s22 * s22) + a01 * a01 + a02 * a02 + a12 * a12;
 #pragma unroll
   for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? T(1) : T(0);
-  for (int sweep = 0; sweep < Eps<T>::max_sweeps; ++sweep) {
-    const T off = a01 * a01 + a02 * a02 + a12 * a12;
-    const T dia = a00 * a00 + a11 * a11 + a22 * a22;
-    if (off <= Eps<T>::conv * dia) break;
-    jacobi_rotate(a00, a11, a01, a02, a12, V, 0, 1);  // (p,q)=(0,1), r=2: arp=a20, arq=a21
-    jacobi_rotate(a00, a22, a02, a01, a12, V, 0, 2);  // (0,2), r=1: a10, a12
-    jacobi_rotate(a11, a22, a12, a01, a02, V, 1, 2);  // (1,2), r=0: a01, a02
+  if (J2 > Eps<T>::tiny + Eps<T>::conv * m * m) {
+    const T J3 = s00 * (s11 * s22 - a12 * a12) - a01 * (a01 * s22 - a12 * a02) + a02 * (a01 * a12 - s11 * a02);
+    const T q3 = J2 * (T(1) / T(3));
+    const T ip = frsqrt(q3);
+    const T p = q3 * ip;
+    T r = T(0.5) * J3 * ip * ip * ip;
+    r = r > T(1) ? T(1) : (r < T(-1) ? T(-1) : r);
+    T c = (T)seed_cos_third((float)r);
+    const T den = T(12) * c * c - T(3);
+    if (den > T(1e-3)) c -= (T(4) * c * c * c - T(3) * c - r) * frcp(den);
+    c = c > T(1) ? T(1) : (c < T(0.5) ? T(0.5) : c);
+    const T x = T(1) - c * c;
+    const T sn = x > T(0) ? x * frsqrt(x) : T(0);
+    const T lmax = m + T(2) * p * c;
+    const T lmin = m + T(2) * p * (T(-0.5) * c - T(0.86602540378443864676) * sn);
+    const T lmid = T(3) * m - lmax - lmin;
+    const T iso = (lmax - lmid >= lmid - lmin) ? lmax : lmin;
+    // null vector of A - iso I: largest cross product of two rows
+    const T r0[3] = {a00 - iso, a01, a02}, r1[3] = {a01, a11 - iso, a12}, r2[3] = {a02, a12, a22 - iso};
+    T v[3], w[3];
+    v[0] = r0[1] * r1[2] - r0[2] * r1[1];
+    v[1] = r0[2] * r1[0] - r0[0] * r1[2];
+    v[2] = r0[0] * r1[1] - r0[1] * r1[0];
+    T nv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    w[0] = r0[1] * r2[2] - r0[2] * r2[1];
+    w[1] = r0[2] * r2[0] - r0[0] * r2[2];
+    w[2] = r0[0] * r2[1] - r0[1] * r2[0];
+    T nw = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    if (nw > nv) { v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; nv = nw; }
+    w[0] = r1[1] * r2[2] - r1[2] * r2[1];
+    w[1] = r1[2] * r2[0] - r1[0] * r2[2];
+    w[2] = r1[0] * r2[1] - r1[1] * r2[0];
+    nw = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    if (nw > nv) { v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; nv = nw; }
+    if (nv > Eps<T>::tiny) {
+      const T in = frsqrt(nv);
+      const T n3[3] = {v[0] * in, v[1] * in, v[2] * in};
+      // completion: n3 x e_k for the axis k where |n3_k| is smallest
+      const T ax = pf_abs(n3[0]), ay = pf_abs(n3[1]), az = pf_abs(n3[2]);
+      T u1[3];
+      if (ax <= ay && ax <= az) { u1[0] = T(0); u1[1] = n3[2]; u1[2] = -n3[1]; }
+      else if (ay <= az) { u1[0] = -n3[2]; u1[1] = T(0); u1[2] = n3[0]; }
+      else { u1[0] = n3[1]; u1[1] = -n3[0]; u1[2] = T(0); }
+      const T iu = frsqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+      u1[0] *= iu; u1[1] *= iu; u1[2] *= iu;
+      const T u2[3] = {n3[1] * u1[2] - n3[2] * u1[1], n3[2] * u1[0] - n3[0] * u1[2], n3[0] * u1[1] - n3[1] * u1[0]};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        V[3 * k + 0] = u1[k];
+        V[3 * k + 1] = u2[k];
+        V[3 * k + 2] = n3[k];
+      }
+    }
   }
-  lam[0] = a00;
-  lam[1] = a11;
-  lam[2] = a22;
+  // B = V^T A V
+  const T Am[9] = {a00, a01, a02, a01, a11, a12, a02, a12, a22};
+  T W[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) W[3 * i + j] = Am[3 * i] * V[j] + Am[3 * i + 1] * V[3 + j] + Am[3 * i + 2] * V[6 + j];
+  T b[6];
+  const int ri[6] = {0, 1, 2, 1, 0, 0}, ci[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = ri[k], j = ci[k];
+    b[k] = V[i] * W[j] + V[3 + i] * W[3 + j] + V[6 + i] * W[6 + j];
+  }
+  T b00 = b[0], b11 = b[1], b22 = b[2], b12 = b[3], b02 = b[4], b01 = b[5];
+  jacobi_rotate(b00, b11, b01, b02, b12, V, 0, 1);
+  jacobi_rotate(b00, b22, b02, b01, b12, V, 0, 2);
+  jacobi_rotate(b11, b22, b12, b01, b02, V, 1, 2);
+  lam[0] = b00;
+  lam[1] = b11;
+  lam[2] = b22;
 }
 
 // (ln b_i - ln b_j) / (b_i - b_j) for b = 1 + beta, finite at b_i == b_j.

@@ -114,3 +114,54 @@ def test_error_paths(pf):
         ctx.check()
     assert e.value.code == pf.PF_ENONPHYSICAL
     ctx.check()  # flag cleared
+
+
+def _degenerate_inputs(kind):
+    """C1 mesh with D = 0 and an exactly uniaxial / isotropic / zero / biaxial displacement,
+    so b_tr has exactly repeated eigenvalues at every point. (Isochoric states such as simple
+    shear are avoided: there tr eps = ln det F = 0 sits exactly on the split switch, where the
+    tangent is one-sided and the branch taken depends on the last bit of rounding.)"""
+    d = I.make_inputs("C1", "base")
+    m = d["mesh"]
+    X = I._coords_1d(m.nx, m.p, m.lx, I.gll_points(m.p))
+    nx1, ny1, nz1 = m.node_dims
+    Zg, Yg, Xg = [a.reshape(-1) for a in np.meshgrid(X, X, X, indexing="ij")]
+    z = d["z"].copy()
+    z[:3] = 0.0
+    if kind == "uniaxial":
+        z[2] = 2e-3 * Zg
+    elif kind == "isotropic":
+        z[0], z[1], z[2] = 1e-3 * Xg, 1e-3 * Yg, 1e-3 * Zg
+    elif kind == "biaxial":
+        z[0], z[1] = 2e-3 * Xg, 2e-3 * Yg
+    st = d["state"].copy()
+    st[:6] = 0.0
+    d = dict(d, z=z, state=st)
+    return d
+
+
+@pytest.mark.parametrize("kind", ["uniaxial", "isotropic", "zero", "biaxial"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_repeated_eigenvalues(pf, oracle_lib, kind, p):
+    d = _degenerate_inputs(kind)
+    if p != 2:
+        base = I.make_inputs("C1", "base", p=p, n=3)
+        m = base["mesh"]
+        X = I._coords_1d(m.nx, m.p, m.lx, I.gll_points(m.p))
+        Zg, Yg, Xg = [a.reshape(-1) for a in np.meshgrid(X, X, X, indexing="ij")]
+        z = base["z"].copy(); z[:3] = 0.0
+        if kind == "uniaxial":
+            z[2] = 2e-3 * Zg
+        elif kind == "isotropic":
+            z[0], z[1], z[2] = 1e-3 * Xg, 1e-3 * Yg, 1e-3 * Zg
+        elif kind == "biaxial":
+            z[0], z[1] = 2e-3 * Xg, 2e-3 * Yg
+        st = base["state"].copy(); st[:6] = 0.0
+        d = dict(base, z=z, state=st)
+    orc = oracle_lib.Oracle.from_inputs(d)
+    ctx = pf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    check_blocks(ctx.apply_residual(z).cpu().numpy(), orc.residual(d["z"]), FP64_TOL, "residual")
+    check_blocks(ctx.apply_jacobian(z, dz).cpu().numpy(), orc.jacobian(d["z"], d["dz"]), FP64_TOL, "jacobian")
+    gz, _ = ctx.apply_adjoint(z, v)
+    check_blocks(gz.cpu().numpy(), orc.adjoint(d["z"], d["v_rand"])[0], FP64_TOL, "adjoint")
