@@ -24,6 +24,56 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VEC_PEAK_TFLOPS = 78.6
+CSRC = os.path.join(ROOT, "paper_2607_21150_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_op64_q3_jacobian_C3_hbm_counters.md")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources (sorted by name): identifies the kernels the counters belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config):
+    """HBM bytes per Jacobian apply from the committed counter summary, or None when the summary is
+    missing, was taken on another workload, or the kernel sources changed since it was taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("- ") and " = " in line:
+                    k, v = line[2:].split(" = ", 1)
+                    kv[k.strip().strip("`")] = v.strip().strip("`")
+        if kv.get("source_sha256") != kernel_source_digest() or kv.get("config") != config:
+            return None
+        return float(kv["hbm_bytes_per_apply"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of a known size: achievable HBM GB/s (read + write) on this GPU. Its
+    kernel also calibrates the FETCH_SIZE / WRITE_SIZE counters."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return {"bytes_per_copy": 2 * nbytes, "ms": t * 1e3, "gbs": 2 * nbytes / t / 1e9}
 
 
 def alg_bytes(mesh, kind):
@@ -143,6 +193,7 @@ def main():
     wall = time.perf_counter() - t0
     ms = {k: float(np.mean([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
     ms_min = {k: float(np.min([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
+    ms_med = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
     print(f"[bench] timed {args.steps} steps in {wall:.2f} s: {ms}", file=sys.stderr, flush=True)
 
     # errors against the oracle on sampled nodes (FP64 bar 1e-12)
@@ -161,10 +212,15 @@ def main():
     except Exception as exc:  # the oracle is a checker; its absence does not stop the benchmark
         errs["error"] = str(exc)
 
+    copy = copy_probe(torch)
+    print(f"[bench] copy probe {copy}", file=sys.stderr, flush=True)
+
     t_jac = ms["jacobian"] * 1e-3
     value = mesh.n_dof / t_jac
     bj = alg_bytes(mesh, "jacobian")
     achieved = bj / t_jac / 1e9
+    traffic = measured_traffic(args.config + "/" + args.variant)
+    kname = "pfmf::k_op64_q3<1>" if mesh.p == 3 else f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>"
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(d, args.cpu_seconds)
@@ -193,13 +249,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_op64<JAC> (8 colour launches per apply)",
+            "traffic": traffic,
+            "kernel": f"{kname} (one Jacobian apply = 8 colour launches; bytes and time per apply)",
             "alg_bytes_per_apply": bj,
+            "copy_probe_gbs": copy["gbs"],
         },
         "cpu_baseline": cpu,
         "ms": ms,
         "ms_min": ms_min,
+        "ms_median": ms_med,
         "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("residual", "jacobian", "adjoint", "fp32_apply")},
         "gbs_alg": {k: alg_bytes(mesh, k) / (ms[k] * 1e-3) / 1e9 for k in ("residual", "jacobian", "adjoint",
                                                                               "fp32_apply")},

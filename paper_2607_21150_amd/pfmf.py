@@ -232,3 +232,37 @@ class Context:
 
     def check(self):
         _check(load().pf_check(self._h))
+
+
+class PhaseFieldResidual(torch.autograd.Function):
+    """r = R(z; params) as a differentiable torch op on the device.
+
+    forward(z, params, op): ``z`` is the [4][n_nodes] FP64 device solution, ``params`` the
+    [n_phases][3] per-phase (Gc, sigma0, visc) tensor, ``op`` a ``Context``. The context's
+    parameters are set to ``params`` (they stay set after the call).
+    backward(v): the hand-written adjoint kernel returns J(z)^T v and the per-phase partials
+    dot(v, dR/d(Gc, sigma0, visc)); the pointwise linearisation is recomputed from z and the
+    state, nothing is stored between forward and backward. Residual and its transposed
+    linearisation follow the matrix-free residual and Jacobian of Section 4.
+    """
+
+    @staticmethod
+    def forward(ctx, z, params, op):
+        op.set_params(params.detach().to("cpu", torch.float64).numpy())
+        r = op.apply_residual(z.detach().contiguous())
+        ctx.save_for_backward(z, params)
+        ctx.op = op
+        return r
+
+    @staticmethod
+    def backward(ctx, v):
+        z, params = ctx.saved_tensors
+        op = ctx.op
+        op.set_params(params.detach().to("cpu", torch.float64).numpy())
+        gz, gp = op.apply_adjoint(z.detach().contiguous(), v.detach().to(torch.float64).contiguous())
+        return gz, gp.to(device=params.device, dtype=params.dtype), None
+
+
+def phase_field_residual(z, params, op):
+    """Functional form of ``PhaseFieldResidual``."""
+    return PhaseFieldResidual.apply(z, params, op)
