@@ -200,8 +200,13 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
   const int ql = qx + 4 * qy + 16 * qz;
   const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
   const double wdet = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * (a.m.hx * a.m.hy * a.m.hz * 0.125);
-  int pids[2] = {-1, -1};
-  double gpar[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  // adjoint: parameter partials and phase id of every point of the brick (slot, lane)
+  __shared__ double gpq[MODE == M_ADJ ? 8 * 3 * 64 : 1];
+  __shared__ unsigned char gpid[MODE == M_ADJ ? 8 * 64 : 1];
+  if (MODE == M_ADJ) {
+    gpid[wv * 64 + l] = 255;
+    gpid[(wv + 4) * 64 + l] = 255;
+  }
   bool any_bad = false;
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
@@ -303,9 +308,9 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
         gsum[1] += -w3q * s.ddg_s0 * base;
         gsum[2] += -w3q * s.ddg_visc * base;
       }
-      pids[half] = pid;
+      gpid[slot * 64 + l] = (unsigned char)pid;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) gpar[half][k] = gsum[k];
+      for (int k = 0; k < 3; ++k) gpq[(slot * 3 + k) * 64 + l] = gsum[k];
     }
     // backward into the element vector
     {
@@ -325,17 +330,41 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     }
   }
   if (MODE == M_ADJ) {
-    // deterministic per-phase block reduction of the parameter partials
-    for (int ph = 0; ph < a.nph; ++ph) {
-      for (int k = 0; k < 3; ++k) {
-        red[threadIdx.x] = (pids[0] == ph ? gpar[0][k] : 0.0) + (pids[1] == ph ? gpar[1][k] : 0.0);
-        __syncthreads();
-        for (int st = NT / 2; st > 0; st >>= 1) {
-          if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    // deterministic per-phase reduction of the parameter partials: a butterfly inside
+    // each wave, then the 4 wave sums added in wave order
+    // (each thread owns the points (wv, l) and (wv + 4, l), which it wrote itself)
+    const int nv = 3 * a.nph;
+    const int pid0 = gpid[wv * 64 + l], pid1 = gpid[(wv + 4) * 64 + l];
+    if (nv * (NT / 64) <= NT) {
+      for (int idx = 0; idx < nv; ++idx) {
+        const int ph = idx / 3, k = idx - 3 * ph;
+        const double g0 = pid0 == ph ? gpq[(wv * 3 + k) * 64 + l] : 0.0;
+        const double g1 = pid1 == ph ? gpq[((wv + 4) * 3 + k) * 64 + l] : 0.0;
+        double v = g0 + g1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (l == 0) red[wv * nv + idx] = v;
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < nv) {
+        double t = red[threadIdx.x];
+        for (int w = 1; w < NT / 64; ++w) t += red[w * nv + threadIdx.x];
+        a.gpart[(int64_t)(a.brick_base + blockIdx.x) * nv + threadIdx.x] = t;
+      }
+    } else {
+      for (int ph = 0; ph < a.nph; ++ph) {
+        for (int k = 0; k < 3; ++k) {
+          const double g0 = pid0 == ph ? gpq[(wv * 3 + k) * 64 + l] : 0.0;
+          const double g1 = pid1 == ph ? gpq[((wv + 4) * 3 + k) * 64 + l] : 0.0;
+          red[threadIdx.x] = g0 + g1;
+          __syncthreads();
+          for (int st = NT / 2; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+          }
+          if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + blockIdx.x) * a.nph + ph) * 3 + k] = red[0];
           __syncthreads();
         }
-        if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + blockIdx.x) * a.nph + ph) * 3 + k] = red[0];
-        __syncthreads();
       }
     }
   }

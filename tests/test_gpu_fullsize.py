@@ -1,0 +1,92 @@
+"""Full-size parity: the workloads bench.py times, launched the same way (one context per
+workload, 8 colour launches per apply), against the oracle.
+
+* Q2 32^3 (1.1 M DoFs): the oracle evaluates the whole mesh; element-by-element bar 1e-12.
+* Q3 48^3 (12.2 M DoFs) and Q4 40^3 (16.7 M DoFs): the oracle recomputes the elements around
+  sampled nodes (node values there are complete sums), bar 1e-12 for FP64 and 1e-5 for the FP32
+  fine-level apply; plus the dot-product identity <v, J w> = <J^T v, w>, a property that holds
+  at any size.
+"""
+import numpy as np
+import pytest
+
+from paper_2607_21150_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_2607_21150_amd import pfmf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pfmf.load()
+    return pfmf
+
+
+def dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def sampled(mesh, gpu, ref_fn, rng, n=96):
+    """GPU vs oracle on n random nodes plus the 8 lattice corners (boundary nodes)."""
+    nx1, ny1, nz1 = mesh.node_dims
+    corners = [i + nx1 * (j + ny1 * k) for i in (0, nx1 - 1) for j in (0, ny1 - 1) for k in (0, nz1 - 1)]
+    nodes = np.unique(np.concatenate([rng.choice(mesh.n_nodes, size=n, replace=False), corners]))
+    ref = ref_fn(I.elements_touching_nodes(mesh, nodes))
+    return relerr(gpu[:, nodes], ref[:, nodes])
+
+
+def test_q2_32_full_mesh(pf, oracle_lib):
+    print("case C2 plastic full mesh: residual, Jacobian, adjoint", flush=True)
+    d = I.make_inputs("C2", "plastic")
+    ctx = pf.Context.from_inputs(d)
+    orc = oracle_lib.Oracle.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r = ctx.apply_residual(z).cpu().numpy()
+    y = ctx.apply_jacobian(z, dz).cpu().numpy()
+    gz, _ = ctx.apply_adjoint(z, v)
+    ctx.check()
+    assert relerr(r, orc.residual(d["z"])) <= FP64_TOL
+    assert relerr(y, orc.jacobian(d["z"], d["dz"])) <= FP64_TOL
+    assert relerr(gz.cpu().numpy(), orc.adjoint(d["z"], d["v_rand"])[0]) <= FP64_TOL
+
+
+@pytest.mark.parametrize("name,variant", [("C3", "base"), ("C3", "plastic"), ("C5", "base")])
+def test_large_sampled(pf, oracle_lib, name, variant):
+    print(f"case {name} {variant} full size, sampled nodes", flush=True)
+    d = I.make_inputs(name, variant)
+    mesh = d["mesh"]
+    ctx = pf.Context.from_inputs(d)
+    orc = oracle_lib.Oracle.from_inputs(d)
+    rng = np.random.default_rng(11)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r = ctx.apply_residual(z).cpu().numpy()
+    y_t = ctx.apply_jacobian(z, dz)
+    gz_t, _ = ctx.apply_adjoint(z, v)
+    ctx.check()
+    # property at any size: <v, J dz> = <J^T v, dz>
+    a = float(torch.sum(v * y_t))
+    b = float(torch.sum(gz_t * dz))
+    assert abs(a - b) <= 1e-12 * float(torch.linalg.norm(gz_t) * torch.linalg.norm(dz)), (a, b)
+    y, gz = y_t.cpu().numpy(), gz_t.cpu().numpy()
+    e = sampled(mesh, r, lambda el: orc.residual(d["z"], elems=el), rng)
+    assert e <= FP64_TOL, ("residual", e)
+    e = sampled(mesh, y, lambda el: orc.jacobian(d["z"], d["dz"], elems=el), rng)
+    assert e <= FP64_TOL, ("jacobian", e)
+    e = sampled(mesh, gz, lambda el: orc.adjoint(d["z"], d["v_rand"], elems=el)[0], rng)
+    assert e <= FP64_TOL, ("adjoint", e)
+    if name == "C3":
+        ctx.linearize(z)
+        y32 = ctx.apply_jacobian_f32(0, dz.float()).double().cpu().numpy()
+        ctx.check()
+        e = sampled(mesh, y32, lambda el: orc.jacobian(d["z"], d["dz"], elems=el), rng)
+        assert e <= FP32_TOL, ("fp32 fine apply", e)
