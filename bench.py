@@ -163,13 +163,17 @@ def main():
     ctx.linearize(z)
     ctx.apply_jacobian_f32(0, dz32, b32)
 
+    # Order within a step: the linearisation synchronises the host (power iteration), so the
+    # queue is empty after it; the V-cycle follows it (its many launches dwarf the first
+    # launch's host latency), and the single applies are enqueued while earlier work still
+    # runs, so their event pairs measure device time, not host launch latency.
     ops = {
+        "linearize": lambda: ctx.linearize(z),
+        "vcycle": lambda: ctx.pmg_vcycle(b32, x32),
+        "fp32_apply": lambda: ctx.apply_jacobian_f32(0, dz32, y32),
         "residual": lambda: ctx.apply_residual(z, r),
         "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
         "adjoint": lambda: ctx.apply_adjoint(z, v, gz, gp),
-        "linearize": lambda: ctx.linearize(z),
-        "fp32_apply": lambda: ctx.apply_jacobian_f32(0, dz32, y32),
-        "vcycle": lambda: ctx.pmg_vcycle(b32, x32),
     }
     for _ in range(args.warmup):
         for f in ops.values():

@@ -65,6 +65,26 @@ __device__ inline BrickGeom decode_brick(const MeshDev& m, int colour, int b) {
   return g;
 }
 
+// XCD-aware workgroup order. Workgroups are dispatched to the 8 XCDs round-robin by id,
+// and each XCD has its own L2. Within one colour only bricks of the same x-row share
+// cache lines of the nodal vectors (a 128-byte line spans 16 nodes, a brick 7), so the
+// bricks of one x-row are given ids 8 apart: they run on one XCD, back to back, and
+// re-read the shared lines from its L2. xcd_grid is the padded grid size;
+// xcd_brick maps an id to the brick index of decode_brick, or -1 for padding.
+__host__ __device__ inline int xcd_grid(int nbx, int nby, int nbz, int colour) {
+  const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
+  const int CX = (nbx - cx + 1) / 2, CY = (nby - cy + 1) / 2, CZ = (nbz - cz + 1) / 2;
+  const int rows = CY * CZ;
+  return CX == 0 || rows == 0 ? 0 : ((rows + 7) / 8) * 8 * CX;
+}
+__device__ inline int xcd_brick(const MeshDev& m, int colour, int id) {
+  const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
+  const int CX = (m.nbx - cx + 1) / 2, CY = (m.nby - cy + 1) / 2, CZ = (m.nbz - cz + 1) / 2;
+  const int t = id >> 3;
+  const int row = (t / CX) * 8 + (id & 7);
+  return row < CY * CZ ? (t % CX) + CX * row : -1;
+}
+
 __host__ __device__ inline int bricks_in_colour(int nbx, int nby, int nbz, int colour) {
   const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
   return ((nbx - cx + 1) / 2) * ((nby - cy + 1) / 2) * ((nbz - cz + 1) / 2);

@@ -193,7 +193,9 @@ template <int MODE>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
-  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
   const Basis4 bs = load_basis4<4>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       if ((int)threadIdx.x < nv) {
         double t = red[threadIdx.x];
         for (int w = 1; w < NT / 64; ++w) t += red[w * nv + threadIdx.x];
-        a.gpart[(int64_t)(a.brick_base + blockIdx.x) * nv + threadIdx.x] = t;
+        a.gpart[(int64_t)(a.brick_base + brick) * nv + threadIdx.x] = t;
       }
     } else {
       for (int ph = 0; ph < a.nph; ++ph) {
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
             if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
             __syncthreads();
           }
-          if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + blockIdx.x) * a.nph + ph) * 3 + k] = red[0];
+          if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + brick) * a.nph + ph) * 3 + k] = red[0];
           __syncthreads();
         }
       }
@@ -383,7 +385,9 @@ namespace pfmf {
 template <int PC>
 __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTables* __restrict__ tabs) {
   __shared__ float ev[8 * 4 * 64];
-  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
   const Basis4 bf = load_basis4<4>(tabs);
   const Basis4 bc = load_basis4<PC>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -406,16 +410,9 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
     const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
     const int64_t gq = e * 64 + ql;
     LinRecord rc;
-    rc.c = a.rec.rec[0 * a.n_q + gq];
-    rc.kq = a.rec.rec[1 * a.n_q + gq];
-    rc.kphi = a.rec.rec[2 * a.n_q + gq];
-    rc.g = a.rec.rec[3 * a.n_q + gq];
-    rc.gp = a.rec.rec[4 * a.n_q + gq];
-    rc.dL = a.rec.rec[5 * a.n_q + gq];
-    rc.flags = a.rec.flags[gq];
-    float D[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) D[k] = a.rec.D32[k * a.n_q + gq];
+    for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
+    rc.flags = a.rec.flags[gq];
     const int pid = a.phase[gq];
     float G[9], W[9], wphi, gw[3];
     {
@@ -439,7 +436,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
     }
     const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
     QPState<float> s;
-    qp_state_lin<float>(mp, G, D, rc, s);
+    qp_state_lin<float>(mp, G, rc, s);
     float Fu[9], dL;
     qp_tangent<float>(mp, s, W, wphi, Fu, dL);
     const float kfg = a.fr.kf * mp.Gc;

@@ -18,9 +18,8 @@
 namespace pfmf {
 
 struct RecordSoA {
-  float* rec;      // [6][n_q]: c, kq, kphi, g, gp, dL
+  float* rec;      // [REC_N][n_q], slots as in LinRecord
   uint8_t* flags;  // [n_q]
-  float* D32;      // [6][n_q]
 };
 
 struct LevelDev {
@@ -49,7 +48,7 @@ struct MGState {
   int n_levels = 0;
   MGLevel lv[5];
   float* z32 = nullptr;  // FP32 mirror of u on the fine level [3][n_nodes]
-  RecordSoA rec{nullptr, nullptr, nullptr};
+  RecordSoA rec{nullptr, nullptr};
   float* tmpA = nullptr;
   float* tmpB = nullptr;
   double* red = nullptr;  // reduction scratch
@@ -73,7 +72,6 @@ inline void mg_free(MGState& mg) {
   (void)hipFree(mg.z32);
   (void)hipFree(mg.rec.rec);
   (void)hipFree(mg.rec.flags);
-  (void)hipFree(mg.rec.D32);
   (void)hipFree(mg.tmpA);
   (void)hipFree(mg.tmpB);
   (void)hipFree(mg.red);
@@ -107,7 +105,9 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
   double* zb = lds;
   double* tmp = zb + 4 * NB3;
   double* tab = tmp + S::TMP;
-  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
   for (int t = threadIdx.x; t < Q * P; t += NT) {
     tab[t] = tabs->B[P][Q][t / P][t % P];
     tab[Q * P + t] = tabs->D[P][Q][t / P][t % P];
@@ -157,16 +157,10 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
       qp_state<double>(mp, a.fr, G, phi, 0.0, st, s);
       any_bad |= s.bad;
       LinRecord rc;
-      record_from_state<double>(s, rc);
-      a.rec.rec[0 * a.n_q + gq] = rc.c;
-      a.rec.rec[1 * a.n_q + gq] = rc.kq;
-      a.rec.rec[2 * a.n_q + gq] = rc.kphi;
-      a.rec.rec[3 * a.n_q + gq] = rc.g;
-      a.rec.rec[4 * a.n_q + gq] = rc.gp;
-      a.rec.rec[5 * a.n_q + gq] = rc.dL;
-      a.rec.flags[gq] = rc.flags;
+      record_from_state(s, rc);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) a.rec.D32[k * a.n_q + gq] = (float)st[k];
+      for (int k = 0; k < REC_N; ++k) a.rec.rec[k * a.n_q + gq] = rc.v[k];
+      a.rec.flags[gq] = rc.flags;
     }
   }
   if (any_bad) a.flag[0] = 1;
@@ -219,7 +213,9 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
   float* ev = wb + 4 * NBC3;        // [8][4][PC3]
   float* tmp = ev + S::EV;
   float* tab = tmp + S::TMP;        // Bf, Df (Q x PF), Bc, Dc (Q x PC), w (Q)
-  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
   for (int t = threadIdx.x; t < Q * PF; t += NT) {
     tab[t] = tabs->B[PF][Q][t / PF][t % PF];
     tab[Q * PF + t] = tabs->D[PF][Q][t / PF][t % PF];
@@ -296,19 +292,12 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
       const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
       const int64_t gq = e * Q3 + ql;
       LinRecord rc;
-      rc.c = a.rec.rec[0 * a.n_q + gq];
-      rc.kq = a.rec.rec[1 * a.n_q + gq];
-      rc.kphi = a.rec.rec[2 * a.n_q + gq];
-      rc.g = a.rec.rec[3 * a.n_q + gq];
-      rc.gp = a.rec.rec[4 * a.n_q + gq];
-      rc.dL = a.rec.rec[5 * a.n_q + gq];
-      rc.flags = a.rec.flags[gq];
-      float D[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) D[k] = a.rec.D32[k * a.n_q + gq];
+      for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
+      rc.flags = a.rec.flags[gq];
       const int pid = a.phase[gq];
       mp = a.mats[pid < a.nph ? pid : 0];
-      qp_state_lin<float>(mp, G, D, rc, s);
+      qp_state_lin<float>(mp, G, rc, s);
       wdet = wq[qx] * wq[qy] * wq[qz] * jdet;
       if (MODE == 0) {
         float dL;

@@ -91,9 +91,8 @@ pf_status mg_alloc(pf_ctx* c) {
   }
   const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
   if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
-      hipMalloc(&mg.rec.rec, 6 * c->n_q * sizeof(float)) != hipSuccess ||
+      hipMalloc(&mg.rec.rec, REC_N * c->n_q * sizeof(float)) != hipSuccess ||
       hipMalloc(&mg.rec.flags, c->n_q) != hipSuccess ||
-      hipMalloc(&mg.rec.D32, 6 * c->n_q * sizeof(float)) != hipSuccess ||
       hipMalloc(&mg.tmpA, nfine) != hipSuccess || hipMalloc(&mg.tmpB, nfine) != hipSuccess ||
       hipMalloc(&mg.red, VEC_BLOCKS * sizeof(double)) != hipSuccess)
     return fail(PF_ENOMEM, "multigrid allocation failed");
@@ -129,7 +128,7 @@ pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
-    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
     HIPCHK(hipGetLastError());
@@ -152,7 +151,7 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
 template <int PC>
 pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
-    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     hipLaunchKernelGGL((k_a32_q3<PC>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
@@ -191,7 +190,7 @@ pf_status launch_linearize(pf_ctx* c, const LinArgs& a, hipStream_t s) {
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
-    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     hipLaunchKernelGGL((k_linearize<P, P>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());

@@ -53,7 +53,9 @@ __global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __
   double* tab = tmp + S::TMP;             // B[Q*P], D[Q*P], w[Q]
   double* red = tab + S::TAB;
 
-  const BrickGeom g = decode_brick(a.m, colour, blockIdx.x);
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
   for (int t = threadIdx.x; t < Q * P; t += NT) {
     tab[t] = tabs->B[P][Q][t / P][t % P];
     tab[Q * P + t] = tabs->D[P][Q][t / P][t % P];
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __
             __syncthreads();
           }
           if (t == 0) {
-            double* gp = a.gpart + ((int64_t)(a.brick_base + blockIdx.x) * a.nph + ph) * 3 + k;
+            double* gp = a.gpart + ((int64_t)(a.brick_base + brick) * a.nph + ph) * 3 + k;
             *gp = (r == 0 ? 0.0 : *gp) + red[0];
           }
           __syncthreads();

@@ -252,6 +252,7 @@ template <typename T> struct QPState {
   T Fi[9];      // F^-1
   T b[6];       // b_tr = I + A
   T N[9];       // eigenvectors of b_tr (columns)
+  T bd[3];      // principal values b_i of b_tr
   T hinv[3];    // 1 / (2 b_i)
   T e[3];       // deviatoric principal trial log strain
   T theta;      // tr eps
@@ -323,7 +324,8 @@ __device__ inline void qp_kin(const T* G, const T* st, QPState<T>& s, T* beta, T
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     eps[i] = half_log1p(beta[i]);
-    s.hinv[i] = T(0.5) * frcp(T(1) + beta[i]);
+    s.bd[i] = T(1) + beta[i];
+    s.hinv[i] = T(0.5) * frcp(s.bd[i]);
     s.theta += eps[i];
   }
   const T th3 = s.theta * (T(1) / T(3));
@@ -411,40 +413,115 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
 }
 
 // Linearisation record of one point, taken in FP64 once per linearisation and
-// stored in FP32: the return-mapping factor and its tangent coefficients, the
-// degradation and the local phase-field coefficient, and the switch decisions.
+// stored in FP32 (19 values + a flag byte): the return-mapping factor and its
+// tangent coefficients, the degradation and the local phase-field coefficient,
+// the principal frame of b_tr as a unit quaternion, the principal values b_i,
+// the principal log strains and the off-diagonal tangent factors. The FP32
+// applies recompute only F^-1 from the FP32 displacement mirror.
+constexpr int REC_N = 19;
+enum RecSlot { R_C = 0, R_KQ, R_KPHI, R_G, R_GP, R_DL, R_Q0, R_B0 = R_Q0 + 4, R_E0 = R_B0 + 3, R_O0 = R_E0 + 3 };
 struct LinRecord {
-  float c, kq, kphi, g, gp, dL;  // dL = dL/dphi at fixed history
-  uint8_t flags;                  // bit0 tension, bit1 history active, bit2 plastic
+  float v[REC_N];
+  uint8_t flags;  // bit0 tension, bit1 history active, bit2 plastic
 };
 
+// Unit quaternion (w, x, y, z) of a rotation matrix R (row-major), by the
+// largest-diagonal-element case split of Shepperd's method (no cancellation).
+__device__ inline void rot_to_quat(const double* R, double* q) {
+  const double tr = R[0] + R[4] + R[8];
+  if (tr > 0.0) {
+    const double s = 2.0 * sqrt(tr + 1.0);
+    q[0] = 0.25 * s; q[1] = (R[7] - R[5]) / s; q[2] = (R[2] - R[6]) / s; q[3] = (R[3] - R[1]) / s;
+  } else if (R[0] > R[4] && R[0] > R[8]) {
+    const double s = 2.0 * sqrt(1.0 + R[0] - R[4] - R[8]);
+    q[0] = (R[7] - R[5]) / s; q[1] = 0.25 * s; q[2] = (R[1] + R[3]) / s; q[3] = (R[2] + R[6]) / s;
+  } else if (R[4] > R[8]) {
+    const double s = 2.0 * sqrt(1.0 + R[4] - R[0] - R[8]);
+    q[0] = (R[2] - R[6]) / s; q[1] = (R[1] + R[3]) / s; q[2] = 0.25 * s; q[3] = (R[5] + R[7]) / s;
+  } else {
+    const double s = 2.0 * sqrt(1.0 + R[8] - R[0] - R[4]);
+    q[0] = (R[3] - R[1]) / s; q[1] = (R[2] + R[6]) / s; q[2] = (R[5] + R[7]) / s; q[3] = 0.25 * s;
+  }
+  const double n = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; ++k) q[k] *= n;
+}
+
 template <typename T>
-__device__ inline void record_from_state(const QPState<T>& s, LinRecord& r) {
-  r.c = (float)s.c;
-  r.kq = (float)s.kq;
-  r.kphi = (float)s.kphi;
-  r.g = (float)s.g;
-  r.gp = (float)s.gp;
-  r.dL = (float)s.dLcoef;
+__device__ inline void quat_to_rot(const T* q, T* R) {
+  const T w = q[0], x = q[1], y = q[2], z = q[3];
+  const T xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z, wx = w * x, wy = w * y, wz = w * z;
+  R[0] = T(1) - T(2) * (yy + zz); R[1] = T(2) * (xy - wz);          R[2] = T(2) * (xz + wy);
+  R[3] = T(2) * (xy + wz);          R[4] = T(1) - T(2) * (xx + zz); R[5] = T(2) * (yz - wx);
+  R[6] = T(2) * (xz - wy);          R[7] = T(2) * (yz + wx);          R[8] = T(1) - T(2) * (xx + yy);
+}
+
+__device__ inline void record_from_state(const QPState<double>& s, LinRecord& r) {
+  r.v[R_C] = (float)s.c;
+  r.v[R_KQ] = (float)s.kq;
+  r.v[R_KPHI] = (float)s.kphi;
+  r.v[R_G] = (float)s.g;
+  r.v[R_GP] = (float)s.gp;
+  r.v[R_DL] = (float)s.dLcoef;
+  // a proper rotation: flipping an eigenvector's sign leaves the tangent unchanged
+  double R[9];
+  for (int k = 0; k < 9; ++k) R[k] = s.N[k];
+  const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                     R[2] * (R[3] * R[7] - R[4] * R[6]);
+  if (det < 0.0) R[0] = -R[0], R[3] = -R[3], R[6] = -R[6];
+  double q[4];
+  rot_to_quat(R, q);
+  for (int k = 0; k < 4; ++k) r.v[R_Q0 + k] = (float)q[k];
+  const double th3 = s.theta * (1.0 / 3.0);
+  for (int i = 0; i < 3; ++i) {
+    r.v[R_B0 + i] = (float)s.bd[i];
+    r.v[R_E0 + i] = (float)(s.e[i] + th3);
+    r.v[R_O0 + i] = (float)s.coef[i];
+  }
   r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0);
 }
 
-// State for the linearised FP32 apply: kinematics recomputed from the FP32
-// mirrors, every decision and coefficient taken from the record.
+// State for the linearised FP32 apply: F^-1 from the FP32 displacement mirror,
+// everything else (frame, principal values, decisions, coefficients) from the record.
 template <typename T>
-__device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const T* D, const LinRecord& r,
-                                    QPState<T>& s) {
-  T beta[3], eps[3];
-  qp_kin<T>(G, D, s, beta, eps);
-  s.c = (T)r.c;
-  s.kq = (T)r.kq;
-  s.kphi = (T)r.kphi;
-  s.g = (T)r.g;
-  s.gp = (T)r.gp;
-  s.dLcoef = (T)r.dL;
+__device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const LinRecord& r, QPState<T>& s) {
+  T F[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? T(1) : T(0));
+  const T c00 = F[4] * F[8] - F[5] * F[7];
+  const T c01 = F[5] * F[6] - F[3] * F[8];
+  const T c02 = F[3] * F[7] - F[4] * F[6];
+  const T idet = frcp(F[0] * c00 + F[1] * c01 + F[2] * c02);
+  s.Fi[0] = c00 * idet;
+  s.Fi[3] = c01 * idet;
+  s.Fi[6] = c02 * idet;
+  s.Fi[1] = (F[2] * F[7] - F[1] * F[8]) * idet;
+  s.Fi[4] = (F[0] * F[8] - F[2] * F[6]) * idet;
+  s.Fi[7] = (F[1] * F[6] - F[0] * F[7]) * idet;
+  s.Fi[2] = (F[1] * F[5] - F[2] * F[4]) * idet;
+  s.Fi[5] = (F[2] * F[3] - F[0] * F[5]) * idet;
+  s.Fi[8] = (F[0] * F[4] - F[1] * F[3]) * idet;
+  T q[4] = {(T)r.v[R_Q0], (T)r.v[R_Q0 + 1], (T)r.v[R_Q0 + 2], (T)r.v[R_Q0 + 3]};
+  quat_to_rot<T>(q, s.N);
+  s.c = (T)r.v[R_C];
+  s.kq = (T)r.v[R_KQ];
+  s.kphi = (T)r.v[R_KPHI];
+  s.g = (T)r.v[R_G];
+  s.gp = (T)r.v[R_GP];
+  s.dLcoef = (T)r.v[R_DL];
   s.tension = r.flags & 1;
   s.hactive = (r.flags >> 1) & 1;
   s.plastic = (r.flags >> 2) & 1;
+  s.theta = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.bd[i] = (T)r.v[R_B0 + i];
+    s.hinv[i] = T(0.5) * frcp(s.bd[i]);
+    s.theta += (T)r.v[R_E0 + i];
+    s.coef[i] = (T)r.v[R_O0 + i];
+  }
+  const T th3 = s.theta * (T(1) / T(3));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) s.e[i] = (T)r.v[R_E0 + i] - th3;
   const T kt = m.kappa * s.theta;
   const T tmu = T(2) * m.mu * s.c;
 #pragma unroll
@@ -452,7 +529,6 @@ __device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const T* 
     s.taub[i] = tmu * s.e[i] + kt;
     s.taud[i] = s.tension ? s.g * s.taub[i] : s.g * (tmu * s.e[i]) + kt;
   }
-  qp_frame_stress<T>(m, beta, eps, s);
 }
 
 // First Piola stress P = tau_degr F^-T (eq:mechanical-gradient-transformation).
@@ -468,10 +544,16 @@ __device__ inline void piola(const QPState<T>& s, T* P) {
 }
 
 // Directional derivative (Appendices B-C): (dG, dphi) -> (dP, dL).
+// Evaluated in the principal frame of b_tr: with dl = dG F^-1 and Lt = N^T dl N,
+// the rotated perturbation N^T (dl b + b dl^T) N is Lt diag(b) + diag(b) Lt^T, and
+// dP = N (dtau_rot - diag(tau_d) Lt^T) N^T F^-T, where dtau_rot carries the principal
+// increments on the diagonal and the divided-difference terms off it, and the second
+// term is the geometric part -tau_degr dl^T expressed in the frame.
 // The phase-field gradient term is linear and handled by the caller.
 template <typename T>
 __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
                                   T* dP, T& dL) {
+  const T* N = s.N;
   // dl = dG F^-1
   T dl[9];
 #pragma unroll
@@ -479,37 +561,24 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       dl[3 * i + j] = dG[3 * i] * s.Fi[j] + dG[3 * i + 1] * s.Fi[3 + j] + dG[3 * i + 2] * s.Fi[6 + j];
-  // db_tr = dl b + b dl^T  (symmetric)
-  const T* b = s.b;
-  const T bm[9] = {b[0], b[5], b[4], b[5], b[1], b[3], b[4], b[3], b[2]};
-  T M[9];
+  // Lt = N^T (dl N)
+  T dN[9], Lt[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      M[3 * i + j] = dl[3 * i] * bm[j] + dl[3 * i + 1] * bm[3 + j] + dl[3 * i + 2] * bm[6 + j];
-  const T dA[9] = {2 * M[0],    M[1] + M[3], M[2] + M[6], M[1] + M[3], 2 * M[4],
-                   M[5] + M[7], M[2] + M[6], M[5] + M[7], 2 * M[8]};
-  // rotate into the eigenframe: W = dA N, dbt = N^T W
-  const T* N = s.N;
-  T W[9];
+      dN[3 * i + j] = dl[3 * i] * N[j] + dl[3 * i + 1] * N[3 + j] + dl[3 * i + 2] * N[6 + j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      W[3 * i + j] = dA[3 * i] * N[j] + dA[3 * i + 1] * N[3 + j] + dA[3 * i + 2] * N[6 + j];
-  T dbd[3], dbo[3];  // diagonal, and off-diagonal pairs (1,2),(0,2),(0,1)
-#pragma unroll
-  for (int i = 0; i < 3; ++i) dbd[i] = N[i] * W[i] + N[3 + i] * W[3 + i] + N[6 + i] * W[6 + i];
-  dbo[0] = N[1] * W[2] + N[4] * W[5] + N[7] * W[8];
-  dbo[1] = N[0] * W[2] + N[3] * W[5] + N[6] * W[8];
-  dbo[2] = N[0] * W[1] + N[3] * W[4] + N[6] * W[7];
-  // principal strain increments
+    for (int j = 0; j < 3; ++j) Lt[3 * i + j] = N[i] * dN[j] + N[3 + i] * dN[3 + j] + N[6 + i] * dN[6 + j];
+  const T* bd = s.bd;
+  // principal strain increments from the diagonal (eq:hencky-stress-linearization)
   T deps[3];
   T dth = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    deps[i] = dbd[i] * s.hinv[i];
+    deps[i] = T(2) * Lt[4 * i] * bd[i] * s.hinv[i];
     dth += deps[i];
   }
   const T dth3 = dth * (T(1) / T(3));
@@ -531,26 +600,27 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
     else
       X[i] = s.g * (tm2 * dce[i]) + kdt + s.gp * dphi * (s.taub[i] - m.kappa * s.theta);
   }
-  const T o12 = dbo[0] * s.coef[0], o02 = dbo[1] * s.coef[1], o01 = dbo[2] * s.coef[2];
-  // dtau = N Xfull N^T, Xfull = [[X0,o01,o02],[o01,X1,o12],[o02,o12,X2]]
-  T Y[9];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const T n0 = N[3 * i], n1 = N[3 * i + 1], n2 = N[3 * i + 2];
-    Y[3 * i + 0] = n0 * X[0] + n1 * o01 + n2 * o02;
-    Y[3 * i + 1] = n0 * o01 + n1 * X[1] + n2 * o12;
-    Y[3 * i + 2] = n0 * o02 + n1 * o12 + n2 * X[2];
-  }
-  // Mm = dtau - tau dl^T ; dP = Mm F^-T
-  const T* t = s.tau;
-  const T tm[9] = {t[0], t[5], t[4], t[5], t[1], t[3], t[4], t[3], t[2]};
-  T Mm[9];
+  // off-diagonal increments: rotated db_ij times the divided-difference factors
+  const T o12 = (Lt[5] * bd[2] + bd[1] * Lt[7]) * s.coef[0];
+  const T o02 = (Lt[2] * bd[2] + bd[0] * Lt[6]) * s.coef[1];
+  const T o01 = (Lt[1] * bd[1] + bd[0] * Lt[3]) * s.coef[2];
+  // Z = dtau_rot - diag(tau_d) Lt^T
+  const T* td = s.taud;
+  const T Z[9] = {X[0] - td[0] * Lt[0], o01 - td[0] * Lt[3], o02 - td[0] * Lt[6],
+                  o01 - td[1] * Lt[1], X[1] - td[1] * Lt[4], o12 - td[1] * Lt[7],
+                  o02 - td[2] * Lt[2], o12 - td[2] * Lt[5], X[2] - td[2] * Lt[8]};
+  // Mm = N Z N^T ; dP = Mm F^-T
+  T NZ[9], Mm[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      Mm[3 * i + j] = (Y[3 * i] * N[3 * j] + Y[3 * i + 1] * N[3 * j + 1] + Y[3 * i + 2] * N[3 * j + 2]) -
-                      (tm[3 * i] * dl[3 * j] + tm[3 * i + 1] * dl[3 * j + 1] + tm[3 * i + 2] * dl[3 * j + 2]);
+      NZ[3 * i + j] = N[3 * i] * Z[j] + N[3 * i + 1] * Z[3 + j] + N[3 * i + 2] * Z[6 + j];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Mm[3 * i + j] = NZ[3 * i] * N[3 * j] + NZ[3 * i + 1] * N[3 * j + 1] + NZ[3 * i + 2] * N[3 * j + 2];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll

@@ -177,7 +177,7 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
-    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
+    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     a.brick_base = c->colour_base[col];
     hipLaunchKernelGGL((k_op64<MODE, P, Q>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tab);
@@ -189,10 +189,10 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
 template <int MODE>
 pf_status launch_op64_q3(pf_ctx* c, OpArgs a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
-    const int nb = bricks_in_colour(c->nbx, c->nby, c->nbz, col);
-    if (nb == 0) continue;
+    const int ng = xcd_grid(c->nbx, c->nby, c->nbz, col);
+    if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
-    hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
