@@ -253,6 +253,13 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       sf4_fwd_n<1>(&pn, bs, 0x1u, 0x0u, v, d);
       phin = v[0];
     }
+    // pointwise function
+    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<double> s;
+    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+    any_bad |= s.bad;
+    // direction (or cotangent) at the points, interpolated after the state so that its
+    // 13 values are not live across the state computation
     double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
     if (MODE != M_RES) {
       double v[4], d[4][3];
@@ -265,11 +272,6 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
 #pragma unroll
       for (int J = 0; J < 3; ++J) gw[J] = d[3][J] * ih[J];
     }
-    // pointwise function
-    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
-    QPState<double> s;
-    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
-    any_bad |= s.bad;
     const double kfg = a.fr.kf * mp.Gc;
     double Fu[9], f0, f1[3];
     if (MODE == M_RES) {
