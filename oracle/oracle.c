@@ -170,11 +170,11 @@ static void voigt_to_mat(const double v[6], double M[3][3]) {
 /* Cyclic Jacobi in long double, run to convergence. Eigenvalues ascending,
  * eigenvectors as the columns of V. Any backward-stable symmetric solver
  * serves (the paper only asks for the spectral decomposition). */
-static void eig_sym3(const double A[3][3], double lam[3], double V[3][3]) {
+static void eig_sym3_ld(const long double A[3][3], long double lam[3], long double V[3][3]) {
   long double a[3][3], v[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
-      a[i][j] = 0.5L * ((long double)A[i][j] + (long double)A[j][i]);
+      a[i][j] = 0.5L * (A[i][j] + A[j][i]);
       v[i][j] = (i == j) ? 1.0L : 0.0L;
     }
   for (int sweep = 0; sweep < 60; sweep++) {
@@ -220,8 +220,19 @@ static void eig_sym3(const double A[3][3], double lam[3], double V[3][3]) {
     for (int j = i + 1; j < 3; j++)
       if (a[idx[j]][idx[j]] < a[idx[i]][idx[i]]) { int t = idx[i]; idx[i] = idx[j]; idx[j] = t; }
   for (int i = 0; i < 3; i++) {
-    lam[i] = (double)a[idx[i]][idx[i]];
-    for (int r = 0; r < 3; r++) V[r][i] = (double)v[r][idx[i]];
+    lam[i] = a[idx[i]][idx[i]];
+    for (int r = 0; r < 3; r++) V[r][i] = v[r][idx[i]];
+  }
+}
+
+static void eig_sym3(const double A[3][3], double lam[3], double V[3][3]) {
+  long double Al[3][3], l[3], Vl[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) Al[i][j] = A[i][j];
+  eig_sym3_ld(Al, l, Vl);
+  for (int i = 0; i < 3; i++) {
+    lam[i] = (double)l[i];
+    for (int r = 0; r < 3; r++) V[r][i] = (double)Vl[r][i];
   }
 }
 
@@ -542,6 +553,78 @@ void or_qf_param_partials(const or_phase* ph, const or_frac* fr, const double G[
 }
 
 /* ------------------------------------------------------------------------ */
+/* State commit after a converged step (Section 2, exponential-map update).  */
+/* ------------------------------------------------------------------------ */
+
+/* New per-point state from the converged (u, phi): the elastic log strain is the
+ * trial one with its deviator scaled by the return factor c and the volumetric part
+ * kept (eq:inelasticity-deviatoric-strain-update-2), b^e = exp(2 eps^e) in the
+ * principal frame of b_tr, Cin^-1_{n+1} = F^-1 b^e F^-T
+ * (eq:inelasticity-deviatoric-strain-update-3), stored as D = Cin^-1 - I; the
+ * accumulated plastic strain grows by dgamma (eq:plasticity-accumulated-plastic-update)
+ * and the history field becomes max(H_n, psi^+). The decisions and c, dgamma, psi^+
+ * come from the same pointwise evaluation as the residual; the frame, the
+ * exponential and the products are taken in long double. */
+void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], double phi,
+                  const double st[8], double st_new[8]) {
+  mat_t m = make_mat(ph, fr);
+  qp_state s;
+  qp_eval(&m, fr, G, phi, phi, st, &s);
+  long double F[3][3], A[3][3], D[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) F[i][j] = (i == j ? 1.0L : 0.0L) + (long double)G[i * 3 + j];
+  D[0][0] = st[0]; D[1][1] = st[1]; D[2][2] = st[2];
+  D[1][2] = D[2][1] = st[3];
+  D[0][2] = D[2][0] = st[4];
+  D[0][1] = D[1][0] = st[5];
+  /* b_tr - I = F (I + D) F^T - I */
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      long double sum = 0.0L;
+      for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) sum += F[i][k] * ((k == l ? 1.0L : 0.0L) + D[k][l]) * F[j][l];
+      A[i][j] = sum - (i == j ? 1.0L : 0.0L);
+    }
+  long double beta[3], N[3][3], eps[3], th = 0.0L;
+  eig_sym3_ld(A, beta, N);
+  for (int i = 0; i < 3; i++) {
+    eps[i] = 0.5L * log1pl(beta[i]);
+    th += eps[i];
+  }
+  long double be[3][3] = {{0}}, bev[3];
+  for (int i = 0; i < 3; i++) bev[i] = expl(2.0L * ((long double)s.c * (eps[i] - th / 3.0L) + th / 3.0L));
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      for (int k = 0; k < 3; k++) be[i][j] += bev[k] * N[i][k] * N[j][k];
+  /* F^-1 by cofactors */
+  long double det = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                    F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                    F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  long double Fi[3][3];
+  Fi[0][0] = (F[1][1] * F[2][2] - F[1][2] * F[2][1]) / det;
+  Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) / det;
+  Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) / det;
+  Fi[1][0] = (F[1][2] * F[2][0] - F[1][0] * F[2][2]) / det;
+  Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) / det;
+  Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) / det;
+  Fi[2][0] = (F[1][0] * F[2][1] - F[1][1] * F[2][0]) / det;
+  Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) / det;
+  Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) / det;
+  long double C[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      long double sum = 0.0L;
+      for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++) sum += Fi[i][k] * be[k][l] * Fi[j][l];
+      C[i][j] = sum - (i == j ? 1.0L : 0.0L);
+    }
+  st_new[0] = (double)C[0][0]; st_new[1] = (double)C[1][1]; st_new[2] = (double)C[2][2];
+  st_new[3] = (double)C[1][2]; st_new[4] = (double)C[0][2]; st_new[5] = (double)C[0][1];
+  st_new[6] = st[6] + s.dgamma;
+  st_new[7] = s.H;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Element operators with dense element matrices (Section 4).                */
 /* ------------------------------------------------------------------------ */
 
@@ -822,4 +905,40 @@ int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_
   }
   free(unit); free(col); free(idx); free(ze); free(we); free_tab(&t);
   return bad;
+}
+
+/* Commit over all points of the mesh: state_new[8][n_q] from z (see or_qf_commit). */
+int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
+                    const double* state, const double* z, double* state_new) {
+  elem_tab t;
+  if (make_tab(m, &t)) return -1;
+  int nP = t.nP, nQ = t.nQ;
+  int64_t n_nodes = (int64_t)t.nx1 * t.ny1 * (m->p * m->nz + 1);
+  int64_t n_el = (int64_t)m->nx * m->ny * m->nz;
+  int64_t n_q = n_el * nQ;
+  int err = 0;
+#pragma omp parallel
+  {
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * nP);
+    double* ze = (double*)malloc(sizeof(double) * 4 * nP);
+#pragma omp for schedule(static)
+    for (int64_t e = 0; e < n_el; e++) {
+      elem_nodes(m, &t, e, idx);
+      for (int f = 0; f < 4; f++)
+        for (int a = 0; a < nP; a++) ze[f * nP + a] = z[f * n_nodes + idx[a]];
+      for (int qq = 0; qq < nQ; qq++) {
+        int64_t gq = e * nQ + qq;
+        int pid = phase[gq];
+        if (pid >= nph) { err = 1; continue; }
+        double G[9], phi, gphi[3], st[8], sn[8];
+        interp_qp(&t, qq, ze, G, &phi, gphi);
+        for (int k = 0; k < 8; k++) st[k] = state[k * n_q + gq];
+        or_qf_commit(&ph[pid], fr, G, phi, st, sn);
+        for (int k = 0; k < 8; k++) state_new[k * n_q + gq] = sn[k];
+      }
+    }
+    free(idx); free(ze);
+  }
+  free_tab(&t);
+  return err ? -1 : 0;
 }

@@ -94,6 +94,13 @@ int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_
                         const uint8_t* phase, const double* state, const double* phi_n,
                         const double* z, int64_t e, double* Ke);
 
+/* State commit after a converged step: new per-point state (D, ebar_p, H) from the
+ * converged fields (exponential-map update of Section 2, history maximum of Section 3). */
+void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], double phi,
+                  const double st[8], double st_new[8]);
+int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
+                    const uint8_t* phase, const double* state, const double* z, double* state_new);
+
 /* Number of OpenMP threads the applies use (1 when built without OpenMP). */
 int or_num_threads(void);
 

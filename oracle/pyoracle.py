@@ -72,6 +72,10 @@ def lib():
         L.or_jacobian.argtypes = common + [_D, _D, C.c_void_p, C.c_int64]
         L.or_adjoint.argtypes = common + [_D, _D, _D, C.c_void_p, C.c_int64]
         L.or_element_jacobian.argtypes = common + [C.c_int64, _D]
+        L.or_qf_commit.argtypes = [C.POINTER(OrPhase), C.POINTER(OrFrac), _D, C.c_double, _D, _D]
+        L.or_commit_state.argtypes = [C.POINTER(OrMesh), C.POINTER(OrPhase), C.c_int, C.POINTER(OrFrac),
+                                      C.c_void_p, _D, _D, _D]
+        L.or_commit_state.restype = C.c_int
         for f in ("or_residual", "or_jacobian", "or_adjoint", "or_element_jacobian"):
             getattr(L, f).restype = C.c_int
         L.or_num_threads.restype = C.c_int
@@ -143,6 +147,14 @@ def qf_param_partials(ph, fr, G, phi, gphi, phi_n, st):
     return dP.reshape(3, 3, 3), df0, df1.reshape(3, 3)
 
 
+def qf_commit(ph, fr, G, phi, st):
+    """New per-point state (D[6], ebar_p, H) after a converged step."""
+    G = _f64(np.reshape(G, 9)); st = _f64(st)
+    out = np.zeros(8)
+    lib().or_qf_commit(C.byref(phase_struct(ph)), C.byref(frac_struct(fr)), _p(G), float(phi), _p(st), _p(out))
+    return out
+
+
 class Oracle:
     """Oracle bound to one set of inputs (as produced by ``inputs.make_inputs``)."""
 
@@ -201,6 +213,16 @@ class Oracle:
         if rc < 0 or (check and rc):
             raise RuntimeError(f"oracle adjoint failed: {rc}")
         return g, gp.reshape(self._nph, 3)
+
+    def commit_state(self, z):
+        """State [8][n_q] after a converged step at z (exponential-map update)."""
+        z = _f64(z)
+        out = np.zeros_like(self.state)
+        rc = lib().or_commit_state(C.byref(self._m), self._ph, self._nph, C.byref(self._fr),
+                                   self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(z), _p(out))
+        if rc < 0:
+            raise RuntimeError("oracle commit failed")
+        return out
 
     def element_jacobian(self, z, e):
         z = _f64(z)
