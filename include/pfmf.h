@@ -65,7 +65,8 @@ typedef enum {
   PF_EHIP = -2,          /* a HIP runtime call failed */
   PF_ENOMEM = -3,        /* device allocation failed */
   PF_EUNSUPPORTED = -4,  /* order / configuration not built */
-  PF_ENONPHYSICAL = -5   /* a quadrature point left the physical domain */
+  PF_ENONPHYSICAL = -5,  /* a quadrature point left the physical domain */
+  PF_ENOCONV = -6        /* an iterative solve missed its tolerance (the result is still written) */
 } pf_status;
 
 /* Structured box of order-p hexahedra (p = 1..4). */
@@ -84,8 +85,8 @@ typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; } pf_phase;
  * 1 or 2 (eq:AT1-AT2). */
 typedef struct { double l0, eta, zeta, dt, s_phi; int at; } pf_fracture;
 
-/* p-multigrid V-cycle options. Levels p, p-1, ... down to coarse_p (>= 1), all
- * evaluated at the fine quadrature. cheb_degree smoothing steps of Chebyshev with
+/* p-multigrid V-cycle options. Levels as set by pf_set_pmg_levels (default p, p-1,
+ * ..., 1), all evaluated at the fine quadrature; coarse_p must equal the last order. cheb_degree smoothing steps of Chebyshev with
  * point-Jacobi before and after the coarse correction; coarse_sweeps Chebyshev
  * applications on the coarsest level. Zero fields take defaults (3, 1, 4). */
 typedef struct { int cheb_degree; int coarse_p; int coarse_sweeps; int reserved; } pf_pmg_opts;
@@ -121,10 +122,62 @@ pf_status pf_apply_adjoint(pf_ctx* ctx, const double* z, const double* v, double
                            double* gparams, void* stream);
 
 /* Linearise at z for the FP32 multigrid: the return-mapping, split and history
- * decisions and their scalars are taken in FP64 and stored per point as an FP32
- * record together with FP32 mirrors of z and D; builds every level's point-Jacobi
- * diagonal and Chebyshev bounds. Synchronises the stream (eigenvalue estimates). */
+ * decisions, their scalars, the principal frame of b_tr (a unit quaternion), its
+ * principal values, the log strains and the off-diagonal tangent factors are taken in
+ * FP64 and stored per point as an FP32 record (Appendices A-C evaluated once), with
+ * an FP32 mirror of u; builds every level's point-Jacobi diagonal and Chebyshev
+ * bounds (power iteration on the device). Synchronises the stream once. */
 pf_status pf_linearize(pf_ctx* ctx, const double* z, void* stream);
+
+/* Multigrid level orders, fine first: orders[0] = p > orders[1] > ... >= 1,
+ * 2 <= n_levels <= 5 (n_levels = 0 restores the default p, p-1, ..., 1). Every level
+ * is evaluated at the fine quadrature. Frees the hierarchy: call pf_linearize again. */
+pf_status pf_set_pmg_levels(pf_ctx* ctx, const int* orders, int n_levels);
+
+/* Dirichlet faces for the multigrid and the Newton step: bit f of face_fields[k]
+ * constrains field f (u_x, u_y, u_z, phi) on face k (x = 0, x = lx, y = 0, y = ly,
+ * z = 0, z = lz) (the essential conditions of the weak form, Section 3). With faces set,
+ * the FP32 level operators return M A x (M zeroes constrained entries), the V-cycle
+ * works on the masked right-hand side, and its output vanishes on constrained
+ * entries. The FP64 applies are unaffected. Call pf_linearize again afterwards. */
+pf_status pf_set_dirichlet(pf_ctx* ctx, const uint32_t face_fields[6]);
+
+/* State commit after a converged step (Section 2, exponential-map update): from the
+ * converged z and the context's state, state_out[8][n_q] (device double, same layout)
+ * gets D_{n+1} = F^-1 b^e F^-T - I with b^e = exp(2 eps^e), eps^e the trial log strain
+ * with its deviator scaled by the return factor, ebar_p + dgamma and max(H_n, psi^+).
+ * state_out must not alias the context's state or z. To advance a step, copy it into
+ * the state buffer given to pf_setup_mesh (and phi into phi_n) once the stream is done. */
+pf_status pf_commit_state(pf_ctx* ctx, const double* z, double* state_out, void* stream);
+
+/* Newton step options: relative tolerance of the linear solve (default 1e-8),
+ * FGMRES restart length (30, at most 60), iteration limit (300), and the V-cycle
+ * smoother (Chebyshev degree 3, 4 coarsest sweeps). Zero fields take defaults. */
+typedef struct {
+  double rtol;
+  int restart, max_iters, cheb_degree, coarse_sweeps;
+  int reserved[3];
+} pf_newton_opts;
+
+/* Newton step report: FGMRES iterations, convergence flag, ||b|| with b = -M R(z),
+ * the FGMRES residual estimate, the true residual ||b - M J dz||, and host wall times
+ * (linearisation, whole step) in milliseconds. */
+typedef struct {
+  int iterations, converged;
+  double res0, res_lin, res_true;
+  double t_linearize_ms, t_total_ms;
+} pf_newton_stats;
+
+/* One Newton update z += dz of the coupled problem with the Dirichlet faces of
+ * pf_set_dirichlet: M J(z) dz = -M R(z) (M zeroes constrained entries, which z must
+ * already hold at their prescribed values), solved by restarted flexible GMRES with
+ * the FP64 Jacobian apply and one FP32 p-multigrid V-cycle per iteration as right
+ * preconditioner (re-linearised at z; the paper's solver is GMRES with p-multigrid,
+ * Section 5). Allocates its Krylov workspace ((2 restart + 4) vectors of 4 n_nodes
+ * doubles) on first use and keeps it. Synchronises the stream. Returns PF_ENOCONV when
+ * the tolerance is missed (z is still updated). */
+pf_status pf_newton_step(pf_ctx* ctx, double* z, const pf_newton_opts* opts, pf_newton_stats* stats,
+                         void* stream);
 
 /* Number of multigrid levels available after pf_linearize (level 0 = fine), and the
  * order and node count of one level. */

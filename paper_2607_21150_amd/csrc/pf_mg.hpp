@@ -82,6 +82,7 @@ inline void mg_free(MGState& mg) {
 // Linearisation: FP64 decisions -> FP32 record (one launch over all bricks).
 // ---------------------------------------------------------------------------
 
+// MODE 0: linearisation record; MODE 1: state commit into state_out.
 struct LinArgs {
   MeshDev m;
   int nx1, ny1;
@@ -94,10 +95,11 @@ struct LinArgs {
   int nph;
   FracParams<double> fr;
   RecordSoA rec;
+  double* state_out;
   int* flag;
 };
 
-template <int P, int Q>
+template <int P, int Q, int MODE>
 __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTables* __restrict__ tabs) {
   using S = OpShape<P, Q>;
   constexpr int NB3 = S::NB3, Q3 = S::Q3, ER = S::ER;
@@ -156,11 +158,18 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
       QPState<double> s;
       qp_state<double>(mp, a.fr, G, phi, 0.0, st, s);
       any_bad |= s.bad;
-      LinRecord rc;
-      record_from_state(s, rc);
+      if (MODE == 0) {
+        LinRecord rc;
+        record_from_state(s, rc);
 #pragma unroll
-      for (int k = 0; k < REC_N; ++k) a.rec.rec[k * a.n_q + gq] = rc.v[k];
-      a.rec.flags[gq] = rc.flags;
+        for (int k = 0; k < REC_N; ++k) a.rec.rec[k * a.n_q + gq] = rc.v[k];
+        a.rec.flags[gq] = rc.flags;
+      } else {
+        double ns[8];
+        commit_from_state(s, G, st, ns);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a.state_out[k * a.n_q + gq] = ns[k];
+      }
     }
   }
   if (any_bad) a.flag[0] = 1;

@@ -62,12 +62,18 @@ pf_status mg_alloc(pf_ctx* c) {
   MGState& mg = c->mg;
   if (mg.n_levels > 0) return PF_OK;
   const int p = c->mesh.p;
-  const int coarse = 1;
-  mg.n_levels = p - coarse + 1;
+  int orders[5];
+  if (c->n_orders > 0) {
+    mg.n_levels = c->n_orders;
+    for (int l = 0; l < c->n_orders; ++l) orders[l] = c->orders[l];
+  } else {
+    mg.n_levels = p;
+    for (int l = 0; l < p; ++l) orders[l] = p - l;
+  }
   const int N[3] = {c->mesh.nx, c->mesh.ny, c->mesh.nz};
   for (int l = 0; l < mg.n_levels; ++l) {
     MGLevel& L = mg.lv[l];
-    L.p = p - l;
+    L.p = orders[l];
     L.P = L.p + 1;
     L.nx1 = L.p * N[0] + 1;
     L.ny1 = L.p * N[1] + 1;
@@ -81,7 +87,7 @@ pf_status mg_alloc(pf_ctx* c) {
       for (int k = 0; k < 3; ++k) {
         std::vector<int> pb, rb;
         std::vector<float> pw, rw;
-        transfer_rows_1d(L.p, L.p - 1, N[k], pb, pw, rb, rw);
+        transfer_rows_1d(L.p, orders[l + 1], N[k], pb, pw, rb, rw);
         pf_status st;
         if ((st = upload(&L.pbase[k], pb)) || (st = upload(&L.pw[k], pw)) || (st = upload(&L.rbase[k], rb)) ||
             (st = upload(&L.rw[k], rw)))
@@ -94,8 +100,24 @@ pf_status mg_alloc(pf_ctx* c) {
       hipMalloc(&mg.rec.rec, REC_N * c->n_q * sizeof(float)) != hipSuccess ||
       hipMalloc(&mg.rec.flags, c->n_q) != hipSuccess ||
       hipMalloc(&mg.tmpA, nfine) != hipSuccess || hipMalloc(&mg.tmpB, nfine) != hipSuccess ||
-      hipMalloc(&mg.red, VEC_BLOCKS * sizeof(double)) != hipSuccess)
+      hipMalloc(&mg.red, (VEC_BLOCKS + 16) * sizeof(double)) != hipSuccess)
     return fail(PF_ENOMEM, "multigrid allocation failed");
+  return PF_OK;
+}
+
+// Zero the constrained entries of a level vector (no-op without Dirichlet faces).
+pf_status mask_level(pf_ctx* c, int level, float* v, hipStream_t s) {
+  if (!c->has_dir) return PF_OK;
+  const MGLevel& L = c->mg.lv[level];
+  hipLaunchKernelGGL(k_mask<float>, dim3(vec_grid(L.n_nodes)), dim3(NT), 0, s, v, L.nx1, L.ny1, L.nz1, c->dir);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status mask_fine64(pf_ctx* c, double* v, hipStream_t s) {
+  if (!c->has_dir) return PF_OK;
+  hipLaunchKernelGGL(k_mask<double>, dim3(vec_grid(c->n_nodes)), dim3(NT), 0, s, v, c->nx1, c->ny1, c->nz1, c->dir);
+  HIPCHK(hipGetLastError());
   return PF_OK;
 }
 
@@ -160,7 +182,7 @@ pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
 }
 
 template <int MODE>
-pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
+pf_status level_op_raw(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
   const A32Args a = a32_args(c, level, dz, out);
   const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
   if (MODE == 0 && PF == 4) {
@@ -180,19 +202,29 @@ pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_
   }
 }
 
-template <int P>
+// Level operator; with Dirichlet faces the applied output is masked (M A x), so that
+// vectors that vanish on constrained entries stay in that subspace.
+template <int MODE>
+pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
+  pf_status st = level_op_raw<MODE>(c, level, dz, out, s);
+  if (st || MODE != 0) return st;
+  return mask_level(c, level, out, s);
+}
+
+template <int P, int MODE>
 pf_status launch_linearize(pf_ctx* c, const LinArgs& a, hipStream_t s) {
   using S = OpShape<P, P>;
   const size_t lds = (4 * S::NB3 + S::TMP + S::TAB) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_linearize<P, P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIPCHK(hipFuncSetAttribute((const void*)k_linearize<P, P, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_linearize<P, P>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_linearize<P, P, MODE>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -228,7 +260,7 @@ pf_status prolong(pf_ctx* c, int l, const float* xc, float* xf, hipStream_t s) {
   hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, B, xf, F.nx1, F.ny1, F.nz1, F.nx1, F.ny1,
                      C.nz1, 2, F.pbase[2], F.pw[2], C.P);
   HIPCHK(hipGetLastError());
-  return PF_OK;
+  return mask_level(c, l, xf, s);
 }
 
 // rc = P^T rf (level l -> coarse level l+1).
@@ -249,7 +281,7 @@ pf_status restrict_(pf_ctx* c, int l, const float* rf, float* rc, hipStream_t s)
   hipLaunchKernelGGL(k_transfer_1d, dim3(vec_grid(n)), dim3(NT), 0, s, B, rc, C.nx1, C.ny1, C.nz1, C.nx1, C.ny1,
                      F.nz1, 2, F.rbase[2], F.rw[2], nw);
   HIPCHK(hipGetLastError());
-  return PF_OK;
+  return mask_level(c, l + 1, rc, s);
 }
 
 // Chebyshev(k) with point Jacobi on level l for A x = b, bounds [0.1, 1.1] * lmax.
@@ -340,44 +372,118 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.nph = (int)c->phases.size();
   a.fr = frac_params<double>(c->fr);
   a.rec = mg.rec;
+  a.state_out = nullptr;
   a.flag = c->d_flag;
   switch (c->mesh.p) {
-    case 1: st = launch_linearize<2>(c, a, s); break;
-    case 2: st = launch_linearize<3>(c, a, s); break;
-    case 3: st = launch_linearize<4>(c, a, s); break;
-    case 4: st = launch_linearize<5>(c, a, s); break;
+    case 1: st = launch_linearize<2, 0>(c, a, s); break;
+    case 2: st = launch_linearize<3, 0>(c, a, s); break;
+    case 3: st = launch_linearize<4, 0>(c, a, s); break;
+    case 4: st = launch_linearize<5, 0>(c, a, s); break;
     default: st = fail(PF_EUNSUPPORTED, "order not built");
   }
   if (st) return st;
   mg.linearized = true;
-  std::mt19937_64 rng(21150);
-  std::uniform_real_distribution<float> U(-1.f, 1.f);
+  // lambda_max(D^-1 A) per level by 15 power iterations, normalised on the device
+  // (no host round trip inside the loop); one synchronisation at the end
+  constexpr int POWER_ITS = 15;
+  double* nrm = mg.red + VEC_BLOCKS;             // [n_levels] final norms
+  float* inv = (float*)(mg.red + VEC_BLOCKS + 8);  // scale of the next normalisation
   for (int l = 0; l < mg.n_levels; ++l) {
     MGLevel& L = mg.lv[l];
     const int64_t n = 4 * L.n_nodes;
     const int g = vec_grid(n);
     if ((st = level_op<1>(c, l, nullptr, L.diag, s))) return st;
     hipLaunchKernelGGL(k_vec_inv, dim3(g), dim3(NT), 0, s, L.diag, L.dinv, n);
-    // lambda_max(D^-1 A) by power iteration
-    std::vector<float> h(n);
-    for (auto& v : h) v = U(rng);
-    HIPCHK(hipMemcpyAsync(L.d, h.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
-    double nrm2;
-    if ((st = sumsq(c, L.d, n, s, &nrm2))) return st;
-    hipLaunchKernelGGL(k_vec_axs, dim3(g), dim3(NT), 0, s, L.d, L.d, (float)(1.0 / std::sqrt(nrm2)), n);
-    double lam = 0.0;
-    for (int it = 0; it < 15; ++it) {
+    hipLaunchKernelGGL(k_hash_fill, dim3(g), dim3(NT), 0, s, L.d, n, (uint64_t)(21150 + l));
+    if ((st = mask_level(c, l, L.d, s))) return st;
+    hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(NT), 0, s, L.d, n, mg.red);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, mg.red, g, nrm + l, inv);
+    hipLaunchKernelGGL(k_vec_axs_dev, dim3(g), dim3(NT), 0, s, L.d, L.d, inv, n);
+    for (int it = 0; it < POWER_ITS; ++it) {
       if ((st = level_op<0>(c, l, L.d, L.t, s))) return st;
       hipLaunchKernelGGL(k_vec_scale, dim3(g), dim3(NT), 0, s, L.dinv, L.t, n);
-      if ((st = sumsq(c, L.t, n, s, &nrm2))) return st;
-      lam = std::sqrt(nrm2);
-      if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PF_ENONPHYSICAL, "eigenvalue estimate failed on level %d", l);
-      hipLaunchKernelGGL(k_vec_axs, dim3(g), dim3(NT), 0, s, L.t, L.d, (float)(1.0 / lam), n);
+      hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(NT), 0, s, L.t, n, mg.red);
+      hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, mg.red, g, nrm + l, inv);
+      hipLaunchKernelGGL(k_vec_axs_dev, dim3(g), dim3(NT), 0, s, L.t, L.d, inv, n);
     }
-    L.lmax = lam;
     HIPCHK(hipGetLastError());
   }
+  double lam[5];
+  HIPCHK(hipMemcpyAsync(lam, nrm, mg.n_levels * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  for (int l = 0; l < mg.n_levels; ++l) {
+    if (!(lam[l] > 0.0) || !std::isfinite(lam[l])) return fail(PF_ENONPHYSICAL, "eigenvalue estimate failed on level %d", l);
+    mg.lv[l].lmax = lam[l];
+  }
+  return PF_OK;
+}
+
+// New per-point state after a converged step (see commit_from_state).
+pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!z || !state_out) return fail(PF_EINVAL, "null argument");
+  const size_t ns = 8 * c->n_q * sizeof(double);
+  if (overlaps(state_out, ns, c->qp_state, ns)) return fail(PF_EINVAL, "state_out aliases the context's state");
+  if (overlaps(state_out, ns, z, 4 * c->n_nodes * sizeof(double))) return fail(PF_EINVAL, "state_out aliases z");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  LinArgs a;
+  a.m = mesh_dev(c);
+  a.nx1 = c->nx1;
+  a.ny1 = c->ny1;
+  a.n_nodes = c->n_nodes;
+  a.n_q = c->n_q;
+  a.z = z;
+  a.phin = c->phi_n;
+  a.state = c->qp_state;
+  a.phase = c->qp_phase;
+  a.mats = c->d_mats;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<double>(c->fr);
+  a.rec = RecordSoA{nullptr, nullptr};
+  a.state_out = state_out;
+  a.flag = c->d_flag;
+  switch (c->mesh.p) {
+    case 1: return launch_linearize<2, 1>(c, a, s);
+    case 2: return launch_linearize<3, 1>(c, a, s);
+    case 3: return launch_linearize<4, 1>(c, a, s);
+    case 4: return launch_linearize<5, 1>(c, a, s);
+    default: return fail(PF_EUNSUPPORTED, "order not built");
+  }
+}
+
+pf_status pf_set_pmg_levels(pf_ctx* c, const int* orders, int n_levels) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (n_levels < 0 || n_levels > 5) return fail(PF_EINVAL, "n_levels=%d outside 0..5", n_levels);
+  if (n_levels > 0 && !orders) return fail(PF_EINVAL, "null orders");
+  if (n_levels > 0) {
+    if (orders[0] != c->mesh.p) return fail(PF_EINVAL, "the first level must be the mesh order %d", c->mesh.p);
+    if (n_levels < 2) return fail(PF_EINVAL, "at least two levels");
+    for (int l = 1; l < n_levels; ++l)
+      if (!(orders[l] >= 1 && orders[l] < orders[l - 1])) return fail(PF_EINVAL, "orders must decrease to >= 1");
+  }
+  HIPCHK(hipDeviceSynchronize());
+  mg_free(c->mg);
+  c->n_orders = n_levels;
+  for (int l = 0; l < n_levels; ++l) c->orders[l] = orders[l];
+  return PF_OK;
+}
+
+pf_status pf_set_dirichlet(pf_ctx* c, const uint32_t* face_fields) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!face_fields) return fail(PF_EINVAL, "null face_fields");
+  bool any = false;
+  for (int k = 0; k < 6; ++k) {
+    if (face_fields[k] & ~0xFu) return fail(PF_EINVAL, "face %d: only bits 0..3 (fields) allowed", k);
+    c->dir.face[k] = face_fields[k];
+    any |= face_fields[k] != 0;
+  }
+  c->has_dir = any;
+  // the diagonals and eigenvalue bounds depend on the mask: linearise again
+  c->mg.linearized = false;
   return PF_OK;
 }
 
@@ -434,16 +540,27 @@ pf_status pf_pmg_vcycle(pf_ctx* c, const float* b, float* x, const pf_pmg_opts* 
   if (!b || !x) return fail(PF_EINVAL, "null vector");
   const size_t nb = 4 * c->n_nodes * sizeof(float);
   if (overlaps(b, nb, x, nb)) return fail(PF_EINVAL, "x aliases b");
-  pf_pmg_opts opt{3, 1, 4, 0};
+  pf_pmg_opts opt{3, c->mg.lv[c->mg.n_levels - 1].p, 4, 0};
   if (o) {
     if (o->cheb_degree > 0) opt.cheb_degree = o->cheb_degree;
     if (o->coarse_p > 0) opt.coarse_p = o->coarse_p;
     if (o->coarse_sweeps > 0) opt.coarse_sweeps = o->coarse_sweeps;
   }
   if (opt.cheb_degree > 32 || opt.coarse_sweeps > 64) return fail(PF_EINVAL, "smoother degree too large");
-  if (opt.coarse_p != 1) return fail(PF_EUNSUPPORTED, "only coarse_p = 1 is built");
+  if (opt.coarse_p != c->mg.lv[c->mg.n_levels - 1].p)
+    return fail(PF_EINVAL, "coarse_p=%d differs from the coarsest level order %d", opt.coarse_p,
+                c->mg.lv[c->mg.n_levels - 1].p);
   c->last_stream = (hipStream_t)stream;
-  return vcycle(c, 0, b, x, opt, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if (c->has_dir) {
+    // work on the masked right-hand side (the V-cycle acts on the unconstrained subspace)
+    MGLevel& L = c->mg.lv[0];
+    const int64_t n = 4 * L.n_nodes;
+    hipLaunchKernelGGL(k_vec_copy, dim3(vec_grid(n)), dim3(NT), 0, s, b, L.b, n);
+    if ((st = mask_level(c, 0, L.b, s))) return st;
+    return vcycle(c, 0, L.b, x, opt, s);
+  }
+  return vcycle(c, 0, b, x, opt, s);
 }
 
 }  // extern "C"

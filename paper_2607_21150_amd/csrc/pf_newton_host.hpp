@@ -1,0 +1,235 @@
+// Host side of the Newton step (included at the end of pfmf.hip): one Newton update
+// of the coupled residual with flexible GMRES (right preconditioning, restarted),
+// the FP64 Jacobian apply as the Krylov operator and one FP32 p-multigrid V-cycle
+// at the FP64 linearisation as the preconditioner. Every vector operation runs in
+// the kernels of pf_step.hpp; the host holds only the small Hessenberg system.
+#pragma once
+#include <chrono>
+
+namespace {
+
+// Deterministic dot products <V_j, w>, j = 0..k-1, summed on the host in block order.
+pf_status mdot(pf_ctx* c, const double* V, int64_t ld, int k, const double* w, int64_t n, hipStream_t s,
+               double* out) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_mdot, dim3(g, k), dim3(NT), 0, s, V, ld, k, w, n, c->kpart);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h((size_t)g * k);
+  HIPCHK(hipMemcpyAsync(h.data(), c->kpart, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    double acc = 0.0;
+    for (int b = 0; b < g; ++b) acc += h[(size_t)j * g + b];
+    out[j] = acc;
+  }
+  return PF_OK;
+}
+
+// w += sum_j coef[j] V_j (coef copied from the host, k <= 64)
+pf_status maxpy(pf_ctx* c, const double* V, int64_t ld, int k, const double* coef, double* w, int64_t n,
+                hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c->kcoef, coef, k * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));  // coef is host stack memory
+  hipLaunchKernelGGL(k_maxpy, dim3(vec_grid(n)), dim3(NT), 0, s, V, ld, k, c->kcoef, w, n);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status newton_alloc(pf_ctx* c, int m) {
+  if (c->kry && c->kry_m >= m) return PF_OK;
+  (void)hipFree(c->kry);
+  (void)hipFree(c->kpart);
+  (void)hipFree(c->kcoef);
+  (void)hipFree(c->k32);
+  c->kry = nullptr;
+  c->kpart = nullptr;
+  c->kcoef = nullptr;
+  c->k32 = nullptr;
+  c->kry_m = 0;
+  const int64_t n = 4 * c->n_nodes;
+  // V[m+1], Z[m], r, dz, w-spare
+  if (hipMalloc(&c->kry, (size_t)(2 * m + 4) * n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->kpart, (size_t)(m + 2) * VEC_BLOCKS * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->kcoef, 64 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->k32, (size_t)2 * n * sizeof(float)) != hipSuccess)
+    return fail(PF_ENOMEM, "Newton workspace allocation failed (restart %d)", m);
+  c->kry_m = m;
+  return PF_OK;
+}
+
+// x = M^-1 v: FP64 -> FP32, one V-cycle, FP32 -> FP64, masked.
+pf_status precondition(pf_ctx* c, const double* v, double* x, const pf_pmg_opts& o, hipStream_t s) {
+  const int64_t n = 4 * c->n_nodes;
+  const int g = vec_grid(n);
+  float* b32 = c->k32;
+  float* x32 = c->k32 + n;
+  hipLaunchKernelGGL(k_d2f, dim3(g), dim3(NT), 0, s, v, b32, n);
+  pf_status st;
+  if ((st = mask_level(c, 0, b32, s))) return st;
+  if ((st = vcycle(c, 0, b32, x32, o, s))) return st;
+  hipLaunchKernelGGL(k_f2d, dim3(g), dim3(NT), 0, s, x32, x, n);
+  HIPCHK(hipGetLastError());
+  return mask_fine64(c, x, s);
+}
+
+// y = M J x on the unconstrained subspace (x vanishes on constrained entries)
+pf_status masked_jacobian(pf_ctx* c, const double* z, const double* x, double* y, hipStream_t s) {
+  OpArgs a = op_args(c);
+  a.z = z;
+  a.w = x;
+  a.out = y;
+  pf_status st = dispatch_op64<M_JAC>(c, a, s);
+  if (st) return st;
+  return mask_fine64(c, y, s);
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newton_stats* out, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!z) return fail(PF_EINVAL, "null z");
+  pf_newton_opts opt{1e-8, 30, 300, 3, 4, {0, 0, 0}};
+  if (o) {
+    if (o->rtol > 0) opt.rtol = o->rtol;
+    if (o->restart > 0) opt.restart = o->restart;
+    if (o->max_iters > 0) opt.max_iters = o->max_iters;
+    if (o->cheb_degree > 0) opt.cheb_degree = o->cheb_degree;
+    if (o->coarse_sweeps > 0) opt.coarse_sweeps = o->coarse_sweeps;
+  }
+  if (opt.restart > 60) return fail(PF_EINVAL, "restart %d above 60", opt.restart);
+  if (opt.cheb_degree > 32 || opt.coarse_sweeps > 64) return fail(PF_EINVAL, "smoother degree too large");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const double t0 = now_ms();
+  const int m = opt.restart;
+  if ((st = newton_alloc(c, m))) return st;
+  const int64_t n = 4 * c->n_nodes;
+  const int g = vec_grid(n);
+  double* V = c->kry;                          // V_j = V + j n, j = 0..m
+  double* Z = c->kry + (int64_t)(m + 1) * n;   // Z_j = Z + j n, j = 0..m-1
+  double* rhs = Z + (int64_t)m * n;            // b = -M R(z)
+  double* dz = rhs + n;                        // accumulated update
+  double* w = dz + n;                          // residual of the linear system at restarts
+  // right-hand side
+  {
+    OpArgs a = op_args(c);
+    a.z = z;
+    a.out = rhs;
+    if ((st = dispatch_op64<M_RES>(c, a, s))) return st;
+    if ((st = mask_fine64(c, rhs, s))) return st;
+    hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, -1.0, rhs, rhs, n, 0);
+    hipLaunchKernelGGL(k_dzero, dim3(g), dim3(NT), 0, s, dz, n);
+    HIPCHK(hipGetLastError());
+  }
+  double bnorm;
+  if ((st = mdot(c, rhs, n, 1, rhs, n, s, &bnorm))) return st;
+  bnorm = std::sqrt(bnorm);
+  // preconditioner at z
+  const double t1 = now_ms();
+  if ((st = pf_linearize(c, z, stream))) return st;
+  const double t2 = now_ms();
+  const pf_pmg_opts po{opt.cheb_degree, c->mg.lv[c->mg.n_levels - 1].p, opt.coarse_sweeps, 0};
+  int its = 0;
+  bool conv = bnorm == 0.0;
+  double res = bnorm;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
+  while (!conv && its < opt.max_iters) {
+    // r = b - J dz (dz = 0 on the first cycle)
+    double beta;
+    if (its == 0) {
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, rhs, w, n, 0);
+    } else {
+      if ((st = masked_jacobian(c, z, dz, w, s))) return st;
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, -1.0, w, w, n, 0);
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, rhs, w, n, 1);
+    }
+    if ((st = mdot(c, w, n, 1, w, n, s, &beta))) return st;
+    beta = std::sqrt(beta);
+    res = beta;
+    if (beta <= opt.rtol * bnorm) { conv = true; break; }
+    hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0 / beta, w, V, n, 0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int k = 0;
+    for (; k < m && its < opt.max_iters; ++k, ++its) {
+      double* Vk = V + (int64_t)k * n;
+      double* Zk = Z + (int64_t)k * n;
+      double* Vn = V + (int64_t)(k + 1) * n;
+      if ((st = precondition(c, Vk, Zk, po, s))) return st;
+      if ((st = masked_jacobian(c, z, Zk, Vn, s))) return st;
+      // classical Gram-Schmidt, twice
+      if ((st = mdot(c, V, n, k + 1, Vn, n, s, h.data()))) return st;
+      for (int j = 0; j <= k; ++j) y[j] = -h[j];
+      if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+      if ((st = mdot(c, V, n, k + 1, Vn, n, s, h2.data()))) return st;
+      for (int j = 0; j <= k; ++j) {
+        y[j] = -h2[j];
+        h[j] += h2[j];
+      }
+      if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+      double hn;
+      if ((st = mdot(c, Vn, n, 1, Vn, n, s, &hn))) return st;
+      hn = std::sqrt(hn);
+      h[k + 1] = hn;
+      if (hn > 0.0) hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0 / hn, Vn, Vn, n, 0);
+      // Givens rotations on the new column
+      for (int j = 0; j < k; ++j) {
+        const double t = cs[j] * h[j] + sn[j] * h[j + 1];
+        h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+        h[j] = t;
+      }
+      const double r = std::hypot(h[k], h[k + 1]);
+      cs[k] = r > 0.0 ? h[k] / r : 1.0;
+      sn[k] = r > 0.0 ? h[k + 1] / r : 0.0;
+      h[k] = r;
+      h[k + 1] = 0.0;
+      gv[k + 1] = -sn[k] * gv[k];
+      gv[k] = cs[k] * gv[k];
+      for (int j = 0; j <= k; ++j) H[(size_t)j * m + k] = h[j];
+      res = std::fabs(gv[k + 1]);
+      if (res <= opt.rtol * bnorm || hn == 0.0) {
+        ++k;
+        ++its;
+        conv = true;
+        break;
+      }
+    }
+    // y = R^-1 g, dz += Z y
+    for (int i = k - 1; i >= 0; --i) {
+      double acc = gv[i];
+      for (int j = i + 1; j < k; ++j) acc -= H[(size_t)i * m + j] * y[j];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    if ((st = maxpy(c, Z, n, k, y.data(), dz, n, s))) return st;
+  }
+  // true linear residual ||b - M J dz|| / ||b||, then z += dz
+  if ((st = masked_jacobian(c, z, dz, w, s))) return st;
+  hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, -1.0, w, w, n, 0);
+  hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, rhs, w, n, 1);
+  double rt;
+  if ((st = mdot(c, w, n, 1, w, n, s, &rt))) return st;
+  hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, dz, z, n, 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  const double t3 = now_ms();
+  if (out) {
+    out->iterations = its;
+    out->converged = conv ? 1 : 0;
+    out->res0 = bnorm;
+    out->res_lin = res;
+    out->res_true = std::sqrt(rt);
+    out->t_linearize_ms = t2 - t1;
+    out->t_total_ms = t3 - t0;
+  }
+  return conv ? PF_OK : fail(PF_ENOCONV, "FGMRES did not reach rtol %.1e in %d iterations (%.3e)", opt.rtol,
+                             its, bnorm > 0 ? res / bnorm : 0.0);
+}
+
+}  // extern "C"

@@ -266,6 +266,7 @@ template <typename T> struct QPState {
   T psi, H, L;  // psi^+, max(H_n, psi^+), local phase-field residual
   T dLcoef;     // dL / dphi at fixed history
   T ddg_s0, ddg_visc;  // d dgamma / d sigma0, d dgamma / d visc (0 when elastic)
+  T dg;         // plastic multiplier increment (0 when elastic)
   bool tension, hactive, plastic, bad;
 };
 
@@ -375,11 +376,13 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   s.kphi = T(0);
   s.ddg_s0 = T(0);
   s.ddg_visc = T(0);
+  s.dg = T(0);
   if (s.plastic) {
     const T B = T(3) * s.g * m.mu + m.H + m.a * sn;
     const T disc = B * B + T(4) * m.a * m.H * f;
     const T dg = T(2) * f * frcp(B + disc * frsqrt(disc));
     const T iq = frcp(q);
+    s.dg = dg;
     s.c = T(1) - T(3) * m.mu * dg * iq;
     const T sy = sn + m.H * dg;
     const T den = T(3) * s.g * m.mu + m.H * (T(1) + m.a * dg) + m.a * sy;
@@ -478,6 +481,42 @@ __device__ inline void record_from_state(const QPState<double>& s, LinRecord& r)
     r.v[R_O0 + i] = (float)s.coef[i];
   }
   r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0);
+}
+
+// New per-point state after a converged step (Section 2): the elastic log strain
+// keeps the trial volumetric part and the return-scaled deviator
+// (eq:inelasticity-deviatoric-strain-update-2), b^e = exp(2 eps^e) in the frame of
+// b_tr and Cin^-1_{n+1} = F^-1 b^e F^-T (eq:inelasticity-deviatoric-strain-update-3);
+// the accumulated plastic strain grows by dgamma
+// (eq:plasticity-accumulated-plastic-update) and H = max(H_n, psi^+).
+// D = Cin^-1 - I is formed without cancellation as
+// F^-1 [sum_i expm1(2 eps^e_i) n_i n_i^T - (G + G^T + G G^T)] F^-T,
+// using b^e - F F^T = (b^e - I) - (G + G^T + G G^T).
+__device__ inline void commit_from_state(const QPState<double>& s, const double* G, const double* st,
+                                         double* out) {
+  const double th3 = s.theta * (1.0 / 3.0);
+  double ex[3];
+  for (int i = 0; i < 3; ++i) ex[i] = expm1(2.0 * (s.c * s.e[i] + th3));
+  double M[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = ex[0] * s.N[3 * i] * s.N[3 * j] + ex[1] * s.N[3 * i + 1] * s.N[3 * j + 1] +
+                 ex[2] * s.N[3 * i + 2] * s.N[3 * j + 2];
+      v -= G[3 * i + j] + G[3 * j + i] + G[3 * i] * G[3 * j] + G[3 * i + 1] * G[3 * j + 1] + G[3 * i + 2] * G[3 * j + 2];
+      M[3 * i + j] = v;
+    }
+  // W = F^-1 M F^-T
+  double T1[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      T1[3 * i + j] = s.Fi[3 * i] * M[j] + s.Fi[3 * i + 1] * M[3 + j] + s.Fi[3 * i + 2] * M[6 + j];
+  const int ri[6] = {0, 1, 2, 1, 0, 0}, ci[6] = {0, 1, 2, 2, 2, 1};
+  for (int k = 0; k < 6; ++k) {
+    const int i = ri[k], j = ci[k];
+    out[k] = T1[3 * i] * s.Fi[3 * j] + T1[3 * i + 1] * s.Fi[3 * j + 1] + T1[3 * i + 2] * s.Fi[3 * j + 2];
+  }
+  out[6] = st[6] + s.dg;
+  out[7] = s.H;
 }
 
 // State for the linearised FP32 apply: F^-1 from the FP32 displacement mirror,

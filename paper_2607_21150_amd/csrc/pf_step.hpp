@@ -1,0 +1,133 @@
+// Kernels around the operator for a Newton step: Dirichlet face masks, FP64
+// Krylov vector operations with deterministic reductions, precision conversions,
+// and the device-side pieces of the power iteration (start vector, norms).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pf_brick.hpp"
+
+namespace pfmf {
+
+// Fields constrained on each face of the box: bit f of face[k] set means field f
+// (u_x, u_y, u_z, phi) is prescribed on face k = x0, x1, y0, y1, z0, z1.
+struct DirMask {
+  uint32_t face[6];
+};
+
+__device__ inline uint32_t dir_fields(int64_t i, int nx1, int ny1, int nz1, const DirMask& d) {
+  const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
+  uint32_t f = 0;
+  if (ix == 0) f |= d.face[0];
+  if (ix == nx1 - 1) f |= d.face[1];
+  if (iy == 0) f |= d.face[2];
+  if (iy == ny1 - 1) f |= d.face[3];
+  if (iz == 0) f |= d.face[4];
+  if (iz == nz1 - 1) f |= d.face[5];
+  return f;
+}
+
+// v[f][i] = 0 for every constrained (node, field) of a [4][n] vector on a lattice.
+template <typename T>
+__global__ void k_mask(T* __restrict__ v, int nx1, int ny1, int nz1, DirMask d) {
+  const int64_t n = (int64_t)nx1 * ny1 * nz1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t f = dir_fields(i, nx1, ny1, nz1, d);
+    if (f == 0) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((f >> k) & 1u) v[k * n + i] = T(0);
+  }
+}
+
+// Start vector of the power iteration: uniform values in [-1, 1) from a
+// counter-based mix (SplitMix64 finaliser) of (seed, index).
+__global__ void k_hash_fill(float* __restrict__ x, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  }
+}
+
+// Sum of the first n partials in index order (one block): out[0] = sqrt(sum),
+// inv[0] = 1 / sqrt(sum) (0 when the sum vanishes).
+__global__ void k_norm_finish(const double* __restrict__ part, int n, double* __restrict__ out,
+                              float* __restrict__ inv) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  const double r = sqrt(s);
+  out[0] = r;
+  inv[0] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+}
+
+// b = s[0] * a (scale held in device memory)
+__global__ void k_vec_axs_dev(const float* __restrict__ a, float* __restrict__ b, const float* __restrict__ s,
+                              int64_t n) {
+  const float f = s[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = f * a[i];
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Krylov vectors. Reductions are per-block partials in a fixed order,
+// summed on the host in index order, so every result is bitwise reproducible.
+// ---------------------------------------------------------------------------
+
+// part[j * gridDim.x + b] = block b's share of <V_j, w>, j = 0..k-1, V_j = V + j * ld.
+__global__ void k_mdot(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ w, int64_t n,
+                       double* __restrict__ part) {
+  __shared__ double red[NT];
+  const int j = blockIdx.y;
+  if (j >= k) return;
+  const double* v = V + (int64_t)j * ld;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += v[i] * w[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+
+// w += sum_j c[j] V_j  (c in device memory, k <= 64)
+__global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c,
+                        double* __restrict__ w, int64_t n) {
+  __shared__ double cs[64];
+  if ((int)threadIdx.x < k) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc += cs[j] * V[(int64_t)j * ld + i];
+    w[i] = acc;
+  }
+}
+
+// y = a x (+ y when accumulate); x may be y
+__global__ void k_daxpy(double a, const double* x, double* y, int64_t n, int accumulate) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + (accumulate ? y[i] : 0.0);
+}
+
+__global__ void k_dzero(double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = 0.0;
+}
+
+__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+__global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+}  // namespace pfmf

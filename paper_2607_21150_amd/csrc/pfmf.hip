@@ -13,6 +13,7 @@
 #include "pf_ops.hpp"
 #include "pf_mg.hpp"
 #include "pf_mfma.hpp"
+#include "pf_step.hpp"
 #include "pf_tables.hpp"
 
 using namespace pfmf;
@@ -61,6 +62,19 @@ struct pf_ctx {
   int* d_flag = nullptr;
   hipStream_t last_stream = nullptr;
   MGState mg;
+  // multigrid level orders (fine first); n_orders = 0 means p, p-1, ..., 1
+  int orders[5] = {0, 0, 0, 0, 0};
+  int n_orders = 0;
+  // Dirichlet faces (multigrid and Newton step)
+  DirMask dir{{0, 0, 0, 0, 0, 0}};
+  bool has_dir = false;
+  // Newton step workspace: Krylov basis V[m+1], preconditioned vectors Z[m], residual,
+  // update; reduction partials; coefficients; FP32 right-hand side and correction
+  double* kry = nullptr;
+  int kry_m = 0;
+  double* kpart = nullptr;
+  double* kcoef = nullptr;
+  float* k32 = nullptr;
 };
 
 namespace {
@@ -398,6 +412,10 @@ void pf_destroy(pf_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   mg_free(c->mg);
+  (void)hipFree(c->kry);
+  (void)hipFree(c->kpart);
+  (void)hipFree(c->kcoef);
+  (void)hipFree(c->k32);
   (void)hipFree(c->d_tab);
   (void)hipFree(c->d_tabf);
   (void)hipFree(c->d_mats);
@@ -410,3 +428,4 @@ void pf_destroy(pf_ctx* c) {
 }  // extern "C"
 
 #include "pf_mg_host.hpp"
+#include "pf_newton_host.hpp"

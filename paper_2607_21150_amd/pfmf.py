@@ -16,13 +16,18 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfmf.so")
 
-PF_OK, PF_EINVAL, PF_EHIP, PF_ENOMEM, PF_EUNSUPPORTED, PF_ENONPHYSICAL = 0, -1, -2, -3, -4, -5
+PF_OK, PF_EINVAL, PF_EHIP, PF_ENOMEM, PF_EUNSUPPORTED, PF_ENONPHYSICAL, PF_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = [
     "pf_setup_mesh", "pf_sizes", "pf_set_params", "pf_apply_residual", "pf_apply_jacobian",
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
+    "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step",
 ]
+
+# face indices of pf_set_dirichlet and field bits
+FACES = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
+FIELD_BITS = {"ux": 1, "uy": 2, "uz": 4, "phi": 8}
 
 
 class PfError(RuntimeError):
@@ -49,6 +54,19 @@ class FractureDesc(C.Structure):
 class PmgOpts(C.Structure):
     _fields_ = [("cheb_degree", C.c_int), ("coarse_p", C.c_int), ("coarse_sweeps", C.c_int),
                 ("reserved", C.c_int)]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("cheb_degree", C.c_int),
+                ("coarse_sweeps", C.c_int), ("reserved", C.c_int * 3)]
+
+
+class NewtonStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("res0", C.c_double), ("res_lin", C.c_double),
+                ("res_true", C.c_double), ("t_linearize_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -78,6 +96,10 @@ def load():
     L.pf_restrict.argtypes = [vp, C.c_int, vp, vp, vp]
     L.pf_level_diagonal.argtypes = [vp, C.c_int, vp, vp]
     L.pf_pmg_vcycle.argtypes = [vp, vp, vp, C.POINTER(PmgOpts), vp]
+    L.pf_set_pmg_levels.argtypes = [vp, vp, C.c_int]
+    L.pf_set_dirichlet.argtypes = [vp, vp]
+    L.pf_commit_state.argtypes = [vp, vp, vp, vp]
+    L.pf_newton_step.argtypes = [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -229,6 +251,37 @@ class Context:
         o = PmgOpts(cheb_degree, coarse_p, coarse_sweeps, 0)
         _check(load().pf_pmg_vcycle(self._h, _ptr(b), _ptr(x), C.byref(o), _stream(stream)))
         return x
+
+    def set_pmg_levels(self, orders):
+        """Multigrid level orders, fine first (e.g. [4, 2, 1]); [] restores the default."""
+        a = (C.c_int * max(len(orders), 1))(*orders)
+        _check(load().pf_set_pmg_levels(self._h, C.cast(a, C.c_void_p), len(orders)))
+
+    def set_dirichlet(self, faces):
+        """faces: dict face name ('x0', 'x1', ...) -> iterable of field names ('ux', 'uy', 'uz', 'phi')."""
+        arr = (C.c_uint32 * 6)()
+        for face, fields in faces.items():
+            arr[FACES[face]] = sum(FIELD_BITS[f] for f in fields)
+        _check(load().pf_set_dirichlet(self._h, C.cast(arr, C.c_void_p)))
+
+    def commit_state(self, z, out=None, stream=None):
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        if out is None:
+            out = torch.empty((8, self.n_q), dtype=torch.float64, device=z.device)
+        _req(out, torch.float64, (8, self.n_q), "state_out")
+        _check(load().pf_commit_state(self._h, _ptr(z), _ptr(out), _stream(stream)))
+        return out
+
+    def newton_step(self, z, rtol=1e-8, restart=30, max_iters=300, cheb_degree=3, coarse_sweeps=4,
+                    stream=None, raise_on_noconv=True):
+        """One Newton update of z in place; returns the solver report as a dict."""
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        o = NewtonOpts(rtol, restart, max_iters, cheb_degree, coarse_sweeps)
+        st = NewtonStats()
+        code = load().pf_newton_step(self._h, _ptr(z), C.byref(o), C.byref(st), _stream(stream))
+        if code != PF_OK and not (code == PF_ENOCONV and not raise_on_noconv):
+            _check(code)
+        return st.as_dict()
 
     def check(self):
         _check(load().pf_check(self._h))
