@@ -123,6 +123,60 @@ def cpu_baseline(d, seconds=10.0):
                       f"took {t:.2f} s; scaled to the full apply"}
 
 
+def newton_leg(torch, I, pfmf, config):
+    """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
+    z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
+    (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1), FP64 Jacobian as the operator."""
+    t_gen = time.perf_counter()
+    d = I.make_inputs(config, "base")
+    mesh = d["mesh"]
+    print(f"[bench] newton inputs {config}: {mesh.n_dof} DoFs, generated in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    nx1, ny1, nz1 = mesh.node_dims
+    i = np.arange(mesh.n_nodes)
+    ix, iy, iz = i % nx1, (i // nx1) % ny1, i // (nx1 * ny1)
+    z0 = d["z"].copy()
+    z0[0, ix == 0] = 0.0
+    z0[1, iy == 0] = 0.0
+    z0[2, iz == 0] = 0.0
+    z0[2, iz == nz1 - 1] = d["e0"] * mesh.lz
+    ctx = pfmf.Context.from_inputs(d)
+    levels = [4, 2, 1] if mesh.p == 4 else list(range(mesh.p, 0, -1))
+    ctx.set_pmg_levels(levels)
+    ctx.set_dirichlet({"x0": ["ux"], "y0": ["uy"], "z0": ["uz"], "z1": ["uz"]})
+    z = torch.as_tensor(z0).to("cuda", torch.float64)
+    dz = torch.as_tensor(np.ascontiguousarray(d["dz"])).to("cuda", torch.float64)
+    # FP64 and FP32 fine applies on this workload (device time of 10 back-to-back applies)
+    ctx.linearize(z)
+    y = torch.empty_like(z)
+    dz32 = dz.float()
+    y32 = torch.empty_like(dz32)
+    ms = {}
+    for name, f in (("jacobian", lambda: ctx.apply_jacobian(z, dz, y)),
+                    ("fp32_apply", lambda: ctx.apply_jacobian_f32(0, dz32, y32)),
+                    ("vcycle", lambda: ctx.pmg_vcycle(dz32, y32))):
+        f()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        ms[name] = a.elapsed_time(b) / 10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.newton_step(z, rtol=1e-8, restart=30, max_iters=300, raise_on_noconv=False)
+    t_step = time.perf_counter() - t0
+    print(f"[bench] newton step {rep} in {t_step:.2f} s", file=sys.stderr, flush=True)
+    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}",
+            "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
+            "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
+            "t_linearize_ms": rep["t_linearize_ms"], "ms": ms,
+            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "fp32_apply")},
+            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +186,9 @@ def main():
     ap.add_argument("--variant", default="base")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--newton", action="store_true",
+                    help="also time one Newton step (FGMRES + FP32 p-MG) on --newton-config")
+    ap.add_argument("--newton-config", default="C5")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
@@ -268,6 +325,10 @@ def main():
         "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
+    if args.newton:
+        del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32
+        torch.cuda.empty_cache()
+        out["newton"] = newton_leg(torch, I, pfmf, args.newton_config)
     print(json.dumps(out), flush=True)
 
 

@@ -397,13 +397,13 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
     hipLaunchKernelGGL(k_hash_fill, dim3(g), dim3(NT), 0, s, L.d, n, (uint64_t)(21150 + l));
     if ((st = mask_level(c, l, L.d, s))) return st;
     hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(NT), 0, s, L.d, n, mg.red);
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, mg.red, g, nrm + l, inv);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NT), 0, s, mg.red, g, nrm + l, inv);
     hipLaunchKernelGGL(k_vec_axs_dev, dim3(g), dim3(NT), 0, s, L.d, L.d, inv, n);
     for (int it = 0; it < POWER_ITS; ++it) {
       if ((st = level_op<0>(c, l, L.d, L.t, s))) return st;
       hipLaunchKernelGGL(k_vec_scale, dim3(g), dim3(NT), 0, s, L.dinv, L.t, n);
       hipLaunchKernelGGL(k_sumsq, dim3(g), dim3(NT), 0, s, L.t, n, mg.red);
-      hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(64), 0, s, mg.red, g, nrm + l, inv);
+      hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NT), 0, s, mg.red, g, nrm + l, inv);
       hipLaunchKernelGGL(k_vec_axs_dev, dim3(g), dim3(NT), 0, s, L.t, L.d, inv, n);
     }
     HIPCHK(hipGetLastError());

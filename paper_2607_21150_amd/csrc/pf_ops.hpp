@@ -41,7 +41,7 @@ template <int P, int Q> struct OpShape {
 };
 
 template <int MODE, int P, int Q>
-__global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+__global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   using S = OpShape<P, Q>;
   constexpr int NB3 = S::NB3, P3 = S::P3, Q3 = S::Q3, ER = S::ER;
   extern __shared__ double lds[];
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __
     // ---- forward sum factorisation: values at this thread's quadrature point
     double G[9], phi = 0.0, gphi[3] = {0, 0, 0}, phin = 0.0;
     double W[9], wphi = 0.0, gwphi[3] = {0, 0, 0};
-#pragma unroll 1
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
       const bool grad = (f < 3) || MODE != M_JAC;
       fwd_xy<double, P, Q, ER>(zb + f * NB3, slot0, g, tb, grad, xb, xd, ybb, ydb, ybd);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __
       __syncthreads();
     }
     if (MODE != M_RES) {
-#pragma unroll 1
+#pragma unroll
       for (int f = 0; f < 4; ++f) {
         fwd_xy<double, P, Q, ER>(wb + f * NB3, slot0, g, tb, true, xb, xd, ybb, ydb, ybd);
         if (t < ER * Q3) {
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(NT) void k_op64(OpArgs a, int colour, DevTables* __
       // field-major quadrature arrays reused per output field
       q0[t] = f0;
     }
-#pragma unroll 1
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
       if (t < ER * Q3) {
         if (f < 3) {

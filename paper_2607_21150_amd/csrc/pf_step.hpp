@@ -52,16 +52,24 @@ __global__ void k_hash_fill(float* __restrict__ x, int64_t n, uint64_t seed) {
   }
 }
 
-// Sum of the first n partials in index order (one block): out[0] = sqrt(sum),
-// inv[0] = 1 / sqrt(sum) (0 when the sum vanishes).
+// Sum of the first n partials (one block of NT threads, fixed strided order and a
+// fixed tree): out[0] = sqrt(sum), inv[0] = 1 / sqrt(sum) (0 when the sum vanishes).
 __global__ void k_norm_finish(const double* __restrict__ part, int n, double* __restrict__ out,
                               float* __restrict__ inv) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  __shared__ double red[NT];
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += part[i];
-  const double r = sqrt(s);
-  out[0] = r;
-  inv[0] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+  for (int i = threadIdx.x; i < n; i += NT) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(red[0]);
+    out[0] = r;
+    inv[0] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+  }
 }
 
 // b = s[0] * a (scale held in device memory)
