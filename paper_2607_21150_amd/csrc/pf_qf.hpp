@@ -135,7 +135,24 @@ __device__ inline void jacobi_rotate(T& app, T& aqq, T& apq, T& arp, T& arq, T* 
   }
 }
 
-__device__ inline float seed_cos_third(float r) { return cosf(acosf(r) * (1.0f / 3.0f)); }
+// Seed of c = cos(acos(r) / 3) for r in [-1, 1]. With t = sqrt((1 + r) / 2) =
+// cos(acos(r) / 2), c = cos(2 acos(t) / 3) is analytic in t on [0, 1]; it is taken
+// as 0.5 + t q(t) with q a degree-7 least-squares Chebyshev-node fit of (c - 0.5) / t
+// (exact at r = -1, error below 4e-8 with t from the FP32 square root).
+template <typename T>
+__device__ inline T seed_cos_third(T r) {
+  const float tf = __builtin_sqrtf((float)(T(0.5) * (T(1) + r)));
+  const T t = (T)tf;
+  T q = T(-0.0008711068611442343);
+  q = fma(q, t, T(0.004603595835898712));
+  q = fma(q, t, T(-0.011722732125447858));
+  q = fma(q, t, T(0.020800135207323198));
+  q = fma(q, t, T(-0.03245631158654394));
+  q = fma(q, t, T(0.05340486896259051));
+  q = fma(q, t, T(-0.11110871404718346));
+  q = fma(q, t, T(0.5773502512952833));
+  return fma(t, q, T(0.5));
+}
 
 // Symmetric 3x3 eigen-decomposition A = V diag(lam) V^T (eigenvectors in the
 // columns of V). Closed-form eigenvalues of the deviator (cos(acos(r)/3), seeded
@@ -159,7 +176,7 @@ __device__ inline void eig_sym3(const T* A, T* lam, T* V) {
     const T p = q3 * ip;
     T r = T(0.5) * J3 * ip * ip * ip;
     r = r > T(1) ? T(1) : (r < T(-1) ? T(-1) : r);
-    T c = (T)seed_cos_third((float)r);
+    T c = seed_cos_third<T>(r);
     const T den = T(12) * c * c - T(3);
     if (den > T(1e-3)) c -= (T(4) * c * c * c - T(3) * c - r) * frcp(den);
     c = c > T(1) ? T(1) : (c < T(0.5) ? T(0.5) : c);
@@ -676,70 +693,67 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
 }
 
 // Reverse (transpose) of qp_tangent: cotangents (Pb = dP-bar, Lb = dL-bar) ->
-// (Gb = dG-bar, phib = dphi-bar). Also returns the diagonal of the rotated stress
+// (Gb = dG-bar, phib = dphi-bar), step by step in the reverse order of the forward
+// map, in the principal frame. Also returns the diagonal of the rotated stress
 // cotangent Xd_i = [N^T (Pb F^-1) N]_ii used by the parameter partials.
 template <typename T>
 __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, const T* Pb, T Lb, T* Gb,
                                     T& phib, T* Xd) {
   const T* N = s.N;
+  const T* bd = s.bd;
   const T tm2 = T(2) * m.mu;
   // dL = dLcoef dphi + gp dH
   phib = s.dLcoef * Lb;
   const T Hb = s.gp * Lb;
-  // Mmb = Pb F^-1   (dP = Mm F^-T)
+  // dP = Mm F^-T  ->  Mmb = Pb F^-1
   T Mmb[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       Mmb[3 * i + k] = Pb[3 * i] * s.Fi[k] + Pb[3 * i + 1] * s.Fi[3 + k] + Pb[3 * i + 2] * s.Fi[6 + k];
-  // dl-bar from -tau dl^T:  dlb = -Mmb^T tau
-  const T* t = s.tau;
-  const T tm[9] = {t[0], t[5], t[4], t[5], t[1], t[3], t[4], t[3], t[2]};
-  T dlb[9];
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      dlb[3 * j + k] = -(Mmb[j] * tm[k] + Mmb[3 + j] * tm[3 + k] + Mmb[6 + j] * tm[6 + k]);
-  // Xb = N^T Mmb N
-  T Z[9];
+  // Mm = N Z N^T  ->  Zb = N^T Mmb N
+  T Zt[9], Zb[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      Z[3 * i + j] = Mmb[3 * i] * N[j] + Mmb[3 * i + 1] * N[3 + j] + Mmb[3 * i + 2] * N[6 + j];
-  T Xb[9];
+      Zt[3 * i + j] = Mmb[3 * i] * N[j] + Mmb[3 * i + 1] * N[3 + j] + Mmb[3 * i + 2] * N[6 + j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Xb[3 * i + j] = N[i] * Z[j] + N[3 + i] * Z[3 + j] + N[6 + i] * Z[6 + j];
-  Xd[0] = Xb[0];
-  Xd[1] = Xb[4];
-  Xd[2] = Xb[8];
-  // off-diagonal: X_ij = dbt_ij coef_ij (both (i,j) and (j,i))
-  T dbtb[9];
-  dbtb[5] = dbtb[7] = (Xb[5] + Xb[7]) * s.coef[0];  // (1,2)
-  dbtb[2] = dbtb[6] = (Xb[2] + Xb[6]) * s.coef[1];  // (0,2)
-  dbtb[1] = dbtb[3] = (Xb[1] + Xb[3]) * s.coef[2];  // (0,1)
-  // each off-diagonal dbt entry of the symmetric forward matrix appears in both
-  // positions of the full product, so its cotangent is shared equally
-  dbtb[5] *= T(0.5); dbtb[7] *= T(0.5);
-  dbtb[2] *= T(0.5); dbtb[6] *= T(0.5);
-  dbtb[1] *= T(0.5); dbtb[3] *= T(0.5);
-  // diagonal stress increments
-  T dceb[3] = {T(0), T(0), T(0)};
+    for (int j = 0; j < 3; ++j) Zb[3 * i + j] = N[i] * Zt[j] + N[3 + i] * Zt[3 + j] + N[6 + i] * Zt[6 + j];
+  Xd[0] = Zb[0];
+  Xd[1] = Zb[4];
+  Xd[2] = Zb[8];
+  // Z = Xfull - diag(tau_d) Lt^T: off-diagonal increments and the geometric term
+  const T* td = s.taud;
+  T Ltb[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Ltb[3 * a + b] = -td[b] * Zb[3 * b + a];
+  const T ob12 = (Zb[5] + Zb[7]) * s.coef[0];
+  const T ob02 = (Zb[2] + Zb[6]) * s.coef[1];
+  const T ob01 = (Zb[1] + Zb[3]) * s.coef[2];
+  Ltb[5] += bd[2] * ob12;
+  Ltb[7] += bd[1] * ob12;
+  Ltb[2] += bd[2] * ob02;
+  Ltb[6] += bd[0] * ob02;
+  Ltb[1] += bd[1] * ob01;
+  Ltb[3] += bd[0] * ob01;
+  // principal stress increments
+  T dceb[3];
   T dthb = T(0);
   const T kapth = m.kappa * s.theta;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T xb = Xb[4 * i];
+    const T xb = Zb[4 * i];
+    dceb[i] = s.g * tm2 * xb;
     if (s.tension) {
-      dceb[i] += s.g * tm2 * xb;
       dthb += s.g * m.kappa * xb;
       phib += s.gp * s.taub[i] * xb;
     } else {
-      dceb[i] += s.g * tm2 * xb;
       dthb += m.kappa * xb;
       phib += s.gp * (s.taub[i] - kapth) * xb;
     }
@@ -756,34 +770,22 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
 #pragma unroll
   for (int i = 0; i < 3; ++i) deb[i] = s.c * dceb[i] + s.kq * sdot * s.e[i];
   phib += s.kphi * sdot;
-  // de_i = deps_i - dth/3, dth = sum deps
+  // de_i = deps_i - dth/3, dth = sum deps, deps_i = 2 b_i (1/(2 b_i)) Lt_ii
   const T mdeb = (deb[0] + deb[1] + deb[2]) * (T(1) / T(3));
 #pragma unroll
-  for (int i = 0; i < 3; ++i) dbtb[4 * i] = (deb[i] - mdeb + dthb) * s.hinv[i];
-  // dbt = N^T dA N  ->  dAb = N dbtb N^T
-  T R[9];
+  for (int i = 0; i < 3; ++i) Ltb[4 * i] += (deb[i] - mdeb + dthb) * (T(2) * bd[i] * s.hinv[i]);
+  // Lt = N^T dl N  ->  dlb = N Ltb N^T
+  T R[9], dlb[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      R[3 * i + j] = N[3 * i] * dbtb[j] + N[3 * i + 1] * dbtb[3 + j] + N[3 * i + 2] * dbtb[6 + j];
-  T dAb[9];
+      R[3 * i + j] = N[3 * i] * Ltb[j] + N[3 * i + 1] * Ltb[3 + j] + N[3 * i + 2] * Ltb[6 + j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) dAb[3 * i + j] = R[3 * i] * N[3 * j] + R[3 * i + 1] * N[3 * j + 1] + R[3 * i + 2] * N[3 * j + 2];
-  // dA = M + M^T, M = dl b  ->  Mb = dAb + dAb^T ; dlb += Mb b
-  const T* b = s.b;
-  const T bm[9] = {b[0], b[5], b[4], b[5], b[1], b[3], b[4], b[3], b[2]};
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      T acc = T(0);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) acc += (dAb[3 * i + j] + dAb[3 * j + i]) * bm[3 * k + j];
-      dlb[3 * i + k] += acc;
-    }
+    for (int j = 0; j < 3; ++j)
+      dlb[3 * i + j] = R[3 * i] * N[3 * j] + R[3 * i + 1] * N[3 * j + 1] + R[3 * i + 2] * N[3 * j + 2];
   // dl = dG F^-1  ->  Gb = dlb F^-T
 #pragma unroll
   for (int i = 0; i < 3; ++i)
