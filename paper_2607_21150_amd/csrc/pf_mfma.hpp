@@ -55,6 +55,26 @@ __device__ inline Basis4 load_basis4(const DevTables* __restrict__ t) {
   return b;
 }
 
+// Basis operands of a (P, Q) pair with P, Q <= 4, zero-padded to 4 x 4: the padded
+// points carry zero values and zero test functions.
+template <int P, int Q>
+__device__ inline Basis4 load_basis_pq(const DevTables* __restrict__ t) {
+  const int l = threadIdx.x & 63;
+  const int a = l & 3, c = l >> 4;
+  Basis4 b;
+  b.fB = (c < P && a < Q) ? t->B[P][Q][a][c] : 0.0;
+  b.fD = (c < P && a < Q) ? t->D[P][Q][a][c] : 0.0;
+  b.bB = (a < P && c < Q) ? t->B[P][Q][c][a] : 0.0;
+  b.bD = (a < P && c < Q) ? t->D[P][Q][c][a] : 0.0;
+  return b;
+}
+
+// Value of lane src (0..63) of the wave, for a double.
+__device__ inline double lane_read(double v, int src) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_ds_bpermute(src << 2, hi), __builtin_amdgcn_ds_bpermute(src << 2, lo));
+}
+
 // Forward for NF fields in lockstep (independent chains interleaved): nodal
 // values u[f] (layout x,y,z) -> value v[f] and reference gradient d[f][0..2] at
 // the lane's point (layout qx,qz,qy). grad_mask / val_mask select the outputs.
@@ -374,6 +394,235 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
   }
   __syncthreads();
   scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  if (any_bad) a.flag[0] = 1;
+}
+
+}  // namespace pfmf
+
+namespace pfmf {
+
+// FP64 residual / Jacobian / adjoint on Q2 elements (3 nodes, 3 Gauss points per
+// direction). Sum factorisation on the matrix cores with the bases zero-padded to
+// 4 x 4 (one element per pass, 27 of 64 lanes carry points); the pointwise function
+// then runs on a packed layout holding both elements of the wave (lanes 0-26 and
+// 32-58), moved there and back by lane permutes, so that it is evaluated once for
+// two elements.
+template <int MODE>
+__global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ double ev[8 * 4 * 64];
+  __shared__ double red[NT];
+  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = decode_brick(a.m, colour, brick);
+  const Basis4 bs = load_basis_pq<3, 3>(tabs);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave's two elements: slot wv (sz = 0) and slot wv + 4 (sz = 1)
+  const int sx = wv & 1, sy = wv >> 1;
+  const bool hasA = sx < g.nex && sy < g.ney;  // uniform per wave
+  const bool hasB = hasA && g.nez > 1;
+  // packed layout: lane l holds point q = l & 31 (q < 27) of element E = l >> 5
+  const int E = l >> 5, q = l & 31;
+  const int cqx = q % 3, cqy = (q / 3) % 3, cqz = q / 9;
+  const bool valid = q < 27 && (E == 0 ? hasA : hasB);
+  const int src_fwd = cqx + 4 * cqz + 16 * cqy;  // padded point lane (qx, qz, qy) of point q
+  // padded point layout of this lane (backward input) and its packed source
+  const int pqx = l & 3, pqz = (l >> 2) & 3, pqy = l >> 4;
+  const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
+  const int pq = pqx + 3 * pqy + 9 * pqz;
+  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
+  const double wdet = tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz] *
+                      (a.m.hx * a.m.hy * a.m.hz * 0.125);
+  bool any_bad = false;
+  int pid = 255;
+  double gsum[3] = {0.0, 0.0, 0.0};
+  if (hasA) {
+    // ---- gather and forward interpolation of z (and phi_n), packed into this lane's point
+    double G[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double phi = 0.0, gphi[3] = {0.0, 0.0, 0.0}, phin = 0.0;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (half == 1 && !hasB) break;  // uniform
+      const int64_t gn = lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
+      double zu[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) zu[f] = gn >= 0 ? a.z[f * a.n_nodes + gn] : 0.0;
+      double v[4], d[4][3];
+      sf4_fwd_n<4>(zu, bs, 0x8u, MODE == M_JAC ? 0x7u : 0xFu, v, d);
+      const bool mine = E == half;
+#pragma unroll
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double r = lane_read(d[f][J], src_fwd);
+          if (mine) G[3 * f + J] = r * ih[J];
+        }
+      const double rp = lane_read(v[3], src_fwd);
+      if (mine) phi = rp;
+      if (MODE != M_JAC) {
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double r = lane_read(d[3][J], src_fwd);
+          if (mine) gphi[J] = r * ih[J];
+        }
+      }
+      if (MODE == M_RES) {
+        double pn = gn >= 0 ? a.phin[gn] : 0.0, pv[1], pd[1][3];
+        sf4_fwd_n<1>(&pn, bs, 0x1u, 0x0u, pv, pd);
+        const double r = lane_read(pv[0], src_fwd);
+        if (mine) phin = r;
+      }
+    }
+    // ---- per-point state (packed layout)
+    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
+    const int64_t gq = e * 27 + q;
+    double st[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st[k] = valid ? a.state[k * a.n_q + gq] : 0.0;
+    pid = valid ? a.phase[gq] : 255;
+    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<double> s;
+    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+    any_bad |= valid && s.bad;
+    // ---- direction / cotangent at the point
+    double W[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
+    if (MODE != M_RES) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        if (half == 1 && !hasB) break;
+        const int64_t gn = lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
+        double wu[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) wu[f] = gn >= 0 ? a.w[f * a.n_nodes + gn] : 0.0;
+        double v[4], d[4][3];
+        sf4_fwd_n<4>(wu, bs, 0x8u, 0xFu, v, d);
+        const bool mine = E == half;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+          for (int J = 0; J < 3; ++J) {
+            const double r = lane_read(d[f][J], src_fwd);
+            if (mine) W[3 * f + J] = r * ih[J];
+          }
+        const double rp = lane_read(v[3], src_fwd);
+        if (mine) wphi = rp;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double r = lane_read(d[3][J], src_fwd);
+          if (mine) gw[J] = r * ih[J];
+        }
+      }
+    }
+    // ---- pointwise function (packed layout)
+    const double kfg = a.fr.kf * mp.Gc;
+    double Fu[9], f0, f1[3];
+    if (MODE == M_RES) {
+      piola<double>(s, Fu);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+      f0 = wdet * a.fr.s_phi * s.L;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
+    } else if (MODE == M_JAC) {
+      double dL;
+      qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+      f0 = wdet * a.fr.s_phi * dL;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gw[J];
+    } else {
+      double Pb[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
+      const double f0b = wdet * wphi;
+      const double Lb = a.fr.s_phi * f0b;
+      double phib, Xd[3];
+      qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
+      f0 = phib;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
+      const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
+      gsum[0] = alpha_p * a.fr.inv_c0l0 * Lb + a.fr.kf * wdet * (gphi[0] * gw[0] + gphi[1] * gw[1] + gphi[2] * gw[2]);
+      if (s.plastic) {
+        const double ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
+        const double qv = 2.0 * mp.mu * sqrt(1.5 * ee);
+        const double w3q = 3.0 * mp.mu / qv;
+        const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
+        const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        gsum[1] = -w3q * s.ddg_s0 * base;
+        gsum[2] = -w3q * s.ddg_visc * base;
+      }
+      if (!valid) gsum[0] = gsum[1] = gsum[2] = 0.0;
+    }
+    // ---- back to the padded layout of each element, transposed interpolation
+    double b1p[4][3];
+    double b0p[4];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1p[f][J] = Fu[3 * f + J] * ih[J];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) b1p[3][J] = f1[J] * ih[J];
+    b0p[3] = f0;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (half == 1 && !hasB) break;
+      const int src = pvalid ? 32 * half + pq : l;  // lanes 0..63 only
+      double b0[4], b1[4][3], r[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        b0[f] = 0.0;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double v = lane_read(b1p[f][J], src);
+          b1[f][J] = pvalid ? v : 0.0;
+        }
+      }
+      {
+        const double v = lane_read(b0p[3], src);
+        b0[3] = pvalid ? v : 0.0;
+      }
+      sf4_bwd_n<4>(b0, b1, 0x8u, bs, r);
+      const int slot = wv + 4 * half;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];
+    }
+  }
+  if (MODE == M_ADJ) {
+    // deterministic per-phase reduction: butterfly inside each wave, wave sums in order
+    const int nv = 3 * a.nph;
+    if (nv * (NT / 64) <= NT) {
+      for (int idx = 0; idx < nv; ++idx) {
+        const int ph = idx / 3, k = idx - 3 * ph;
+        double v = pid == ph ? (k == 0 ? gsum[0] : (k == 1 ? gsum[1] : gsum[2])) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (l == 0) red[wv * nv + idx] = v;
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < nv) {
+        double t = red[threadIdx.x];
+        for (int w = 1; w < NT / 64; ++w) t += red[w * nv + threadIdx.x];
+        a.gpart[(int64_t)(a.brick_base + brick) * nv + threadIdx.x] = t;
+      }
+    } else {
+      for (int ph = 0; ph < a.nph; ++ph) {
+        for (int k = 0; k < 3; ++k) {
+          red[threadIdx.x] = pid == ph ? (k == 0 ? gsum[0] : (k == 1 ? gsum[1] : gsum[2])) : 0.0;
+          __syncthreads();
+          for (int st = NT / 2; st > 0; st >>= 1) {
+            if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+          }
+          if (threadIdx.x == 0) a.gpart[((int64_t)(a.brick_base + brick) * a.nph + ph) * 3 + k] = red[0];
+          __syncthreads();
+        }
+      }
+    }
+  }
+  __syncthreads();
+  scatter_brick4<double, 3, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
 }
 

@@ -200,13 +200,16 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   return PF_OK;
 }
 
-template <int MODE>
-pf_status launch_op64_q3(pf_ctx* c, OpArgs a, hipStream_t s) {
+template <int MODE, int P>
+pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
-    hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+    if (P == 4)
+      hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+    else
+      hipLaunchKernelGGL((k_op64_q2<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -216,8 +219,8 @@ template <int MODE>
 pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   switch (c->mesh.p) {
     case 1: return launch_op64<MODE, 2, 2>(c, a, s);
-    case 2: return launch_op64<MODE, 3, 3>(c, a, s);
-    case 3: return launch_op64_q3<MODE>(c, a, s);
+    case 2: return launch_op64_mfma<MODE, 3>(c, a, s);
+    case 3: return launch_op64_mfma<MODE, 4>(c, a, s);
     case 4: return launch_op64<MODE, 5, 5>(c, a, s);
     default: return fail(PF_EUNSUPPORTED, "order p=%d not built", c->mesh.p);
   }

@@ -45,6 +45,7 @@ CASES = [
     ("C1", "plastic", 3, 3),   # Q3, odd
     ("C1", "base", 4, 2),      # Q4
     ("C2", "plastic", 2, 6),   # Q2, several bricks per direction
+    ("C1", "plastic", 2, 5),   # Q2, odd element count (bricks with one element layer)
 ]
 
 
