@@ -13,6 +13,13 @@
  * (Section 4). Element operators use dense element matrices built from the 1-D
  * Lagrange basis (no sum factorisation).
  *
+ * Pins (tests/test_oracle_pins.py, tests/test_oracle_commit_pins.py) tie every
+ * function here to closed forms, library routines, invariants or finite
+ * differences. Parity unpinned: the overstress factor (1 + visc dgamma / dt) of the
+ * Prandtl branch is a reading, not the paper's; it is pinned only at visc = 0
+ * (Box 2), by its own root-finding (bisection, Newton) and by finite differences.
+ * The global phase-field scale s_phi is an input, not derived here.
+ *
  * Conventions (shared interface, see inputs.py): nodes lexicographic x-fastest,
  * z = SoA [4][n_nodes] (u_x,u_y,u_z,phi), qp = e*Q^3 + qx + Q*(qy + Q*qz),
  * state = SoA [8][n_q] (D xx,yy,zz,yz,xz,xy = Cin^-1 - I; ebar_p; H_n),
