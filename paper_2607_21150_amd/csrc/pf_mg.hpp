@@ -52,6 +52,8 @@ struct MGState {
   float* tmpA = nullptr;
   float* tmpB = nullptr;
   double* red = nullptr;  // reduction scratch
+  float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
+  int ebe_level = -1;
   bool linearized = false;
 };
 
@@ -75,6 +77,7 @@ inline void mg_free(MGState& mg) {
   (void)hipFree(mg.tmpA);
   (void)hipFree(mg.tmpB);
   (void)hipFree(mg.red);
+  (void)hipFree(mg.ebe);
   mg = MGState();
 }
 

@@ -95,6 +95,12 @@ pf_status mg_alloc(pf_ctx* c) {
       }
     }
   }
+  if (mg.lv[mg.n_levels - 1].p == 1) {
+    const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
+    if (hipMalloc(&mg.ebe, (size_t)n_elem * 1024 * sizeof(float)) != hipSuccess)
+      return fail(PF_ENOMEM, "coarse element matrices: allocation failed");
+    mg.ebe_level = mg.n_levels - 1;
+  }
   const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
   if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
       hipMalloc(&mg.rec.rec, REC_N * c->n_q * sizeof(float)) != hipSuccess ||
@@ -181,8 +187,55 @@ pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
   return PF_OK;
 }
 
+EbeArgs ebe_args(pf_ctx* c, const float* x, float* out) {
+  EbeArgs a;
+  a.m = mesh_dev(c);
+  const MGLevel& F = c->mg.lv[0];
+  const MGLevel& L = c->mg.lv[c->mg.ebe_level];
+  a.fine = LevelDev{F.P, F.nx1, F.ny1, F.n_nodes};
+  a.lev = LevelDev{L.P, L.nx1, L.ny1, L.n_nodes};
+  a.n_q = c->n_q;
+  a.z32 = c->mg.z32;
+  a.rec = c->mg.rec;
+  a.phase = c->qp_phase;
+  a.mats = c->d_matsf;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<float>(c->fr);
+  a.K = c->mg.ebe;
+  a.x = x;
+  a.out = out;
+  return a;
+}
+
+pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
+  const EbeArgs a = ebe_args(c, nullptr, nullptr);
+  const int n_elem = c->mesh.nx * c->mesh.ny * c->mesh.nz;
+  switch (c->mg.lv[0].P) {
+    case 2: hipLaunchKernelGGL(k_ebe_assemble<2>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 3: hipLaunchKernelGGL(k_ebe_assemble<3>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 4: hipLaunchKernelGGL(k_ebe_assemble<4>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 5: hipLaunchKernelGGL(k_ebe_assemble<5>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    default: return fail(PF_EUNSUPPORTED, "order not built");
+  }
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+template <int MODE>
+pf_status ebe_apply(pf_ctx* c, const float* x, float* out, hipStream_t s) {
+  const EbeArgs a = ebe_args(c, x, out);
+  for (int col = 0; col < 8; ++col) {
+    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
+    if (nb == 0) continue;
+    hipLaunchKernelGGL(k_ebe_apply<MODE>, dim3(nb), dim3(NT), 0, s, a, col);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
 template <int MODE>
 pf_status level_op_raw(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
+  if (level == c->mg.ebe_level && c->mg.ebe) return ebe_apply<MODE>(c, dz, out, s);
   const A32Args a = a32_args(c, level, dz, out);
   const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
   if (MODE == 0 && PF == 4) {
@@ -382,6 +435,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
     default: st = fail(PF_EUNSUPPORTED, "order not built");
   }
   if (st) return st;
+  if (mg.ebe_level >= 0 && (st = ebe_assemble(c, s))) return st;
   mg.linearized = true;
   // lambda_max(D^-1 A) per level by 15 power iterations, normalised on the device
   // (no host round trip inside the loop); one synchronisation at the end

@@ -14,6 +14,7 @@
 #include "pf_mg.hpp"
 #include "pf_mfma.hpp"
 #include "pf_step.hpp"
+#include "pf_ebe.hpp"
 #include "pf_tables.hpp"
 
 using namespace pfmf;
