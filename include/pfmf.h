@@ -152,7 +152,7 @@ pf_status pf_commit_state(pf_ctx* ctx, const double* z, double* state_out, void*
 
 /* Newton step options: relative tolerance of the linear solve (default 1e-8),
  * FGMRES restart length (30, at most 60), iteration limit (300), and the V-cycle
- * smoother (Chebyshev degree 3, 4 coarsest sweeps). Zero fields take defaults. */
+ * smoother (Chebyshev degree 3, 32 coarsest sweeps). Zero fields take defaults. */
 typedef struct {
   double rtol;
   int restart, max_iters, cheb_degree, coarse_sweeps;

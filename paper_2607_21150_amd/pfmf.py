@@ -272,7 +272,7 @@ class Context:
         _check(load().pf_commit_state(self._h, _ptr(z), _ptr(out), _stream(stream)))
         return out
 
-    def newton_step(self, z, rtol=1e-8, restart=30, max_iters=300, cheb_degree=3, coarse_sweeps=4,
+    def newton_step(self, z, rtol=1e-8, restart=30, max_iters=300, cheb_degree=3, coarse_sweeps=32,
                     stream=None, raise_on_noconv=True):
         """One Newton update of z in place; returns the solver report as a dict."""
         _req(z, torch.float64, (4, self.n_nodes), "z")
