@@ -44,6 +44,8 @@ struct MeshDev {
   int nx, ny, nz;
   int nbx, nby, nbz;     // bricks per direction
   double hx, hy, hz;
+  double ih[3];          // 2 / h per direction (reference-to-physical gradient factor)
+  double jdet;           // hx hy hz / 8 (affine Jacobian determinant)
 };
 
 __device__ inline BrickGeom decode_brick(const MeshDev& m, int colour, int b) {

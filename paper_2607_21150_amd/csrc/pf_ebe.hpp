@@ -59,8 +59,8 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     ub[i] = a.z32[f * a.fine.n_nodes + gi];
   }
   __syncthreads();
-  const float ih[3] = {(float)(2.0 / a.m.hx), (float)(2.0 / a.m.hy), (float)(2.0 / a.m.hz)};
-  const float jdet = (float)(a.m.hx * a.m.hy * a.m.hz * 0.125);
+  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
+  const float jdet = (float)a.m.jdet;
   for (int q = t; q < Q3; q += NT) {
     const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
     float G[9];

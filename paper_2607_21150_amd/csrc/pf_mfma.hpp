@@ -220,8 +220,8 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
   const int ql = qx + 4 * qy + 16 * qz;
-  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
-  const double wdet = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * (a.m.hx * a.m.hy * a.m.hz * 0.125);
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
+  const double wdet = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet;
   // adjoint: parameter partials and phase id of every point of the brick (slot, lane)
   __shared__ double gpq[MODE == M_ADJ ? 8 * 3 * 64 : 1];
   __shared__ unsigned char gpid[MODE == M_ADJ ? 8 * 64 : 1];
@@ -429,9 +429,9 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTabl
   const int pqx = l & 3, pqz = (l >> 2) & 3, pqy = l >> 4;
   const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
   const int pq = pqx + 3 * pqy + 9 * pqz;
-  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
   const double wdet = tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz] *
-                      (a.m.hx * a.m.hy * a.m.hz * 0.125);
+                      a.m.jdet;
   bool any_bad = false;
   int pid = 255;
   double gsum[3] = {0.0, 0.0, 0.0};
@@ -644,8 +644,8 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
   const int ql = qx + 4 * qy + 16 * qz;
-  const float ih[3] = {(float)(2.0 / a.m.hx), (float)(2.0 / a.m.hy), (float)(2.0 / a.m.hz)};
-  const float wdet = (float)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * (a.m.hx * a.m.hy * a.m.hz * 0.125));
+  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
+  const float wdet = (float)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet);
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
     const int slot = wv + 4 * half;

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
   stage_brick<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, zb);
   __syncthreads();
   const TabRef<double> tb{tab, tab + Q * P};
-  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
   double* xb = tmp;
   double* xd = xb + ER * P * P * Q;
   double* ybb = xd + ER * P * P * Q;
@@ -243,8 +243,8 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
   const TabRef<float> tf{tab, tab + Q * PF};
   const TabRef<float> tc{tab + 2 * Q * PF, tab + 2 * Q * PF + Q * PC};
   const float* wq = tab + 2 * Q * PF + 2 * Q * PC;
-  const float ih[3] = {(float)(2.0 / a.m.hx), (float)(2.0 / a.m.hy), (float)(2.0 / a.m.hz)};
-  const float jdet = (float)(a.m.hx * a.m.hy * a.m.hz * 0.125);
+  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
+  const float jdet = (float)a.m.jdet;
   float* xb = tmp;
   float* xd = xb + ER * PM * PM * Q;
   float* ybb = xd + ER * PM * PM * Q;

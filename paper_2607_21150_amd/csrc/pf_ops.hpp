@@ -68,8 +68,8 @@ __global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colou
   const TabRef<double> tb{tab, tab + Q * P};
   const double* wq = tab + 2 * Q * P;
 
-  const double ih[3] = {2.0 / a.m.hx, 2.0 / a.m.hy, 2.0 / a.m.hz};
-  const double jdet = a.m.hx * a.m.hy * a.m.hz * 0.125;
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
+  const double jdet = a.m.jdet;
   double gsum[3] = {0.0, 0.0, 0.0};   // adjoint parameter partials of this thread
   int my_pid = -1;
   bool any_bad = false;

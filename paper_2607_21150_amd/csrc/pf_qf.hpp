@@ -77,8 +77,15 @@ template <> struct Eps<float> {
 };
 
 // 1 + s^2/3 + s^4/5 + ... (atanh(s)/s), Horner in s^2
+// (6 terms when s2 <= 1e-3: the truncation is then below s2^6 / 13 < 1e-19)
 template <typename T>
 __device__ inline T atanh_ratio(T s2) {
+  if (Eps<T>::nterms > 6 && s2 <= T(1e-3)) {
+    T r = T(1) / T(11);
+#pragma unroll
+    for (int k = 4; k >= 0; --k) r = fma(r, s2, T(1) / T(2 * k + 1));
+    return r;
+  }
   T r = T(1) / T(2 * Eps<T>::nterms - 1);
 #pragma unroll
   for (int k = Eps<T>::nterms - 2; k >= 0; --k) r = fma(r, s2, T(1) / T(2 * k + 1));
@@ -610,20 +617,20 @@ template <typename T>
 __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
                                   T* dP, T& dL) {
   const T* N = s.N;
-  // dl = dG F^-1
-  T dl[9];
+  // FiN = F^-1 N serves both ends: dl N = dG FiN and F^-T at the output
+  T FiN[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      dl[3 * i + j] = dG[3 * i] * s.Fi[j] + dG[3 * i + 1] * s.Fi[3 + j] + dG[3 * i + 2] * s.Fi[6 + j];
-  // Lt = N^T (dl N)
+      FiN[3 * i + j] = s.Fi[3 * i] * N[j] + s.Fi[3 * i + 1] * N[3 + j] + s.Fi[3 * i + 2] * N[6 + j];
+  // Lt = N^T (dl N), dl = dG F^-1
   T dN[9], Lt[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      dN[3 * i + j] = dl[3 * i] * N[j] + dl[3 * i + 1] * N[3 + j] + dl[3 * i + 2] * N[6 + j];
+      dN[3 * i + j] = dG[3 * i] * FiN[j] + dG[3 * i + 1] * FiN[3 + j] + dG[3 * i + 2] * FiN[6 + j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -665,8 +672,8 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
   const T Z[9] = {X[0] - td[0] * Lt[0], o01 - td[0] * Lt[3], o02 - td[0] * Lt[6],
                   o01 - td[1] * Lt[1], X[1] - td[1] * Lt[4], o12 - td[1] * Lt[7],
                   o02 - td[2] * Lt[2], o12 - td[2] * Lt[5], X[2] - td[2] * Lt[8]};
-  // Mm = N Z N^T ; dP = Mm F^-T
-  T NZ[9], Mm[9];
+  // dP = (N Z N^T) F^-T = (N Z) (F^-1 N)^T
+  T NZ[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -675,13 +682,8 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      Mm[3 * i + j] = NZ[3 * i] * N[3 * j] + NZ[3 * i + 1] * N[3 * j + 1] + NZ[3 * i + 2] * N[3 * j + 2];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
     for (int J = 0; J < 3; ++J)
-      dP[3 * i + J] = Mm[3 * i] * s.Fi[3 * J] + Mm[3 * i + 1] * s.Fi[3 * J + 1] + Mm[3 * i + 2] * s.Fi[3 * J + 2];
+      dP[3 * i + J] = NZ[3 * i] * FiN[3 * J] + NZ[3 * i + 1] * FiN[3 * J + 1] + NZ[3 * i + 2] * FiN[3 * J + 2];
   // history and local phase-field residual (eq:history-field-linearization,
   // eq:energy-displacement-linearization, eq:linearized-local-damage-residual)
   T dH = T(0);
@@ -705,20 +707,20 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
   // dL = dLcoef dphi + gp dH
   phib = s.dLcoef * Lb;
   const T Hb = s.gp * Lb;
-  // dP = Mm F^-T  ->  Mmb = Pb F^-1
-  T Mmb[9];
+  // FiN = F^-1 N (both ends, as in the forward map)
+  T FiN[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      Mmb[3 * i + k] = Pb[3 * i] * s.Fi[k] + Pb[3 * i + 1] * s.Fi[3 + k] + Pb[3 * i + 2] * s.Fi[6 + k];
-  // Mm = N Z N^T  ->  Zb = N^T Mmb N
+    for (int j = 0; j < 3; ++j)
+      FiN[3 * i + j] = s.Fi[3 * i] * N[j] + s.Fi[3 * i + 1] * N[3 + j] + s.Fi[3 * i + 2] * N[6 + j];
+  // dP = (N Z) FiN^T  ->  Zb = N^T (Pb FiN)
   T Zt[9], Zb[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      Zt[3 * i + j] = Mmb[3 * i] * N[j] + Mmb[3 * i + 1] * N[3 + j] + Mmb[3 * i + 2] * N[6 + j];
+      Zt[3 * i + j] = Pb[3 * i] * FiN[j] + Pb[3 * i + 1] * FiN[3 + j] + Pb[3 * i + 2] * FiN[6 + j];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -774,8 +776,8 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
   const T mdeb = (deb[0] + deb[1] + deb[2]) * (T(1) / T(3));
 #pragma unroll
   for (int i = 0; i < 3; ++i) Ltb[4 * i] += (deb[i] - mdeb + dthb) * (T(2) * bd[i] * s.hinv[i]);
-  // Lt = N^T dl N  ->  dlb = N Ltb N^T
-  T R[9], dlb[9];
+  // Lt = N^T dG FiN  ->  Gb = (N Ltb) FiN^T
+  T R[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -784,14 +786,8 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      dlb[3 * i + j] = R[3 * i] * N[3 * j] + R[3 * i + 1] * N[3 * j + 1] + R[3 * i + 2] * N[3 * j + 2];
-  // dl = dG F^-1  ->  Gb = dlb F^-T
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
     for (int J = 0; J < 3; ++J)
-      Gb[3 * i + J] = dlb[3 * i] * s.Fi[3 * J] + dlb[3 * i + 1] * s.Fi[3 * J + 1] + dlb[3 * i + 2] * s.Fi[3 * J + 2];
+      Gb[3 * i + J] = R[3 * i] * FiN[3 * J] + R[3 * i + 1] * FiN[3 * J + 1] + R[3 * i + 2] * FiN[3 * J + 2];
 }
 
 }  // namespace pfmf

@@ -91,6 +91,10 @@ MeshDev mesh_dev(const pf_ctx* c) {
   m.hx = c->mesh.lx / c->mesh.nx;
   m.hy = c->mesh.ly / c->mesh.ny;
   m.hz = c->mesh.lz / c->mesh.nz;
+  m.ih[0] = 2.0 / m.hx;
+  m.ih[1] = 2.0 / m.hy;
+  m.ih[2] = 2.0 / m.hz;
+  m.jdet = m.hx * m.hy * m.hz * 0.125;
   return m;
 }
 
