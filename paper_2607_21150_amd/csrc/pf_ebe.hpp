@@ -4,8 +4,9 @@
 // operator: its element matrix K_e[r][c] (r, c = field * 8 + node, 32 x 32) is the
 // fine-quadrature sum of the pointwise tangent tested and tried with the order-1
 // basis. It is assembled once per linearisation from the FP32 record and then
-// applied element by element: the same operator as the matrix-free level apply at
-// the fine quadrature, at a fraction of its cost.
+// summed into a 27-point block stencil (4 x 4 blocks per neighbour), which the
+// smoother applies: the same operator as the matrix-free level apply at the fine
+// quadrature, at a fraction of its cost.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -26,19 +27,20 @@ struct EbeArgs {
   int nph;
   FracParams<float> fr;
   float* K;             // [n_elem][32][32]
-  const float* x;       // level vector (apply)
-  float* out;           // level vector
 };
 
-// One workgroup per element. Threads q < Q^3 evaluate the tangent of their point on
-// the 10 unit directions (dG_ij, dphi) into LDS; then every thread sums 4 entries of
-// the element matrix over the points.
+// One workgroup per element. The threads evaluate the tangent of the points on the
+// 10 unit directions (dG_ij, dphi) into LDS; the element matrix is then the
+// point sum of (test basis) x tangent x (trial basis), contracted in two steps.
 template <int PF>
 __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __restrict__ tabs) {
   constexpr int Q = PF, Q3 = Q * Q * Q, P3 = PF * PF * PF;
   __shared__ float ub[3 * P3];      // fine u of the element
   __shared__ float Cq[Q3][101];     // tangent columns (10 x 10) and wdet per point
   __shared__ float Bf[Q * PF], Df[Q * PF], B1[Q * 2], D1[Q * 2], wq[Q];
+  constexpr int QC = 8;              // points per chunk of the second contraction
+  __shared__ float Nq[Q3][8], Gq[Q3][8][3], kq[Q3];
+  __shared__ float Tq[QC][10][32];
   const int64_t e = blockIdx.x;
   const int ex = (int)(e % a.m.nx), ey = (int)((e / a.m.nx) % a.m.ny), ez = (int)(e / ((int64_t)a.m.nx * a.m.ny));
   const int t = threadIdx.x;
@@ -61,7 +63,12 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
   __syncthreads();
   const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
   const float jdet = (float)a.m.jdet;
-  for (int q = t; q < Q3; q += NT) {
+  // NG thread groups per point share its 10 tangent directions (each recomputes G and
+  // the point state)
+  constexpr int NG = (NT / Q3) < 10 ? (NT / Q3) : 10;
+  static_assert(NG >= 1, "a point per thread");
+  if (t < NG * Q3) {
+    const int q = t % Q3, grp = t / Q3;
     const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
     float G[9];
 #pragma unroll
@@ -89,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
     QPState<float> s;
     qp_state_lin<float>(mp, G, rc, s);
-    for (int in = 0; in < 10; ++in) {
+    for (int in = grp; in < 10; in += NG) {
       float dG[9], dP[9], dL;
 #pragma unroll
       for (int k = 0; k < 9; ++k) dG[k] = (k == in) ? 1.f : 0.f;
@@ -98,84 +105,139 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
       for (int o = 0; o < 9; ++o) Cq[q][o * 10 + in] = dP[o];
       Cq[q][90 + in] = dL;
     }
-    Cq[q][100] = wq[qx] * wq[qy] * wq[qz] * jdet;
+    if (grp == 0) Cq[q][100] = wq[qx] * wq[qy] * wq[qz] * jdet;
   }
-  __syncthreads();
-  for (int r0 = t; r0 < 1024; r0 += NT) {
-    const int r = r0 >> 5, c = r0 & 31;
-    const int f = r >> 3, na = r & 7, g = c >> 3, nb = c & 7;
-    const int ax = na & 1, ay = (na >> 1) & 1, az = na >> 2;
+  // order-1 basis at the points (values and physical gradients) and the fracture
+  // gradient coefficient of each point's phase
+  for (int i = t; i < Q3 * 8; i += NT) {
+    const int q = i >> 3, nb = i & 7;
+    const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
     const int bx = nb & 1, by = (nb >> 1) & 1, bz = nb >> 2;
-    float acc = 0.f;
-    for (int q = 0; q < Q3; ++q) {
-      const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
-      const float Na = B1[qx * 2 + ax] * B1[qy * 2 + ay] * B1[qz * 2 + az];
-      const float ga[3] = {D1[qx * 2 + ax] * B1[qy * 2 + ay] * B1[qz * 2 + az] * ih[0],
-                           B1[qx * 2 + ax] * D1[qy * 2 + ay] * B1[qz * 2 + az] * ih[1],
-                           B1[qx * 2 + ax] * B1[qy * 2 + ay] * D1[qz * 2 + az] * ih[2]};
-      const float Nb = B1[qx * 2 + bx] * B1[qy * 2 + by] * B1[qz * 2 + bz];
-      const float gb[3] = {D1[qx * 2 + bx] * B1[qy * 2 + by] * B1[qz * 2 + bz] * ih[0],
-                           B1[qx * 2 + bx] * D1[qy * 2 + by] * B1[qz * 2 + bz] * ih[1],
-                           B1[qx * 2 + bx] * B1[qy * 2 + by] * D1[qz * 2 + bz] * ih[2]};
+    const float vx = B1[qx * 2 + bx], vy = B1[qy * 2 + by], vz = B1[qz * 2 + bz];
+    Nq[q][nb] = vx * vy * vz;
+    Gq[q][nb][0] = D1[qx * 2 + bx] * vy * vz * ih[0];
+    Gq[q][nb][1] = vx * D1[qy * 2 + by] * vz * ih[1];
+    Gq[q][nb][2] = vx * vy * D1[qz * 2 + bz] * ih[2];
+  }
+  for (int q = t; q < Q3; q += NT) {
+    const int pid = a.phase[e * Q3 + q];
+    kq[q] = a.fr.kf * a.mats[pid < a.nph ? pid : 0].Gc;
+  }
+  // Each thread owns row node na = t / 32 and column c = t % 32 (field g, node nb) for
+  // the four row fields. Per chunk of points: T[q][i][c] = tangent row i applied to the
+  // column's trial function, then K[f na][c] += wdet grad N_na . T[q][3f..3f+2][c]
+  // (f < 3) and wdet (s_phi N_na T[q][9][c] + kf Gc grad N_na . grad N_nb [g = 3]).
+  static_assert(NT == 256, "one thread per (row node, column)");
+  const int na = t >> 5, c = t & 31, g = c >> 3, nbc = c & 7;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+  for (int q0 = 0; q0 < Q3; q0 += QC) {
+    const int nq = Q3 - q0 < QC ? Q3 - q0 : QC;
+#pragma unroll 1
+    for (int i = t; i < nq * 320; i += NT) {
+      const int qq = i / 320, rem = i - qq * 320, row = rem >> 5, cc = rem & 31;
+      const int gg = cc >> 3, nb = cc & 7, q = q0 + qq;
       const float* C = Cq[q];
-      float v = 0.f;
-      if (f < 3 && g < 3) {
-#pragma unroll
-        for (int J = 0; J < 3; ++J)
-#pragma unroll
-          for (int Kk = 0; Kk < 3; ++Kk) v += ga[J] * C[(3 * f + J) * 10 + 3 * g + Kk] * gb[Kk];
-      } else if (f < 3) {
-#pragma unroll
-        for (int J = 0; J < 3; ++J) v += ga[J] * C[(3 * f + J) * 10 + 9] * Nb;
-      } else if (g < 3) {
-#pragma unroll
-        for (int Kk = 0; Kk < 3; ++Kk) v += Na * a.fr.s_phi * C[90 + 3 * g + Kk] * gb[Kk];
-      } else {
-        const int64_t gq = e * Q3 + q;
-        const int pid = a.phase[gq];
-        const float kf = a.fr.kf * a.mats[pid < a.nph ? pid : 0].Gc;
-        v = Na * a.fr.s_phi * C[99] * Nb + kf * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
-      }
-      acc += C[100] * v;
+      float v;
+      if (gg < 3)
+        v = C[row * 10 + 3 * gg] * Gq[q][nb][0] + C[row * 10 + 3 * gg + 1] * Gq[q][nb][1] +
+            C[row * 10 + 3 * gg + 2] * Gq[q][nb][2];
+      else
+        v = C[row * 10 + 9] * Nq[q][nb];
+      Tq[qq][row][cc] = v;
     }
-    a.K[e * 1024 + r0] = acc;
+    __syncthreads();
+    {
+#pragma unroll 2
+      for (int qq = 0; qq < nq; ++qq) {
+        const int q = q0 + qq;
+        const float w = Cq[q][100];
+        const float g0 = Gq[q][na][0], g1 = Gq[q][na][1], g2 = Gq[q][na][2];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+          acc[f] += w * (g0 * Tq[qq][3 * f][c] + g1 * Tq[qq][3 * f + 1][c] + g2 * Tq[qq][3 * f + 2][c]);
+        float v = a.fr.s_phi * Nq[q][na] * Tq[qq][9][c];
+        if (g == 3) v += kq[q] * (g0 * Gq[q][nbc][0] + g1 * Gq[q][nbc][1] + g2 * Gq[q][nbc][2]);
+        acc[3] += w * v;
+      }
+    }
+    __syncthreads();
+  }
+  {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) a.K[e * 1024 + (f * 8 + na) * 32 + c] = acc[f];
   }
 }
 
-// Apply (MODE 0: out = K x) or diagonal (MODE 1: out = diag K) of the order-1 level,
-// brick-coloured like the other level kernels; thread = (element slot, row).
-template <int MODE>
-__global__ __launch_bounds__(NT) void k_ebe_apply(EbeArgs a, int colour) {
-  __shared__ float xe[8][32];
-  __shared__ float ev[8 * 4 * 8];
-  const int brick = xcd_brick(a.m, colour, blockIdx.x);
-  if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = decode_brick(a.m, colour, brick);
-  const int t = threadIdx.x;
-  const int slot = t >> 5, r = t & 31;
-  const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
-  const bool active = sx < g.nex && sy < g.ney && sz < g.nez;
-  const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
-  if (MODE == 0 && active) {
-    const int f = r >> 3, n = r & 7;
-    const int64_t gi = (int64_t)(g.ex0 + sx + (n & 1)) +
-                       (int64_t)a.lev.nx1 * ((g.ey0 + sy + ((n >> 1) & 1)) + (int64_t)a.lev.ny1 * (g.ez0 + sz + (n >> 2)));
-    xe[slot][r] = a.x[f * a.lev.n_nodes + gi];
-  }
-  __syncthreads();
-  if (active) {
-    const float* Kr = a.K + e * 1024 + r * 32;
-    float acc = 0.f;
-    if (MODE == 0) {
-#pragma unroll 8
-      for (int c = 0; c < 32; ++c) acc += Kr[c] * xe[slot][c];
-    } else {
-      acc = Kr[r];
+// The order-1 level as a 27-point block stencil: S[o][f][g][i] couples field f of
+// node i with field g of node i + o, o = (dx + 1) + 3 (dy + 1) + 9 (dz + 1). Each
+// entry sums the matching element-matrix entries over the (up to 8) elements that
+// hold both nodes, in a fixed order, so the result is deterministic. One thread per
+// (offset, node), nodes fastest.
+__global__ __launch_bounds__(NT) void k_stencil_from_ebe(const float* __restrict__ K, int nx, int ny, int nz,
+                                                         int64_t n_nodes, float* __restrict__ S) {
+  const int nx1 = nx + 1, ny1 = ny + 1;
+  const int64_t n_all = 27 * n_nodes;
+  for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n_all; t += (int64_t)gridDim.x * NT) {
+    const int o = (int)(t / n_nodes);
+    const int64_t i = t - (int64_t)o * n_nodes;
+    const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
+    const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
+    float acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+#pragma unroll
+    for (int na = 0; na < 8; ++na) {
+      const int ax = na & 1, ay = (na >> 1) & 1, az = na >> 2;
+      const int bx = ax + dx, by = ay + dy, bz = az + dz;
+      const int ex = ix - ax, ey = iy - ay, ez = iz - az;
+      if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+      if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+      const int nb = bx + 2 * by + 4 * bz;
+      const float* Ke = K + ((int64_t)ex + (int64_t)nx * (ey + (int64_t)ny * ez)) * 1024;
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[4 * f + g] += Ke[(f * 8 + na) * 32 + g * 8 + nb];
     }
-    ev[(slot * 4 + (r >> 3)) * 8 + (r & 7)] = acc;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) S[((int64_t)o * 16 + k) * n_nodes + i] = acc[k];
   }
-  __syncthreads();
-  scatter_brick<float, 2, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+}
+
+// Apply (MODE 0: out = S x) or diagonal (MODE 1) of the stencil; one thread per
+// (node, output field), blockIdx.y = field. Reads of S are coalesced over nodes.
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_stencil_apply(const float* __restrict__ S, int nx1, int ny1, int nz1,
+                                                      int64_t n, const float* __restrict__ x,
+                                                      float* __restrict__ out) {
+  const int f = blockIdx.y;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+    if (MODE == 1) {
+      out[f * n + i] = S[((int64_t)13 * 16 + 5 * f) * n + i];
+      continue;
+    }
+    const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
+    float acc = 0.f;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      if (iz + dz < 0 || iz + dz >= nz1) continue;
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (iy + dy < 0 || iy + dy >= ny1) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          if (ix + dx < 0 || ix + dx >= nx1) continue;
+          const int o = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+          const int64_t j = i + dx + (int64_t)nx1 * (dy + (int64_t)ny1 * dz);
+          const float* So = S + ((int64_t)o * 16 + 4 * f) * n + i;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) acc += So[g * n] * x[g * n + j];
+        }
+      }
+    }
+    out[f * n + i] = acc;
+  }
 }
 
 }  // namespace pfmf

@@ -53,6 +53,7 @@ struct MGState {
   float* tmpB = nullptr;
   double* red = nullptr;  // reduction scratch
   float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
+  float* stencil = nullptr;  // the same level as a block stencil [27][4][4][n_nodes]
   int ebe_level = -1;
   bool linearized = false;
 };
@@ -78,6 +79,7 @@ inline void mg_free(MGState& mg) {
   (void)hipFree(mg.tmpB);
   (void)hipFree(mg.red);
   (void)hipFree(mg.ebe);
+  (void)hipFree(mg.stencil);
   mg = MGState();
 }
 

@@ -97,7 +97,8 @@ pf_status mg_alloc(pf_ctx* c) {
   }
   if (mg.lv[mg.n_levels - 1].p == 1) {
     const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
-    if (hipMalloc(&mg.ebe, (size_t)n_elem * 1024 * sizeof(float)) != hipSuccess)
+    if (hipMalloc(&mg.ebe, (size_t)n_elem * 1024 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&mg.stencil, (size_t)27 * 16 * mg.lv[mg.n_levels - 1].n_nodes * sizeof(float)) != hipSuccess)
       return fail(PF_ENOMEM, "coarse element matrices: allocation failed");
     mg.ebe_level = mg.n_levels - 1;
   }
@@ -187,7 +188,7 @@ pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
   return PF_OK;
 }
 
-EbeArgs ebe_args(pf_ctx* c, const float* x, float* out) {
+EbeArgs ebe_args(pf_ctx* c) {
   EbeArgs a;
   a.m = mesh_dev(c);
   const MGLevel& F = c->mg.lv[0];
@@ -202,13 +203,11 @@ EbeArgs ebe_args(pf_ctx* c, const float* x, float* out) {
   a.nph = (int)c->phases.size();
   a.fr = frac_params<float>(c->fr);
   a.K = c->mg.ebe;
-  a.x = x;
-  a.out = out;
   return a;
 }
 
 pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
-  const EbeArgs a = ebe_args(c, nullptr, nullptr);
+  const EbeArgs a = ebe_args(c);
   const int n_elem = c->mesh.nx * c->mesh.ny * c->mesh.nz;
   switch (c->mg.lv[0].P) {
     case 2: hipLaunchKernelGGL(k_ebe_assemble<2>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
@@ -218,18 +217,22 @@ pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
     default: return fail(PF_EUNSUPPORTED, "order not built");
   }
   HIPCHK(hipGetLastError());
+  const MGLevel& L = c->mg.lv[c->mg.ebe_level];
+  const int64_t nall = 27 * L.n_nodes;
+  const int nb = (int)std::min<int64_t>((nall + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_stencil_from_ebe, dim3(nb), dim3(NT), 0, s, c->mg.ebe, c->mesh.nx, c->mesh.ny, c->mesh.nz,
+                     L.n_nodes, c->mg.stencil);
+  HIPCHK(hipGetLastError());
   return PF_OK;
 }
 
 template <int MODE>
 pf_status ebe_apply(pf_ctx* c, const float* x, float* out, hipStream_t s) {
-  const EbeArgs a = ebe_args(c, x, out);
-  for (int col = 0; col < 8; ++col) {
-    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
-    if (nb == 0) continue;
-    hipLaunchKernelGGL(k_ebe_apply<MODE>, dim3(nb), dim3(NT), 0, s, a, col);
-    HIPCHK(hipGetLastError());
-  }
+  const MGLevel& L = c->mg.lv[c->mg.ebe_level];
+  const int nb = (int)std::min<int64_t>((L.n_nodes + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_stencil_apply<MODE>, dim3(nb, 4), dim3(NT), 0, s, c->mg.stencil, L.nx1, L.ny1, L.nz1,
+                     L.n_nodes, x, out);
+  HIPCHK(hipGetLastError());
   return PF_OK;
 }
 

@@ -133,22 +133,34 @@ def test_restriction_is_prolongation_transpose_and_matches_numpy(pf):
         assert relerr(Rr, refr) <= 1e-6
 
 
-def test_coarse_operator_is_galerkin_product(pf, oracle_lib):
+@pytest.mark.parametrize("level", [1, 2])
+def test_coarse_operator_is_galerkin_product(pf, oracle_lib, level):
     """A_c = P^T A_f P (coarse levels share the fine quadrature and record); checked against the
-    FP64 oracle's fine Jacobian with a numpy prolongation."""
+    FP64 oracle's fine Jacobian with a numpy prolongation. Level 2 is the order-1 level, which is
+    assembled from element matrices into a block stencil."""
     d = I.make_inputs("C1", "plastic", p=3, n=3)
     ctx = lin_ctx(pf, d)
     m = d["mesh"]
     orc = oracle_lib.Oracle.from_inputs(d)
     rng = np.random.default_rng(1)
-    _, n1 = ctx.level_info(1)
-    xc = rng.standard_normal((4, n1))
-    yc = ctx.apply_jacobian_f32(1, dev(xc, torch.float32)).cpu().numpy()
-    Pxc, _ = prolong_np(xc, m.nx, m.p, m.p - 1)
-    ref = restrict_np(orc.jacobian(d["z"], Pxc), m.nx, m.p, m.p - 1)
+    _, nl = ctx.level_info(level)
+    xc = rng.standard_normal((4, nl))
+    yc = ctx.apply_jacobian_f32(level, dev(xc, torch.float32)).cpu().numpy()
+    Pxc = xc
+    for q in range(m.p - level, m.p):
+        Pxc, _ = prolong_np(Pxc, m.nx, q + 1, q)
+    ref = orc.jacobian(d["z"], Pxc)
+    for q in range(m.p, m.p - level, -1):
+        ref = restrict_np(ref, m.nx, q, q - 1)
     assert relerr(yc, ref) <= FP32_TOL, relerr(yc, ref)
     # and on the GPU alone: R A_f P x vs A_c x
-    y2 = ctx.restrict(0, ctx.apply_jacobian_f32(0, ctx.prolong(0, dev(xc, torch.float32)))).cpu().numpy()
+    v = dev(xc, torch.float32)
+    for l in range(level - 1, -1, -1):
+        v = ctx.prolong(l, v)
+    v = ctx.apply_jacobian_f32(0, v)
+    for l in range(level):
+        v = ctx.restrict(l, v)
+    y2 = v.cpu().numpy()
     assert relerr(yc, y2) <= FP32_TOL
 
 
