@@ -188,6 +188,17 @@ pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
   return PF_OK;
 }
 
+template <int PC>
+pf_status launch_a32_q4(pf_ctx* c, const A32Args& a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
+    if (ng == 0) continue;
+    hipLaunchKernelGGL((k_a32_q4<PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
 EbeArgs ebe_args(pf_ctx* c) {
   EbeArgs a;
   a.m = mesh_dev(c);
@@ -241,6 +252,15 @@ pf_status level_op_raw(pf_ctx* c, int level, const float* dz, float* out, hipStr
   if (level == c->mg.ebe_level && c->mg.ebe) return ebe_apply<MODE>(c, dz, out, s);
   const A32Args a = a32_args(c, level, dz, out);
   const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
+  if (MODE == 0 && PF == 5) {
+    switch (PC) {
+      case 5: return launch_a32_q4<5>(c, a, s);
+      case 4: return launch_a32_q4<4>(c, a, s);
+      case 3: return launch_a32_q4<3>(c, a, s);
+      case 2: return launch_a32_q4<2>(c, a, s);
+      default: break;
+    }
+  }
   if (MODE == 0 && PF == 4) {
     switch (PC) {
       case 4: return launch_a32_q3<4>(c, a, s);

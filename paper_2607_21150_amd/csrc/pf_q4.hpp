@@ -1,0 +1,465 @@
+// Order-4 elements (5 nodes and 5 Gauss points per direction): FP64 operator
+// kernels and the FP32 multigrid level apply.
+//
+// One element per 128-thread workgroup. Elements are launched in 8 colours by the
+// parity of their coordinates; elements of one colour share no node, and a node is
+// stored by the first colour that touches it and accumulated by the later ones, so
+// the scatter-add is deterministic without atomics.
+//
+// Sum factorisation (Section 4, B_I and B_xi) runs on up to four fields at once in
+// row layout: a pass contracts one direction, and each thread owns one (field, row)
+// of the element, holds the row's P inputs in registers and produces all Q outputs
+// along it. Per field that is P (or Q) LDS reads per Q outputs, against P reads per
+// output when each thread owns one output. The passes run x, y, z forward and z, y,
+// x backward, ping-ponging two LDS buffers; the pointwise function then runs with one
+// thread per quadrature point (125 of the 128 threads). The 1-D tables are read with
+// compile-time indices, so they live in scalar registers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pf_brick.hpp"
+#include "pf_mg.hpp"
+#include "pf_ops.hpp"
+#include "pf_qf.hpp"
+
+namespace pfmf {
+
+constexpr int NT5 = 128;  // threads per workgroup (one element)
+
+// Element of colour `colour` for workgroup id (XCD-aware order as for bricks: one
+// colour's elements of an x-row run on one XCD back to back); -1 for padding.
+struct ElemGeom {
+  int ex, ey, ez;
+};
+__device__ inline bool xcd_elem(const MeshDev& m, int colour, int id, ElemGeom& g) {
+  const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
+  const int CX = (m.nx - cx + 1) / 2, CY = (m.ny - cy + 1) / 2, CZ = (m.nz - cz + 1) / 2;
+  const int t = id >> 3;
+  const int row = (t / CX) * 8 + (id & 7);
+  if (row >= CY * CZ) return false;
+  g.ex = cx + 2 * (t % CX);
+  g.ey = cy + 2 * (row % CY);
+  g.ez = cz + 2 * (row / CY);
+  return true;
+}
+
+// Gather NF fields of the element's P^3 nodes (order P-1 lattice with nx1 x ny1
+// nodes per layer) into U[f][k][j][i].
+template <typename T, typename S, int P, int NF>
+__device__ inline void gather_elem(const S* __restrict__ src, int64_t n_nodes, int nx1, int ny1, const ElemGeom& g,
+                                   T* U) {
+  constexpr int p = P - 1, P3 = P * P * P;
+  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
+    const int f = t / P3, n = t - f * P3;
+    const int i = n % P, j = (n / P) % P, k = n / (P * P);
+    const int64_t gi = (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
+    U[t] = (T)src[f * n_nodes + gi];
+  }
+}
+
+// Add the element vector R[f][k][j][i] into dst with the colour rule.
+template <typename T, int P, int NF>
+__device__ inline void scatter_elem(const T* R, const MeshDev& m, int nx1, int ny1, int64_t n_nodes,
+                                    const ElemGeom& g, T* __restrict__ dst) {
+  constexpr int p = P - 1, P3 = P * P * P;
+  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
+    const int f = t / P3, n = t - f * P3;
+    const int i = n % P, j = (n / P) % P, k = n / (P * P);
+    const bool shx = (i == 0 && g.ex > 0) || (i == p && g.ex < m.nx - 1);
+    const bool shy = (j == 0 && g.ey > 0) || (j == p && g.ey < m.ny - 1);
+    const bool shz = (k == 0 && g.ez > 0) || (k == p && g.ez < m.nz - 1);
+    const bool store = !((shx && (g.ex & 1)) || (shy && (g.ey & 1)) || (shz && (g.ez & 1)));
+    const int64_t gi = (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
+    T* d = dst + f * n_nodes + gi;
+    if (store) *d = R[t];
+    else *d += R[t];
+  }
+}
+
+// Forward: U[f][k][j][i] (P^3 per field) -> Qo[f][c][qz][qy][qx] (Q^3 per field and
+// component c = value, d/dxi_x, d/dxi_y, d/dxi_z). X holds 2 NF P^2 Q values, Y
+// (aliasing U) 3 NF Q^2 P. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF>
+__device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb) {
+  constexpr int P2 = P * P, P3 = P2 * P, Q3 = Q * Q * Q;
+  const int t = threadIdx.x;
+  // x: thread (f, j, k); X[f][c][k][j][qx], c = B_x, D_x
+  if (t < NF * P2) {
+    const int f = t / P2, r = t - f * P2;
+    T u[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = UY[f * P3 + r * P + i];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T b = T(0), d = T(0);
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        b += (T)tb->B[P][Q][q][i] * u[i];
+        d += (T)tb->D[P][Q][q][i] * u[i];
+      }
+      XQ[(2 * f) * P2 * Q + r * Q + q] = b;
+      XQ[(2 * f + 1) * P2 * Q + r * Q + q] = d;
+    }
+  }
+  __syncthreads();
+  // y: thread (f, qx, k); Y[f][c][qy][qx][k], c = B_y B_x, D_y B_x, B_y D_x
+  if (t < NF * Q * P) {
+    const int f = t / (Q * P), s = t - f * (Q * P);
+    const int qx = s % Q, k = s / Q;
+    T xb[P], xd[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      xb[j] = XQ[(2 * f) * P2 * Q + (j + P * k) * Q + qx];
+      xd[j] = XQ[(2 * f + 1) * P2 * Q + (j + P * k) * Q + qx];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T bb = T(0), db = T(0), bd = T(0);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        bb += (T)tb->B[P][Q][q][j] * xb[j];
+        db += (T)tb->D[P][Q][q][j] * xb[j];
+        bd += (T)tb->B[P][Q][q][j] * xd[j];
+      }
+      const int o = (qx + Q * q) * P + k;
+      UY[(3 * f) * Q * Q * P + o] = bb;
+      UY[(3 * f + 1) * Q * Q * P + o] = db;
+      UY[(3 * f + 2) * Q * Q * P + o] = bd;
+    }
+  }
+  __syncthreads();
+  // z: thread (f, qx, qy); Qo[f][c][q]
+  if (t < NF * Q * Q) {
+    const int f = t / (Q * Q), s = t - f * (Q * Q);
+    T yb[P], yd[P], yx[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      yb[k] = UY[(3 * f) * Q * Q * P + s * P + k];
+      yd[k] = UY[(3 * f + 1) * Q * Q * P + s * P + k];
+      yx[k] = UY[(3 * f + 2) * Q * Q * P + s * P + k];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T v = T(0), dz = T(0), dy = T(0), dx = T(0);
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const T bz = (T)tb->B[P][Q][q][k];
+        v += bz * yb[k];
+        dz += (T)tb->D[P][Q][q][k] * yb[k];
+        dy += bz * yd[k];
+        dx += bz * yx[k];
+      }
+      const int o = s + Q * Q * q;
+      XQ[(4 * f) * Q3 + o] = v;
+      XQ[(4 * f + 1) * Q3 + o] = dx;
+      XQ[(4 * f + 2) * Q3 + o] = dy;
+      XQ[(4 * f + 3) * Q3 + o] = dz;
+    }
+  }
+  __syncthreads();
+}
+
+// Transposed: Qi[f][c][q] (c = value test, tests against d/dxi_x, d/dxi_y, d/dxi_z;
+// in XQ) -> R[f][k][j][i] (in ZR). Z (in ZR) holds 3 NF P Q^2 values, Y (in XQ)
+// 2 NF P^2 Q. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF>
+__device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb) {
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+  const int t = threadIdx.x;
+  // z^T: thread (f, qx, qy); Z[f][c][k][qy][qx], c = value chain, x tests, y tests
+  T z0[P], zx[P], zy[P];
+  const bool az = t < NF * Q2;
+  if (az) {
+    const int f = t / Q2, s = t - f * Q2;
+#pragma unroll
+    for (int k = 0; k < P; ++k) z0[k] = zx[k] = zy[k] = T(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int o = s + Q2 * q;
+      const T f0 = XQ[(4 * f) * Q3 + o], fx = XQ[(4 * f + 1) * Q3 + o];
+      const T fy = XQ[(4 * f + 2) * Q3 + o], fz = XQ[(4 * f + 3) * Q3 + o];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const T bz = (T)tb->B[P][Q][q][k];
+        z0[k] += bz * f0 + (T)tb->D[P][Q][q][k] * fz;
+        zx[k] += bz * fx;
+        zy[k] += bz * fy;
+      }
+    }
+  }
+  // Z aliases nothing that is still read: ZR is free until here
+  if (az) {
+    const int f = t / Q2, s = t - f * Q2;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      ZR[(3 * f) * P * Q2 + k * Q2 + s] = z0[k];
+      ZR[(3 * f + 1) * P * Q2 + k * Q2 + s] = zx[k];
+      ZR[(3 * f + 2) * P * Q2 + k * Q2 + s] = zy[k];
+    }
+  }
+  __syncthreads();
+  // y^T: thread (f, qx, k); Y[f][c][k][j][qx], c = value chain, x tests
+  if (t < NF * Q * P) {
+    const int f = t / (Q * P), s = t - f * (Q * P);
+    const int qx = s % Q, k = s / Q;
+    T a0[P], ax[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) a0[j] = ax[j] = T(0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int o = k * Q2 + q * Q + qx;
+      const T v0 = ZR[(3 * f) * P * Q2 + o], vx = ZR[(3 * f + 1) * P * Q2 + o], vy = ZR[(3 * f + 2) * P * Q2 + o];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const T by = (T)tb->B[P][Q][q][j];
+        a0[j] += by * v0 + (T)tb->D[P][Q][q][j] * vy;
+        ax[j] += by * vx;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      XQ[(2 * f) * P2 * Q + (j + P * k) * Q + qx] = a0[j];
+      XQ[(2 * f + 1) * P2 * Q + (j + P * k) * Q + qx] = ax[j];
+    }
+  }
+  __syncthreads();
+  // x^T: thread (f, j, k); R[f][k][j][i]
+  if (t < NF * P2) {
+    const int f = t / P2, r = t - f * P2;
+    T y0[Q], yx[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      y0[q] = XQ[(2 * f) * P2 * Q + r * Q + q];
+      yx[q] = XQ[(2 * f + 1) * P2 * Q + r * Q + q];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      T a = T(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][i] * y0[q] + (T)tb->D[P][Q][q][i] * yx[q];
+      ZR[f * P3 + r * P + i] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// LDS sizes (values) of the two buffers for up to 4 fields.
+template <int P, int Q> struct Q5Lds {
+  static constexpr int a0 = 4 * P * P * P, a1 = 12 * Q * Q * P;
+  static constexpr int A = a0 > a1 ? a0 : a1;  // U / Y (forward), Z / R (backward)
+  static constexpr int b0 = 8 * P * P * Q, b1 = 16 * Q * Q * Q;
+  static constexpr int B = b0 > b1 ? b0 : b1;  // X / Qo (forward), Qi / Y (backward)
+};
+
+// FP64 residual / Jacobian / adjoint on order-4 elements.
+template <int MODE>
+__global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+  constexpr int P = 5, Q = 5, Q3 = 125;
+  using L = Q5Lds<P, Q>;
+  __shared__ double bufA[L::A];
+  __shared__ double bufB[L::B];
+  __shared__ double red[2 * 3 * 8];
+  ElemGeom g;
+  if (!xcd_elem(a.m, colour, blockIdx.x, g)) return;  // padding workgroup (uniform)
+  const int t = threadIdx.x;
+  const bool pt = t < Q3;
+  const int ql = pt ? t : 0;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
+  const int64_t gq = e * Q3 + ql;
+  // per-point state, issued before the gathers
+  double st[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) st[k] = pt ? a.state[k * a.n_q + gq] : 0.0;
+  const int pid = pt ? a.phase[gq] : 0;
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
+  const double wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * a.m.jdet;
+  gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
+  __syncthreads();
+  sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
+  double G[9], phi, gphi[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  phi = bufB[12 * Q3 + ql];
+#pragma unroll
+  for (int J = 0; J < 3; ++J) gphi[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
+  double phin = 0.0;
+  __syncthreads();
+  if (MODE == M_RES) {
+    gather_elem<double, double, P, 1>(a.phin, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    __syncthreads();
+    sf5_fwd<double, DevTables, P, Q, 1>(bufA, bufB, tabs);
+    phin = bufB[ql];
+    __syncthreads();
+  }
+  const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+  QPState<double> s;
+  qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+  const bool bad = pt && s.bad;
+  double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
+  if (MODE != M_RES) {
+    gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    __syncthreads();
+    sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) W[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+    wphi = bufB[12 * Q3 + ql];
+#pragma unroll
+    for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
+    __syncthreads();
+  }
+  const double kfg = a.fr.kf * mp.Gc;
+  double Fu[9], f0, f1[3];
+  double gsum[3] = {0.0, 0.0, 0.0};
+  if (MODE == M_RES) {
+    piola<double>(s, Fu);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+    f0 = wdet * a.fr.s_phi * s.L;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
+  } else if (MODE == M_JAC) {
+    double dL;
+    qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+    f0 = wdet * a.fr.s_phi * dL;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gw[J];
+  } else {
+    double Pb[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
+    const double f0b = wdet * wphi;
+    const double Lb = a.fr.s_phi * f0b;
+    double phib, Xd[3];
+    qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
+    f0 = phib;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
+    const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
+    gsum[0] = alpha_p * a.fr.inv_c0l0 * Lb + a.fr.kf * wdet * (gphi[0] * gw[0] + gphi[1] * gw[1] + gphi[2] * gw[2]);
+    if (s.plastic) {
+      const double ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
+      const double q = 2.0 * mp.mu * sqrt(1.5 * ee);
+      const double w3q = 3.0 * mp.mu / q;
+      const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
+      const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+      gsum[1] = -w3q * s.ddg_s0 * base;
+      gsum[2] = -w3q * s.ddg_visc * base;
+    }
+  }
+  // point coefficients into Qi[f][c][q] (bufB is free: every thread has read its values)
+  if (pt) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      bufB[(4 * f) * Q3 + ql] = 0.0;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) bufB[(4 * f + 1 + J) * Q3 + ql] = Fu[3 * f + J] * ih[J];
+    }
+    bufB[12 * Q3 + ql] = f0;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) bufB[(13 + J) * Q3 + ql] = f1[J] * ih[J];
+  }
+  __syncthreads();
+  sf5_bwd<double, DevTables, P, Q, 4>(bufB, bufA, tabs);
+  scatter_elem<double, P, 4>(bufA, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  if (MODE == M_ADJ) {
+    // deterministic per-phase sums of the element's point partials: a butterfly in each
+    // wave, then the two wave sums in wave order
+    const int nv = 3 * a.nph;
+    const int l = t & 63, wv = t >> 6;
+    for (int idx = 0; idx < nv; ++idx) {
+      const int ph = idx / 3, k = idx - 3 * ph;
+      const double gk = k == 0 ? gsum[0] : (k == 1 ? gsum[1] : gsum[2]);
+      double v = (pt && pid == ph) ? gk : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (l == 0 && nv <= 24) red[wv * nv + idx] = v;
+      if (nv > 24) {
+        // many phases: serialise through one LDS slot pair
+        if (l == 0) red[wv] = v;
+        __syncthreads();
+        if (t == 0) a.gpart[e * nv + idx] = red[0] + red[1];
+        __syncthreads();
+      }
+    }
+    if (nv <= 24) {
+      __syncthreads();
+      if (t < nv) a.gpart[e * nv + t] = red[t] + red[nv + t];
+    }
+  }
+  if (bad) a.flag[0] = 1;
+}
+
+// FP32 level apply (direction on a level with PC nodes per direction, kinematics on the
+// fine order-4 lattice) on order-4 fine elements.
+template <int PC>
+__global__ __launch_bounds__(NT5, 2) void k_a32_q4(A32Args a, int colour, DevTablesF* __restrict__ tabs) {
+  constexpr int PF = 5, Q = 5, Q3 = 125;
+  using L = Q5Lds<PF, Q>;
+  __shared__ float bufA[L::A];
+  __shared__ float bufB[L::B];
+  ElemGeom g;
+  if (!xcd_elem(a.m, colour, blockIdx.x, g)) return;  // padding workgroup (uniform)
+  const int t = threadIdx.x;
+  const bool pt = t < Q3;
+  const int ql = pt ? t : 0;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
+  const int64_t gq = e * Q3 + ql;
+  LinRecord rc;
+#pragma unroll
+  for (int k = 0; k < REC_N; ++k) rc.v[k] = pt ? a.rec.rec[k * a.n_q + gq] : 0.f;
+  rc.flags = pt ? a.rec.flags[gq] : 0;
+  const int pid = pt ? a.phase[gq] : 0;
+  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
+  const float wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (float)a.m.jdet;
+  gather_elem<float, float, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, bufA);
+  __syncthreads();
+  sf5_fwd<float, DevTablesF, PF, Q, 3>(bufA, bufB, tabs);
+  float G[9];
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  __syncthreads();
+  gather_elem<float, float, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
+  __syncthreads();
+  sf5_fwd<float, DevTablesF, PC, Q, 4>(bufA, bufB, tabs);
+  float W[9], wphi, gw[3];
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) W[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  wphi = bufB[12 * Q3 + ql];
+#pragma unroll
+  for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
+  __syncthreads();
+  const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
+  QPState<float> s;
+  qp_state_lin<float>(mp, G, rc, s);
+  float Fu[9], dL;
+  qp_tangent<float>(mp, s, W, wphi, Fu, dL);
+  const float kfg = a.fr.kf * mp.Gc;
+  if (pt) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      bufB[(4 * f) * Q3 + ql] = 0.f;
+#pragma unroll
+      for (int J = 0; J < 3; ++J) bufB[(4 * f + 1 + J) * Q3 + ql] = wdet * Fu[3 * f + J] * ih[J];
+    }
+    bufB[12 * Q3 + ql] = wdet * a.fr.s_phi * dL;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) bufB[(13 + J) * Q3 + ql] = wdet * kfg * gw[J] * ih[J];
+  }
+  __syncthreads();
+  sf5_bwd<float, DevTablesF, PC, Q, 4>(bufB, bufA, tabs);
+  scatter_elem<float, PC, 4>(bufA, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+}
+
+}  // namespace pfmf

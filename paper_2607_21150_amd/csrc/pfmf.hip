@@ -13,6 +13,7 @@
 #include "pf_ops.hpp"
 #include "pf_mg.hpp"
 #include "pf_mfma.hpp"
+#include "pf_q4.hpp"
 #include "pf_step.hpp"
 #include "pf_ebe.hpp"
 #include "pf_tables.hpp"
@@ -48,6 +49,7 @@ struct pf_ctx {
   int nx1 = 0, ny1 = 0, nz1 = 0;
   int64_t n_nodes = 0, n_q = 0;
   int nbx = 0, nby = 0, nbz = 0, n_bricks = 0;
+  int n_parts = 0;  // slots of the adjoint's parameter partials
   int colour_base[9] = {0};
   std::vector<pf_phase> phases;
   pf_fracture fr{};
@@ -221,12 +223,23 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
 }
 
 template <int MODE>
+pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
+    if (ng == 0) continue;
+    hipLaunchKernelGGL((k_op64_q4<MODE>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int MODE>
 pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   switch (c->mesh.p) {
     case 1: return launch_op64<MODE, 2, 2>(c, a, s);
     case 2: return launch_op64_mfma<MODE, 3>(c, a, s);
     case 3: return launch_op64_mfma<MODE, 4>(c, a, s);
-    case 4: return launch_op64<MODE, 5, 5>(c, a, s);
+    case 4: return launch_op64_q4<MODE>(c, a, s);
     default: return fail(PF_EUNSUPPORTED, "order p=%d not built", c->mesh.p);
   }
 }
@@ -301,6 +314,8 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
   c->nby = (mesh->ny + 1) / 2;
   c->nbz = (mesh->nz + 1) / 2;
   c->n_bricks = c->nbx * c->nby * c->nbz;
+  // adjoint parameter partials: one slot per brick, or per element for order 4
+  c->n_parts = mesh->p == 4 ? mesh->nx * mesh->ny * mesh->nz : c->n_bricks;
   c->colour_base[0] = 0;
   for (int col = 0; col < 8; ++col)
     c->colour_base[col + 1] = c->colour_base[col] + bricks_in_colour(c->nbx, c->nby, c->nbz, col);
@@ -314,7 +329,7 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
   if (st != PF_OK) { pf_destroy(c); return st; }
   if (hipMalloc(&c->d_mats, n_phases * sizeof(MatParams<double>)) != hipSuccess ||
       hipMalloc(&c->d_matsf, n_phases * sizeof(MatParams<float>)) != hipSuccess ||
-      hipMalloc(&c->d_gpart, (size_t)c->n_bricks * n_phases * 3 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_gpart, (size_t)c->n_parts * n_phases * 3 * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
     pf_destroy(c);
     return fail(PF_ENOMEM, "context allocation failed");
@@ -398,7 +413,7 @@ pf_status pf_apply_adjoint(pf_ctx* c, const double* z, const double* v, double* 
   st = dispatch_op64<M_ADJ>(c, a, (hipStream_t)stream);
   if (st) return st;
   hipLaunchKernelGGL(k_sum_params, dim3((int)c->phases.size() * 3), dim3(NT), 0, (hipStream_t)stream, c->d_gpart,
-                     c->n_bricks, (int)c->phases.size(), gparams);
+                     c->n_parts, (int)c->phases.size(), gparams);
   HIPCHK(hipGetLastError());
   return PF_OK;
 }

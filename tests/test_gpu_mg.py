@@ -71,7 +71,8 @@ def restrict_np(r, mesh_n, pf_order, pc_order):
 
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", None, None),
                                               ("C1", "compress", None, None), ("C1", "plastic", 3, 3),
-                                              ("C2", "plastic", 2, 6)])
+                                              ("C2", "plastic", 2, 6), ("C1", "plastic", 4, 3),
+                                              ("C1", "base", 4, 2)])
 def test_fp32_fine_apply_vs_fp64_oracle(pf, oracle_lib, name, variant, p, n):
     print(f"case {name} {variant} p={p} n={n}", flush=True)
     d = I.make_inputs(name, variant, p=p, n=n)
@@ -133,12 +134,12 @@ def test_restriction_is_prolongation_transpose_and_matches_numpy(pf):
         assert relerr(Rr, refr) <= 1e-6
 
 
-@pytest.mark.parametrize("level", [1, 2])
-def test_coarse_operator_is_galerkin_product(pf, oracle_lib, level):
+@pytest.mark.parametrize("p,level", [(3, 1), (3, 2), (4, 1), (4, 2)])
+def test_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level):
     """A_c = P^T A_f P (coarse levels share the fine quadrature and record); checked against the
     FP64 oracle's fine Jacobian with a numpy prolongation. Level 2 is the order-1 level, which is
     assembled from element matrices into a block stencil."""
-    d = I.make_inputs("C1", "plastic", p=3, n=3)
+    d = I.make_inputs("C1", "plastic", p=p, n=3 if p == 3 else 2)
     ctx = lin_ctx(pf, d)
     m = d["mesh"]
     orc = oracle_lib.Oracle.from_inputs(d)

@@ -44,6 +44,8 @@ CASES = [
     ("C1", "plastic", 1, 5),   # Q1, odd element count (ragged bricks)
     ("C1", "plastic", 3, 3),   # Q3, odd
     ("C1", "base", 4, 2),      # Q4
+    ("C1", "plastic", 4, 3),   # Q4, odd element count (element colours of unequal size)
+    ("C1", "compress", 4, 2),  # Q4, compression (history inactive)
     ("C2", "plastic", 2, 6),   # Q2, several bricks per direction
     ("C1", "plastic", 2, 5),   # Q2, odd element count (bricks with one element layer)
 ]
@@ -71,8 +73,9 @@ def test_residual_jacobian_adjoint_fp64(pf, oracle_lib, name, variant, p, n):
         assert np.abs(col - cref).max() <= 1e-11 * scale, (k, col, cref)
 
 
-def test_bitwise_deterministic(pf):
-    d = I.make_inputs("C1", "plastic", p=2, n=6)
+@pytest.mark.parametrize("p,n", [(2, 6), (4, 3)])
+def test_bitwise_deterministic(pf, p, n):
+    d = I.make_inputs("C1", "plastic", p=p, n=n)
     ctx = pf.Context.from_inputs(d)
     z, dz = dev(d["z"]), dev(d["dz"])
     a = ctx.apply_jacobian(z, dz).cpu().numpy()
