@@ -84,8 +84,8 @@ def alg_bytes(mesh, kind):
         return 72 * nodes + 65 * qps
     if kind in ("jacobian", "adjoint"):  # z, dz read, y written
         return 96 * nodes + 65 * qps
-    if kind == "fp32_apply":    # FP32 u mirror (12), dz (16), y (16) per node; record 76 + flags 1 + phase 1 per point
-        return 44 * nodes + 78 * qps
+    if kind == "fp32_apply":    # FP32 u mirror (12), dz (16), y (16) per node; record 60 + flags 1 + phase 1 per point
+        return 44 * nodes + 62 * qps
     raise ValueError(kind)
 
 

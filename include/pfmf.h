@@ -134,6 +134,21 @@ pf_status pf_linearize(pf_ctx* ctx, const double* z, void* stream);
  * is evaluated at the fine quadrature. Frees the hierarchy: call pf_linearize again. */
 pf_status pf_set_pmg_levels(pf_ctx* ctx, const int* orders, int n_levels);
 
+/* Context options (pf_set_option).
+ * PF_OPT_SCATTER: how the matrix-core applies (FP64 residual, Jacobian and adjoint on
+ * order-2 and order-3 meshes, FP32 level applies on order-3 meshes) add the element
+ * contributions into their output (the scatter-add E^T P^T of Section 4).
+ * 1 = eight colour launches by brick parity that write the output directly;
+ * 2 = one launch over all bricks that stores per-brick node sums in a context-owned
+ * buffer (allocated on first use: 4 x 7^3 values per 2x2x2-element brick, FP64 and
+ * FP32 separately), then a node gather; 0 = automatic (default): 2 while the FP64
+ * buffer stays within PF_SCATTER_AUTO_BYTES, else 1. Both are deterministic and
+ * differ only in the order of the final additions. Order-1 and order-4 meshes ignore
+ * the option (order 4 launches one element per workgroup in 8 parity colours). */
+#define PF_OPT_SCATTER 1
+#define PF_SCATTER_AUTO_BYTES (4LL << 30)
+pf_status pf_set_option(pf_ctx* ctx, int option, int value);
+
 /* Dirichlet faces for the multigrid and the Newton step: bit f of face_fields[k]
  * constrains field f (u_x, u_y, u_z, phi) on face k (x = 0, x = lx, y = 0, y = ly,
  * z = 0, z = lz) (the essential conditions of the weak form, Section 3). With faces set,

@@ -87,6 +87,34 @@ __device__ inline int xcd_brick(const MeshDev& m, int colour, int id) {
   return row < CY * CZ ? (t % CX) + CX * row : -1;
 }
 
+// All bricks in one launch (the brick-buffer scatter): the same XCD-aware order over
+// the whole brick grid. Returns the linear brick index bx + nbx (by + nby bz), or -1.
+__host__ __device__ inline int xcd_grid_all(int nbx, int nby, int nbz) {
+  const int rows = nby * nbz;
+  return ((rows + 7) / 8) * 8 * nbx;
+}
+__device__ inline int xcd_brick_all(const MeshDev& m, int id) {
+  const int t = id >> 3;
+  const int row = (t / m.nbx) * 8 + (id & 7);
+  return row < m.nby * m.nbz ? (t % m.nbx) + m.nbx * row : -1;
+}
+__device__ inline BrickGeom decode_brick_lin(const MeshDev& m, int b) {
+  BrickGeom g;
+  g.bx = b % m.nbx;
+  g.by = (b / m.nbx) % m.nby;
+  g.bz = b / (m.nbx * m.nby);
+  g.ex0 = 2 * g.bx;
+  g.ey0 = 2 * g.by;
+  g.ez0 = 2 * g.bz;
+  g.nex = min(2, m.nx - g.ex0);
+  g.ney = min(2, m.ny - g.ey0);
+  g.nez = min(2, m.nz - g.ez0);
+  g.last_x = g.bx == m.nbx - 1;
+  g.last_y = g.by == m.nby - 1;
+  g.last_z = g.bz == m.nbz - 1;
+  return g;
+}
+
 __host__ __device__ inline int bricks_in_colour(int nbx, int nby, int nbz, int colour) {
   const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
   return ((nbx - cx + 1) / 2) * ((nby - cy + 1) / 2) * ((nbz - cz + 1) / 2);

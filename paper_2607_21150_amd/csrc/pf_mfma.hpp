@@ -197,6 +197,70 @@ __device__ inline void scatter_brick4(const T* ev, const MeshDev& m, int nx1, in
   }
 }
 
+// Brick-buffer scatter, first half: the brick's node sums (same order as
+// scatter_brick4) stored unconditionally to eb[f][lz][ly][lx] (NB^3 per field).
+template <typename T, int P, int NF>
+__device__ inline void store_brick4(const T* ev, const BrickGeom& g, T* __restrict__ eb) {
+  constexpr int p = P - 1, NB = 2 * P - 1, NB3 = NB * NB * NB;
+  const int mx = g.nex * p + 1, my = g.ney * p + 1, mz = g.nez * p + 1;
+  for (int t = threadIdx.x; t < NB3; t += NT) {
+    const int lx = t % NB, ly = (t / NB) % NB, lz = t / (NB * NB);
+    if (!(lx < mx && ly < my && lz < mz)) continue;
+    T acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = T(0);
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz) {
+      const int k = lz - sz * p;
+      if (k < 0 || k > p || sz >= g.nez) continue;
+#pragma unroll
+      for (int sy = 0; sy < 2; ++sy) {
+        const int j = ly - sy * p;
+        if (j < 0 || j > p || sy >= g.ney) continue;
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const int i = lx - sx * p;
+          if (i < 0 || i > p || sx >= g.nex) continue;
+          const int slot = sx + 2 * sy + 4 * sz;
+          const int a = i + 4 * j + 16 * k;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[f] += ev[(slot * NF + f) * 64 + a];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) eb[f * NB3 + t] = acc[f];
+  }
+}
+
+// Brick-buffer scatter, second half: every node sums the stored values of the (up to
+// 8) bricks holding it, lower brick first along each axis, and stores the result.
+template <typename T, int P>
+__global__ __launch_bounds__(NT) void k_gather_bricks(const T* __restrict__ eb, MeshDev m, int nx1, int ny1,
+                                                      int64_t n_nodes, T* __restrict__ out) {
+  constexpr int p = P - 1, NB = 2 * P - 1, NB3 = NB * NB * NB, S = 2 * p;
+  for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < 4 * n_nodes; t += (int64_t)gridDim.x * NT) {
+    const int f = (int)(t / n_nodes);
+    const int64_t i = t - (int64_t)f * n_nodes;
+    const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
+    int bx[2], lx[2], by[2], ly[2], bz[2], lz[2], cx = 0, cy = 0, cz = 0;
+    if (ix % S == 0 && ix >= S) { bx[cx] = ix / S - 1; lx[cx] = S; ++cx; }
+    if (ix / S < m.nbx) { bx[cx] = ix / S; lx[cx] = ix % S; ++cx; }
+    if (iy % S == 0 && iy >= S) { by[cy] = iy / S - 1; ly[cy] = S; ++cy; }
+    if (iy / S < m.nby) { by[cy] = iy / S; ly[cy] = iy % S; ++cy; }
+    if (iz % S == 0 && iz >= S) { bz[cz] = iz / S - 1; lz[cz] = S; ++cz; }
+    if (iz / S < m.nbz) { bz[cz] = iz / S; lz[cz] = iz % S; ++cz; }
+    T acc = T(0);
+    for (int c = 0; c < cz; ++c)
+      for (int b = 0; b < cy; ++b)
+        for (int a = 0; a < cx; ++a) {
+          const int64_t brick = bx[a] + (int64_t)m.nbx * (by[b] + (int64_t)m.nby * bz[c]);
+          acc += eb[(brick * 4 + f) * NB3 + lx[a] + NB * (ly[b] + NB * lz[c])];
+        }
+    out[t] = acc;
+  }
+}
+
 // Global node of lane (x, y, z) of element slot (sx, sy, sz) of the brick; -1 if
 // the lane is outside the element's P^3 nodes.
 template <int P>
@@ -209,13 +273,14 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
 }
 
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
-template <int MODE>
+template <int MODE, bool BB>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
-  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
+  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = decode_brick(a.m, colour, brick);
+  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
   const Basis4 bs = load_basis4<4>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
@@ -393,7 +458,10 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     }
   }
   __syncthreads();
-  scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  if (BB)
+    store_brick4<double, 4, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * 4 - 1) * (2 * 4 - 1) * (2 * 4 - 1));
+  else
+    scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
 }
 
@@ -407,13 +475,14 @@ namespace pfmf {
 // then runs on a packed layout holding both elements of the wave (lanes 0-26 and
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
 // two elements.
-template <int MODE>
+template <int MODE, bool BB>
 __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
-  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
+  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = decode_brick(a.m, colour, brick);
+  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
   const Basis4 bs = load_basis_pq<3, 3>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // the wave's two elements: slot wv (sz = 0) and slot wv + 4 (sz = 1)
@@ -622,7 +691,10 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTabl
     }
   }
   __syncthreads();
-  scatter_brick4<double, 3, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  if (BB)
+    store_brick4<double, 3, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * 3 - 1) * (2 * 3 - 1) * (2 * 3 - 1));
+  else
+    scatter_brick4<double, 3, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
 }
 
@@ -633,12 +705,13 @@ namespace pfmf {
 // FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
 // level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
 // contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).
-template <int PC>
+template <int PC, bool BB>
 __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTables* __restrict__ tabs) {
   __shared__ float ev[8 * 4 * 64];
-  const int brick = xcd_brick(a.m, colour, blockIdx.x);
+  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
+  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = decode_brick(a.m, colour, brick);
+  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
   const Basis4 bf = load_basis4<4>(tabs);
   const Basis4 bc = load_basis4<PC>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -706,7 +779,10 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
     for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (float)r[f];
   }
   __syncthreads();
-  scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+  if (BB)
+    store_brick4<float, PC, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * PC - 1) * (2 * PC - 1) * (2 * PC - 1));
+  else
+    scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }
 
 }  // namespace pfmf

@@ -54,6 +54,7 @@ struct MGState {
   double* red = nullptr;  // reduction scratch
   float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
   float* stencil = nullptr;  // the same level as a block stencil [27][4][4][n_nodes]
+  float* ebuf32 = nullptr;   // brick-buffer scatter of the FP32 level applies
   int ebe_level = -1;
   bool linearized = false;
 };
@@ -80,6 +81,7 @@ inline void mg_free(MGState& mg) {
   (void)hipFree(mg.red);
   (void)hipFree(mg.ebe);
   (void)hipFree(mg.stencil);
+  (void)hipFree(mg.ebuf32);
   mg = MGState();
 }
 
@@ -197,6 +199,7 @@ struct A32Args {
   int nph;
   FracParams<float> fr;
   float* out;
+  float* ebuf;           // brick-buffer scatter: per-brick node sums [n_bricks][4][(2PC-1)^3]
 };
 
 template <int PF, int PC, int Q> struct A32Shape {

@@ -144,6 +144,7 @@ A32Args a32_args(pf_ctx* c, int level, const float* dz, float* out) {
   a.nph = (int)c->phases.size();
   a.fr = frac_params<float>(c->fr);
   a.out = out;
+  a.ebuf = nullptr;
   return a;
 }
 
@@ -178,11 +179,25 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
 }
 
 template <int PC>
-pf_status launch_a32_q3(pf_ctx* c, const A32Args& a, hipStream_t s) {
+pf_status launch_a32_q3(pf_ctx* c, A32Args a, hipStream_t s) {
+  if (use_brick_buffer(c)) {
+    // sized for the largest level (PC = 4); every level of the hierarchy shares it
+    if (!c->mg.ebuf32 && hipMalloc(&c->mg.ebuf32, (size_t)c->n_bricks * 4 * 343 * sizeof(float)) != hipSuccess)
+      return fail(PF_ENOMEM, "brick buffer: allocation failed");
+    a.ebuf = c->mg.ebuf32;
+    const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
+    hipLaunchKernelGGL((k_a32_q3<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    HIPCHK(hipGetLastError());
+    const int nb = (int)std::min<int64_t>((4 * a.lev.n_nodes + NT - 1) / NT, 65536);
+    hipLaunchKernelGGL((k_gather_bricks<float, PC>), dim3(nb), dim3(NT), 0, s, (const float*)c->mg.ebuf32, a.m,
+                       a.lev.nx1, a.lev.ny1, a.lev.n_nodes, a.out);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+  }
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_a32_q3<PC>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_a32_q3<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;

@@ -22,6 +22,7 @@ struct OpArgs {
   double* out;
   double* gpart;        // adjoint: per-brick parameter partials [n_bricks][nph][3]
   int brick_base;       // global id of this colour's first brick (for gpart)
+  double* ebuf;         // brick-buffer scatter: per-brick node sums [n_bricks][4][(2P-1)^3]
   int* flag;            // sticky non-physical flag (device)
 };
 

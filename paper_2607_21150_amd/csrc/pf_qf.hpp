@@ -59,6 +59,9 @@ __device__ inline double frsqrt(double x) {
   return fma(y, t, y);
 }
 __device__ inline float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+// exp for the FP32 record path: the hardware 2^x with a scaled argument (a few ulp)
+__device__ inline double fexp(double x) { return exp(x); }
+__device__ inline float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
 template <typename T> struct Eps;
 template <> struct Eps<double> {
@@ -451,11 +454,16 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
 // the principal frame of b_tr as a unit quaternion, the principal values b_i,
 // the principal log strains and the off-diagonal tangent factors. The FP32
 // applies recompute only F^-1 from the FP32 displacement mirror.
-constexpr int REC_N = 19;
-enum RecSlot { R_C = 0, R_KQ, R_KPHI, R_G, R_GP, R_DL, R_Q0, R_B0 = R_Q0 + 4, R_E0 = R_B0 + 3, R_O0 = R_E0 + 3 };
+// Record slots: return factor, tangent scalars, degradation and its derivative, the
+// history term's coefficient, the frame of b_tr as the three smallest components of a
+// unit quaternion (the largest, made positive, is recovered from the norm; its index is
+// in the flags), the principal trial log strains (b_i = exp(2 eps_i) is recomputed) and
+// the off-diagonal divided-difference coefficients.
+constexpr int REC_N = 15;
+enum RecSlot { R_C = 0, R_KQ, R_KPHI, R_G, R_GP, R_DL, R_Q0, R_E0 = R_Q0 + 3, R_O0 = R_E0 + 3 };
 struct LinRecord {
   float v[REC_N];
-  uint8_t flags;  // bit0 tension, bit1 history active, bit2 plastic
+  uint8_t flags;  // bit0 tension, bit1 history active, bit2 plastic, bits 3-4 dropped quaternion index
 };
 
 // Unit quaternion (w, x, y, z) of a rotation matrix R (row-major), by the
@@ -503,14 +511,19 @@ __device__ inline void record_from_state(const QPState<double>& s, LinRecord& r)
   if (det < 0.0) R[0] = -R[0], R[3] = -R[3], R[6] = -R[6];
   double q[4];
   rot_to_quat(R, q);
-  for (int k = 0; k < 4; ++k) r.v[R_Q0 + k] = (float)q[k];
+  // q and -q are the same rotation: keep the largest component positive and drop it
+  int m = 0;
+  for (int k = 1; k < 4; ++k)
+    if (fabs(q[k]) > fabs(q[m])) m = k;
+  const double sg = q[m] < 0.0 ? -1.0 : 1.0;
+  for (int k = 0, o = 0; k < 4; ++k)
+    if (k != m) r.v[R_Q0 + o++] = (float)(sg * q[k]);
   const double th3 = s.theta * (1.0 / 3.0);
   for (int i = 0; i < 3; ++i) {
-    r.v[R_B0 + i] = (float)s.bd[i];
     r.v[R_E0 + i] = (float)(s.e[i] + th3);
     r.v[R_O0 + i] = (float)s.coef[i];
   }
-  r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0);
+  r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0) | (m << 3);
 }
 
 // New per-point state after a converged step (Section 2): the elastic log strain
@@ -569,8 +582,15 @@ __device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const Lin
   s.Fi[2] = (F[1] * F[5] - F[2] * F[4]) * idet;
   s.Fi[5] = (F[2] * F[3] - F[0] * F[5]) * idet;
   s.Fi[8] = (F[0] * F[4] - F[1] * F[3]) * idet;
-  T q[4] = {(T)r.v[R_Q0], (T)r.v[R_Q0 + 1], (T)r.v[R_Q0 + 2], (T)r.v[R_Q0 + 3]};
-  quat_to_rot<T>(q, s.N);
+  {
+    const int m = (r.flags >> 3) & 3;
+    const T a0 = (T)r.v[R_Q0], a1 = (T)r.v[R_Q0 + 1], a2 = (T)r.v[R_Q0 + 2];
+    const T rest = T(1) - (a0 * a0 + a1 * a1 + a2 * a2);
+    const T qm = sqrt(rest > T(0) ? rest : T(0));  // >= 1/2 by the choice of m
+    const T q[4] = {m == 0 ? qm : a0, m == 1 ? qm : (m == 0 ? a0 : a1), m == 2 ? qm : (m <= 1 ? a1 : a2),
+                    m == 3 ? qm : a2};
+    quat_to_rot<T>(q, s.N);
+  }
   s.c = (T)r.v[R_C];
   s.kq = (T)r.v[R_KQ];
   s.kphi = (T)r.v[R_KPHI];
@@ -583,9 +603,10 @@ __device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const Lin
   s.theta = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    s.bd[i] = (T)r.v[R_B0 + i];
-    s.hinv[i] = T(0.5) * frcp(s.bd[i]);
-    s.theta += (T)r.v[R_E0 + i];
+    const T E = (T)r.v[R_E0 + i];  // principal trial log strain: b_i = exp(2 E)
+    s.bd[i] = fexp(T(2) * E);
+    s.hinv[i] = T(0.5) * fexp(T(-2) * E);
+    s.theta += E;
     s.coef[i] = (T)r.v[R_O0 + i];
   }
   const T th3 = s.theta * (T(1) / T(3));

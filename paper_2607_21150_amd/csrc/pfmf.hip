@@ -62,6 +62,8 @@ struct pf_ctx {
   MatParams<double>* d_mats = nullptr;
   MatParams<float>* d_matsf = nullptr;
   double* d_gpart = nullptr;
+  double* d_ebuf = nullptr;  // brick-buffer scatter (allocated on first use)
+  int scatter_mode = 0;      // PF_OPT_SCATTER
   int* d_flag = nullptr;
   hipStream_t last_stream = nullptr;
   MGState mg;
@@ -207,16 +209,43 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   return PF_OK;
 }
 
+// PF_OPT_SCATTER: brick buffer unless colours were asked for, or the automatic choice
+// meets a buffer above PF_SCATTER_AUTO_BYTES
+inline bool use_brick_buffer(const pf_ctx* c) {
+  if (c->scatter_mode != 0) return c->scatter_mode == 2;
+  return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
+}
+
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
+  const bool bb = use_brick_buffer(c);
+  if (bb) {
+    constexpr int NB = 2 * P - 1;
+    if (!c->d_ebuf &&
+        hipMalloc(&c->d_ebuf, (size_t)c->n_bricks * 4 * NB * NB * NB * sizeof(double)) != hipSuccess)
+      return fail(PF_ENOMEM, "brick buffer: allocation failed");
+    a.ebuf = c->d_ebuf;
+    a.brick_base = 0;
+    const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
+    if (P == 4)
+      hipLaunchKernelGGL((k_op64_q3<MODE, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    else
+      hipLaunchKernelGGL((k_op64_q2<MODE, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    HIPCHK(hipGetLastError());
+    const int nb = (int)std::min<int64_t>((4 * c->n_nodes + NT - 1) / NT, 65536);
+    hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(nb), dim3(NT), 0, s, (const double*)c->d_ebuf, a.m, c->nx1,
+                       c->ny1, c->n_nodes, a.out);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+  }
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
     if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q3<MODE, false>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, false>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -261,6 +290,7 @@ OpArgs op_args(pf_ctx* c) {
   a.fr = frac_params<double>(c->fr);
   a.out = nullptr;
   a.gpart = c->d_gpart;
+  a.ebuf = nullptr;
   a.brick_base = 0;
   a.flag = c->d_flag;
   return a;
@@ -418,6 +448,19 @@ pf_status pf_apply_adjoint(pf_ctx* c, const double* z, const double* v, double* 
   return PF_OK;
 }
 
+pf_status pf_set_option(pf_ctx* c, int option, int value) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  switch (option) {
+    case PF_OPT_SCATTER:
+      if (value < 0 || value > 2) return fail(PF_EINVAL, "PF_OPT_SCATTER takes 0, 1 or 2, not %d", value);
+      c->scatter_mode = value;
+      return PF_OK;
+    default:
+      return fail(PF_EINVAL, "unknown option %d", option);
+  }
+}
+
 pf_status pf_check(pf_ctx* c) {
   pf_status st = check_ctx(c);
   if (st) return st;
@@ -444,6 +487,7 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_mats);
   (void)hipFree(c->d_matsf);
   (void)hipFree(c->d_gpart);
+  (void)hipFree(c->d_ebuf);
   (void)hipFree(c->d_flag);
   delete c;
 }

@@ -22,8 +22,12 @@ EXPORTED = [
     "pf_setup_mesh", "pf_sizes", "pf_set_params", "pf_apply_residual", "pf_apply_jacobian",
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
-    "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step",
+    "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
 ]
+
+# pf_set_option
+PF_OPT_SCATTER = 1
+SCATTER_MODES = {"auto": 0, "colour": 1, "brick_buffer": 2}
 
 # face indices of pf_set_dirichlet and field bits
 FACES = {"x0": 0, "x1": 1, "y0": 2, "y1": 3, "z0": 4, "z1": 5}
@@ -100,6 +104,7 @@ def load():
     L.pf_set_dirichlet.argtypes = [vp, vp]
     L.pf_commit_state.argtypes = [vp, vp, vp, vp]
     L.pf_newton_step.argtypes = [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp]
+    L.pf_set_option.argtypes = [vp, C.c_int, C.c_int]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -263,6 +268,10 @@ class Context:
         for face, fields in faces.items():
             arr[FACES[face]] = sum(FIELD_BITS[f] for f in fields)
         _check(load().pf_set_dirichlet(self._h, C.cast(arr, C.c_void_p)))
+
+    def set_scatter(self, mode):
+        """Scatter-add of the order-2/3 FP64 applies: 'auto', 'colour' or 'brick_buffer'."""
+        _check(load().pf_set_option(self._h, PF_OPT_SCATTER, SCATTER_MODES[mode]))
 
     def commit_state(self, z, out=None, stream=None):
         _req(z, torch.float64, (4, self.n_nodes), "z")

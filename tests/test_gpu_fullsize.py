@@ -90,3 +90,21 @@ def test_large_sampled(pf, oracle_lib, name, variant):
         ctx.check()
         e = sampled(mesh, y32, lambda el: orc.jacobian(d["z"], d["dz"], elems=el), rng)
         assert e <= FP32_TOL, ("fp32 fine apply", e)
+
+
+@pytest.mark.parametrize("name", ["C2", "C3"])
+def test_scatter_modes_agree_at_full_size(pf, name):
+    """The two scatter-adds at full size (where the automatic choice differs): the brick
+    buffer and the colour launches agree to rounding of the final additions."""
+    print(f"case {name} scatter modes", flush=True)
+    d = I.make_inputs(name, "plastic")
+    ctx = pf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    out = {}
+    for mode in ("colour", "brick_buffer"):
+        ctx.set_scatter(mode)
+        out[mode] = (ctx.apply_residual(z), ctx.apply_jacobian(z, dz), ctx.apply_adjoint(z, v)[0])
+    ctx.check()
+    for a, b in zip(out["colour"], out["brick_buffer"]):
+        assert float(torch.linalg.norm(a - b) / torch.linalg.norm(a)) <= 1e-14
+

@@ -73,10 +73,14 @@ def restrict_np(r, mesh_n, pf_order, pc_order):
                                               ("C1", "compress", None, None), ("C1", "plastic", 3, 3),
                                               ("C2", "plastic", 2, 6), ("C1", "plastic", 4, 3),
                                               ("C1", "base", 4, 2)])
-def test_fp32_fine_apply_vs_fp64_oracle(pf, oracle_lib, name, variant, p, n):
-    print(f"case {name} {variant} p={p} n={n}", flush=True)
+@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
+def test_fp32_fine_apply_vs_fp64_oracle(pf, oracle_lib, name, variant, p, n, scatter):
+    print(f"case {name} {variant} p={p} n={n} {scatter}", flush=True)
     d = I.make_inputs(name, variant, p=p, n=n)
-    ctx = lin_ctx(pf, d)
+    ctx = pf.Context.from_inputs(d)
+    ctx.set_scatter(scatter)
+    ctx.linearize(dev(d["z"]))
+    ctx.check()
     y = ctx.apply_jacobian_f32(0, dev(d["dz"], torch.float32)).cpu().numpy()
     ref = oracle_lib.Oracle.from_inputs(d).jacobian(d["z"], d["dz"])
     assert relerr(y, ref) <= FP32_TOL, relerr(y, ref)

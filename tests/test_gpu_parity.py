@@ -51,12 +51,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
 @pytest.mark.parametrize("name,variant,p,n", CASES)
-def test_residual_jacobian_adjoint_fp64(pf, oracle_lib, name, variant, p, n):
-    print(f"case {name} {variant} p={p} n={n}", flush=True)
+def test_residual_jacobian_adjoint_fp64(pf, oracle_lib, name, variant, p, n, scatter):
+    """Both scatter-adds (colour launches, brick buffer + gather) against the oracle; the
+    option applies to orders 2 and 3 and is ignored by the others."""
+    print(f"case {name} {variant} p={p} n={n} {scatter}", flush=True)
     d = I.make_inputs(name, variant, p=p, n=n)
     orc = oracle_lib.Oracle.from_inputs(d)
     ctx = pf.Context.from_inputs(d)
+    ctx.set_scatter(scatter)
     z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
     r = ctx.apply_residual(z).cpu().numpy()
     y = ctx.apply_jacobian(z, dz).cpu().numpy()
@@ -73,10 +77,12 @@ def test_residual_jacobian_adjoint_fp64(pf, oracle_lib, name, variant, p, n):
         assert np.abs(col - cref).max() <= 1e-11 * scale, (k, col, cref)
 
 
-@pytest.mark.parametrize("p,n", [(2, 6), (4, 3)])
-def test_bitwise_deterministic(pf, p, n):
+@pytest.mark.parametrize("p,n,scatter", [(2, 6, "colour"), (2, 6, "brick_buffer"), (3, 3, "brick_buffer"),
+                                         (4, 3, "auto")])
+def test_bitwise_deterministic(pf, p, n, scatter):
     d = I.make_inputs("C1", "plastic", p=p, n=n)
     ctx = pf.Context.from_inputs(d)
+    ctx.set_scatter(scatter)
     z, dz = dev(d["z"]), dev(d["dz"])
     a = ctx.apply_jacobian(z, dz).cpu().numpy()
     b = ctx.apply_jacobian(z, dz).cpu().numpy()
@@ -100,6 +106,10 @@ def test_dot_product_identity(pf):
 def test_error_paths(pf):
     d = I.make_inputs("C1")
     ctx = pf.Context.from_inputs(d)
+    for opt, val in ((pf.PF_OPT_SCATTER, 3), (pf.PF_OPT_SCATTER, -1), (99, 0)):
+        with pytest.raises(pf.PfError) as e:
+            pf._check(pf.load().pf_set_option(ctx._h, opt, val))
+        assert e.value.code == pf.PF_EINVAL
     z = dev(d["z"])
     with pytest.raises(pf.PfError) as e:
         pf._check(pf.load().pf_apply_residual(ctx._h, pf._ptr(z), pf._ptr(z), pf._stream()))
