@@ -197,10 +197,20 @@ __device__ inline void scatter_brick4(const T* ev, const MeshDev& m, int nx1, in
   }
 }
 
-// Brick-buffer scatter, first half: the brick's node sums (same order as
-// scatter_brick4) stored unconditionally to eb[f][lz][ly][lx] (NB^3 per field).
+// Brick-buffer scatter. The buffer is an extended node grid in which every brick owns
+// its own (2P-1)^3 nodes, faces duplicated: brick b's node (lx, ly, lz) sits at
+// extended coordinates (NB bx + lx, NB by + ly, NB bz + lz), NB = 2P-1, field-major,
+// x fastest. A global x-row of nodes then maps to consecutive extended positions
+// (one gap per brick), so both the store and the gather below are coalesced.
+__host__ __device__ inline int64_t ext_index(const MeshDev& m, int NB, int f, int gx, int gy, int gz) {
+  const int64_t NXe = (int64_t)m.nbx * NB, NYe = (int64_t)m.nby * NB, NZe = (int64_t)m.nbz * NB;
+  return ((f * NZe + gz) * NYe + gy) * NXe + gx;
+}
+
+// First half: the brick's node sums (same order as scatter_brick4) stored
+// unconditionally into the extended grid.
 template <typename T, int P, int NF>
-__device__ inline void store_brick4(const T* ev, const BrickGeom& g, T* __restrict__ eb) {
+__device__ inline void store_brick4(const T* ev, const MeshDev& m, const BrickGeom& g, T* __restrict__ eb) {
   constexpr int p = P - 1, NB = 2 * P - 1, NB3 = NB * NB * NB;
   const int mx = g.nex * p + 1, my = g.ney * p + 1, mz = g.nez * p + 1;
   for (int t = threadIdx.x; t < NB3; t += NT) {
@@ -229,35 +239,50 @@ __device__ inline void store_brick4(const T* ev, const BrickGeom& g, T* __restri
       }
     }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) eb[f * NB3 + t] = acc[f];
+    for (int f = 0; f < NF; ++f) eb[ext_index(m, NB, f, NB * g.bx + lx, NB * g.by + ly, NB * g.bz + lz)] = acc[f];
   }
 }
 
-// Brick-buffer scatter, second half: every node sums the stored values of the (up to
-// 8) bricks holding it, lower brick first along each axis, and stores the result.
+// Second half: every node sums the stored values of the (up to 8) bricks holding it
+// and stores the result. Along an axis, node i (brick size S = 2p nodes) sits at
+// extended position i + i / S of its own brick, and a node on a brick face (i % S == 0,
+// i > 0) also at the position just before, in the previous brick. One wave per node
+// row (blockIdx.y * 4 + wave, blockIdx.z = field), so the y and z cases are uniform;
+// lower bricks are added first along each axis.
 template <typename T, int P>
 __global__ __launch_bounds__(NT) void k_gather_bricks(const T* __restrict__ eb, MeshDev m, int nx1, int ny1,
-                                                      int64_t n_nodes, T* __restrict__ out) {
-  constexpr int p = P - 1, NB = 2 * P - 1, NB3 = NB * NB * NB, S = 2 * p;
-  for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < 4 * n_nodes; t += (int64_t)gridDim.x * NT) {
-    const int f = (int)(t / n_nodes);
-    const int64_t i = t - (int64_t)f * n_nodes;
-    const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
-    int bx[2], lx[2], by[2], ly[2], bz[2], lz[2], cx = 0, cy = 0, cz = 0;
-    if (ix % S == 0 && ix >= S) { bx[cx] = ix / S - 1; lx[cx] = S; ++cx; }
-    if (ix / S < m.nbx) { bx[cx] = ix / S; lx[cx] = ix % S; ++cx; }
-    if (iy % S == 0 && iy >= S) { by[cy] = iy / S - 1; ly[cy] = S; ++cy; }
-    if (iy / S < m.nby) { by[cy] = iy / S; ly[cy] = iy % S; ++cy; }
-    if (iz % S == 0 && iz >= S) { bz[cz] = iz / S - 1; lz[cz] = S; ++cz; }
-    if (iz / S < m.nbz) { bz[cz] = iz / S; lz[cz] = iz % S; ++cz; }
-    T acc = T(0);
-    for (int c = 0; c < cz; ++c)
-      for (int b = 0; b < cy; ++b)
-        for (int a = 0; a < cx; ++a) {
-          const int64_t brick = bx[a] + (int64_t)m.nbx * (by[b] + (int64_t)m.nby * bz[c]);
-          acc += eb[(brick * 4 + f) * NB3 + lx[a] + NB * (ly[b] + NB * lz[c])];
+                                                      int n_rows, int64_t n_nodes, T* __restrict__ out) {
+  constexpr int p = P - 1, NB = 2 * P - 1, S = 2 * p;
+  const int f = blockIdx.z, w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t NXe = (int64_t)m.nbx * NB, NYe = (int64_t)m.nby * NB, NZe = (int64_t)m.nbz * NB;
+  const T* ebf = eb + f * NZe * NYe * NXe;
+  for (int r = blockIdx.y * 4 + w; r < n_rows; r += gridDim.y * 4) {
+    const int iz = r / ny1, iy = r - iz * ny1;
+    const bool yo = iy / S < m.nby, yp = iy % S == 0 && iy >= S;
+    const bool zo = iz / S < m.nbz, zp = iz % S == 0 && iz >= S;
+    const int64_t gy = iy + iy / S, gz = iz + iz / S;
+    // extended rows: own / previous brick along z (index 0 / 1) and y (0 / 1)
+    const T* rows[4];
+    int nr = 0;
+    if (zp && yp) rows[nr++] = ebf + ((gz - 1) * NYe + gy - 1) * NXe;
+    if (zp && yo) rows[nr++] = ebf + ((gz - 1) * NYe + gy) * NXe;
+    if (zo && yp) rows[nr++] = ebf + (gz * NYe + gy - 1) * NXe;
+    if (zo && yo) rows[nr++] = ebf + (gz * NYe + gy) * NXe;
+    T* orow = out + f * n_nodes + (int64_t)r * nx1;
+#pragma unroll 4
+    for (int ix = l; ix < nx1; ix += 64) {
+      const int gx = ix + ix / S;
+      const bool xo = ix / S < m.nbx, xp = ix % S == 0 && ix >= S;
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k < nr) {
+          if (xp) acc += rows[k][gx - 1];
+          if (xo) acc += rows[k][gx];
         }
-    out[t] = acc;
+      }
+      orow[ix] = acc;
+    }
   }
 }
 
@@ -459,7 +484,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
   }
   __syncthreads();
   if (BB)
-    store_brick4<double, 4, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * 4 - 1) * (2 * 4 - 1) * (2 * 4 - 1));
+    store_brick4<double, 4, 4>(ev, a.m, g, a.ebuf);
   else
     scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
@@ -692,7 +717,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTabl
   }
   __syncthreads();
   if (BB)
-    store_brick4<double, 3, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * 3 - 1) * (2 * 3 - 1) * (2 * 3 - 1));
+    store_brick4<double, 3, 4>(ev, a.m, g, a.ebuf);
   else
     scatter_brick4<double, 3, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
@@ -780,7 +805,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
   }
   __syncthreads();
   if (BB)
-    store_brick4<float, PC, 4>(ev, g, a.ebuf + (int64_t)brick * 4 * (2 * PC - 1) * (2 * PC - 1) * (2 * PC - 1));
+    store_brick4<float, PC, 4>(ev, a.m, g, a.ebuf);
   else
     scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }

@@ -188,9 +188,9 @@ pf_status launch_a32_q3(pf_ctx* c, A32Args a, hipStream_t s) {
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     hipLaunchKernelGGL((k_a32_q3<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
-    const int nb = (int)std::min<int64_t>((4 * a.lev.n_nodes + NT - 1) / NT, 65536);
-    hipLaunchKernelGGL((k_gather_bricks<float, PC>), dim3(nb), dim3(NT), 0, s, (const float*)c->mg.ebuf32, a.m,
-                       a.lev.nx1, a.lev.ny1, a.lev.n_nodes, a.out);
+    const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
+    hipLaunchKernelGGL((k_gather_bricks<float, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const float*)c->mg.ebuf32, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }

@@ -232,9 +232,9 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_op64_q2<MODE, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
-    const int nb = (int)std::min<int64_t>((4 * c->n_nodes + NT - 1) / NT, 65536);
-    hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(nb), dim3(NT), 0, s, (const double*)c->d_ebuf, a.m, c->nx1,
-                       c->ny1, c->n_nodes, a.out);
+    const int n_rows = c->ny1 * c->nz1;
+    hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const double*)c->d_ebuf, a.m, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }
