@@ -123,11 +123,46 @@ def cpu_baseline(d, seconds=10.0):
                       f"took {t:.2f} s; scaled to the full apply"}
 
 
+def secondary_leg(torch, I, pfmf, config):
+    """Device time of each apply on a second workload (mean of 20 back-to-back applies after
+    3 warm-up ones): the Q2 counterpart of the headline Q3 configuration."""
+    d = I.make_inputs(config, "base")
+    mesh = d["mesh"]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64)
+    ctx = pfmf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_top"])
+    y, g = torch.empty_like(z), torch.empty_like(z)
+    gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
+    ctx.linearize(z)
+    dz32 = dz.float()
+    y32 = torch.empty_like(dz32)
+    ms = {}
+    for name, f in (("residual", lambda: ctx.apply_residual(z, y)),
+                    ("jacobian", lambda: ctx.apply_jacobian(z, dz, y)),
+                    ("adjoint", lambda: ctx.apply_adjoint(z, v, g, gp)),
+                    ("fp32_apply", lambda: ctx.apply_jacobian_f32(0, dz32, y32))):
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        ms[name] = a.elapsed_time(b) / 20
+    ctx.check()
+    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs", "ms": ms,
+            "dofs_per_s": {k: mesh.n_dof / (t * 1e-3) for k, t in ms.items()},
+            "gbs_alg": {k: alg_bytes(mesh, k) / (t * 1e-3) / 1e9 for k, t in ms.items()},
+            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
+
+
 def newton_leg(torch, I, pfmf, config):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
     (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1; Chebyshev(3); 32 sweeps on the order-1
-    element-matrix level), FP64 Jacobian as the operator."""
+    level, assembled as a block stencil), FP64 Jacobian as the operator."""
     t_gen = time.perf_counter()
     d = I.make_inputs(config, "base")
     mesh = d["mesh"]
@@ -191,6 +226,8 @@ def main():
     ap.add_argument("--newton", action="store_true",
                     help="also time one Newton step (FGMRES + FP32 p-MG) on --newton-config")
     ap.add_argument("--newton-config", default="C5")
+    ap.add_argument("--secondary", default="C2",
+                    help="second workload whose applies are timed and reported beside the headline ('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
@@ -283,7 +320,11 @@ def main():
     bj = alg_bytes(mesh, "jacobian")
     achieved = bj / t_jac / 1e9
     traffic = measured_traffic(args.config + "/" + args.variant)
-    kname = "pfmf::k_op64_q3<1>" if mesh.p == 3 else f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>"
+    kname = {2: "pfmf::k_op64_q2<1, true> + pfmf::k_gather_bricks<double, 3>: one launch over all bricks, "
+                "then the node gather",
+             3: "pfmf::k_op64_q3<1, true> + pfmf::k_gather_bricks<double, 4>: one launch over all bricks, "
+                "then the node gather",
+             4: "pfmf::k_op64_q4<1>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(d, args.cpu_seconds)
@@ -313,7 +354,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": f"{kname} (one Jacobian apply = 8 colour launches; bytes and time per apply)",
+            "kernel": f"{kname} (one Jacobian apply; bytes and time per apply)",
             "alg_bytes_per_apply": bj,
             "copy_probe_gbs": copy["gbs"],
         },
@@ -327,9 +368,13 @@ def main():
         "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
-    if args.newton:
+    if args.secondary or args.newton:
         del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32
         torch.cuda.empty_cache()
+    if args.secondary:
+        out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)
+        print(f"[bench] secondary {out['secondary']}", file=sys.stderr, flush=True)
+    if args.newton:
         out["newton"] = newton_leg(torch, I, pfmf, args.newton_config)
     print(json.dumps(out), flush=True)
 

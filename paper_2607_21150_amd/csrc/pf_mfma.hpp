@@ -727,6 +727,131 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTabl
 
 namespace pfmf {
 
+// FP32 linearised level apply on a Q2 fine mesh (fine kinematics on P = 3 nodes, level
+// nodes PC <= 3, 3 Gauss points): the packing of k_op64_q2 (sum factorisation per
+// element on the padded 4 x 4 layout, the pointwise JVP once for both elements of the
+// wave on lanes 0-26 and 32-58) with the FP32 record path of k_a32_q3.
+template <int PC, bool BB>
+__global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ float ev[8 * 4 * 64];
+  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
+  const Basis4 bf = load_basis_pq<3, 3>(tabs);
+  const Basis4 bc = load_basis_pq<PC, 3>(tabs);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sx = wv & 1, sy = wv >> 1;
+  const bool hasA = sx < g.nex && sy < g.ney;  // uniform per wave
+  const bool hasB = hasA && g.nez > 1;
+  const int E = l >> 5, q = l & 31;
+  const int cqx = q % 3, cqy = (q / 3) % 3, cqz = q / 9;
+  const bool valid = q < 27 && (E == 0 ? hasA : hasB);
+  const int src_fwd = cqx + 4 * cqz + 16 * cqy;
+  const int pqx = l & 3, pqz = (l >> 2) & 3, pqy = l >> 4;
+  const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
+  const int pq = pqx + 3 * pqy + 9 * pqz;
+  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
+  const float wdet = (float)(tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz < 3 ? cqz : 0] *
+                             a.m.jdet);
+  if (hasA) {
+    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float wphi = 0.f, gw[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (half == 1 && !hasB) break;  // uniform
+      const int64_t gf = lane_node<3>(g, sx, sy, half, a.fine.nx1, a.fine.ny1);
+      const int64_t gc = lane_node<PC>(g, sx, sy, half, a.lev.nx1, a.lev.ny1);
+      double zu[3], wu[4];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) zu[f] = gf >= 0 ? (double)a.z32[f * a.fine.n_nodes + gf] : 0.0;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) wu[f] = gc >= 0 ? (double)a.dz[f * a.lev.n_nodes + gc] : 0.0;
+      const bool mine = E == half;
+      {
+        double v[3], d[3][3];
+        sf4_fwd_n<3>(zu, bf, 0x0u, 0x7u, v, d);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+          for (int J = 0; J < 3; ++J) {
+            const double r = lane_read(d[f][J], src_fwd);
+            if (mine) G[3 * f + J] = (float)r * ih[J];
+          }
+      }
+      {
+        double v[4], d[4][3];
+        sf4_fwd_n<4>(wu, bc, 0x8u, 0xFu, v, d);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+          for (int J = 0; J < 3; ++J) {
+            const double r = lane_read(d[f][J], src_fwd);
+            if (mine) W[3 * f + J] = (float)r * ih[J];
+          }
+        const double rp = lane_read(v[3], src_fwd);
+        if (mine) wphi = (float)rp;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double r = lane_read(d[3][J], src_fwd);
+          if (mine) gw[J] = (float)r * ih[J];
+        }
+      }
+    }
+    // pointwise JVP from the record (packed layout)
+    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
+    const int64_t gq = e * 27 + q;
+    LinRecord rc;
+#pragma unroll
+    for (int k = 0; k < REC_N; ++k) rc.v[k] = valid ? a.rec.rec[k * a.n_q + gq] : 0.f;
+    rc.flags = valid ? a.rec.flags[gq] : 0;
+    const int pid = valid ? a.phase[gq] : 0;
+    const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<float> s;
+    qp_state_lin<float>(mp, G, rc, s);
+    float Fu[9], dL;
+    qp_tangent<float>(mp, s, W, wphi, Fu, dL);
+    const float kfg = a.fr.kf * mp.Gc;
+    double b1p[4][3], b0p3;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1p[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+#pragma unroll
+    for (int J = 0; J < 3; ++J) b1p[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
+    b0p3 = (double)(wdet * a.fr.s_phi * dL);
+    // back to each element's padded layout, transposed interpolation
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (half == 1 && !hasB) break;
+      const int src = pvalid ? 32 * half + pq : l;
+      double b0[4], b1[4][3], r[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        b0[f] = 0.0;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+          const double v = lane_read(b1p[f][J], src);
+          b1[f][J] = pvalid ? v : 0.0;
+        }
+      }
+      {
+        const double v = lane_read(b0p3, src);
+        b0[3] = pvalid ? v : 0.0;
+      }
+      sf4_bwd_n<4>(b0, b1, 0x8u, bc, r);
+      const int slot = wv + 4 * half;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (float)r[f];
+    }
+  }
+  __syncthreads();
+  if (BB)
+    store_brick4<float, PC, 4>(ev, a.m, g, a.ebuf);
+  else
+    scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+}
+
 // FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
 // level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
 // contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).

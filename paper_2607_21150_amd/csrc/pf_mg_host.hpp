@@ -178,15 +178,20 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
   return fail(PF_EUNSUPPORTED, "level order not built");
 }
 
-template <int PC>
-pf_status launch_a32_q3(pf_ctx* c, A32Args a, hipStream_t s) {
+// FP32 level apply on the matrix cores: PF = 4 (order-3 mesh, k_a32_q3) or PF = 3
+// (order-2 mesh, k_a32_q2)
+template <int PF, int PC>
+pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
   if (use_brick_buffer(c)) {
     // sized for the largest level (PC = 4); every level of the hierarchy shares it
     if (!c->mg.ebuf32 && hipMalloc(&c->mg.ebuf32, (size_t)c->n_bricks * 4 * 343 * sizeof(float)) != hipSuccess)
       return fail(PF_ENOMEM, "brick buffer: allocation failed");
     a.ebuf = c->mg.ebuf32;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
-    hipLaunchKernelGGL((k_a32_q3<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    if constexpr (PF == 4)
+      hipLaunchKernelGGL((k_a32_q3<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    else
+      hipLaunchKernelGGL((k_a32_q2<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
     hipLaunchKernelGGL((k_gather_bricks<float, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -197,7 +202,10 @@ pf_status launch_a32_q3(pf_ctx* c, A32Args a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_a32_q3<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    if constexpr (PF == 4)
+      hipLaunchKernelGGL((k_a32_q3<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    else
+      hipLaunchKernelGGL((k_a32_q2<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -278,9 +286,16 @@ pf_status level_op_raw(pf_ctx* c, int level, const float* dz, float* out, hipStr
   }
   if (MODE == 0 && PF == 4) {
     switch (PC) {
-      case 4: return launch_a32_q3<4>(c, a, s);
-      case 3: return launch_a32_q3<3>(c, a, s);
-      case 2: return launch_a32_q3<2>(c, a, s);
+      case 4: return launch_a32_mfma<4, 4>(c, a, s);
+      case 3: return launch_a32_mfma<4, 3>(c, a, s);
+      case 2: return launch_a32_mfma<4, 2>(c, a, s);
+      default: break;
+    }
+  }
+  if (MODE == 0 && PF == 3) {
+    switch (PC) {
+      case 3: return launch_a32_mfma<3, 3>(c, a, s);
+      case 2: return launch_a32_mfma<3, 2>(c, a, s);
       default: break;
     }
   }
