@@ -122,11 +122,13 @@ pf_status pf_apply_adjoint(pf_ctx* ctx, const double* z, const double* v, double
                            double* gparams, void* stream);
 
 /* Linearise at z for the FP32 multigrid: the return-mapping, split and history
- * decisions, their scalars, the principal frame of b_tr (a unit quaternion), its
- * principal values, the log strains and the off-diagonal tangent factors are taken in
- * FP64 and stored per point as an FP32 record (Appendices A-C evaluated once), with
- * an FP32 mirror of u; builds every level's point-Jacobi diagonal and Chebyshev
- * bounds (power iteration on the device). Synchronises the stream once. */
+ * decisions, their scalars, the principal frame of b_tr (a unit quaternion, its three
+ * smallest components), the principal trial log strains and the off-diagonal tangent
+ * factors are taken in FP64 and stored per point as an FP32 record of 15 values and a
+ * flag byte (Appendices A-C evaluated once), with an FP32 mirror of u; assembles an
+ * order-1 coarsest level into a block stencil; builds every level's point-Jacobi
+ * diagonal and Chebyshev bounds (power iteration on the device). Synchronises the
+ * stream once. */
 pf_status pf_linearize(pf_ctx* ctx, const double* z, void* stream);
 
 /* Multigrid level orders, fine first: orders[0] = p > orders[1] > ... >= 1,
