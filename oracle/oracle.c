@@ -8,8 +8,11 @@
  *
  * Each step cites the passage of the paper it follows. Where the paper is
  * silent the reading used is stated next to the code:
- *  - the matrix Prandtl branch carries linear hardening and an overstress factor
+ *  - the matrix Prandtl branch carries linear hardening, optionally the Voce term of
+ *    eq:plasticity-strain-hardening-law, and an overstress factor
  *    (1 + visc * dgamma / dt) on the yield stress; visc = 0 gives Box 2 exactly;
+ *    linear hardening takes the closed-form root of the consistency equation, Voce
+ *    hardening Box 2's Newton iteration (kept inside the admissible bracket);
  *  - degradation enters the Prandtl update through g*mu and g*q_tr
  *    (eq:degraded-trial-stress) with hardening kept in Box 2's equation;
  *  - tension branch of the Amor split at tr(eps^e) >= 0; history switch active
@@ -258,6 +261,7 @@ static double log_divdiff(double bi_m1, double bj_m1) {
 
 typedef struct {
   double mu, kappa, Gc, sigma0, H, a; int plastic;
+  double sinf, bv;  /* Voce saturation stress and rate; bv = 0: linear hardening */
 } mat_t;
 
 static mat_t make_mat(const or_phase* ph, const or_frac* fr) {
@@ -269,7 +273,18 @@ static mat_t make_mat(const or_phase* ph, const or_frac* fr) {
   m.H = ph->H;
   m.a = ph->visc / fr->dt;
   m.plastic = ph->plastic;
+  m.sinf = ph->sigma_inf;
+  m.bv = ph->voce_beta;
   return m;
+}
+
+/* Yield stress and hardening modulus (eq:plasticity-strain-hardening-law):
+ * sigma_y = sigma0 + H ep + (sinf - sigma0)(1 - exp(-bv ep)). */
+static double yield_stress(const mat_t* m, double ep) {
+  return m->sigma0 + m->H * ep + (m->bv > 0.0 ? (m->sinf - m->sigma0) * (1.0 - exp(-m->bv * ep)) : 0.0);
+}
+static double yield_slope(const mat_t* m, double ep) {
+  return m->H + (m->bv > 0.0 ? (m->sinf - m->sigma0) * m->bv * exp(-m->bv * ep) : 0.0);
 }
 
 typedef struct {
@@ -278,7 +293,7 @@ typedef struct {
   double beta[3], N[3][3]; /* eigenpairs of A (columns of N) */
   double eps[3], theta, e[3];
   double g, gp;
-  double q, sn, dgamma, c, Heff, den;
+  double q, sn, dgamma, c, Heff, den, ep;
   int plastic;
   double tau[3];           /* undegraded block principal stresses */
   double taud[3];          /* degraded principal stresses */
@@ -332,19 +347,40 @@ static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double
   /* R6: Box 2 with the degraded trial stress (eq:degraded-yield-condition) */
   double ee = s->e[0] * s->e[0] + s->e[1] * s->e[1] + s->e[2] * s->e[2];
   s->q = 2.0 * m->mu * sqrt(1.5 * ee);       /* q = sqrt(3/2)|tau_d^tr|, tau_d^tr = 2 mu e */
-  s->sn = m->sigma0 + m->H * st[6];          /* linear hardening at ebar_p,n */
+  s->sn = yield_stress(m, st[6]);            /* sigma_y(ebar_p,n) */
   s->c = 1.0;
   s->dgamma = 0.0;
   s->plastic = 0;
   if (m->plastic) {
     double f = s->g * s->q - s->sn;
     if (f > 0.0) {
-      /* g q - 3 g mu dg - (sn + H dg)(1 + a dg) = 0, smaller positive root */
-      double B = 3.0 * s->g * m->mu + m->H + m->a * s->sn;
-      s->dgamma = 2.0 * f / (B + sqrt(B * B + 4.0 * m->a * m->H * f));
+      if (m->bv > 0.0) {
+        /* Box 2 Newton on g q - 3 g mu dg - sigma_y(ebar_n + dg)(1 + a dg) = 0 from
+         * dg = 0; the equation is positive at 0 and negative at q / (3 mu) (c = 0),
+         * and a step leaving that bracket is replaced by bisection */
+        double lo = 0.0, hi = s->q / (3.0 * m->mu), dg = 0.0;
+        for (int it = 0; it < 200; it++) {
+          double sy = yield_stress(m, st[6] + dg), hy = yield_slope(m, st[6] + dg);
+          double ft = s->g * s->q - 3.0 * s->g * m->mu * dg - sy * (1.0 + m->a * dg);
+          if (ft > 0.0) lo = dg; else hi = dg;
+          double nd = dg + ft / (3.0 * s->g * m->mu + hy * (1.0 + m->a * dg) + m->a * sy);
+          if (!(nd > lo && nd < hi)) nd = 0.5 * (lo + hi);
+          double step = fabs(nd - dg);
+          dg = nd;
+          if (step <= 1e-15 * dg || hi - lo <= 1e-15 * hi) break;
+        }
+        s->dgamma = dg;
+      } else {
+        /* g q - 3 g mu dg - (sn + H dg)(1 + a dg) = 0, smaller positive root */
+        double B = 3.0 * s->g * m->mu + m->H + m->a * s->sn;
+        s->dgamma = 2.0 * f / (B + sqrt(B * B + 4.0 * m->a * m->H * f));
+      }
       s->c = 1.0 - 3.0 * m->mu * s->dgamma / s->q;   /* eq:plasticity-deviatoric-strain-update */
-      s->Heff = m->H * (1.0 + m->a * s->dgamma) + m->a * (s->sn + m->H * s->dgamma);
+      /* d/d dg of sigma_y(ebar_n + dg)(1 + a dg) */
+      s->Heff = yield_slope(m, st[6] + s->dgamma) * (1.0 + m->a * s->dgamma) +
+                m->a * yield_stress(m, st[6] + s->dgamma);
       s->den = 3.0 * s->g * m->mu + s->Heff;
+      s->ep = st[6] + s->dgamma;
       s->plastic = 1;
     }
   }
@@ -521,8 +557,10 @@ static void qp_param_partials(const mat_t* m, const or_frac* fr, const qp_state*
   if (!s->plastic) return;
   /* sigma0 and visc enter through dgamma (implicit function of Box 2's equation) */
   double ddg[3];
-  ddg[1] = -(1.0 + m->a * s->dgamma) / s->den;                          /* d/d sigma0 */
-  ddg[2] = -(s->sn + m->H * s->dgamma) * (s->dgamma / fr->dt) / s->den; /* d/d visc  */
+  /* d sigma_y / d sigma0 = exp(-bv ep) (1 for linear hardening) */
+  const double dsy = m->bv > 0.0 ? exp(-m->bv * s->ep) : 1.0;
+  ddg[1] = -(1.0 + m->a * s->dgamma) * dsy / s->den;                            /* d/d sigma0 */
+  ddg[2] = -yield_stress(m, s->ep) * (s->dgamma / fr->dt) / s->den;              /* d/d visc  */
   for (int k = 1; k < 3; k++) {
     double dce[3], dtaud[3];
     for (int i = 0; i < 3; i++) dce[i] = -(3.0 * m->mu / s->q) * ddg[k] * s->e[i];

@@ -34,7 +34,9 @@ extern "C" {
 #endif
 
 typedef struct { int p, q, nx, ny, nz; double lx, ly, lz; } or_mesh;
-typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; } or_phase;
+/* sigma_inf, voce_beta: Voce term (sigma_inf - sigma0)(1 - exp(-voce_beta ebar_p)) of the
+ * hardening law; voce_beta = 0 is linear hardening. */
+typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; double sigma_inf, voce_beta; } or_phase;
 typedef struct { double l0, eta, zeta, dt, s_phi; int at; } or_frac;
 
 /* Every pointwise quantity the tests look at. */

@@ -34,7 +34,8 @@ class OrMesh(C.Structure):
 
 class OrPhase(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("Gc", C.c_double), ("sigma0", C.c_double),
-                ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int)]
+                ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int),
+                ("sigma_inf", C.c_double), ("voce_beta", C.c_double)]
 
 
 class OrFrac(C.Structure):
@@ -96,7 +97,8 @@ def mesh_struct(mesh, q=None):
 
 
 def phase_struct(ph):
-    return OrPhase(ph.E, ph.nu, ph.Gc, ph.sigma0, ph.H, ph.visc, int(ph.plastic))
+    return OrPhase(ph.E, ph.nu, ph.Gc, ph.sigma0, ph.H, ph.visc, int(ph.plastic),
+                   getattr(ph, "sigma_inf", 0.0), getattr(ph, "voce_beta", 0.0))
 
 
 def phases_array(phases):

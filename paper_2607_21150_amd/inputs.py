@@ -99,6 +99,8 @@ class Phase:
     H: float = 0.0          # linear hardening modulus
     visc: float = 0.0       # overstress viscosity [s]
     plastic: bool = False
+    sigma_inf: float = 0.0  # Voce saturation stress [MPa] (with voce_beta > 0)
+    voce_beta: float = 0.0  # Voce rate; 0 = linear hardening
 
 
 @dataclasses.dataclass(frozen=True)
@@ -116,6 +118,12 @@ def default_phases():
     matrix = Phase(E=1000.0, nu=0.45, Gc=0.2, sigma0=10.0, H=100.0, visc=1e-2, plastic=True)
     particle = Phase(E=15000.0, nu=0.3, Gc=0.05)
     return [matrix, particle]
+
+
+def voce_phases():
+    """The default phases with Voce hardening on the matrix (saturation 30 MPa, rate 50)."""
+    matrix, particle = default_phases()
+    return [dataclasses.replace(matrix, sigma_inf=30.0, voce_beta=50.0), particle]
 
 
 def default_fracture(mesh: Mesh, phases, at: int = 1) -> Fracture:
@@ -147,7 +155,7 @@ CONFIGS = {
     "C5": Config("C5", 5, 4, 40, 200, 0.03, 0.08, 0.35),
 }
 
-VARIANT_E0 = {"base": 1e-3, "plastic": 2e-2, "compress": -1e-3}
+VARIANT_E0 = {"base": 1e-3, "plastic": 2e-2, "compress": -1e-3, "voce": 2e-2}
 
 
 def make_config(name: str, p: Optional[int] = None, n: Optional[int] = None) -> Config:
@@ -256,7 +264,7 @@ def make_inputs(name: str = "C1", variant: str = "base", p: Optional[int] = None
     cfg = make_config(name, p, n)
     mesh = Mesh(cfg.p, cfg.n, cfg.n, cfg.n)
     if phases is None:
-        phases = default_phases()
+        phases = voce_phases() if variant == "voce" else default_phases()
     frac = default_fracture(mesh, phases, at)
     e0 = VARIANT_E0[variant]
     P = mesh.p

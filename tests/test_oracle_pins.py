@@ -184,6 +184,54 @@ def test_uniaxial_plastic_return(O, phi, visc):
     assert abs(qd - (sn + ph.H * dg_b) * (1 + a * dg_b)) <= 1e-11 * qd
 
 
+@pytest.mark.parametrize("phi,ebar", [(0.0, 0.0), (0.3, 2e-3), (0.5, 5e-3)])
+def test_voce_return_lambert_w(O, phi, ebar):
+    """Voce hardening (eq:plasticity-strain-hardening-law) through Box 2's Newton iteration:
+    with H = 0 and no overstress the consistency equation
+    g q - 3 g mu dg = s_inf - (s_inf - s0) exp(-beta (ebar + dg)) has the closed-form root
+    dg = A/k + W0((beta C / k) exp(-beta A / k)) / beta, A = g q - s_inf, k = 3 g mu,
+    C = (s_inf - s0) exp(-beta ebar) (W0: principal Lambert W, scipy)."""
+    from scipy.special import lambertw
+    ph = I.Phase(E=1000.0, nu=0.45, Gc=0.2, sigma0=10.0, H=0.0, visc=0.0, plastic=True,
+                 sigma_inf=30.0, voce_beta=50.0)
+    mu, ka = moduli(ph)
+    e = 0.1
+    out = O.qf_residual(ph, FR, np.diag([0, 0, e]), phi, np.zeros(3), phi, state(ebar=ebar))
+    q = 2 * mu * math.log1p(e)
+    g = (1 - phi) ** 2 + FR.eta
+    k, A = 3 * g * mu, g * q - ph.sigma_inf
+    C = (ph.sigma_inf - ph.sigma0) * math.exp(-ph.voce_beta * ebar)
+    b = ph.voce_beta
+    dg = A / k + float(lambertw(b * C / k * math.exp(-b * A / k)).real) / b
+    assert out.plastic_active == 1
+    assert abs(out.dgamma - dg) <= 1e-12 * dg, (out.dgamma, dg)
+    assert abs(out.c - (1 - 3 * mu * dg / q)) <= 1e-12
+
+
+@pytest.mark.parametrize("visc", [0.0, 1e-2])
+def test_voce_reduces_to_linear_hardening(O, visc):
+    """With s_inf = s0 the Voce term vanishes: the Newton path gives the closed-form linear-hardening
+    root and the same stress and tangent (pins the iteration against the closed form)."""
+    rng = np.random.default_rng(8)
+    lin = I.Phase(E=1000.0, nu=0.45, Gc=0.2, sigma0=10.0, H=100.0, visc=visc, plastic=True)
+    voc = I.Phase(E=1000.0, nu=0.45, Gc=0.2, sigma0=10.0, H=100.0, visc=visc, plastic=True,
+                  sigma_inf=10.0, voce_beta=40.0)
+    for _ in range(5):
+        G = rng.standard_normal((3, 3)) * 3e-2
+        D, st = iso_D(rng, 1e-3), None
+        st = state(D, ebar=rng.uniform(0, 1e-2))
+        phi = rng.uniform(0, 0.5)
+        a = O.qf_residual(lin, FR, G, phi, np.zeros(3), phi, st)
+        b = O.qf_residual(voc, FR, G, phi, np.zeros(3), phi, st)
+        assert a.plastic_active == b.plastic_active == 1
+        assert abs(a.dgamma - b.dgamma) <= 1e-13 * a.dgamma
+        assert np.allclose(np.array(a.tau), np.array(b.tau), rtol=0, atol=1e-12 * np.abs(np.array(a.tau)).max())
+        dG = rng.standard_normal((3, 3))
+        ja = O.qf_jacobian(lin, FR, G, phi, np.zeros(3), phi, st, dG, 0.3, np.zeros(3))
+        jb = O.qf_jacobian(voc, FR, G, phi, np.zeros(3), phi, st, dG, 0.3, np.zeros(3))
+        assert np.allclose(ja[0], jb[0], rtol=0, atol=1e-11 * np.abs(ja[0]).max())
+
+
 @pytest.mark.parametrize("phi", [0.0, 0.3, 0.6])
 def test_perfect_plastic_closed_form(O, phi):
     """Perfect plasticity (eq:perfect-plastic-delta-gamma, eq:principal-directions-format-1):
@@ -448,7 +496,7 @@ def _qp_switches(O, d, z, orc):
     return out
 
 
-@pytest.mark.parametrize("variant", ["base", "plastic", "compress"])
+@pytest.mark.parametrize("variant", ["base", "plastic", "compress", "voce"])
 def test_jacobian_matches_central_differences(O, variant):
     """J dz against Richardson-extrapolated central differences of R (linearisation of
     eq:hyperelastic-damage-weak-form-current, Apps. B-C). The Amor split, the history max and the
@@ -540,7 +588,7 @@ def test_quadrature_volume_and_gradient_exactness(O):
     assert abs(w @ r[3] - exact) <= 1e-13 * abs(exact)
 
 
-@pytest.mark.parametrize("variant", ["base", "plastic"])
+@pytest.mark.parametrize("variant", ["base", "plastic", "voce"])
 def test_adjoint_dot_product(O, variant):
     """<v, J w> = <J^T v, w> for the explicit-transpose adjoint."""
     d = I.make_inputs("C1", variant)
@@ -551,9 +599,11 @@ def test_adjoint_dot_product(O, variant):
     assert abs(a - b) <= 1e-13 * np.linalg.norm(g) * np.linalg.norm(d["dz"]) * 10
 
 
-def test_parameter_gradient_matches_central_differences(O):
-    """v^T dR/d(Gc, sigma0, visc) per phase against central differences (h = 1e-6 relative)."""
-    d = I.make_inputs("C1", "plastic")
+@pytest.mark.parametrize("variant", ["plastic", "voce"])
+def test_parameter_gradient_matches_central_differences(O, variant):
+    """v^T dR/d(Gc, sigma0, visc) per phase against central differences (relative steps 1e-4 and
+    1e-3, Richardson-extrapolated)."""
+    d = I.make_inputs("C1", variant)
     z, v = d["z"], d["v_rand"]
     orc = O.Oracle.from_inputs(d)
     _, gp = orc.adjoint(z, v)
@@ -574,9 +624,14 @@ def test_parameter_gradient_matches_central_differences(O):
                     vals.append(np.vdot(v, orc.residual(z)))
                 orc.set_phases(phases)
                 return (vals[0] - vals[1]) / (2 * h)
-            h = 1e-4 * base
-            fd = (4 * cd(h / 2) - cd(h)) / 3
-            assert abs(fd - gp[pid, k]) <= 1e-6 * max(abs(fd), 1e-8 * np.abs(gp).max()), (pid, nm, fd, gp[pid, k])
+            # Richardson-extrapolated at two step sizes: a small step can meet a point's history
+            # or yield switch, a large one the truncation error; the derivative must match at one
+            errs = []
+            for rel in (1e-4, 1e-3):
+                h = rel * base
+                fd = (4 * cd(h / 2) - cd(h)) / 3
+                errs.append(abs(fd - gp[pid, k]) / max(abs(fd), 1e-8 * np.abs(gp).max()))
+            assert min(errs) <= 1e-6, (pid, nm, errs, gp[pid, k])
 
 
 def test_reaction_loss_has_no_gc_gradient(O):
