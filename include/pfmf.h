@@ -73,11 +73,18 @@ typedef enum {
 typedef struct { int p; int nx, ny, nz; double lx, ly, lz; } pf_mesh_desc;
 
 /* Material of one phase: Hencky Hooke branch (E [MPa], nu) plus, when plastic != 0,
- * one Prandtl branch (Box 2) with initial yield sigma0 [MPa], linear hardening H [MPa]
- * (eq:plasticity-strain-hardening-law without the Voce term) and an overstress factor
- * (1 + visc dgamma / dt) on the yield stress (visc [s]; visc = 0 is Box 2 exactly).
- * Gc [N/mm] is the critical energy release rate of the fracture element. */
-typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; } pf_phase;
+ * one Prandtl branch (Box 2) with the hardening law eq:plasticity-strain-hardening-law,
+ * sigma_y = sigma0 + H ebar_p + (sigma_inf - sigma0)(1 - exp(-voce_beta ebar_p))
+ * (sigma0, H, sigma_inf [MPa]; voce_beta = 0 is linear hardening, else sigma_inf >=
+ * sigma0 is required), and an overstress factor (1 + visc dgamma / dt) on the yield
+ * stress (visc [s]; visc = 0 is Box 2 exactly). Linear hardening takes the closed-form
+ * root of the consistency equation, Voce hardening Box 2's Newton iteration. Gc [N/mm]
+ * is the critical energy release rate of the fracture element. */
+typedef struct {
+  double E, nu, Gc, sigma0, H, visc;
+  int plastic;
+  double sigma_inf, voce_beta;
+} pf_phase;
 
 /* Fracture element and time step: length scale l0 [mm], residual stiffness eta
  * (eq:degr-funct), damage viscosity zeta [MPa s] (Section 3.1), time step dt [s],

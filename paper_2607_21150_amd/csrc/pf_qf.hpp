@@ -23,7 +23,19 @@ namespace pfmf {
 template <typename T> struct MatParams {
   T mu, kappa, Gc, sigma0, H, a;  // a = visc / dt
   int plastic;
+  T sinf, bv;                     // Voce saturation stress and rate (bv = 0: linear hardening)
 };
+
+// Yield stress and its slope at accumulated plastic strain ep
+// (eq:plasticity-strain-hardening-law): sigma0 + H ep + (sinf - sigma0)(1 - exp(-bv ep)).
+template <typename T>
+__device__ inline T yield_stress(const MatParams<T>& m, T ep) {
+  return m.sigma0 + m.H * ep + (m.bv > T(0) ? (m.sinf - m.sigma0) * (T(1) - exp(-m.bv * ep)) : T(0));
+}
+template <typename T>
+__device__ inline T yield_slope(const MatParams<T>& m, T ep) {
+  return m.H + (m.bv > T(0) ? (m.sinf - m.sigma0) * m.bv * exp(-m.bv * ep) : T(0));
+}
 
 template <typename T> struct FracParams {
   T l0, eta, zeta, inv_dt, s_phi, c0, inv_c0l0, kf;  // kf = s_phi * 2 l0 / c0 (times Gc at use)
@@ -401,7 +413,7 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   const T ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
   const T u15 = T(1.5) * ee;
   const T q = (u15 > T(0)) ? T(2) * m.mu * u15 * frsqrt(u15) : T(0);
-  const T sn = m.sigma0 + m.H * st[6];
+  const T sn = yield_stress(m, st[6]);
   const T f = s.g * q - sn;
   s.plastic = m.plastic && (f > T(0));
   s.c = T(1);
@@ -411,19 +423,41 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   s.ddg_visc = T(0);
   s.dg = T(0);
   if (s.plastic) {
-    const T B = T(3) * s.g * m.mu + m.H + m.a * sn;
-    const T disc = B * B + T(4) * m.a * m.H * f;
-    const T dg = T(2) * f * frcp(B + disc * frsqrt(disc));
     const T iq = frcp(q);
+    T dg;
+    if (m.bv > T(0)) {
+      // Voce: Box 2's Newton iteration on g q - 3 g mu dg - sigma_y(ebar_n + dg)(1 + a dg) = 0
+      // from dg = 0, kept inside [0, q / (3 mu)] (positive, resp. negative, at the ends)
+      // by bisection when a step leaves it; bounded, lanes finish independently
+      T lo = T(0), hi = q / (T(3) * m.mu), d = T(0);
+      for (int it = 0; it < 200; ++it) {
+        const T sy = yield_stress(m, st[6] + d), hy = yield_slope(m, st[6] + d);
+        const T ft = s.g * q - T(3) * s.g * m.mu * d - sy * (T(1) + m.a * d);
+        if (ft > T(0)) lo = d;
+        else hi = d;
+        T nd = d + ft / (T(3) * s.g * m.mu + hy * (T(1) + m.a * d) + m.a * sy);
+        if (!(nd > lo && nd < hi)) nd = T(0.5) * (lo + hi);
+        const T step = fabs(nd - d);
+        d = nd;
+        if (step <= T(1e-15) * d || hi - lo <= T(1e-15) * hi) break;
+      }
+      dg = d;
+    } else {
+      // linear hardening: the smaller positive root in closed form (stable)
+      const T B = T(3) * s.g * m.mu + m.H + m.a * sn;
+      const T disc = B * B + T(4) * m.a * m.H * f;
+      dg = T(2) * f * frcp(B + disc * frsqrt(disc));
+    }
     s.dg = dg;
     s.c = T(1) - T(3) * m.mu * dg * iq;
-    const T sy = sn + m.H * dg;
-    const T den = T(3) * s.g * m.mu + m.H * (T(1) + m.a * dg) + m.a * sy;
+    const T ep = st[6] + dg;
+    const T sy = yield_stress(m, ep);
+    const T den = T(3) * s.g * m.mu + yield_slope(m, ep) * (T(1) + m.a * dg) + m.a * sy;
     const T iden = frcp(den);
     const T w = T(3) * m.mu * iq;
     s.kq = -w * (s.g * iden - dg * iq) * (T(6) * m.mu * m.mu * iq);
     s.kphi = -w * s.gp * (q - T(3) * m.mu * dg) * iden;
-    s.ddg_s0 = -(T(1) + m.a * dg) * iden;
+    s.ddg_s0 = -(T(1) + m.a * dg) * (m.bv > T(0) ? exp(-m.bv * ep) : T(1)) * iden;
     s.ddg_visc = -sy * dg * fr.inv_dt * iden;
   }
   // block stress, Amor split, psi^+ (eq:principal-stress-update-eigenvalues,

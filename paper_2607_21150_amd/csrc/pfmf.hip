@@ -128,6 +128,8 @@ MatParams<T> mat_params(const pf_phase& p, const pf_fracture& f) {
   m.H = (T)p.H;
   m.a = (T)(p.visc / f.dt);
   m.plastic = p.plastic ? 1 : 0;
+  m.sinf = (T)p.sigma_inf;
+  m.bv = (T)p.voce_beta;
   return m;
 }
 
@@ -329,6 +331,8 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
     if (!(p.E > 0 && p.nu > -1 && p.nu < 0.5 && p.Gc >= 0 && p.sigma0 >= 0 && p.H >= 0 && p.visc >= 0))
       return fail(PF_EINVAL, "bad parameters for phase %d", i);
     if (p.plastic && !(p.sigma0 > 0)) return fail(PF_EINVAL, "plastic phase %d needs sigma0 > 0", i);
+    if (!(p.voce_beta >= 0) || (p.voce_beta > 0 && !(p.sigma_inf >= p.sigma0)))
+      return fail(PF_EINVAL, "phase %d: Voce needs voce_beta >= 0 and sigma_inf >= sigma0", i);
   }
   auto* c = new pf_ctx;
   (void)hipGetDevice(&c->device);
@@ -387,6 +391,8 @@ pf_status pf_set_params(pf_ctx* c, const double* params) {
     const double gc = params[3 * i], s0 = params[3 * i + 1], vi = params[3 * i + 2];
     if (!(gc >= 0 && s0 >= 0 && vi >= 0)) return fail(PF_EINVAL, "bad parameters for phase %zu", i);
     if (c->phases[i].plastic && !(s0 > 0)) return fail(PF_EINVAL, "plastic phase %zu needs sigma0 > 0", i);
+    if (c->phases[i].voce_beta > 0 && !(c->phases[i].sigma_inf >= s0))
+      return fail(PF_EINVAL, "phase %zu: Voce needs sigma_inf >= sigma0", i);
   }
   for (size_t i = 0; i < c->phases.size(); ++i) {
     c->phases[i].Gc = params[3 * i];

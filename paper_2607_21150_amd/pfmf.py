@@ -47,7 +47,8 @@ class MeshDesc(C.Structure):
 
 class PhaseDesc(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("Gc", C.c_double), ("sigma0", C.c_double),
-                ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int)]
+                ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int),
+                ("sigma_inf", C.c_double), ("voce_beta", C.c_double)]
 
 
 class FractureDesc(C.Structure):
@@ -147,7 +148,9 @@ class Context:
         L = load()
         self._phases = list(phases)
         md = MeshDesc(mesh.p, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz)
-        arr = (PhaseDesc * len(phases))(*[PhaseDesc(p.E, p.nu, p.Gc, p.sigma0, p.H, p.visc, int(p.plastic))
+        arr = (PhaseDesc * len(phases))(*[PhaseDesc(p.E, p.nu, p.Gc, p.sigma0, p.H, p.visc, int(p.plastic),
+                                                                 getattr(p, "sigma_inf", 0.0),
+                                                                 getattr(p, "voce_beta", 0.0))
                                           for p in phases])
         fd = FractureDesc(fracture.l0, fracture.eta, fracture.zeta, fracture.dt, fracture.s_phi, int(fracture.at))
         self.n_nodes = mesh.n_nodes

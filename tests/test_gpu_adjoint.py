@@ -100,7 +100,7 @@ def _loss(pf, op, z, params, v):
         return float(torch.sum(r * v))
 
 
-@pytest.mark.parametrize("case,cot", [("C4", "v_top"), ("small", "v_rand")])
+@pytest.mark.parametrize("case,cot", [("C4", "v_top"), ("small", "v_rand"), ("small_voce", "v_rand")])
 def test_central_differences(pf, c4_plastic, case, cot):
     """Central differences of L = <v, R(z; params)> with relative step 1e-6 against the adjoint.
 
@@ -113,7 +113,7 @@ def test_central_differences(pf, c4_plastic, case, cot):
     if case == "C4":
         d, op = c4_plastic
     else:
-        d = I.make_inputs("C1", "plastic", p=2, n=6)
+        d = I.make_inputs("C1", "voce" if case == "small_voce" else "plastic", p=2, n=6)
         op = pf.Context.from_inputs(d)
     print(f"finite differences, {case}, cotangent {cot}", flush=True)
     h = 1e-6

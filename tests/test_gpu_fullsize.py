@@ -60,7 +60,7 @@ def test_q2_32_full_mesh(pf, oracle_lib):
     assert relerr(gz.cpu().numpy(), orc.adjoint(d["z"], d["v_rand"])[0]) <= FP64_TOL
 
 
-@pytest.mark.parametrize("name,variant", [("C3", "base"), ("C3", "plastic"), ("C5", "base")])
+@pytest.mark.parametrize("name,variant", [("C3", "base"), ("C3", "plastic"), ("C3", "voce"), ("C5", "base")])
 def test_large_sampled(pf, oracle_lib, name, variant):
     print(f"case {name} {variant} full size, sampled nodes", flush=True)
     d = I.make_inputs(name, variant)

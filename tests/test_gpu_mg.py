@@ -72,7 +72,7 @@ def restrict_np(r, mesh_n, pf_order, pc_order):
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", None, None),
                                               ("C1", "compress", None, None), ("C1", "plastic", 3, 3),
                                               ("C2", "plastic", 2, 6), ("C1", "plastic", 4, 3),
-                                              ("C1", "base", 4, 2)])
+                                              ("C1", "base", 4, 2), ("C1", "voce", 3, 3)])
 @pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
 def test_fp32_fine_apply_vs_fp64_oracle(pf, oracle_lib, name, variant, p, n, scatter):
     print(f"case {name} {variant} p={p} n={n} {scatter}", flush=True)

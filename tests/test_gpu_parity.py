@@ -48,6 +48,9 @@ CASES = [
     ("C1", "compress", 4, 2),  # Q4, compression (history inactive)
     ("C2", "plastic", 2, 6),   # Q2, several bricks per direction
     ("C1", "plastic", 2, 5),   # Q2, odd element count (bricks with one element layer)
+    ("C1", "voce", None, None),  # Voce hardening (Box 2 Newton return), Q2
+    ("C1", "voce", 3, 3),      # Voce, Q3
+    ("C1", "voce", 4, 2),      # Voce, Q4
 ]
 
 

@@ -31,7 +31,8 @@ def dev(a, dt=torch.float64):
 
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "plastic", None, None), ("C1", "base", None, None),
                                               ("C1", "plastic", 3, 3), ("C1", "plastic", 4, 2),
-                                              ("C2", "plastic", None, None)])
+                                              ("C2", "plastic", None, None), ("C1", "voce", None, None),
+                                              ("C1", "voce", 3, 3)])
 def test_commit_state_matches_oracle(pf, oracle_lib, name, variant, p, n):
     print(f"case commit {name} {variant} p={p} n={n}", flush=True)
     d = I.make_inputs(name, variant, p=p, n=n)
@@ -43,7 +44,7 @@ def test_commit_state_matches_oracle(pf, oracle_lib, name, variant, p, n):
     assert np.abs(got[:6] - ref[:6]).max() <= 1e-12 * sD, np.abs(got[:6] - ref[:6]).max() / sD
     assert np.abs(got[6] - ref[6]).max() <= 1e-13 * max(np.abs(ref[6]).max(), 1e-300)
     assert np.abs(got[7] - ref[7]).max() <= 1e-13 * np.abs(ref[7]).max()
-    if variant == "plastic" and p is None:
+    if variant in ("plastic", "voce") and p is None:
         assert np.any(got[6] > d["state"][6])  # some points flowed
 
 
