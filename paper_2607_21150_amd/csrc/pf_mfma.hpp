@@ -298,7 +298,7 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
 }
 
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
-template <int MODE, bool BB>
+template <int MODE, bool BB, bool VOCE>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     // pointwise function
     const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
     QPState<double> s;
-    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+    qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= s.bad;
     // direction (or cotangent) at the points, interpolated after the state so that its
     // 13 values are not live across the state computation
@@ -500,7 +500,7 @@ namespace pfmf {
 // then runs on a packed layout holding both elements of the wave (lanes 0-26 and
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
 // two elements.
-template <int MODE, bool BB>
+template <int MODE, bool BB, bool VOCE>
 __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTabl
     pid = valid ? a.phase[gq] : 255;
     const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
     QPState<double> s;
-    qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+    qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= valid && s.bad;
     // ---- direction / cotangent at the point
     double W[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};

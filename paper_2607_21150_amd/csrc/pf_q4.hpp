@@ -252,7 +252,7 @@ template <int P, int Q> struct Q5Lds {
 };
 
 // FP64 residual / Jacobian / adjoint on order-4 elements.
-template <int MODE>
+template <int MODE, bool VOCE>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   constexpr int P = 5, Q = 5, Q3 = 125;
   using L = Q5Lds<P, Q>;
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   }
   const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
   QPState<double> s;
-  qp_state<double>(mp, a.fr, G, phi, phin, st, s);
+  qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
   const bool bad = pt && s.bad;
   double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
   if (MODE != M_RES) {

@@ -400,7 +400,9 @@ __device__ inline void qp_frame_stress(const MatParams<T>& m, const T* beta, con
 // Residual state at one point: steps of Box 1 / Box 2 and Section 3.
 //   G: grad_X u (row-major), phi: phase field at the point, phin: previous phi,
 //   st: D[6] (Voigt), ebar_p, H_n.
-template <typename T>
+//   VOCE = false compiles the linear-hardening return only (kernels launched for
+//   contexts without a Voce phase, so that the iteration widens no register budget).
+template <typename T, bool VOCE = true>
 __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, const T* G, T phi,
                                 T phin, const T* st, QPState<T>& s) {
   T beta[3], eps[3];
@@ -413,7 +415,7 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   const T ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
   const T u15 = T(1.5) * ee;
   const T q = (u15 > T(0)) ? T(2) * m.mu * u15 * frsqrt(u15) : T(0);
-  const T sn = yield_stress(m, st[6]);
+  const T sn = VOCE ? yield_stress(m, st[6]) : m.sigma0 + m.H * st[6];
   const T f = s.g * q - sn;
   s.plastic = m.plastic && (f > T(0));
   s.c = T(1);
@@ -425,7 +427,7 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
   if (s.plastic) {
     const T iq = frcp(q);
     T dg;
-    if (m.bv > T(0)) {
+    if (VOCE && m.bv > T(0)) {
       // Voce: Box 2's Newton iteration on g q - 3 g mu dg - sigma_y(ebar_n + dg)(1 + a dg) = 0
       // from dg = 0, kept inside [0, q / (3 mu)] (positive, resp. negative, at the ends)
       // by bisection when a step leaves it; bounded, lanes finish independently
@@ -451,13 +453,13 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
     s.dg = dg;
     s.c = T(1) - T(3) * m.mu * dg * iq;
     const T ep = st[6] + dg;
-    const T sy = yield_stress(m, ep);
-    const T den = T(3) * s.g * m.mu + yield_slope(m, ep) * (T(1) + m.a * dg) + m.a * sy;
+    const T sy = VOCE ? yield_stress(m, ep) : sn + m.H * dg;
+    const T den = T(3) * s.g * m.mu + (VOCE ? yield_slope(m, ep) : m.H) * (T(1) + m.a * dg) + m.a * sy;
     const T iden = frcp(den);
     const T w = T(3) * m.mu * iq;
     s.kq = -w * (s.g * iden - dg * iq) * (T(6) * m.mu * m.mu * iq);
     s.kphi = -w * s.gp * (q - T(3) * m.mu * dg) * iden;
-    s.ddg_s0 = -(T(1) + m.a * dg) * (m.bv > T(0) ? exp(-m.bv * ep) : T(1)) * iden;
+    s.ddg_s0 = -(T(1) + m.a * dg) * ((VOCE && m.bv > T(0)) ? exp(-m.bv * ep) : T(1)) * iden;
     s.ddg_visc = -sy * dg * fr.inv_dt * iden;
   }
   // block stress, Amor split, psi^+ (eq:principal-stress-update-eigenvalues,

@@ -50,6 +50,7 @@ struct pf_ctx {
   int64_t n_nodes = 0, n_q = 0;
   int nbx = 0, nby = 0, nbz = 0, n_bricks = 0;
   int n_parts = 0;  // slots of the adjoint's parameter partials
+  bool has_voce = false;  // some plastic phase hardens by the Voce law
   int colour_base[9] = {0};
   std::vector<pf_phase> phases;
   pf_fracture fr{};
@@ -218,8 +219,8 @@ inline bool use_brick_buffer(const pf_ctx* c) {
   return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
 }
 
-template <int MODE, int P>
-pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
+template <int MODE, int P, bool VOCE>
+pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   const bool bb = use_brick_buffer(c);
   if (bb) {
     constexpr int NB = 2 * P - 1;
@@ -230,9 +231,9 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
     a.brick_base = 0;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = c->ny1 * c->nz1;
     hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -245,9 +246,26 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
     if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
     if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, false>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, false>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+// kernels without the Voce iteration unless a phase uses it
+template <int MODE, int P>
+pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
+  return c->has_voce ? launch_op64_mfma_v<MODE, P, true>(c, a, s) : launch_op64_mfma_v<MODE, P, false>(c, a, s);
+}
+
+template <int MODE, bool VOCE>
+pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
+    if (ng == 0) continue;
+    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -255,13 +273,7 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE>
 pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
-  for (int col = 0; col < 8; ++col) {
-    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
-    if (ng == 0) continue;
-    hipLaunchKernelGGL((k_op64_q4<MODE>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
-    HIPCHK(hipGetLastError());
-  }
-  return PF_OK;
+  return c->has_voce ? launch_op64_q4_v<MODE, true>(c, a, s) : launch_op64_q4_v<MODE, false>(c, a, s);
 }
 
 template <int MODE>
@@ -354,6 +366,7 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
   for (int col = 0; col < 8; ++col)
     c->colour_base[col + 1] = c->colour_base[col] + bricks_in_colour(c->nbx, c->nby, c->nbz, col);
   c->phases.assign(phases, phases + n_phases);
+  for (int i = 0; i < n_phases; ++i) c->has_voce |= phases[i].plastic && phases[i].voce_beta > 0;
   c->fr = *fr;
   c->qp_phase = qp_phase;
   c->qp_state = qp_state;
