@@ -156,6 +156,10 @@ pf_status pf_set_pmg_levels(pf_ctx* ctx, const int* orders, int n_levels);
  * the option (order 4 launches one element per workgroup in 8 parity colours). */
 #define PF_OPT_SCATTER 1
 #define PF_SCATTER_AUTO_BYTES (4LL << 30)
+/* PF_OPT_STORE_LIN64 (default 1): pf_linearize also stores the linearisation record
+ * in FP64 (15 doubles per point, sharing the FP32 record's flag bytes) and a copy of u,
+ * for pf_apply_jacobian_lin; 0 skips both. */
+#define PF_OPT_STORE_LIN64 2
 pf_status pf_set_option(pf_ctx* ctx, int option, int value);
 
 /* Dirichlet faces for the multigrid and the Newton step: bit f of face_fields[k]
@@ -195,7 +199,9 @@ typedef struct {
 /* One Newton update z += dz of the coupled problem with the Dirichlet faces of
  * pf_set_dirichlet: M J(z) dz = -M R(z) (M zeroes constrained entries, which z must
  * already hold at their prescribed values), solved by restarted flexible GMRES with
- * the FP64 Jacobian apply and one FP32 p-multigrid V-cycle per iteration as right
+ * the FP64 Jacobian apply (from the stored FP64 linearisation when PF_OPT_STORE_LIN64
+ * is on and p >= 2, else recomputed; the reported true residual always uses the
+ * recomputed one) and one FP32 p-multigrid V-cycle per iteration as right
  * preconditioner (re-linearised at z; the paper's solver is GMRES with p-multigrid,
  * Section 5). Allocates its Krylov workspace ((2 restart + 4) vectors of 4 n_nodes
  * doubles) on first use and keeps it. Synchronises the stream. Returns PF_ENOCONV when
@@ -212,6 +218,16 @@ pf_status pf_level_info(const pf_ctx* ctx, int level, int* p, int64_t* n_nodes);
  * dz, y: device float[4][n_nodes(level)]. */
 pf_status pf_apply_jacobian_f32(pf_ctx* ctx, int level, const float* dz, float* y,
                                 void* stream);
+
+/* FP64 Jacobian action at the last linearisation point z (Section 4, with the pointwise
+ * linearisation of Appendices A-C evaluated once by pf_linearize and stored): y = J(z) dz
+ * from the stored FP64 record and the copy of u, orders 2-4. Same operator as
+ * pf_apply_jacobian at that z (the decisions, frame and coefficients are the FP64 ones;
+ * the results differ by rounding only), without recomputing the eigen-frame and return
+ * mapping at every apply: for Krylov iterations at one Newton iterate. dz, y: device
+ * [4][n_nodes] FP64; y must not alias dz. Needs pf_linearize with PF_OPT_STORE_LIN64 on
+ * (PF_EINVAL otherwise); pf_set_params invalidates the linearisation. */
+pf_status pf_apply_jacobian_lin(pf_ctx* ctx, const double* dz, double* y, void* stream);
 
 /* Level transfer: prolongation xf = P xc (coarse level l+1 -> level l, exact
  * interpolation of the coarse field at the fine nodes) and restriction rc = P^T rf.

@@ -731,9 +731,9 @@ namespace pfmf {
 // nodes PC <= 3, 3 Gauss points): the packing of k_op64_q2 (sum factorisation per
 // element on the padded 4 x 4 layout, the pointwise JVP once for both elements of the
 // wave on lanes 0-26 and 32-58) with the FP32 record path of k_a32_q3.
-template <int PC, bool BB>
-__global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTables* __restrict__ tabs) {
-  __shared__ float ev[8 * 4 * 64];
+template <typename V, int PC, bool BB>
+__global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ V ev[8 * 4 * 64];
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
   const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
@@ -750,13 +750,13 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTabl
   const int pqx = l & 3, pqz = (l >> 2) & 3, pqy = l >> 4;
   const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
   const int pq = pqx + 3 * pqy + 9 * pqz;
-  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
-  const float wdet = (float)(tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz < 3 ? cqz : 0] *
+  const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
+  const V wdet = (V)(tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz < 3 ? cqz : 0] *
                              a.m.jdet);
   if (hasA) {
-    float G[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float W[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float wphi = 0.f, gw[3] = {0.f, 0.f, 0.f};
+    V G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    V W[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    V wphi = 0, gw[3] = {0, 0, 0};
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       if (half == 1 && !hasB) break;  // uniform
@@ -776,7 +776,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTabl
 #pragma unroll
           for (int J = 0; J < 3; ++J) {
             const double r = lane_read(d[f][J], src_fwd);
-            if (mine) G[3 * f + J] = (float)r * ih[J];
+            if (mine) G[3 * f + J] = (V)r * ih[J];
           }
       }
       {
@@ -787,31 +787,31 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTabl
 #pragma unroll
           for (int J = 0; J < 3; ++J) {
             const double r = lane_read(d[f][J], src_fwd);
-            if (mine) W[3 * f + J] = (float)r * ih[J];
+            if (mine) W[3 * f + J] = (V)r * ih[J];
           }
         const double rp = lane_read(v[3], src_fwd);
-        if (mine) wphi = (float)rp;
+        if (mine) wphi = (V)rp;
 #pragma unroll
         for (int J = 0; J < 3; ++J) {
           const double r = lane_read(d[3][J], src_fwd);
-          if (mine) gw[J] = (float)r * ih[J];
+          if (mine) gw[J] = (V)r * ih[J];
         }
       }
     }
     // pointwise JVP from the record (packed layout)
     const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
     const int64_t gq = e * 27 + q;
-    LinRecord rc;
+    LinRecordT<V> rc;
 #pragma unroll
-    for (int k = 0; k < REC_N; ++k) rc.v[k] = valid ? a.rec.rec[k * a.n_q + gq] : 0.f;
+    for (int k = 0; k < REC_N; ++k) rc.v[k] = valid ? a.rec.rec[k * a.n_q + gq] : V(0);
     rc.flags = valid ? a.rec.flags[gq] : 0;
     const int pid = valid ? a.phase[gq] : 0;
-    const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
-    QPState<float> s;
-    qp_state_lin<float>(mp, G, rc, s);
-    float Fu[9], dL;
-    qp_tangent<float>(mp, s, W, wphi, Fu, dL);
-    const float kfg = a.fr.kf * mp.Gc;
+    const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<V> s;
+    qp_state_lin<V>(mp, G, rc, s);
+    V Fu[9], dL;
+    qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+    const V kfg = a.fr.kf * mp.Gc;
     double b1p[4][3], b0p3;
 #pragma unroll
     for (int f = 0; f < 3; ++f)
@@ -842,22 +842,22 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(A32Args a, int colour, DevTabl
       sf4_bwd_n<4>(b0, b1, 0x8u, bc, r);
       const int slot = wv + 4 * half;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (float)r[f];
+      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (V)r[f];
     }
   }
   __syncthreads();
   if (BB)
-    store_brick4<float, PC, 4>(ev, a.m, g, a.ebuf);
+    store_brick4<V, PC, 4>(ev, a.m, g, a.ebuf);
   else
-    scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+    scatter_brick4<V, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }
 
 // FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
 // level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
 // contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).
-template <int PC, bool BB>
-__global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTables* __restrict__ tabs) {
-  __shared__ float ev[8 * 4 * 64];
+template <typename V, int PC, bool BB>
+__global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
+  __shared__ V ev[8 * 4 * 64];
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
@@ -867,8 +867,8 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
   const int ql = qx + 4 * qy + 16 * qz;
-  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
-  const float wdet = (float)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet);
+  const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
+  const V wdet = (V)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet);
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
     const int slot = wv + 4 * half;
@@ -883,19 +883,19 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
     for (int f = 0; f < 4; ++f) wu[f] = gc >= 0 ? (double)a.dz[f * a.lev.n_nodes + gc] : 0.0;
     const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
     const int64_t gq = e * 64 + ql;
-    LinRecord rc;
+    LinRecordT<V> rc;
 #pragma unroll
     for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
     rc.flags = a.rec.flags[gq];
     const int pid = a.phase[gq];
-    float G[9], W[9], wphi, gw[3];
+    V G[9], W[9], wphi, gw[3];
     {
       double v[3], d[3][3];
       sf4_fwd_n<3>(zu, bf, 0x0u, 0x7u, v, d);
 #pragma unroll
       for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int J = 0; J < 3; ++J) G[3 * f + J] = (float)d[f][J] * ih[J];
+        for (int J = 0; J < 3; ++J) G[3 * f + J] = (V)d[f][J] * ih[J];
     }
     {
       double v[4], d[4][3];
@@ -903,17 +903,17 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
 #pragma unroll
       for (int f = 0; f < 3; ++f)
 #pragma unroll
-        for (int J = 0; J < 3; ++J) W[3 * f + J] = (float)d[f][J] * ih[J];
-      wphi = (float)v[3];
+        for (int J = 0; J < 3; ++J) W[3 * f + J] = (V)d[f][J] * ih[J];
+      wphi = (V)v[3];
 #pragma unroll
-      for (int J = 0; J < 3; ++J) gw[J] = (float)d[3][J] * ih[J];
+      for (int J = 0; J < 3; ++J) gw[J] = (V)d[3][J] * ih[J];
     }
-    const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
-    QPState<float> s;
-    qp_state_lin<float>(mp, G, rc, s);
-    float Fu[9], dL;
-    qp_tangent<float>(mp, s, W, wphi, Fu, dL);
-    const float kfg = a.fr.kf * mp.Gc;
+    const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+    QPState<V> s;
+    qp_state_lin<V>(mp, G, rc, s);
+    V Fu[9], dL;
+    qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+    const V kfg = a.fr.kf * mp.Gc;
     double b0[4], b1[4][3], r[4];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -926,13 +926,13 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(A32Args a, int colour, DevTabl
     for (int J = 0; J < 3; ++J) b1[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
     sf4_bwd_n<4>(b0, b1, 0x8u, bc, r);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (float)r[f];
+    for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (V)r[f];
   }
   __syncthreads();
   if (BB)
-    store_brick4<float, PC, 4>(ev, a.m, g, a.ebuf);
+    store_brick4<V, PC, 4>(ev, a.m, g, a.ebuf);
   else
-    scatter_brick4<float, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+    scatter_brick4<V, PC, 4>(ev, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }
 
 }  // namespace pfmf

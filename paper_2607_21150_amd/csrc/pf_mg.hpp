@@ -17,10 +17,11 @@
 
 namespace pfmf {
 
-struct RecordSoA {
-  float* rec;      // [REC_N][n_q], slots as in LinRecord
+template <typename V> struct RecordSoAT {
+  V* rec;          // [REC_N][n_q], slots as in LinRecordT
   uint8_t* flags;  // [n_q]
 };
+using RecordSoA = RecordSoAT<float>;
 
 struct LevelDev {
   int P;           // nodes per direction of this level's elements
@@ -55,8 +56,11 @@ struct MGState {
   float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
   float* stencil = nullptr;  // the same level as a block stencil [27][4][4][n_nodes]
   float* ebuf32 = nullptr;   // brick-buffer scatter of the FP32 level applies
+  double* rec64 = nullptr;   // stored FP64 linearisation [REC_N][n_q] (flags in rec.flags)
+  double* u64 = nullptr;     // u at the linearisation point [3][n_nodes]
   int ebe_level = -1;
   bool linearized = false;
+  bool lin64_valid = false;  // rec64 / u64 hold the current linearisation
 };
 
 inline void mg_free_level(MGLevel& L) {
@@ -82,6 +86,8 @@ inline void mg_free(MGState& mg) {
   (void)hipFree(mg.ebe);
   (void)hipFree(mg.stencil);
   (void)hipFree(mg.ebuf32);
+  (void)hipFree(mg.rec64);
+  (void)hipFree(mg.u64);
   mg = MGState();
 }
 
@@ -102,6 +108,7 @@ struct LinArgs {
   int nph;
   FracParams<double> fr;
   RecordSoA rec;
+  double* rec64;         // MODE 0: the same record in FP64 [REC_N][n_q] (flags shared), or null
   double* state_out;
   int* flag;
 };
@@ -171,6 +178,12 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
 #pragma unroll
         for (int k = 0; k < REC_N; ++k) a.rec.rec[k * a.n_q + gq] = rc.v[k];
         a.rec.flags[gq] = rc.flags;
+        if (a.rec64) {
+          LinRecordT<double> r64;
+          record_from_state(s, r64);
+#pragma unroll
+          for (int k = 0; k < REC_N; ++k) a.rec64[k * a.n_q + gq] = r64.v[k];
+        }
       } else {
         double ns[8];
         commit_from_state(s, G, st, ns);
@@ -187,20 +200,23 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
 // PF: fine nodes per direction (kinematics), PC: this level's nodes per direction.
 // ---------------------------------------------------------------------------
 
-struct A32Args {
+// Arguments of the linearised applies from a record: V = float for the FP32 multigrid
+// levels, V = double for the FP64 apply from the stored linearisation (fine level).
+template <typename V> struct LinApplyArgs {
   MeshDev m;
   LevelDev fine, lev;
   int64_t n_q;
-  const float* z32;      // fine u mirror [3][n_fine]
-  const float* dz;       // level vector [4][n_lev]
-  RecordSoA rec;
+  const V* z32;          // fine u at the linearisation point [3][n_fine]
+  const V* dz;           // level vector [4][n_lev]
+  RecordSoAT<V> rec;
   const uint8_t* phase;
-  const MatParams<float>* mats;
+  const MatParams<V>* mats;
   int nph;
-  FracParams<float> fr;
-  float* out;
-  float* ebuf;           // brick-buffer scatter: per-brick node sums [n_bricks][4][(2PC-1)^3]
+  FracParams<V> fr;
+  V* out;
+  V* ebuf;               // brick-buffer scatter (extended node grid)
 };
+using A32Args = LinApplyArgs<float>;
 
 template <int PF, int PC, int Q> struct A32Shape {
   static constexpr int PM = PF > PC ? PF : PC;

@@ -178,24 +178,29 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
   return fail(PF_EUNSUPPORTED, "level order not built");
 }
 
-// FP32 level apply on the matrix cores: PF = 4 (order-3 mesh, k_a32_q3) or PF = 3
-// (order-2 mesh, k_a32_q2)
-template <int PF, int PC>
-pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
+// Linearised apply on the matrix cores: PF = 4 (order-3 mesh, k_a32_q3) or PF = 3
+// (order-2 mesh, k_a32_q2); V = float for the FP32 levels, V = double for the apply
+// from the stored FP64 linearisation (fine level). The brick buffer of each precision
+// is sized for the fine level and shared by the coarser ones.
+template <typename V, int PF, int PC>
+pf_status launch_lin_mfma(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
   if (use_brick_buffer(c)) {
-    // sized for the largest level (PC = 4); every level of the hierarchy shares it
-    if (!c->mg.ebuf32 && hipMalloc(&c->mg.ebuf32, (size_t)c->n_bricks * 4 * 343 * sizeof(float)) != hipSuccess)
+    V** buf;
+    if constexpr (sizeof(V) == 4) buf = &c->mg.ebuf32;
+    else buf = &c->d_ebuf;
+    constexpr int NBF = 2 * PF - 1;
+    if (!*buf && hipMalloc((void**)buf, (size_t)c->n_bricks * 4 * NBF * NBF * NBF * sizeof(V)) != hipSuccess)
       return fail(PF_ENOMEM, "brick buffer: allocation failed");
-    a.ebuf = c->mg.ebuf32;
+    a.ebuf = *buf;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
-    hipLaunchKernelGGL((k_gather_bricks<float, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
-                       (const float*)c->mg.ebuf32, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
+    hipLaunchKernelGGL((k_gather_bricks<V, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const V*)a.ebuf, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }
@@ -203,9 +208,28 @@ pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int PF, int PC>
+pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
+  return launch_lin_mfma<float, PF, PC>(c, a, s);
+}
+
+template <typename V, int PC>
+pf_status launch_lin_q4(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
+  for (int col = 0; col < 8; ++col) {
+    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
+    if (ng == 0) continue;
+    if constexpr (sizeof(V) == 4)
+      hipLaunchKernelGGL((k_a32_q4<V, PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
+    else
+      hipLaunchKernelGGL((k_a32_q4<V, PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -213,13 +237,7 @@ pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
 
 template <int PC>
 pf_status launch_a32_q4(pf_ctx* c, const A32Args& a, hipStream_t s) {
-  for (int col = 0; col < 8; ++col) {
-    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
-    if (ng == 0) continue;
-    hipLaunchKernelGGL((k_a32_q4<PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
-    HIPCHK(hipGetLastError());
-  }
-  return PF_OK;
+  return launch_lin_q4<float, PC>(c, a, s);
 }
 
 EbeArgs ebe_args(pf_ctx* c) {
@@ -464,6 +482,12 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   MGState& mg = c->mg;
   hipLaunchKernelGGL(k_mirror_u, dim3(vec_grid(3 * c->n_nodes)), dim3(NT), 0, s, z, mg.z32, c->n_nodes);
   HIPCHK(hipGetLastError());
+  if (c->store_lin64) {
+    if ((!mg.rec64 && hipMalloc(&mg.rec64, (size_t)REC_N * c->n_q * sizeof(double)) != hipSuccess) ||
+        (!mg.u64 && hipMalloc(&mg.u64, (size_t)3 * c->n_nodes * sizeof(double)) != hipSuccess))
+      return fail(PF_ENOMEM, "stored linearisation: allocation failed");
+    HIPCHK(hipMemcpyAsync(mg.u64, z, (size_t)3 * c->n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   LinArgs a;
   a.m = mesh_dev(c);
   a.nx1 = c->nx1;
@@ -478,6 +502,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.nph = (int)c->phases.size();
   a.fr = frac_params<double>(c->fr);
   a.rec = mg.rec;
+  a.rec64 = c->store_lin64 ? mg.rec64 : nullptr;
   a.state_out = nullptr;
   a.flag = c->d_flag;
   switch (c->mesh.p) {
@@ -490,6 +515,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   if (st) return st;
   if (mg.ebe_level >= 0 && (st = ebe_assemble(c, s))) return st;
   mg.linearized = true;
+  mg.lin64_valid = c->store_lin64;
   // lambda_max(D^-1 A) per level by 15 power iterations, normalised on the device
   // (no host round trip inside the loop); one synchronisation at the end
   constexpr int POWER_ITS = 15;
@@ -611,6 +637,42 @@ pf_status pf_apply_jacobian_f32(pf_ctx* c, int level, const float* dz, float* y,
   if (overlaps(dz, nb, y, nb)) return fail(PF_EINVAL, "y aliases dz");
   c->last_stream = (hipStream_t)stream;
   return level_op<0>(c, level, dz, y, (hipStream_t)stream);
+}
+
+// FP64 Jacobian at the linearisation point from the stored FP64 record: the FP32
+// level apply's kernels instantiated in FP64 on the fine level (u from the copy taken
+// at pf_linearize).
+pf_status pf_apply_jacobian_lin(pf_ctx* c, const double* dz, double* y, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (!c->mg.linearized || !c->mg.lin64_valid)
+    return fail(PF_EINVAL, "call pf_linearize with PF_OPT_STORE_LIN64 on first");
+  if (!dz || !y) return fail(PF_EINVAL, "null vector");
+  const size_t nb = 4 * c->n_nodes * sizeof(double);
+  if (overlaps(dz, nb, y, nb)) return fail(PF_EINVAL, "y aliases dz");
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  LinApplyArgs<double> a;
+  a.m = mesh_dev(c);
+  const MGLevel& F = c->mg.lv[0];
+  a.fine = LevelDev{F.P, F.nx1, F.ny1, F.n_nodes};
+  a.lev = a.fine;
+  a.n_q = c->n_q;
+  a.z32 = c->mg.u64;
+  a.dz = dz;
+  a.rec = RecordSoAT<double>{c->mg.rec64, c->mg.rec.flags};
+  a.phase = c->qp_phase;
+  a.mats = c->d_mats;
+  a.nph = (int)c->phases.size();
+  a.fr = frac_params<double>(c->fr);
+  a.out = y;
+  a.ebuf = nullptr;
+  switch (c->mesh.p) {
+    case 2: return launch_lin_mfma<double, 3, 3>(c, a, s);
+    case 3: return launch_lin_mfma<double, 4, 4>(c, a, s);
+    case 4: return launch_lin_q4<double, 5>(c, a, s);
+    default: return fail(PF_EUNSUPPORTED, "the stored-linearisation apply is built for orders 2-4");
+  }
 }
 
 pf_status pf_prolong(pf_ctx* c, int level, const float* xc, float* xf, void* stream) {

@@ -73,12 +73,20 @@ pf_status precondition(pf_ctx* c, const double* v, double* x, const pf_pmg_opts&
 }
 
 // y = M J x on the unconstrained subspace (x vanishes on constrained entries)
-pf_status masked_jacobian(pf_ctx* c, const double* z, const double* x, double* y, hipStream_t s) {
-  OpArgs a = op_args(c);
-  a.z = z;
-  a.w = x;
-  a.out = y;
-  pf_status st = dispatch_op64<M_JAC>(c, a, s);
+// M J(z) x: from the stored FP64 linearisation when the step linearised with it (the
+// same operator, without recomputing the point state), else recomputed
+pf_status masked_jacobian(pf_ctx* c, const double* z, const double* x, double* y, hipStream_t s,
+                          bool stored = true) {
+  pf_status st;
+  if (stored && c->mg.lin64_valid && c->mesh.p >= 2) {
+    st = pf_apply_jacobian_lin(c, x, y, s);
+  } else {
+    OpArgs a = op_args(c);
+    a.z = z;
+    a.w = x;
+    a.out = y;
+    st = dispatch_op64<M_JAC>(c, a, s);
+  }
   if (st) return st;
   return mask_fine64(c, y, s);
 }
@@ -211,8 +219,9 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
     }
     if ((st = maxpy(c, Z, n, k, y.data(), dz, n, s))) return st;
   }
-  // true linear residual ||b - M J dz|| / ||b||, then z += dz
-  if ((st = masked_jacobian(c, z, dz, w, s))) return st;
+  // true linear residual ||b - M J dz|| / ||b|| with the recomputed Jacobian (an
+  // independent check of the stored one used by the iteration), then z += dz
+  if ((st = masked_jacobian(c, z, dz, w, s, false))) return st;
   hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, -1.0, w, w, n, 0);
   hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, rhs, w, n, 1);
   double rt;

@@ -398,12 +398,18 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
 
 // FP32 level apply (direction on a level with PC nodes per direction, kinematics on the
 // fine order-4 lattice) on order-4 fine elements.
-template <int PC>
-__global__ __launch_bounds__(NT5, 2) void k_a32_q4(A32Args a, int colour, DevTablesF* __restrict__ tabs) {
+template <typename V> struct TablesOf;
+template <> struct TablesOf<float> { using type = DevTablesF; };
+template <> struct TablesOf<double> { using type = DevTables; };
+
+template <typename V, int PC>
+__global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour,
+                                                   const typename TablesOf<V>::type* __restrict__ tabs) {
+  using Tab = typename TablesOf<V>::type;
   constexpr int PF = 5, Q = 5, Q3 = 125;
   using L = Q5Lds<PF, Q>;
-  __shared__ float bufA[L::A];
-  __shared__ float bufB[L::B];
+  __shared__ V bufA[L::A];
+  __shared__ V bufB[L::B];
   ElemGeom g;
   if (!xcd_elem(a.m, colour, blockIdx.x, g)) return;  // padding workgroup (uniform)
   const int t = threadIdx.x;
@@ -412,26 +418,26 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(A32Args a, int colour, DevTab
   const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
   const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
   const int64_t gq = e * Q3 + ql;
-  LinRecord rc;
+  LinRecordT<V> rc;
 #pragma unroll
-  for (int k = 0; k < REC_N; ++k) rc.v[k] = pt ? a.rec.rec[k * a.n_q + gq] : 0.f;
+  for (int k = 0; k < REC_N; ++k) rc.v[k] = pt ? a.rec.rec[k * a.n_q + gq] : V(0);
   rc.flags = pt ? a.rec.flags[gq] : 0;
   const int pid = pt ? a.phase[gq] : 0;
-  const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
-  const float wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (float)a.m.jdet;
-  gather_elem<float, float, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, bufA);
+  const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
+  const V wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (V)a.m.jdet;
+  gather_elem<V, V, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, bufA);
   __syncthreads();
-  sf5_fwd<float, DevTablesF, PF, Q, 3>(bufA, bufB, tabs);
-  float G[9];
+  sf5_fwd<V, Tab, PF, Q, 3>(bufA, bufB, tabs);
+  V G[9];
 #pragma unroll
   for (int f = 0; f < 3; ++f)
 #pragma unroll
     for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
   __syncthreads();
-  gather_elem<float, float, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
+  gather_elem<V, V, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
   __syncthreads();
-  sf5_fwd<float, DevTablesF, PC, Q, 4>(bufA, bufB, tabs);
-  float W[9], wphi, gw[3];
+  sf5_fwd<V, Tab, PC, Q, 4>(bufA, bufB, tabs);
+  V W[9], wphi, gw[3];
 #pragma unroll
   for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -440,16 +446,16 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(A32Args a, int colour, DevTab
 #pragma unroll
   for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
   __syncthreads();
-  const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
-  QPState<float> s;
-  qp_state_lin<float>(mp, G, rc, s);
-  float Fu[9], dL;
-  qp_tangent<float>(mp, s, W, wphi, Fu, dL);
-  const float kfg = a.fr.kf * mp.Gc;
+  const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+  QPState<V> s;
+  qp_state_lin<V>(mp, G, rc, s);
+  V Fu[9], dL;
+  qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+  const V kfg = a.fr.kf * mp.Gc;
   if (pt) {
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      bufB[(4 * f) * Q3 + ql] = 0.f;
+      bufB[(4 * f) * Q3 + ql] = V(0);
 #pragma unroll
       for (int J = 0; J < 3; ++J) bufB[(4 * f + 1 + J) * Q3 + ql] = wdet * Fu[3 * f + J] * ih[J];
     }
@@ -458,8 +464,8 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(A32Args a, int colour, DevTab
     for (int J = 0; J < 3; ++J) bufB[(13 + J) * Q3 + ql] = wdet * kfg * gw[J] * ih[J];
   }
   __syncthreads();
-  sf5_bwd<float, DevTablesF, PC, Q, 4>(bufB, bufA, tabs);
-  scatter_elem<float, PC, 4>(bufA, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+  sf5_bwd<V, Tab, PC, Q, 4>(bufB, bufA, tabs);
+  scatter_elem<V, PC, 4>(bufA, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }
 
 }  // namespace pfmf

@@ -497,10 +497,12 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
 // the off-diagonal divided-difference coefficients.
 constexpr int REC_N = 15;
 enum RecSlot { R_C = 0, R_KQ, R_KPHI, R_G, R_GP, R_DL, R_Q0, R_E0 = R_Q0 + 3, R_O0 = R_E0 + 3 };
-struct LinRecord {
-  float v[REC_N];
+// V = float: the FP32 multigrid record; V = double: the stored FP64 linearisation.
+template <typename V> struct LinRecordT {
+  V v[REC_N];
   uint8_t flags;  // bit0 tension, bit1 history active, bit2 plastic, bits 3-4 dropped quaternion index
 };
+using LinRecord = LinRecordT<float>;
 
 // Unit quaternion (w, x, y, z) of a rotation matrix R (row-major), by the
 // largest-diagonal-element case split of Shepperd's method (no cancellation).
@@ -532,13 +534,14 @@ __device__ inline void quat_to_rot(const T* q, T* R) {
   R[6] = T(2) * (xz - wy);          R[7] = T(2) * (yz + wx);          R[8] = T(1) - T(2) * (xx + yy);
 }
 
-__device__ inline void record_from_state(const QPState<double>& s, LinRecord& r) {
-  r.v[R_C] = (float)s.c;
-  r.v[R_KQ] = (float)s.kq;
-  r.v[R_KPHI] = (float)s.kphi;
-  r.v[R_G] = (float)s.g;
-  r.v[R_GP] = (float)s.gp;
-  r.v[R_DL] = (float)s.dLcoef;
+template <typename V>
+__device__ inline void record_from_state(const QPState<double>& s, LinRecordT<V>& r) {
+  r.v[R_C] = (V)s.c;
+  r.v[R_KQ] = (V)s.kq;
+  r.v[R_KPHI] = (V)s.kphi;
+  r.v[R_G] = (V)s.g;
+  r.v[R_GP] = (V)s.gp;
+  r.v[R_DL] = (V)s.dLcoef;
   // a proper rotation: flipping an eigenvector's sign leaves the tangent unchanged
   double R[9];
   for (int k = 0; k < 9; ++k) R[k] = s.N[k];
@@ -553,11 +556,11 @@ __device__ inline void record_from_state(const QPState<double>& s, LinRecord& r)
     if (fabs(q[k]) > fabs(q[m])) m = k;
   const double sg = q[m] < 0.0 ? -1.0 : 1.0;
   for (int k = 0, o = 0; k < 4; ++k)
-    if (k != m) r.v[R_Q0 + o++] = (float)(sg * q[k]);
+    if (k != m) r.v[R_Q0 + o++] = (V)(sg * q[k]);
   const double th3 = s.theta * (1.0 / 3.0);
   for (int i = 0; i < 3; ++i) {
-    r.v[R_E0 + i] = (float)(s.e[i] + th3);
-    r.v[R_O0 + i] = (float)s.coef[i];
+    r.v[R_E0 + i] = (V)(s.e[i] + th3);
+    r.v[R_O0 + i] = (V)s.coef[i];
   }
   r.flags = (s.tension ? 1 : 0) | (s.hactive ? 2 : 0) | (s.plastic ? 4 : 0) | (m << 3);
 }
@@ -601,7 +604,7 @@ __device__ inline void commit_from_state(const QPState<double>& s, const double*
 // State for the linearised FP32 apply: F^-1 from the FP32 displacement mirror,
 // everything else (frame, principal values, decisions, coefficients) from the record.
 template <typename T>
-__device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const LinRecord& r, QPState<T>& s) {
+__device__ inline void qp_state_lin(const MatParams<T>& m, const T* G, const LinRecordT<T>& r, QPState<T>& s) {
   T F[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) F[k] = G[k] + ((k % 4 == 0) ? T(1) : T(0));

@@ -65,6 +65,7 @@ struct pf_ctx {
   double* d_gpart = nullptr;
   double* d_ebuf = nullptr;  // brick-buffer scatter (allocated on first use)
   int scatter_mode = 0;      // PF_OPT_SCATTER
+  bool store_lin64 = true;   // PF_OPT_STORE_LIN64
   int* d_flag = nullptr;
   hipStream_t last_stream = nullptr;
   MGState mg;
@@ -407,6 +408,8 @@ pf_status pf_set_params(pf_ctx* c, const double* params) {
     if (c->phases[i].voce_beta > 0 && !(c->phases[i].sigma_inf >= s0))
       return fail(PF_EINVAL, "phase %zu: Voce needs sigma_inf >= sigma0", i);
   }
+  c->mg.linearized = false;  // the records hold decisions taken with the old parameters
+  c->mg.lin64_valid = false;
   for (size_t i = 0; i < c->phases.size(); ++i) {
     c->phases[i].Gc = params[3 * i];
     c->phases[i].sigma0 = params[3 * i + 1];
@@ -474,6 +477,11 @@ pf_status pf_set_option(pf_ctx* c, int option, int value) {
     case PF_OPT_SCATTER:
       if (value < 0 || value > 2) return fail(PF_EINVAL, "PF_OPT_SCATTER takes 0, 1 or 2, not %d", value);
       c->scatter_mode = value;
+      return PF_OK;
+    case PF_OPT_STORE_LIN64:
+      if (value < 0 || value > 1) return fail(PF_EINVAL, "PF_OPT_STORE_LIN64 takes 0 or 1, not %d", value);
+      c->store_lin64 = value != 0;
+      c->mg.lin64_valid = false;
       return PF_OK;
     default:
       return fail(PF_EINVAL, "unknown option %d", option);

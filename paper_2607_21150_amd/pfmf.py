@@ -23,10 +23,12 @@ EXPORTED = [
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
+    "pf_apply_jacobian_lin",
 ]
 
 # pf_set_option
 PF_OPT_SCATTER = 1
+PF_OPT_STORE_LIN64 = 2
 SCATTER_MODES = {"auto": 0, "colour": 1, "brick_buffer": 2}
 
 # face indices of pf_set_dirichlet and field bits
@@ -106,6 +108,7 @@ def load():
     L.pf_commit_state.argtypes = [vp, vp, vp, vp]
     L.pf_newton_step.argtypes = [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp]
     L.pf_set_option.argtypes = [vp, C.c_int, C.c_int]
+    L.pf_apply_jacobian_lin.argtypes = [vp, vp, vp, vp]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -230,6 +233,16 @@ class Context:
         y = torch.empty_like(dz) if y is None else _req(y, torch.float32, (4, n), "y")
         _check(load().pf_apply_jacobian_f32(self._h, int(level), _ptr(dz), _ptr(y), _stream(stream)))
         return y
+
+    def apply_jacobian_lin(self, dz, y=None, stream=None):
+        """FP64 Jacobian at the last linearisation point, from the stored FP64 record."""
+        _req(dz, torch.float64, (4, self.n_nodes), "dz")
+        y = torch.empty_like(dz) if y is None else _req(y, torch.float64, (4, self.n_nodes), "y")
+        _check(load().pf_apply_jacobian_lin(self._h, _ptr(dz), _ptr(y), _stream(stream)))
+        return y
+
+    def set_store_lin64(self, on):
+        _check(load().pf_set_option(self._h, PF_OPT_STORE_LIN64, int(bool(on))))
 
     def prolong(self, level, xc, xf=None, stream=None):
         _, nf = self.level_info(level)

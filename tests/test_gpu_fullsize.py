@@ -86,6 +86,9 @@ def test_large_sampled(pf, oracle_lib, name, variant):
     assert e <= FP64_TOL, ("adjoint", e)
     if name in ("C3", "C5"):
         ctx.linearize(z)
+        ylin = ctx.apply_jacobian_lin(dz).cpu().numpy()
+        e = sampled(mesh, ylin, lambda el: orc.jacobian(d["z"], d["dz"], elems=el), rng)
+        assert e <= FP64_TOL, ("stored-linearisation jacobian", e)
         y32 = ctx.apply_jacobian_f32(0, dz.float()).double().cpu().numpy()
         ctx.check()
         e = sampled(mesh, y32, lambda el: orc.jacobian(d["z"], d["dz"], elems=el), rng)

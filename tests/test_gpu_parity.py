@@ -95,6 +95,50 @@ def test_bitwise_deterministic(pf, p, n, scatter):
     assert np.array_equal(r1, r2)
 
 
+@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
+@pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", 2, 5),
+                                              ("C1", "plastic", 3, 3), ("C1", "compress", 3, 2),
+                                              ("C1", "voce", 3, 3), ("C1", "plastic", 4, 3),
+                                              ("C1", "voce", 4, 2)])
+def test_stored_linearisation_jacobian(pf, oracle_lib, name, variant, p, n, scatter):
+    """J dz from the FP64 record stored by pf_linearize equals the oracle's Jacobian (1e-12) and the
+    recomputed apply (1e-13): the record holds the FP64 decisions, frame and coefficients."""
+    print(f"case stored J {name} {variant} p={p} n={n} {scatter}", flush=True)
+    d = I.make_inputs(name, variant, p=p, n=n)
+    ctx = pf.Context.from_inputs(d)
+    ctx.set_scatter(scatter)
+    z, dz = dev(d["z"]), dev(d["dz"])
+    ctx.linearize(z)
+    y = ctx.apply_jacobian_lin(dz)
+    y2 = ctx.apply_jacobian_lin(dz)
+    ctx.check()
+    yr = ctx.apply_jacobian(z, dz).cpu().numpy()
+    got = y.cpu().numpy()
+    assert np.array_equal(got, y2.cpu().numpy())  # deterministic
+    check_blocks(got, oracle_lib.Oracle.from_inputs(d).jacobian(d["z"], d["dz"]), FP64_TOL, "stored jacobian")
+    assert relerr(got, yr) <= 1e-13, relerr(got, yr)
+
+
+def test_stored_linearisation_needs_linearize(pf):
+    d = I.make_inputs("C1", "plastic", p=3, n=2)
+    ctx = pf.Context.from_inputs(d)
+    z, dz = dev(d["z"]), dev(d["dz"])
+    with pytest.raises(pf.PfError):
+        ctx.apply_jacobian_lin(dz)  # not linearised
+    ctx.set_store_lin64(False)
+    ctx.linearize(z)
+    with pytest.raises(pf.PfError):
+        ctx.apply_jacobian_lin(dz)  # linearised without the FP64 record
+    ctx.set_store_lin64(True)
+    ctx.linearize(z)
+    ctx.apply_jacobian_lin(dz)
+    ctx.set_params(np.array([[ph.Gc, ph.sigma0, ph.visc] for ph in d["phases"]]))
+    with pytest.raises(pf.PfError):
+        ctx.apply_jacobian_lin(dz)  # parameters changed since the linearisation
+    with pytest.raises(pf.PfError):
+        ctx.apply_jacobian_lin(dz, y=dz)  # aliasing
+
+
 def test_dot_product_identity(pf):
     d = I.make_inputs("C1", "plastic", p=3, n=4)
     ctx = pf.Context.from_inputs(d)
