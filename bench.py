@@ -86,6 +86,8 @@ def alg_bytes(mesh, kind):
         return 96 * nodes + 65 * qps
     if kind == "fp32_apply":    # FP32 u mirror (12), dz (16), y (16) per node; record 60 + flags 1 + phase 1 per point
         return 44 * nodes + 62 * qps
+    if kind == "jacobian_stored":  # FP64 u copy (24), dz (32), y (32) per node; record 120 + flags 1 + phase 1
+        return 88 * nodes + 122 * qps
     raise ValueError(kind)
 
 
@@ -140,7 +142,8 @@ def secondary_leg(torch, I, pfmf, config):
     for name, f in (("residual", lambda: ctx.apply_residual(z, y)),
                     ("jacobian", lambda: ctx.apply_jacobian(z, dz, y)),
                     ("adjoint", lambda: ctx.apply_adjoint(z, v, g, gp)),
-                    ("fp32_apply", lambda: ctx.apply_jacobian_f32(0, dz32, y32))):
+                    ("fp32_apply", lambda: ctx.apply_jacobian_f32(0, dz32, y32)),
+                    ("jacobian_stored", lambda: ctx.apply_jacobian_lin(dz, g))):
         for _ in range(3):
             f()
         torch.cuda.synchronize()
@@ -188,7 +191,9 @@ def newton_leg(torch, I, pfmf, config):
     dz32 = dz.float()
     y32 = torch.empty_like(dz32)
     ms = {}
+    ys = torch.empty_like(z)
     for name, f in (("jacobian", lambda: ctx.apply_jacobian(z, dz, y)),
+                    ("jacobian_stored", lambda: ctx.apply_jacobian_lin(dz, ys)),
                     ("fp32_apply", lambda: ctx.apply_jacobian_f32(0, dz32, y32)),
                     ("vcycle", lambda: ctx.pmg_vcycle(dz32, y32))):
         f()
@@ -210,7 +215,7 @@ def newton_leg(torch, I, pfmf, config):
             "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
             "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
             "t_linearize_ms": rep["t_linearize_ms"], "ms": ms,
-            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "fp32_apply")},
+            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "jacobian_stored", "fp32_apply")},
             "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
 
 
@@ -252,6 +257,7 @@ def main():
     gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
+    ys = torch.empty_like(z)
     dz32 = dz.float()
     y32 = torch.empty_like(dz32)
     b32 = torch.empty_like(dz32)
@@ -270,6 +276,7 @@ def main():
         "residual": lambda: ctx.apply_residual(z, r),
         "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
         "adjoint": lambda: ctx.apply_adjoint(z, v, gz, gp),
+        "jacobian_stored": lambda: ctx.apply_jacobian_lin(dz, ys),
     }
     for _ in range(args.warmup):
         for f in ops.values():
@@ -309,6 +316,8 @@ def main():
         errs["adjoint"] = sampled_rel_err(orc, mesh, gg, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
         y32h = y32.double().cpu().numpy()
         errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32h, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        errs["jacobian_stored"] = sampled_rel_err(orc, mesh, ys.cpu().numpy(),
+                                                  lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
     except Exception as exc:  # the oracle is a checker; its absence does not stop the benchmark
         errs["error"] = str(exc)
 
@@ -362,14 +371,26 @@ def main():
         "ms": ms,
         "ms_min": ms_min,
         "ms_median": ms_med,
-        "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("residual", "jacobian", "adjoint", "fp32_apply")},
+        "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("residual", "jacobian", "adjoint", "fp32_apply",
+                                                                 "jacobian_stored")},
         "gbs_alg": {k: alg_bytes(mesh, k) / (ms[k] * 1e-3) / 1e9 for k in ("residual", "jacobian", "adjoint",
-                                                                              "fp32_apply")},
+                                                                              "fp32_apply", "jacobian_stored")},
+        # the FP64 Jacobian from the linearisation stored by pf_linearize (same operator at the same
+        # z, record read instead of the point state recomputed): HBM-bound, reported beside the
+        # recompute apply above, which is `value`
+        "roofline_jacobian_stored": {
+            "bound": "hbm",
+            "achieved": alg_bytes(mesh, "jacobian_stored") / (ms["jacobian_stored"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": alg_bytes(mesh, "jacobian_stored") / (ms["jacobian_stored"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "alg_bytes_per_apply": alg_bytes(mesh, "jacobian_stored"),
+        },
         "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
     if args.secondary or args.newton:
-        del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32
+        del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32, ys
         torch.cuda.empty_cache()
     if args.secondary:
         out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)
