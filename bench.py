@@ -213,6 +213,7 @@ def newton_leg(torch, I, pfmf, config):
     print(f"[bench] newton step {rep} in {t_step:.2f} s", file=sys.stderr, flush=True)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}",
             "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
+            "gram_schmidt_refinements": rep["refinements"],
             "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
             "t_linearize_ms": rep["t_linearize_ms"], "ms": ms,
             "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "jacobian_stored", "fp32_apply")},

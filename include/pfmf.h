@@ -188,12 +188,14 @@ typedef struct {
 } pf_newton_opts;
 
 /* Newton step report: FGMRES iterations, convergence flag, ||b|| with b = -M R(z),
- * the FGMRES residual estimate, the true residual ||b - M J dz||, and host wall times
- * (linearisation, whole step) in milliseconds. */
+ * the FGMRES residual estimate, the true residual ||b - M J dz||, host wall times
+ * (linearisation, whole step) in milliseconds, and the number of iterations whose
+ * Gram-Schmidt needed the second (refinement) pass. */
 typedef struct {
   int iterations, converged;
   double res0, res_lin, res_true;
   double t_linearize_ms, t_total_ms;
+  int refinements;
 } pf_newton_stats;
 
 /* One Newton update z += dz of the coupled problem with the Dirichlet faces of

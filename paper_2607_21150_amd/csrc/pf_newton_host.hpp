@@ -146,7 +146,7 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
   if ((st = pf_linearize(c, z, stream))) return st;
   const double t2 = now_ms();
   const pf_pmg_opts po{opt.cheb_degree, c->mg.lv[c->mg.n_levels - 1].p, opt.coarse_sweeps, 0};
-  int its = 0;
+  int its = 0, refinements = 0;
   bool conv = bnorm == 0.0;
   double res = bnorm;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
@@ -174,16 +174,27 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
       double* Vn = V + (int64_t)(k + 1) * n;
       if ((st = precondition(c, Vk, Zk, po, s))) return st;
       if ((st = masked_jacobian(c, z, Zk, Vn, s))) return st;
-      // classical Gram-Schmidt, twice
-      if ((st = mdot(c, V, n, k + 1, Vn, n, s, h.data()))) return st;
-      for (int j = 0; j <= k; ++j) y[j] = -h[j];
-      if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
-      if ((st = mdot(c, V, n, k + 1, Vn, n, s, h2.data()))) return st;
+      // classical Gram-Schmidt with adaptive refinement (the GMRES variant of Section 5):
+      // the first pass also returns ||w||^2 (Vn follows V_k in memory); a second pass runs
+      // only when the first removed more than half of it, ||w1||^2 = ||w||^2 - sum h_j^2
+      // < ||w||^2 / 2, the point where orthogonality can be lost
+      if ((st = mdot(c, V, n, k + 2, Vn, n, s, h.data()))) return st;
+      const double w0 = h[k + 1];
+      double proj = 0.0;
       for (int j = 0; j <= k; ++j) {
-        y[j] = -h2[j];
-        h[j] += h2[j];
+        y[j] = -h[j];
+        proj += h[j] * h[j];
       }
       if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+      if (!(w0 - proj > 0.5 * w0)) {
+        ++refinements;
+        if ((st = mdot(c, V, n, k + 1, Vn, n, s, h2.data()))) return st;
+        for (int j = 0; j <= k; ++j) {
+          y[j] = -h2[j];
+          h[j] += h2[j];
+        }
+        if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+      }
       double hn;
       if ((st = mdot(c, Vn, n, 1, Vn, n, s, &hn))) return st;
       hn = std::sqrt(hn);
@@ -238,6 +249,7 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
     out->res_true = std::sqrt(rt);
     out->t_linearize_ms = t2 - t1;
     out->t_total_ms = t3 - t0;
+    out->refinements = refinements;
   }
   return conv ? PF_OK : fail(PF_ENOCONV, "FGMRES did not reach rtol %.1e in %d iterations (%.3e)", opt.rtol,
                              its, bnorm > 0 ? res / bnorm : 0.0);

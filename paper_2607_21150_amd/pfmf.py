@@ -70,7 +70,8 @@ class NewtonOpts(C.Structure):
 
 class NewtonStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("res0", C.c_double), ("res_lin", C.c_double),
-                ("res_true", C.c_double), ("t_linearize_ms", C.c_double), ("t_total_ms", C.c_double)]
+                ("res_true", C.c_double), ("t_linearize_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("refinements", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
