@@ -501,7 +501,7 @@ namespace pfmf {
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
 // two elements.
 template <int MODE, bool BB, bool VOCE>
-__global__ __launch_bounds__(NT, 2) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+__global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
