@@ -40,9 +40,10 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(config):
-    """HBM bytes per Jacobian apply from the committed counter summary, or None when the summary is
-    missing, was taken on another workload, or the kernel sources changed since it was taken."""
+def measured_counters(config):
+    """Per-Jacobian-apply counter values from the committed summary (HBM bytes, FP64 VALU and
+    matrix-core FLOPs), or {} when the summary is missing, was taken on another workload, or the
+    kernel sources changed since it was taken."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -51,10 +52,16 @@ def measured_traffic(config):
                     k, v = line[2:].split(" = ", 1)
                     kv[k.strip().strip("`")] = v.strip().strip("`")
         if kv.get("source_sha256") != kernel_source_digest() or kv.get("config") != config:
-            return None
-        return float(kv["hbm_bytes_per_apply"])
+            return {}
+        return {k: float(kv[k]) for k in ("hbm_bytes_per_apply", "valu_fp64_flops_per_apply",
+                                          "mfma_f64_flops_per_apply") if k in kv}
     except (OSError, KeyError, ValueError):
-        return None
+        return {}
+
+
+def measured_traffic(config):
+    """HBM bytes per Jacobian apply from the committed counter summary, or None (see measured_counters)."""
+    return measured_counters(config).get("hbm_bytes_per_apply")
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=10):
@@ -120,9 +127,26 @@ def cpu_baseline(d, seconds=10.0):
     t = time.perf_counter() - t0
     frac = n / mesh.n_elem
     dofs_per_s = mesh.n_dof / (t / frac)
-    return {"value": dofs_per_s, "unit": "DoF/s", "cores": pyoracle.num_threads(), "kind": "oracle",
+    cores = pyoracle.num_threads()
+    # the same on one core, on a sample of 1/cores of the elements
+    n1 = max(1, n // max(cores, 1))
+    pyoracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    orc.jacobian(d["z"], d["dz"], elems=np.arange(n1, dtype=np.int32), check=False)
+    t1 = time.perf_counter() - t0
+    pyoracle.set_num_threads(cores)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": dofs_per_s, "unit": "DoF/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 Jacobian apply on elements 0..{n - 1} ({n} of {mesh.n_elem}, {frac:.3f} of the work) "
-                      f"took {t:.2f} s; scaled to the full apply"}
+                      f"took {t:.2f} s on {cores} threads; scaled to the full apply",
+            "value_1core": mesh.n_dof / (t1 * mesh.n_elem / n1),
+            "sample_1core": f"elements 0..{n1 - 1} on 1 thread took {t1:.2f} s",
+            "cpu_model": model, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
 
 
 def secondary_leg(torch, I, pfmf, config):
@@ -325,16 +349,18 @@ def main():
     copy = copy_probe(torch)
     print(f"[bench] copy probe {copy}", file=sys.stderr, flush=True)
 
-    t_jac = ms["jacobian"] * 1e-3
+    # DoF/s and GB/s from the median apply time (the mean, min and median are all reported)
+    t_jac = ms_med["jacobian"] * 1e-3
     value = mesh.n_dof / t_jac
     bj = alg_bytes(mesh, "jacobian")
     achieved = bj / t_jac / 1e9
-    traffic = measured_traffic(args.config + "/" + args.variant)
-    kname = {2: "pfmf::k_op64_q2<1, true> + pfmf::k_gather_bricks<double, 3>: one launch over all bricks, "
-                "then the node gather",
-             3: "pfmf::k_op64_q3<1, true> + pfmf::k_gather_bricks<double, 4>: one launch over all bricks, "
-                "then the node gather",
-             4: "pfmf::k_op64_q4<1>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
+    counters = measured_counters(args.config + "/" + args.variant)
+    traffic = counters.get("hbm_bytes_per_apply")
+    kname = {2: "pfmf::k_op64_q2<1, true, false> + pfmf::k_gather_bricks<double, 3>: one launch over all "
+                "bricks, then the node gather",
+             3: "pfmf::k_op64_q3<1, true, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
+                "bricks, then the node gather",
+             4: "pfmf::k_op64_q4<1, false>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(d, args.cpu_seconds)
@@ -368,26 +394,38 @@ def main():
             "alg_bytes_per_apply": bj,
             "copy_probe_gbs": copy["gbs"],
         },
+        # achieved FP64 FLOP/s of the Jacobian apply: counted FLOPs per apply (rocprofv3, the
+        # committed summary of these kernel sources) over the median apply time, against the FP64
+        # peak; null when the summary does not match the sources
+        "alu": ({"bound": "alu", "unit": "TFLOP/s",
+                 "achieved": (counters["valu_fp64_flops_per_apply"] + counters["mfma_f64_flops_per_apply"])
+                 / t_jac / 1e12,
+                 "peak": FP64_VEC_PEAK_TFLOPS,
+                 "frac": (counters["valu_fp64_flops_per_apply"] + counters["mfma_f64_flops_per_apply"])
+                 / t_jac / 1e12 / FP64_VEC_PEAK_TFLOPS,
+                 "valu_fp64_flops_per_apply": counters["valu_fp64_flops_per_apply"],
+                 "mfma_f64_flops_per_apply": counters["mfma_f64_flops_per_apply"]}
+                if "valu_fp64_flops_per_apply" in counters and "mfma_f64_flops_per_apply" in counters else None),
         "cpu_baseline": cpu,
         "ms": ms,
         "ms_min": ms_min,
         "ms_median": ms_med,
-        "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("residual", "jacobian", "adjoint", "fp32_apply",
-                                                                 "jacobian_stored")},
-        "gbs_alg": {k: alg_bytes(mesh, k) / (ms[k] * 1e-3) / 1e9 for k in ("residual", "jacobian", "adjoint",
-                                                                              "fp32_apply", "jacobian_stored")},
+        "dofs_per_s": {k: mesh.n_dof / (ms_med[k] * 1e-3) for k in ("residual", "jacobian", "adjoint",
+                                                                     "fp32_apply", "jacobian_stored")},
+        "gbs_alg": {k: alg_bytes(mesh, k) / (ms_med[k] * 1e-3) / 1e9 for k in ("residual", "jacobian", "adjoint",
+                                                                                  "fp32_apply", "jacobian_stored")},
         # the FP64 Jacobian from the linearisation stored by pf_linearize (same operator at the same
         # z, record read instead of the point state recomputed): HBM-bound, reported beside the
         # recompute apply above, which is `value`
         "roofline_jacobian_stored": {
             "bound": "hbm",
-            "achieved": alg_bytes(mesh, "jacobian_stored") / (ms["jacobian_stored"] * 1e-3) / 1e9,
+            "achieved": alg_bytes(mesh, "jacobian_stored") / (ms_med["jacobian_stored"] * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": alg_bytes(mesh, "jacobian_stored") / (ms["jacobian_stored"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "frac": alg_bytes(mesh, "jacobian_stored") / (ms_med["jacobian_stored"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "alg_bytes_per_apply": alg_bytes(mesh, "jacobian_stored"),
         },
-        "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
+        "fp32_over_fp64_apply_speedup": ms_med["jacobian"] / ms_med["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
     if args.secondary or args.newton:

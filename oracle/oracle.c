@@ -40,6 +40,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* 1-D rules: Legendre polynomials by the three-term recurrence, roots by    */
 /* bisection (slow and obviously convergent), all in long double.            */

@@ -112,6 +112,7 @@ int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac
 
 /* Number of OpenMP threads the applies use (1 when built without OpenMP). */
 int or_num_threads(void);
+void or_set_num_threads(int n);  /* OpenMP threads of the element loops (timing only) */
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,7 @@ def lib():
         for f in ("or_residual", "or_jacobian", "or_adjoint", "or_element_jacobian"):
             getattr(L, f).restype = C.c_int
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -249,3 +250,7 @@ class Oracle:
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_num_threads(n):
+    lib().or_set_num_threads(int(n))
