@@ -707,7 +707,7 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
   T dth = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    deps[i] = T(2) * Lt[4 * i] * bd[i] * s.hinv[i];
+    deps[i] = Lt[4 * i];  // d eps_i = d b_i / (2 b_i) with d b_i = 2 b_i Lt_ii
     dth += deps[i];
   }
   const T dth3 = dth * (T(1) / T(3));
@@ -721,20 +721,23 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
   // degraded principal stress increments (eq:linear-degraded-stress-linearization)
   const T kdt = m.kappa * dth;
   const T tm2 = T(2) * m.mu;
-  T X[3];
+  T X[3], td[3];
+  const T kt = m.kappa * s.theta, tmc = tm2 * s.c;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
+    // block (undegraded) deviatoric and degraded principal stresses, from e, c and theta
+    const T taubd = tmc * s.e[i];
+    td[i] = s.tension ? s.g * (taubd + kt) : s.g * taubd + kt;
     if (s.tension)
-      X[i] = s.g * (tm2 * dce[i] + kdt) + s.gp * dphi * s.taub[i];
+      X[i] = s.g * (tm2 * dce[i] + kdt) + s.gp * dphi * (taubd + kt);
     else
-      X[i] = s.g * (tm2 * dce[i]) + kdt + s.gp * dphi * (s.taub[i] - m.kappa * s.theta);
+      X[i] = s.g * (tm2 * dce[i]) + kdt + s.gp * dphi * taubd;
   }
   // off-diagonal increments: rotated db_ij times the divided-difference factors
   const T o12 = (Lt[5] * bd[2] + bd[1] * Lt[7]) * s.coef[0];
   const T o02 = (Lt[2] * bd[2] + bd[0] * Lt[6]) * s.coef[1];
   const T o01 = (Lt[1] * bd[1] + bd[0] * Lt[3]) * s.coef[2];
   // Z = dtau_rot - diag(tau_d) Lt^T
-  const T* td = s.taud;
   const T Z[9] = {X[0] - td[0] * Lt[0], o01 - td[0] * Lt[3], o02 - td[0] * Lt[6],
                   o01 - td[1] * Lt[1], X[1] - td[1] * Lt[4], o12 - td[1] * Lt[7],
                   o02 - td[2] * Lt[2], o12 - td[2] * Lt[5], X[2] - td[2] * Lt[8]};
@@ -795,7 +798,14 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
   Xd[1] = Zb[4];
   Xd[2] = Zb[8];
   // Z = Xfull - diag(tau_d) Lt^T: off-diagonal increments and the geometric term
-  const T* td = s.taud;
+  // (block deviatoric and degraded principal stresses recomputed from e, c and theta)
+  const T kapth = m.kappa * s.theta, tmc = tm2 * s.c;
+  T taubd[3], td[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    taubd[i] = tmc * s.e[i];
+    td[i] = s.tension ? s.g * (taubd[i] + kapth) : s.g * taubd[i] + kapth;
+  }
   T Ltb[9];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
@@ -813,17 +823,16 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
   // principal stress increments
   T dceb[3];
   T dthb = T(0);
-  const T kapth = m.kappa * s.theta;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const T xb = Zb[4 * i];
     dceb[i] = s.g * tm2 * xb;
     if (s.tension) {
       dthb += s.g * m.kappa * xb;
-      phib += s.gp * s.taub[i] * xb;
+      phib += s.gp * (taubd[i] + kapth) * xb;
     } else {
       dthb += m.kappa * xb;
-      phib += s.gp * (s.taub[i] - kapth) * xb;
+      phib += s.gp * taubd[i] * xb;
     }
   }
   // history: dH = hactive (2 mu c e.dce + tension kappa theta dth)
@@ -838,10 +847,10 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
 #pragma unroll
   for (int i = 0; i < 3; ++i) deb[i] = s.c * dceb[i] + s.kq * sdot * s.e[i];
   phib += s.kphi * sdot;
-  // de_i = deps_i - dth/3, dth = sum deps, deps_i = 2 b_i (1/(2 b_i)) Lt_ii
+  // de_i = deps_i - dth/3, dth = sum deps, deps_i = Lt_ii
   const T mdeb = (deb[0] + deb[1] + deb[2]) * (T(1) / T(3));
 #pragma unroll
-  for (int i = 0; i < 3; ++i) Ltb[4 * i] += (deb[i] - mdeb + dthb) * (T(2) * bd[i] * s.hinv[i]);
+  for (int i = 0; i < 3; ++i) Ltb[4 * i] += deb[i] - mdeb + dthb;
   // Lt = N^T dG FiN  ->  Gb = (N Ltb) FiN^T
   T R[9];
 #pragma unroll
