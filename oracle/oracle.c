@@ -21,7 +21,14 @@
  *    (ln b_i - ln b_j)/(b_i - b_j), which equals the printed distinct-eigenvalue
  *    expression and stays finite when eigenvalues coincide;
  *  - the inelastic state is stored as D = Cin^-1 - I so that b_tr - I is formed
- *    without cancellation before log1p (Appendix A's log1p remark).
+ *    without cancellation before log1p (Appendix A's log1p remark);
+ *  - extra branches in parallel (Section 2.3): each has its own spring (mu_k,
+ *    kappa_k), its own state and principal frame; every branch is degraded by the
+ *    Amor split of its own trial volumetric strain, the total psi^+ is the sum of
+ *    the branches' and drives the history, and the per-phase parameters (Gc,
+ *    sigma0, visc) are those of the phase's first block. A Maxwell branch uses the
+ *    degraded modulus g mu in its closed-form update
+ *    (eq:principal-directions-format-1); an extra Hooke branch has Cin^-1 = I.
  */
 #include "oracle.h"
 
@@ -270,6 +277,8 @@ static double log_divdiff(double bi_m1, double bj_m1) {
 typedef struct {
   double mu, kappa, Gc, sigma0, H, a; int plastic;
   double sinf, bv;  /* Voce saturation stress and rate; bv = 0: linear hardening */
+  int maxwell;      /* Maxwell branch (Section 2.3.2) */
+  double am;        /* mu dt / eta_d of a Maxwell branch */
 } mat_t;
 
 static mat_t make_mat(const or_phase* ph, const or_frac* fr) {
@@ -283,6 +292,30 @@ static mat_t make_mat(const or_phase* ph, const or_frac* fr) {
   m.plastic = ph->plastic;
   m.sinf = ph->sigma_inf;
   m.bv = ph->voce_beta;
+  m.maxwell = 0;
+  m.am = 0.0;
+  return m;
+}
+
+/* Material of an extra branch (Section 2.3): its own spring; a Prandtl branch as the
+ * first block's; a Maxwell branch with am = mu dt / eta_d. Gc is the phase's. */
+static mat_t make_branch_mat(const or_branch* b, const or_frac* fr, double Gc) {
+  mat_t m;
+  memset(&m, 0, sizeof m);
+  m.mu = b->E / (2.0 * (1.0 + b->nu));
+  m.kappa = b->E / (3.0 * (1.0 - 2.0 * b->nu));
+  m.Gc = Gc;
+  if (b->kind == OR_BR_PRANDTL) {
+    m.plastic = 1;
+    m.sigma0 = b->sigma0;
+    m.H = b->H;
+    m.a = b->visc / fr->dt;
+    m.sinf = b->sigma_inf;
+    m.bv = b->voce_beta;
+  } else if (b->kind == OR_BR_MAXWELL) {
+    m.maxwell = 1;
+    m.am = m.mu * fr->dt / b->eta_d;
+  }
   return m;
 }
 
@@ -313,8 +346,9 @@ typedef struct {
   int nonphysical;
 } qp_state;
 
-static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double phi,
-                    double phi_n, const double st[8], qp_state* s) {
+/* Steps R1-R8 and R11 of one branch: st = D[6] (Voigt), ebar_p. */
+static void qp_branch(const mat_t* m, const or_frac* fr, const double G[9], double phi,
+                      const double st[7], qp_state* s) {
   memset(s, 0, sizeof *s);
   double Gm[3][3];
   for (int i = 0; i < 3; i++)
@@ -391,6 +425,10 @@ static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double
       s->ep = st[6] + s->dgamma;
       s->plastic = 1;
     }
+  } else if (m->maxwell) {
+    /* Maxwell branch, closed form with the degraded modulus g mu
+     * (eq:viscoelasticity-deviatoric-strain-update-hencky, eq:principal-directions-format-1) */
+    s->c = 1.0 / (1.0 + m->am * s->g);
   }
   /* R7: block principal stress (eq:principal-stress-update-eigenvalues) */
   for (int i = 0; i < 3; i++) s->tau[i] = 2.0 * m->mu * s->c * s->e[i] + m->kappa * s->theta;
@@ -404,14 +442,6 @@ static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double
       s->taud[i] = s->g * (s->tau[i] - m->kappa * s->theta) + m->kappa * s->theta;
     s->psi = m->mu * cee;
   }
-  /* R9: history (Miehe), strict switch */
-  s->Hn = st[7];
-  s->Hactive = (s->psi > s->Hn);
-  s->H = s->Hactive ? s->psi : s->Hn;
-  /* R10: L (eq:L-viscous), AT1/AT2 (eq:AT1-AT2) */
-  if (fr->at == 2) { s->c0 = 2.0; s->alpha_p = 2.0 * phi; s->alpha_pp = 2.0; }
-  else { s->c0 = 8.0 / 3.0; s->alpha_p = 1.0; s->alpha_pp = 0.0; }
-  s->L = s->gp * s->H + m->Gc / (s->c0 * fr->l0) * s->alpha_p + fr->zeta * (phi - phi_n) / fr->dt;
   /* R11: tau_degr = sum_i taud_i n_i (x) n_i (eq:principal-stress-update-eigenvalues-2) */
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) {
@@ -419,6 +449,26 @@ static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double
       for (int k = 0; k < 3; k++) sum += s->taud[k] * s->N[i][k] * s->N[j][k];
       s->tau_degr[i][j] = sum;
     }
+}
+
+/* Steps R9-R10: history and local phase-field residual from the point's total psi^+. */
+static void qp_fracture(const mat_t* m, const or_frac* fr, double phi, double phi_n, double Hn,
+                        double psi, qp_state* s) {
+  /* R9: history (Miehe), strict switch */
+  s->Hn = Hn;
+  s->Hactive = (psi > s->Hn);
+  s->H = s->Hactive ? psi : s->Hn;
+  /* R10: L (eq:L-viscous), AT1/AT2 (eq:AT1-AT2) */
+  if (fr->at == 2) { s->c0 = 2.0; s->alpha_p = 2.0 * phi; s->alpha_pp = 2.0; }
+  else { s->c0 = 8.0 / 3.0; s->alpha_p = 1.0; s->alpha_pp = 0.0; }
+  s->L = s->gp * s->H + m->Gc / (s->c0 * fr->l0) * s->alpha_p + fr->zeta * (phi - phi_n) / fr->dt;
+}
+
+/* Single block: R1-R11 with st = D[6], ebar_p, H_n. */
+static void qp_eval(const mat_t* m, const or_frac* fr, const double G[9], double phi,
+                    double phi_n, const double st[8], qp_state* s) {
+  qp_branch(m, fr, G, phi, st, s);
+  qp_fracture(m, fr, phi, phi_n, st[7], s->psi, s);
 }
 
 static void first_piola(const double tau[3][3], const double Fi[3][3], double P[9]) {
@@ -461,8 +511,10 @@ void or_qf_residual(const or_phase* ph, const or_frac* fr, const double G[9], do
 /* Pointwise directional derivative: J1-J12 (Appendices B and C).            */
 /* ------------------------------------------------------------------------ */
 
-static void qp_tangent(const mat_t* m, const or_frac* fr, const qp_state* s, const double dG[9],
-                       double dphi, const double dgphi[3], double dP[9], double* df0, double df1[3]) {
+/* Steps J1-J10 of one branch: dP of its degraded stress and d psi^+ (before the history
+ * switch). */
+static void qp_tangent_branch(const mat_t* m, const qp_state* s, const double dG[9], double dphi,
+                              double dP[9], double* dpsi) {
   double dGm[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) dGm[i][j] = dG[i * 3 + j];
@@ -493,6 +545,10 @@ static void qp_tangent(const mat_t* m, const or_frac* fr, const qp_state* s, con
     double dq = 6.0 * m->mu * m->mu * (s->e[0] * de[0] + s->e[1] * de[1] + s->e[2] * de[2]) / s->q;
     double ddg = (s->g * dq + s->gp * (s->q - 3.0 * m->mu * s->dgamma) * dphi) / s->den;
     double k = -(3.0 * m->mu / s->q) * (ddg - s->dgamma * dq / s->q);
+    for (int i = 0; i < 3; i++) dce[i] = s->c * de[i] + k * s->e[i];
+  } else if (m->maxwell) {
+    /* c = 1 / (1 + am g): dc = -am g' c^2 dphi (eq:maxwell-dtau-dphi) */
+    double k = -m->am * s->gp * s->c * s->c * dphi;
     for (int i = 0; i < 3; i++) dce[i] = s->c * de[i] + k * s->e[i];
   } else {
     for (int i = 0; i < 3; i++) dce[i] = de[i];
@@ -525,14 +581,17 @@ static void qp_tangent(const mat_t* m, const or_frac* fr, const qp_state* s, con
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) M[i][j] = dtau_degr[i][j] - tdl[i][j];
   first_piola(M, s->Fi, dP);
-  /* J10: history derivative (eq:history-field-linearization, eq:energy-displacement-linearization) */
-  double dH = 0.0;
-  if (s->Hactive) {
-    double ce_dce = 0.0;
-    for (int i = 0; i < 3; i++) ce_dce += s->c * s->e[i] * dce[i];
-    dH = 2.0 * m->mu * ce_dce;
-    if (s->theta >= 0.0) dH += m->kappa * s->theta * dth;
-  }
+  /* J10: psi^+ derivative (eq:energy-displacement-linearization, eq:maxwell-energy-dphi) */
+  double ce_dce = 0.0;
+  for (int i = 0; i < 3; i++) ce_dce += s->c * s->e[i] * dce[i];
+  *dpsi = 2.0 * m->mu * ce_dce;
+  if (s->theta >= 0.0) *dpsi += m->kappa * s->theta * dth;
+}
+
+/* Steps J11-J12 from the history derivative dH (eq:history-field-linearization: zero
+ * when the switch is off); s carries the point's H, c0 and alpha''. */
+static void qp_tangent_fracture(const mat_t* m, const or_frac* fr, const qp_state* s, double dH,
+                                double dphi, const double dgphi[3], double* df0, double df1[3]) {
   /* J11: dL (eq:linearized-local-damage-residual), g'' = 2 */
   double dL = (2.0 * s->H + m->Gc / (s->c0 * fr->l0) * s->alpha_pp + fr->zeta / fr->dt) * dphi
               + s->gp * dH;
@@ -540,6 +599,13 @@ static void qp_tangent(const mat_t* m, const or_frac* fr, const qp_state* s, con
   *df0 = fr->s_phi * dL;
   double kf = fr->s_phi * 2.0 * m->Gc * fr->l0 / s->c0;
   for (int J = 0; J < 3; J++) df1[J] = kf * dgphi[J];
+}
+
+static void qp_tangent(const mat_t* m, const or_frac* fr, const qp_state* s, const double dG[9],
+                       double dphi, const double dgphi[3], double dP[9], double* df0, double df1[3]) {
+  double dpsi;
+  qp_tangent_branch(m, s, dG, dphi, dP, &dpsi);
+  qp_tangent_fracture(m, fr, s, s->Hactive ? dpsi : 0.0, dphi, dgphi, df0, df1);
 }
 
 void or_qf_jacobian(const or_phase* ph, const or_frac* fr, const double G[9], double phi,
@@ -596,6 +662,97 @@ void or_qf_param_partials(const or_phase* ph, const or_frac* fr, const double G[
   qp_state s;
   qp_eval(&m, fr, G, phi, phi_n, st, &s);
   qp_param_partials(&m, fr, &s, gphi, dP, df0, df1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Branches in parallel (Section 2.3): tau = sum_k tau_k, psi = sum_k psi_k.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int nb;                        /* branches evaluated: the block, then the extra ones */
+  mat_t m[1 + OR_MAX_EXTRA];
+  qp_state s[1 + OR_MAX_EXTRA];  /* s[0] also holds the point's H, switch and L */
+  double tau_degr[3][3];         /* total degraded Kirchhoff stress */
+  double psi;                    /* total psi^+ */
+  int nonphysical;
+} mb_point;
+
+/* xs: the extra branches' states, 7 values each (D[6] Voigt, ebar_p); an extra Hooke
+ * branch has Cin^-1 = I and reads none. */
+static void mb_eval(const or_phase* ph, const or_branch* xb, int n_extra, const or_frac* fr,
+                    const double G[9], double phi, double phi_n, const double st[8], const double* xs,
+                    mb_point* p) {
+  static const double zero7[7] = {0, 0, 0, 0, 0, 0, 0};
+  p->m[0] = make_mat(ph, fr);
+  qp_branch(&p->m[0], fr, G, phi, st, &p->s[0]);
+  p->nb = 1;
+  for (int j = 0; j < n_extra; j++) {
+    if (xb[j].kind == OR_BR_NONE) continue;
+    p->m[p->nb] = make_branch_mat(&xb[j], fr, ph->Gc);
+    qp_branch(&p->m[p->nb], fr, G, phi, xb[j].kind == OR_BR_HOOKE ? zero7 : xs + 7 * j, &p->s[p->nb]);
+    p->nb++;
+  }
+  p->psi = 0.0;
+  p->nonphysical = 0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) p->tau_degr[i][j] = 0.0;
+  for (int k = 0; k < p->nb; k++) {
+    p->psi += p->s[k].psi;
+    p->nonphysical |= p->s[k].nonphysical;
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) p->tau_degr[i][j] += p->s[k].tau_degr[i][j];
+  }
+  qp_fracture(&p->m[0], fr, phi, phi_n, st[7], p->psi, &p->s[0]);
+}
+
+/* Directional derivative of the point: the branches' dP and d psi^+ summed, the
+ * history switch of the total psi^+. */
+static void mb_tangent(const mb_point* p, const or_frac* fr, const double dG[9], double dphi,
+                       const double dgphi[3], double dP[9], double* df0, double df1[3]) {
+  double dpsi = 0.0;
+  for (int r = 0; r < 9; r++) dP[r] = 0.0;
+  for (int k = 0; k < p->nb; k++) {
+    double dPk[9], dpk;
+    qp_tangent_branch(&p->m[k], &p->s[k], dG, dphi, dPk, &dpk);
+    for (int r = 0; r < 9; r++) dP[r] += dPk[r];
+    dpsi += dpk;
+  }
+  qp_tangent_fracture(&p->m[0], fr, &p->s[0], p->s[0].Hactive ? dpsi : 0.0, dphi, dgphi, df0, df1);
+}
+
+void or_qf_residual_mb(const or_phase* ph, const or_branch* xb, int n_extra, const or_frac* fr,
+                       const double G[9], double phi, const double gphi[3], double phi_n,
+                       const double st[8], const double* xs, or_qp_out* out) {
+  mb_point p;
+  mb_eval(ph, xb, n_extra, fr, G, phi, phi_n, st, xs, &p);
+  const qp_state* s = &p.s[0];
+  first_piola(p.tau_degr, s->Fi, out->P);
+  out->f0 = fr->s_phi * s->L;
+  double kf = fr->s_phi * 2.0 * p.m[0].Gc * fr->l0 / s->c0;
+  for (int J = 0; J < 3; J++) out->f1[J] = kf * gphi[J];
+  out->tau[0] = p.tau_degr[0][0]; out->tau[1] = p.tau_degr[1][1]; out->tau[2] = p.tau_degr[2][2];
+  out->tau[3] = p.tau_degr[1][2]; out->tau[4] = p.tau_degr[0][2]; out->tau[5] = p.tau_degr[0][1];
+  for (int i = 0; i < 3; i++) { out->beta[i] = s->beta[i]; out->eps[i] = s->eps[i]; }
+  out->theta = s->theta;
+  out->q = s->q;
+  out->dgamma = s->dgamma;
+  out->c = s->c;
+  out->psi_plus = p.psi;
+  out->H = s->H;
+  out->L = s->L;
+  out->g = s->g;
+  out->plastic_active = s->plastic;
+  out->nonphysical = p.nonphysical;
+}
+
+void or_qf_jacobian_mb(const or_phase* ph, const or_branch* xb, int n_extra, const or_frac* fr,
+                       const double G[9], double phi, const double gphi[3], double phi_n,
+                       const double st[8], const double* xs, const double dG[9], double dphi,
+                       const double dgphi[3], double dP[9], double* df0, double df1[3]) {
+  mb_point p;
+  (void)gphi;
+  mb_eval(ph, xb, n_extra, fr, G, phi, phi_n, st, xs, &p);
+  mb_tangent(&p, fr, dG, dphi, dgphi, dP, df0, df1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -764,8 +921,10 @@ static void test_qp(const elem_tab* t, int qq, double wdet, const double P[9], d
 enum { K_RES = 0, K_JAC = 1, K_ADJ = 2 };
 
 typedef struct {
-  const or_mesh* m; const or_phase* ph; int nph; const or_frac* fr;
-  const uint8_t* phase; const double* state; const double* phi_n;
+  const or_mesh* m; const or_phase* ph; int nph;
+  const or_branch* xbr; int n_extra;  /* [nph][n_extra] extra branches */
+  const or_frac* fr;
+  const uint8_t* phase; const double* state; const double* xstate; const double* phi_n;
   const double* z; const double* w; /* dz or v */
 } apply_args;
 
@@ -788,26 +947,27 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
     int64_t gq = e * nQ + qq;
     int pid = A->phase[gq];
     if (pid >= A->nph) return -1;
-    mat_t mat = make_mat(&A->ph[pid], A->fr);
-    double G[9], phi, gphi[3], st[8];
+    double G[9], phi, gphi[3], st[8], xs[7 * OR_MAX_EXTRA];
     interp_qp(t, qq, ze, G, &phi, gphi);
     double phin = 0.0;
     for (int a = 0; a < nP; a++) phin += A->phi_n[idx[a]] * t->N[qq * nP + a];
     for (int k = 0; k < 8; k++) st[k] = A->state[k * n_q + gq];
-    qp_state s;
-    qp_eval(&mat, A->fr, G, phi, phin, st, &s);
-    bad |= s.nonphysical;
+    for (int k = 0; k < 7 * A->n_extra; k++) xs[k] = A->xstate[k * n_q + gq];
+    mb_point pt;
+    mb_eval(&A->ph[pid], A->xbr + (size_t)pid * A->n_extra, A->n_extra, A->fr, G, phi, phin, st, xs, &pt);
+    const qp_state* s = &pt.s[0];
+    bad |= pt.nonphysical;
     double wdet = t->wdet[qq];
-    double c0 = s.c0, kf = A->fr->s_phi * 2.0 * mat.Gc * A->fr->l0 / c0;
+    double c0 = s->c0, kf = A->fr->s_phi * 2.0 * pt.m[0].Gc * A->fr->l0 / c0;
     if (kind == K_RES) {
       double P[9], f1[3];
-      first_piola(s.tau_degr, s.Fi, P);
+      first_piola(pt.tau_degr, s->Fi, P);
       for (int J = 0; J < 3; J++) f1[J] = kf * gphi[J];
-      test_qp(t, qq, wdet, P, A->fr->s_phi * s.L, f1, out);
+      test_qp(t, qq, wdet, P, A->fr->s_phi * s->L, f1, out);
     } else if (kind == K_JAC) {
       double dG[9], dphi, dgphi[3], dP[9], df0, df1[3];
       interp_qp(t, qq, we, dG, &dphi, dgphi);
-      qp_tangent(&mat, A->fr, &s, dG, dphi, dgphi, dP, &df0, df1);
+      mb_tangent(&pt, A->fr, dG, dphi, dgphi, dP, &df0, df1);
       test_qp(t, qq, wdet, dP, df0, df1, out);
     } else {
       /* cotangent at the qp, in the output pairing of test_qp: (grad v_u, v_phi, grad v_phi) */
@@ -820,7 +980,7 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
         double in[13] = {0};
         in[k] = 1.0;
         double dP[9], df0, df1[3];
-        qp_tangent(&mat, A->fr, &s, in, in[9], in + 10, dP, &df0, df1);
+        mb_tangent(&pt, A->fr, in, in[9], in + 10, dP, &df0, df1);
         for (int r = 0; r < 9; r++) T[r][k] = dP[r];
         T[9][k] = df0;
         for (int r = 0; r < 3; r++) T[10 + r][k] = df1[r];
@@ -834,7 +994,7 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
       test_qp(t, qq, wdet, g, g[9], g + 10, out);
       /* parameter partials, paired with the same cotangent */
       double dPp[27], df0p[3], df1p[9];
-      qp_param_partials(&mat, A->fr, &s, gphi, dPp, df0p, df1p);
+      qp_param_partials(&pt.m[0], A->fr, s, gphi, dPp, df0p, df1p);
       for (int k = 0; k < 3; k++) {
         double sum = df0p[k] * cv[9];
         for (int r = 0; r < 9; r++) sum += dPp[9 * k + r] * cv[r];
@@ -850,6 +1010,7 @@ static int run_apply(const apply_args* A, int kind, double* outv, double* gparam
                      const int32_t* elems, int64_t n_elems) {
   const or_mesh* m = A->m;
   if (!m || !A->ph || A->nph < 1 || !A->fr || !A->phase || !A->state || !A->z || !outv) return -1;
+  if (A->n_extra < 0 || A->n_extra > OR_MAX_EXTRA || (A->n_extra > 0 && (!A->xbr || !A->xstate))) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
   int64_t ne_all = (int64_t)m->nx * m->ny * m->nz;
@@ -900,32 +1061,35 @@ static int run_apply(const apply_args* A, int kind, double* outv, double* gparam
   return bad ? 1 : 0;
 }
 
-int or_residual(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
-                const double* state, const double* phi_n, const double* z, double* r,
-                const int32_t* elems, int64_t n_elems) {
-  apply_args A = {m, ph, nph, fr, phase, state, phi_n, z, NULL};
+int or_residual(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+                const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+                const double* phi_n, const double* z, double* r, const int32_t* elems, int64_t n_elems) {
+  apply_args A = {m, ph, nph, xbr, n_extra, fr, phase, state, xstate, phi_n, z, NULL};
   return run_apply(&A, K_RES, r, NULL, elems, n_elems);
 }
 
-int or_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
-                const double* state, const double* phi_n, const double* z, const double* dz, double* y,
+int or_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+                const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+                const double* phi_n, const double* z, const double* dz, double* y,
                 const int32_t* elems, int64_t n_elems) {
   if (!dz) return -1;
-  apply_args A = {m, ph, nph, fr, phase, state, phi_n, z, dz};
+  apply_args A = {m, ph, nph, xbr, n_extra, fr, phase, state, xstate, phi_n, z, dz};
   return run_apply(&A, K_JAC, y, NULL, elems, n_elems);
 }
 
-int or_adjoint(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
-               const double* state, const double* phi_n, const double* z, const double* v, double* gz,
-               double* gparams, const int32_t* elems, int64_t n_elems) {
+int or_adjoint(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+               const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+               const double* phi_n, const double* z, const double* v, double* gz, double* gparams,
+               const int32_t* elems, int64_t n_elems) {
   if (!v) return -1;
-  apply_args A = {m, ph, nph, fr, phase, state, phi_n, z, v};
+  apply_args A = {m, ph, nph, xbr, n_extra, fr, phase, state, xstate, phi_n, z, v};
   return run_apply(&A, K_ADJ, gz, gparams, elems, n_elems);
 }
 
-int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
-                        const uint8_t* phase, const double* state, const double* phi_n, const double* z,
-                        int64_t e, double* Ke) {
+int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+                        const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+                        const double* phi_n, const double* z, int64_t e, double* Ke) {
+  if (n_extra < 0 || n_extra > OR_MAX_EXTRA || (n_extra > 0 && (!xbr || !xstate))) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
   int nP = t.nP, nd = 4 * nP;
@@ -937,7 +1101,7 @@ int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_
   int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * nP);
   double* ze = (double*)malloc(sizeof(double) * nd);
   double* we = (double*)malloc(sizeof(double) * nd);
-  apply_args A = {m, ph, nph, fr, phase, state, phi_n, z, unit};
+  apply_args A = {m, ph, nph, xbr, n_extra, fr, phase, state, xstate, phi_n, z, unit};
   int bad = 0;
   elem_nodes(m, &t, e, idx);
   for (int j = 0; j < nd; j++) {

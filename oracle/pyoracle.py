@@ -38,6 +38,15 @@ class OrPhase(C.Structure):
                 ("sigma_inf", C.c_double), ("voce_beta", C.c_double)]
 
 
+class OrBranch(C.Structure):
+    _fields_ = [("kind", C.c_int), ("E", C.c_double), ("nu", C.c_double), ("eta_d", C.c_double),
+                ("sigma0", C.c_double), ("H", C.c_double), ("visc", C.c_double), ("sigma_inf", C.c_double),
+                ("voce_beta", C.c_double)]
+
+
+MAX_EXTRA = 2
+
+
 class OrFrac(C.Structure):
     _fields_ = [("l0", C.c_double), ("eta", C.c_double), ("zeta", C.c_double), ("dt", C.c_double),
                 ("s_phi", C.c_double), ("at", C.c_int)]
@@ -68,7 +77,12 @@ def lib():
                                      _D, _D, C.c_double, _D, _D, _D, _D]
         L.or_qf_param_partials.argtypes = [C.POINTER(OrPhase), C.POINTER(OrFrac), _D, C.c_double, _D,
                                            C.c_double, _D, _D, _D, _D]
-        common = [C.POINTER(OrMesh), C.POINTER(OrPhase), C.c_int, C.POINTER(OrFrac), C.c_void_p, _D, _D, _D]
+        L.or_qf_residual_mb.argtypes = [C.POINTER(OrPhase), C.POINTER(OrBranch), C.c_int, C.POINTER(OrFrac), _D,
+                                        C.c_double, _D, C.c_double, _D, _D, C.POINTER(OrQpOut)]
+        L.or_qf_jacobian_mb.argtypes = [C.POINTER(OrPhase), C.POINTER(OrBranch), C.c_int, C.POINTER(OrFrac), _D,
+                                        C.c_double, _D, C.c_double, _D, _D, _D, C.c_double, _D, _D, _D, _D]
+        common = [C.POINTER(OrMesh), C.POINTER(OrPhase), C.c_int, C.POINTER(OrBranch), C.c_int,
+                  C.POINTER(OrFrac), C.c_void_p, _D, _D, _D, _D]
         L.or_residual.argtypes = common + [_D, C.c_void_p, C.c_int64]
         L.or_jacobian.argtypes = common + [_D, _D, C.c_void_p, C.c_int64]
         L.or_adjoint.argtypes = common + [_D, _D, _D, C.c_void_p, C.c_int64]
@@ -109,6 +123,26 @@ def phases_array(phases):
     return arr
 
 
+def branch_struct(b):
+    """b: inputs.Branch-like (kind, E, nu, eta_d, sigma0, H, visc, sigma_inf, voce_beta) or None."""
+    if b is None:
+        return OrBranch(0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+    return OrBranch(int(b.kind), b.E, b.nu, b.eta_d, b.sigma0, b.H, b.visc, b.sigma_inf, b.voce_beta)
+
+
+def branches_array(branches):
+    """branches: list over phases of lists (length n_extra) of branches; -> (array, n_extra)."""
+    if not branches:
+        return None, 0
+    n_extra = len(branches[0])
+    assert all(len(b) == n_extra for b in branches) and 0 <= n_extra <= MAX_EXTRA
+    arr = (OrBranch * max(1, len(branches) * n_extra))()
+    for i, row in enumerate(branches):
+        for j, b in enumerate(row):
+            arr[i * n_extra + j] = branch_struct(b)
+    return arr, n_extra
+
+
 def frac_struct(fr):
     return OrFrac(fr.l0, fr.eta, fr.zeta, fr.dt, fr.s_phi, int(fr.at))
 
@@ -142,6 +176,27 @@ def qf_jacobian(ph, fr, G, phi, gphi, phi_n, st, dG, dphi, dgphi):
     return dP.reshape(3, 3), df0[0], df1
 
 
+def qf_residual_mb(ph, xb, fr, G, phi, gphi, phi_n, st, xs):
+    """Point with the extra branches xb (list, length n_extra) and their states xs[7*n_extra]."""
+    out = OrQpOut()
+    arr, n_extra = branches_array([xb])
+    G = _f64(np.reshape(G, 9)); gphi = _f64(gphi); st = _f64(st); xs = _f64(np.reshape(xs, -1) if n_extra else np.zeros(1))
+    lib().or_qf_residual_mb(C.byref(phase_struct(ph)), arr, n_extra, C.byref(frac_struct(fr)), _p(G), float(phi),
+                            _p(gphi), float(phi_n), _p(st), _p(xs), C.byref(out))
+    return out
+
+
+def qf_jacobian_mb(ph, xb, fr, G, phi, gphi, phi_n, st, xs, dG, dphi, dgphi):
+    arr, n_extra = branches_array([xb])
+    G = _f64(np.reshape(G, 9)); gphi = _f64(gphi); st = _f64(st); xs = _f64(np.reshape(xs, -1) if n_extra else np.zeros(1))
+    dG = _f64(np.reshape(dG, 9)); dgphi = _f64(dgphi)
+    dP = np.zeros(9); df0 = np.zeros(1); df1 = np.zeros(3)
+    lib().or_qf_jacobian_mb(C.byref(phase_struct(ph)), arr, n_extra, C.byref(frac_struct(fr)), _p(G), float(phi),
+                            _p(gphi), float(phi_n), _p(st), _p(xs), _p(dG), float(dphi), _p(dgphi), _p(dP),
+                            _p(df0), _p(df1))
+    return dP.reshape(3, 3), df0[0], df1
+
+
 def qf_param_partials(ph, fr, G, phi, gphi, phi_n, st):
     G = _f64(np.reshape(G, 9)); gphi = _f64(gphi); st = _f64(st)
     dP = np.zeros(27); df0 = np.zeros(3); df1 = np.zeros(9)
@@ -161,7 +216,7 @@ def qf_commit(ph, fr, G, phi, st):
 class Oracle:
     """Oracle bound to one set of inputs (as produced by ``inputs.make_inputs``)."""
 
-    def __init__(self, mesh, phases, fracture, phase, state, phi_n):
+    def __init__(self, mesh, phases, fracture, phase, state, phi_n, branches=None, xstate=None):
         self.mesh = mesh
         self._m = mesh_struct(mesh)
         self._ph = phases_array(phases)
@@ -170,10 +225,23 @@ class Oracle:
         self.phase = np.ascontiguousarray(phase, dtype=np.uint8)
         self.state = _f64(state)
         self.phi_n = _f64(phi_n)
+        self.set_branches(branches, xstate)
 
     @classmethod
     def from_inputs(cls, d):
-        return cls(d["mesh"], d["phases"], d["fracture"], d["phase"], d["state"], d["phi_n"])
+        return cls(d["mesh"], d["phases"], d["fracture"], d["phase"], d["state"], d["phi_n"],
+                   d.get("branches"), d.get("xstate"))
+
+    def set_branches(self, branches, xstate):
+        """Extra branches per phase (list over phases of lists of length n_extra) and their
+        states [7*n_extra][n_q]; None detaches."""
+        self._xbr, self._nx = branches_array(branches)
+        if self._nx:
+            assert len(branches) == self._nph
+            self.xstate = _f64(xstate)
+            assert self.xstate.shape == (7 * self._nx, self.state.shape[1])
+        else:
+            self.xstate = np.zeros(1)
 
     def set_phases(self, phases):
         self._ph = phases_array(phases)
@@ -186,8 +254,8 @@ class Oracle:
         return e.ctypes.data_as(C.c_void_p), len(e), e
 
     def _common(self):
-        return (C.byref(self._m), self._ph, self._nph, C.byref(self._fr),
-                self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(self.phi_n))
+        return (C.byref(self._m), self._ph, self._nph, self._xbr, self._nx, C.byref(self._fr),
+                self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(self.xstate), _p(self.phi_n))
 
     def residual(self, z, elems=None, check=True):
         z = _f64(z)
@@ -218,7 +286,9 @@ class Oracle:
         return g, gp.reshape(self._nph, 3)
 
     def commit_state(self, z):
-        """State [8][n_q] after a converged step at z (exponential-map update)."""
+        """State [8][n_q] after a converged step at z (exponential-map update; single block)."""
+        if self._nx:
+            raise ValueError("state commit covers the single block only")
         z = _f64(z)
         out = np.zeros_like(self.state)
         rc = lib().or_commit_state(C.byref(self._m), self._ph, self._nph, C.byref(self._fr),

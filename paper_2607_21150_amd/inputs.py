@@ -17,7 +17,10 @@ Data layout shared by every consumer (an interface convention, not arithmetic):
 * per-point state is SoA ``[8][n_q]`` float64: ``D`` (6, Voigt order
   xx, yy, zz, yz, xz, xy) with ``D = C^{in,-1}_n - I``, the accumulated plastic
   strain, and the history field ``H_n``; the phase id is ``uint8[n_q]``
-  (0 = matrix, 1 = particle).
+  (0 = matrix, 1 = particle);
+* with extra branches in parallel (variant ``ex3``), their state is SoA
+  ``[7*n_extra][n_q]`` float64: per branch ``D`` (6) and its accumulated plastic
+  strain.
 
 Units are mm, MPa, s and N/mm (so G_c in N/mm = kJ/m^2).
 
@@ -43,14 +46,17 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Mesh", "Phase", "Fracture", "Config", "CONFIGS", "make_config",
+    "Mesh", "Phase", "Branch", "Fracture", "Config", "CONFIGS", "make_config",
     "make_inputs", "gll_points", "gauss_points", "default_phases",
     "default_fracture",
 ]
 
 SEED_BASE = 21150
 # one independent random stream per purpose
-STREAM_SPHERES, STREAM_PHI, STREAM_SINES, STREAM_STATE, STREAM_DIR, STREAM_COT = range(6)
+STREAM_SPHERES, STREAM_PHI, STREAM_SINES, STREAM_STATE, STREAM_DIR, STREAM_COT, STREAM_XSTATE = range(7)
+
+# kinds of extra branches in parallel with a phase's block
+BRANCH_NONE, BRANCH_HOOKE, BRANCH_MAXWELL, BRANCH_PRANDTL = 0, 1, 2, 3
 
 
 @dataclasses.dataclass(frozen=True)
@@ -104,6 +110,22 @@ class Phase:
 
 
 @dataclasses.dataclass(frozen=True)
+class Branch:
+    """Extra rheological branch in parallel with a phase's block: its own spring
+    (E, nu), a Maxwell branch's deviatoric viscosity eta_d [MPa s], a Prandtl
+    branch's hardening and overstress (as in Phase)."""
+    kind: int
+    E: float = 0.0
+    nu: float = 0.0
+    eta_d: float = 0.0
+    sigma0: float = 0.0
+    H: float = 0.0
+    visc: float = 0.0
+    sigma_inf: float = 0.0
+    voce_beta: float = 0.0
+
+
+@dataclasses.dataclass(frozen=True)
 class Fracture:
     l0: float
     eta: float = 1e-3       # residual stiffness factor
@@ -124,6 +146,19 @@ def voce_phases():
     """The default phases with Voce hardening on the matrix (saturation 30 MPa, rate 50)."""
     matrix, particle = default_phases()
     return [dataclasses.replace(matrix, sigma_inf=30.0, voce_beta=50.0), particle]
+
+
+def ex3_phases():
+    """The visco-elastoplastic matrix and the particle of the paper's third example
+    (its material table, in MPa, MPa s and N/mm): matrix = perfectly plastic Prandtl
+    block (E2 = 198 GPa, nu = 0.3, sigma0 = 500 MPa) in parallel with a Hooke spring
+    (1 GPa, 0.3) and a Maxwell branch (1 GPa, 0.3, eta_d = 0.01 GPa s); particle =
+    Hooke (400 GPa, 0.25). Returns (phases, branches[n_phases][2])."""
+    matrix = Phase(E=198000.0, nu=0.3, Gc=0.8, sigma0=500.0, H=0.0, visc=0.0, plastic=True)
+    particle = Phase(E=400000.0, nu=0.25, Gc=8.0)
+    xb_matrix = [Branch(BRANCH_HOOKE, E=1000.0, nu=0.3), Branch(BRANCH_MAXWELL, E=1000.0, nu=0.3, eta_d=10.0)]
+    xb_particle = [Branch(BRANCH_NONE), Branch(BRANCH_NONE)]
+    return [matrix, particle], [xb_matrix, xb_particle]
 
 
 def default_fracture(mesh: Mesh, phases, at: int = 1) -> Fracture:
@@ -155,7 +190,8 @@ CONFIGS = {
     "C5": Config("C5", 5, 4, 40, 200, 0.03, 0.08, 0.35),
 }
 
-VARIANT_E0 = {"base": 1e-3, "plastic": 2e-2, "compress": -1e-3, "voce": 2e-2}
+VARIANT_E0 = {"base": 1e-3, "plastic": 2e-2, "compress": -1e-3, "voce": 2e-2, "ex3": 1e-2,
+              "ex3_compress": -5e-3}
 
 
 def make_config(name: str, p: Optional[int] = None, n: Optional[int] = None) -> Config:
@@ -259,11 +295,15 @@ def make_inputs(name: str = "C1", variant: str = "base", p: Optional[int] = None
     Returns a dict with ``mesh``, ``phases``, ``fracture``, ``z`` [4][n_nodes],
     ``phi_n`` [n_nodes], ``state`` [8][n_q], ``phase`` uint8[n_q],
     ``dz`` [4][n_nodes] (unit l2 norm), ``v_top`` (top-face u_z indicator) and
-    ``v_rand`` [4][n_nodes] (unit l2 norm).
+    ``v_rand`` [4][n_nodes] (unit l2 norm). The ``ex3`` variants add ``branches``
+    (per phase, the extra branches) and ``xstate`` [7*n_extra][n_q].
     """
     cfg = make_config(name, p, n)
     mesh = Mesh(cfg.p, cfg.n, cfg.n, cfg.n)
-    if phases is None:
+    branches = None
+    if variant.startswith("ex3"):
+        phases, branches = ex3_phases()
+    elif phases is None:
         phases = voce_phases() if variant == "voce" else default_phases()
     frac = default_fracture(mesh, phases, at)
     e0 = VARIANT_E0[variant]
@@ -345,6 +385,31 @@ def make_inputs(name: str = "C1", variant: str = "base", p: Optional[int] = None
     out = dict(mesh=mesh, phases=list(phases), fracture=frac, z=z, phi_n=phi_n,
                state=state, phase=phase, cfg=cfg, variant=variant, e0=e0,
                sphere_scale=scale, vol_frac=float(phase.mean()))
+    if branches is not None:
+        # extra branches' states: an isochoric D per inelastic branch drawn like the
+        # block's (accumulated plastic strain 0), zero in the particles
+        n_extra = len(branches[0])
+        rng = _rng(cfg.cfg_id, STREAM_XSTATE)
+        xstate = np.zeros((7 * n_extra, nq))
+        for j in range(n_extra):
+            ep = rng.uniform(-1e-4, 1e-4, size=(nq, 6))
+            tr = (ep[:, 0] + ep[:, 1] + ep[:, 2]) / 3.0
+            ep[:, :3] -= tr[:, None]
+            E = np.zeros((nq, 3, 3))
+            E[:, 0, 0], E[:, 1, 1], E[:, 2, 2] = ep[:, 0], ep[:, 1], ep[:, 2]
+            E[:, 1, 2] = E[:, 2, 1] = ep[:, 3]
+            E[:, 0, 2] = E[:, 2, 0] = ep[:, 4]
+            E[:, 0, 1] = E[:, 1, 0] = ep[:, 5]
+            lam, V = np.linalg.eigh(E)
+            Dm = np.einsum("qij,qj,qkj->qik", V, np.expm1(-2.0 * lam), V)
+            del E, V, lam
+            r = 7 * j
+            xstate[r], xstate[r + 1], xstate[r + 2] = Dm[:, 0, 0], Dm[:, 1, 1], Dm[:, 2, 2]
+            xstate[r + 3], xstate[r + 4], xstate[r + 5] = Dm[:, 1, 2], Dm[:, 0, 2], Dm[:, 0, 1]
+            del Dm
+        xstate[:, part] = 0.0
+        out["branches"] = branches
+        out["xstate"] = xstate
     if with_dir:
         rng = _rng(cfg.cfg_id, STREAM_DIR)
         dz = rng.standard_normal((4, mesh.n_nodes))
