@@ -86,6 +86,26 @@ typedef struct {
   double sigma_inf, voce_beta;
 } pf_phase;
 
+/* Extra rheological branch in parallel with a phase's block (Section 2.3 and Box 1:
+ * tau = sum_k tau_k, psi = sum_k psi_k, each branch with its own Cin^-1): kind
+ * PF_BRANCH_HOOKE (spring E [MPa], nu; Cin^-1 = I), PF_BRANCH_MAXWELL (spring plus the
+ * deviatoric viscosity eta_d [MPa s]; closed-form update
+ * eq:viscoelasticity-deviatoric-strain-update-hencky with the degraded modulus g mu,
+ * eq:principal-directions-format-1) or PF_BRANCH_PRANDTL (spring plus sigma0, H, visc,
+ * sigma_inf, voce_beta as in pf_phase); PF_BRANCH_NONE leaves the slot empty. Every
+ * branch is degraded by the Amor split of its own trial volumetric strain; the point's
+ * psi^+ (history field and phase-field residual) is the sum over the block and the
+ * branches. */
+#define PF_BRANCH_NONE 0
+#define PF_BRANCH_HOOKE 1
+#define PF_BRANCH_MAXWELL 2
+#define PF_BRANCH_PRANDTL 3
+#define PF_MAX_EXTRA_BRANCHES 2
+typedef struct {
+  int kind;
+  double E, nu, eta_d, sigma0, H, visc, sigma_inf, voce_beta;
+} pf_branch;
+
 /* Fracture element and time step: length scale l0 [mm], residual stiffness eta
  * (eq:degr-funct), damage viscosity zeta [MPa s] (Section 3.1), time step dt [s],
  * global phase-field residual scale s_phi (eq:damage-residual-scaling), AT model
@@ -110,6 +130,20 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
 
 /* Sizes of the fine level. Any output pointer may be NULL. */
 pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n_dof);
+
+/* Attach n_extra (0..PF_MAX_EXTRA_BRANCHES) extra branches to every phase:
+ * branches[n_phases][n_extra] in host memory (copied), xstate a device pointer kept by
+ * the context, double[7*n_extra][n_q]: rows 7j..7j+5 the D = Cin^-1 - I (Voigt) of
+ * extra branch j, row 7j+6 its accumulated plastic strain (a Hooke branch reads none of
+ * them). n_extra = 0 detaches (branches and xstate may then be NULL). Orders 2-4; the
+ * FP64 residual, Jacobian and adjoint (with the block's parameter partials) include the
+ * branches. The linearisation-based calls (pf_linearize and what needs it: the FP32
+ * levels, the V-cycle, pf_apply_jacobian_lin, pf_newton_step) and pf_commit_state cover
+ * the single block only and return PF_EUNSUPPORTED while branches are attached.
+ * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
+ * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
+ * p = 1, PF_ENOMEM / PF_EHIP from the device copy. */
+pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, const double* xstate);
 
 /* Replace the per-phase parameters (Gc, sigma0, visc) from host memory
  * params[n_phases][3]. Takes effect for applies enqueued after the call. */

@@ -19,6 +19,7 @@
 #include "pf_brick.hpp"
 #include "pf_mg.hpp"
 #include "pf_ops.hpp"
+#include "pf_branch.hpp"
 #include "pf_qf.hpp"
 
 namespace pfmf {
@@ -298,7 +299,7 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
 }
 
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
-template <int MODE, bool BB, bool VOCE>
+template <int MODE, bool BB, bool VOCE, bool MB>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
@@ -364,7 +365,11 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       phin = v[0];
     }
     // pointwise function
-    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+    const int pidc = pid < a.nph ? pid : 0;
+    const MatParams<double> mp = a.mats[pidc];
+    // branches in parallel, adjoint: the extra branches' psi^+ decides the switch
+    double psi_x = 0.0;
+    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, true, G, phi, any_bad);
     QPState<double> s;
     qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= s.bad;
@@ -386,14 +391,19 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     double Fu[9], f0, f1[3];
     if (MODE == M_RES) {
       piola<double>(s, Fu);
+      double L = s.L;
+      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, true, G, phi, phin, st[7], s.psi, s.gp, Fu, any_bad);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
-      f0 = wdet * a.fr.s_phi * s.L;
+      f0 = wdet * a.fr.s_phi * L;
 #pragma unroll
       for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
     } else if (MODE == M_JAC) {
       double dL;
-      qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+      if (MB)
+        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, true, G, phi, phi, st[7], W, wphi, Fu, any_bad);
+      else
+        qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
       f0 = wdet * a.fr.s_phi * dL;
@@ -405,9 +415,11 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
       const double f0b = wdet * wphi;
       const double Lb = a.fr.s_phi * f0b;
-      double phib, Xd[3];
-      qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
-      f0 = phib;
+      double phib, Xd[3], Hb = 0.0;
+      if (MB)
+        Hb = mb_adjoint_block(a, mp, s, psi_x, phi, phi, st[7], Pb, Lb, Fu, phib, Xd);
+      else
+        qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
 #pragma unroll
       for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
       double gsum[3] = {0.0, 0.0, 0.0};
@@ -418,10 +430,13 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
         const double q = 2.0 * mp.mu * sqrt(1.5 * ee);
         const double w3q = 3.0 * mp.mu / q;
         const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
-        const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        const double hterm = MB ? Hb * 2.0 * mp.mu * s.c * ee : (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        const double base = s.g * 2.0 * mp.mu * xe + hterm;
         gsum[1] += -w3q * s.ddg_s0 * base;
         gsum[2] += -w3q * s.ddg_visc * base;
       }
+      if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, true, G, phi, Pb, Hb, Fu, phib);
+      f0 = phib;
       gpid[slot * 64 + l] = (unsigned char)pid;
 #pragma unroll
       for (int k = 0; k < 3; ++k) gpq[(slot * 3 + k) * 64 + l] = gsum[k];
@@ -500,8 +515,9 @@ namespace pfmf {
 // then runs on a packed layout holding both elements of the wave (lanes 0-26 and
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
 // two elements.
-template <int MODE, bool BB, bool VOCE>
-__global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+template <int MODE, bool BB, bool VOCE, bool MB>
+__global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
+                                                                              DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
@@ -573,7 +589,12 @@ __global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a,
 #pragma unroll
     for (int k = 0; k < 8; ++k) st[k] = valid ? a.state[k * a.n_q + gq] : 0.0;
     pid = valid ? a.phase[gq] : 255;
-    const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+    const int pidc = pid < a.nph ? pid : 0;
+    const MatParams<double> mp = a.mats[pidc];
+    // branches in parallel (flags of lanes without a point are dropped)
+    bool xbad = false;
+    double psi_x = 0.0;
+    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, valid, G, phi, xbad);
     QPState<double> s;
     qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= valid && s.bad;
@@ -612,14 +633,19 @@ __global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a,
     double Fu[9], f0, f1[3];
     if (MODE == M_RES) {
       piola<double>(s, Fu);
+      double L = s.L;
+      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, valid, G, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
-      f0 = wdet * a.fr.s_phi * s.L;
+      f0 = wdet * a.fr.s_phi * L;
 #pragma unroll
       for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
     } else if (MODE == M_JAC) {
       double dL;
-      qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+      if (MB)
+        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, valid, G, phi, phi, st[7], W, wphi, Fu, xbad);
+      else
+        qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
       f0 = wdet * a.fr.s_phi * dL;
@@ -631,9 +657,11 @@ __global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a,
       for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
       const double f0b = wdet * wphi;
       const double Lb = a.fr.s_phi * f0b;
-      double phib, Xd[3];
-      qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
-      f0 = phib;
+      double phib, Xd[3], Hb = 0.0;
+      if (MB)
+        Hb = mb_adjoint_block(a, mp, s, psi_x, phi, phi, st[7], Pb, Lb, Fu, phib, Xd);
+      else
+        qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
 #pragma unroll
       for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
       const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
@@ -643,12 +671,16 @@ __global__ __launch_bounds__(NT, MODE == M_ADJ ? 2 : 3) void k_op64_q2(OpArgs a,
         const double qv = 2.0 * mp.mu * sqrt(1.5 * ee);
         const double w3q = 3.0 * mp.mu / qv;
         const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
-        const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        const double hterm = MB ? Hb * 2.0 * mp.mu * s.c * ee : (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+        const double base = s.g * 2.0 * mp.mu * xe + hterm;
         gsum[1] = -w3q * s.ddg_s0 * base;
         gsum[2] = -w3q * s.ddg_visc * base;
       }
+      if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, valid, G, phi, Pb, Hb, Fu, phib);
+      f0 = phib;
       if (!valid) gsum[0] = gsum[1] = gsum[2] = 0.0;
     }
+    if (MB) any_bad |= valid && xbad;
     // ---- back to the padded layout of each element, transposed interpolation
     double b1p[4][3];
     double b0p[4];

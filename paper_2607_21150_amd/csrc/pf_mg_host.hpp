@@ -476,6 +476,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!z) return fail(PF_EINVAL, "null z");
+  if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "the linearisation covers the single block (extra branches attached)");
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   if ((st = mg_alloc(c))) return st;
@@ -556,6 +557,7 @@ pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* s
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!z || !state_out) return fail(PF_EINVAL, "null argument");
+  if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "the state commit covers the single block (extra branches attached)");
   const size_t ns = 8 * c->n_q * sizeof(double);
   if (overlaps(state_out, ns, c->qp_state, ns)) return fail(PF_EINVAL, "state_out aliases the context's state");
   if (overlaps(state_out, ns, z, 4 * c->n_nodes * sizeof(double))) return fail(PF_EINVAL, "state_out aliases z");

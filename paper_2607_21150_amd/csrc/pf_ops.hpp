@@ -7,6 +7,16 @@ namespace pfmf {
 
 enum OpMode { M_RES = 0, M_JAC = 1, M_ADJ = 2 };
 
+// Extra rheological branch of a phase, in parallel with its block (Section 2.3):
+// kind XB_NONE (empty slot), XB_HOOKE (spring, Cin^-1 = I), XB_MAXWELL (m.am > 0) or
+// XB_PRANDTL (m.plastic); m holds the branch's own spring and parameters.
+enum { XB_NONE = 0, XB_HOOKE = 1, XB_MAXWELL = 2, XB_PRANDTL = 3 };
+constexpr int MAX_EXTRA = 2;
+struct XBranch {
+  MatParams<double> m;
+  int kind;
+};
+
 struct OpArgs {
   MeshDev m;
   int nx1, ny1;
@@ -24,6 +34,9 @@ struct OpArgs {
   int brick_base;       // global id of this colour's first brick (for gpart)
   double* ebuf;         // brick-buffer scatter: per-brick node sums [n_bricks][4][(2P-1)^3]
   int* flag;            // sticky non-physical flag (device)
+  const XBranch* xb;    // extra branches [nph][n_extra] (n_extra = 0: none)
+  const double* xstate; // their states [7*n_extra][n_q]: D[6], ebar_p per branch
+  int n_extra;
 };
 
 template <int P, int Q> struct OpShape {

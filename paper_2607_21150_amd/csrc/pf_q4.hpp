@@ -20,6 +20,7 @@
 #include "pf_brick.hpp"
 #include "pf_mg.hpp"
 #include "pf_ops.hpp"
+#include "pf_branch.hpp"
 #include "pf_qf.hpp"
 
 namespace pfmf {
@@ -252,7 +253,7 @@ template <int P, int Q> struct Q5Lds {
 };
 
 // FP64 residual / Jacobian / adjoint on order-4 elements.
-template <int MODE, bool VOCE>
+template <int MODE, bool VOCE, bool MB>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   constexpr int P = 5, Q = 5, Q3 = 125;
   using L = Q5Lds<P, Q>;
@@ -294,10 +295,15 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     phin = bufB[ql];
     __syncthreads();
   }
-  const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
+  const int pidc = pid < a.nph ? pid : 0;
+  const MatParams<double> mp = a.mats[pidc];
+  // branches in parallel (flags of threads without a point are dropped)
+  bool xbad = false;
+  double psi_x = 0.0;
+  if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, pt, G, phi, xbad);
   QPState<double> s;
   qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
-  const bool bad = pt && s.bad;
+  bool bad = pt && s.bad;
   double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
   if (MODE != M_RES) {
     gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
@@ -317,14 +323,19 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   double gsum[3] = {0.0, 0.0, 0.0};
   if (MODE == M_RES) {
     piola<double>(s, Fu);
+    double Lr = s.L;
+    if (MB) Lr = mb_residual<VOCE>(a, mp, pidc, gq, pt, G, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
-    f0 = wdet * a.fr.s_phi * s.L;
+    f0 = wdet * a.fr.s_phi * Lr;
 #pragma unroll
     for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
   } else if (MODE == M_JAC) {
     double dL;
-    qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+    if (MB)
+      dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, pt, G, phi, phi, st[7], W, wphi, Fu, xbad);
+    else
+      qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
     f0 = wdet * a.fr.s_phi * dL;
@@ -336,9 +347,11 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
     const double f0b = wdet * wphi;
     const double Lb = a.fr.s_phi * f0b;
-    double phib, Xd[3];
-    qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
-    f0 = phib;
+    double phib, Xd[3], Hb = 0.0;
+    if (MB)
+      Hb = mb_adjoint_block(a, mp, s, psi_x, phi, phi, st[7], Pb, Lb, Fu, phib, Xd);
+    else
+      qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
 #pragma unroll
     for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
     const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
@@ -348,11 +361,15 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
       const double q = 2.0 * mp.mu * sqrt(1.5 * ee);
       const double w3q = 3.0 * mp.mu / q;
       const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
-      const double base = s.g * 2.0 * mp.mu * xe + (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+      const double hterm = MB ? Hb * 2.0 * mp.mu * s.c * ee : (s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0);
+      const double base = s.g * 2.0 * mp.mu * xe + hterm;
       gsum[1] = -w3q * s.ddg_s0 * base;
       gsum[2] = -w3q * s.ddg_visc * base;
     }
+    if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, pt, G, phi, Pb, Hb, Fu, phib);
+    f0 = phib;
   }
+  if (MB) bad |= pt && xbad;
   // point coefficients into Qi[f][c][q] (bufB is free: every thread has read its values)
   if (pt) {
 #pragma unroll

@@ -24,6 +24,7 @@ template <typename T> struct MatParams {
   T mu, kappa, Gc, sigma0, H, a;  // a = visc / dt
   int plastic;
   T sinf, bv;                     // Voce saturation stress and rate (bv = 0: linear hardening)
+  T am;                           // Maxwell branch: mu dt / eta_d (0 for other branches)
 };
 
 // Yield stress and its slope at accumulated plastic strain ep
@@ -401,8 +402,9 @@ __device__ inline void qp_frame_stress(const MatParams<T>& m, const T* beta, con
 //   G: grad_X u (row-major), phi: phase field at the point, phin: previous phi,
 //   st: D[6] (Voigt), ebar_p, H_n.
 //   VOCE = false compiles the linear-hardening return only (kernels launched for
-//   contexts without a Voce phase, so that the iteration widens no register budget).
-template <typename T, bool VOCE = true>
+//   contexts without a Voce phase, so that the iteration widens no register budget);
+//   MAXW = true adds the Maxwell update of a branch with m.am > 0.
+template <typename T, bool VOCE = true, bool MAXW = false>
 __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, const T* G, T phi,
                                 T phin, const T* st, QPState<T>& s) {
   T beta[3], eps[3];
@@ -461,6 +463,13 @@ __device__ inline void qp_state(const MatParams<T>& m, const FracParams<T>& fr, 
     s.kphi = -w * s.gp * (q - T(3) * m.mu * dg) * iden;
     s.ddg_s0 = -(T(1) + m.a * dg) * ((VOCE && m.bv > T(0)) ? exp(-m.bv * ep) : T(1)) * iden;
     s.ddg_visc = -sy * dg * fr.inv_dt * iden;
+  }
+  if (MAXW && m.am > T(0)) {
+    // Maxwell branch with the degraded modulus g mu: eps_d^e = c eps_d^e,tr with
+    // c = 1 / (1 + g mu dt / eta_d) and dc/dphi = -(mu dt / eta_d) g' c^2
+    // (eq:principal-directions-format-1, eq:maxwell-dtau-dphi)
+    s.c = frcp(T(1) + m.am * s.g);
+    s.kphi = -m.am * s.gp * s.c * s.c;
   }
   // block stress, Amor split, psi^+ (eq:principal-stress-update-eigenvalues,
   // eq:linear-degraded-stress, principal psi^+ of Appendix A)
@@ -680,8 +689,8 @@ __device__ inline void piola(const QPState<T>& s, T* P) {
 // term is the geometric part -tau_degr dl^T expressed in the frame.
 // The phase-field gradient term is linear and handled by the caller.
 template <typename T>
-__device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
-                                  T* dP, T& dL) {
+__device__ inline void qp_tangent_psi(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
+                                      T* dP, T& dpsi) {
   const T* N = s.N;
   // FiN = F^-1 N serves both ends: dl N = dG FiN and F^-T at the output
   T FiN[9];
@@ -753,29 +762,35 @@ __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, co
 #pragma unroll
     for (int J = 0; J < 3; ++J)
       dP[3 * i + J] = NZ[3 * i] * FiN[3 * J] + NZ[3 * i + 1] * FiN[3 * J + 1] + NZ[3 * i + 2] * FiN[3 * J + 2];
-  // history and local phase-field residual (eq:history-field-linearization,
-  // eq:energy-displacement-linearization, eq:linearized-local-damage-residual)
-  T dH = T(0);
-  if (s.hactive) {
-    dH = tm2 * s.c * (s.e[0] * dce[0] + s.e[1] * dce[1] + s.e[2] * dce[2]);
-    if (s.tension) dH += m.kappa * s.theta * dth;
-  }
-  dL = s.dLcoef * dphi + s.gp * dH;
+  // psi^+ increment of this branch (eq:energy-displacement-linearization)
+  dpsi = tm2 * s.c * (s.e[0] * dce[0] + s.e[1] * dce[1] + s.e[2] * dce[2]);
+  if (s.tension) dpsi += m.kappa * s.theta * dth;
+}
+
+// The tangent of a single block: dP and the local phase-field increment
+// dL = dLcoef dphi + g' dH with dH = dpsi^+ when the history switch is on
+// (eq:history-field-linearization, eq:linearized-local-damage-residual).
+template <typename T>
+__device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
+                                  T* dP, T& dL) {
+  T dpsi;
+  qp_tangent_psi<T>(m, s, dG, dphi, dP, dpsi);
+  dL = s.dLcoef * dphi + s.gp * (s.hactive ? dpsi : T(0));
 }
 
 // Reverse (transpose) of qp_tangent: cotangents (Pb = dP-bar, Lb = dL-bar) ->
 // (Gb = dG-bar, phib = dphi-bar), step by step in the reverse order of the forward
 // map, in the principal frame. Also returns the diagonal of the rotated stress
 // cotangent Xd_i = [N^T (Pb F^-1) N]_ii used by the parameter partials.
+// Core: Hb = the cotangent of psi^+ (zero when the history switch is off); phib
+// starts from phib0 and collects the branch's terms.
 template <typename T>
-__device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, const T* Pb, T Lb, T* Gb,
-                                    T& phib, T* Xd) {
+__device__ inline void qp_tangent_T_psi(const MatParams<T>& m, const QPState<T>& s, const T* Pb, T Hb, T phib0,
+                                        T* Gb, T& phib, T* Xd) {
   const T* N = s.N;
   const T* bd = s.bd;
   const T tm2 = T(2) * m.mu;
-  // dL = dLcoef dphi + gp dH
-  phib = s.dLcoef * Lb;
-  const T Hb = s.gp * Lb;
+  phib = phib0;
   // FiN = F^-1 N (both ends, as in the forward map)
   T FiN[9];
 #pragma unroll
@@ -835,8 +850,8 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
       phib += s.gp * taubd[i] * xb;
     }
   }
-  // history: dH = hactive (2 mu c e.dce + tension kappa theta dth)
-  if (s.hactive) {
+  // psi^+: dpsi = 2 mu c e.dce + tension kappa theta dth
+  if (Hb != T(0)) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) dceb[i] += tm2 * s.c * s.e[i] * Hb;
     if (s.tension) dthb += kapth * Hb;
@@ -863,6 +878,14 @@ __device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, 
 #pragma unroll
     for (int J = 0; J < 3; ++J)
       Gb[3 * i + J] = R[3 * i] * FiN[3 * J] + R[3 * i + 1] * FiN[3 * J + 1] + R[3 * i + 2] * FiN[3 * J + 2];
+}
+
+// Transpose of the single block's tangent: dL = dLcoef dphi + g' dH, dH = dpsi^+ when
+// the history switch is on.
+template <typename T>
+__device__ inline void qp_tangent_T(const MatParams<T>& m, const QPState<T>& s, const T* Pb, T Lb, T* Gb,
+                                    T& phib, T* Xd) {
+  qp_tangent_T_psi<T>(m, s, Pb, s.hactive ? s.gp * Lb : T(0), s.dLcoef * Lb, Gb, phib, Xd);
 }
 
 }  // namespace pfmf

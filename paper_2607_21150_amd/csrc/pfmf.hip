@@ -57,6 +57,10 @@ struct pf_ctx {
   const uint8_t* qp_phase = nullptr;
   const double* qp_state = nullptr;
   const double* phi_n = nullptr;
+  // extra branches in parallel (pf_set_branches)
+  int n_extra = 0;
+  XBranch* d_xb = nullptr;
+  const double* xstate = nullptr;
   // device buffers
   DevTables* d_tab = nullptr;
   DevTablesF* d_tabf = nullptr;
@@ -132,6 +136,26 @@ MatParams<T> mat_params(const pf_phase& p, const pf_fracture& f) {
   m.plastic = p.plastic ? 1 : 0;
   m.sinf = (T)p.sigma_inf;
   m.bv = (T)p.voce_beta;
+  m.am = (T)0;
+  return m;
+}
+
+// Device material of an extra branch (its own spring; Prandtl and Maxwell parameters).
+MatParams<double> branch_params(const pf_branch& b, const pf_fracture& f, double Gc) {
+  MatParams<double> m{};
+  m.mu = b.E / (2.0 * (1.0 + b.nu));
+  m.kappa = b.E / (3.0 * (1.0 - 2.0 * b.nu));
+  m.Gc = Gc;
+  if (b.kind == PF_BRANCH_PRANDTL) {
+    m.plastic = 1;
+    m.sigma0 = b.sigma0;
+    m.H = b.H;
+    m.a = b.visc / f.dt;
+    m.sinf = b.sigma_inf;
+    m.bv = b.voce_beta;
+  } else if (b.kind == PF_BRANCH_MAXWELL) {
+    m.am = m.mu * f.dt / b.eta_d;
+  }
   return m;
 }
 
@@ -220,7 +244,7 @@ inline bool use_brick_buffer(const pf_ctx* c) {
   return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
 }
 
-template <int MODE, int P, bool VOCE>
+template <int MODE, int P, bool VOCE, bool MB>
 pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   const bool bb = use_brick_buffer(c);
   if (bb) {
@@ -232,9 +256,9 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     a.brick_base = 0;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = c->ny1 * c->nz1;
     hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -247,26 +271,29 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
     if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
 }
 
-// kernels without the Voce iteration unless a phase uses it
+// kernels without the Voce iteration unless a phase uses it; with extra branches
+// attached, the branch variant (which carries the Voce iteration for any branch)
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
-  return c->has_voce ? launch_op64_mfma_v<MODE, P, true>(c, a, s) : launch_op64_mfma_v<MODE, P, false>(c, a, s);
+  if (c->n_extra > 0) return launch_op64_mfma_v<MODE, P, true, true>(c, a, s);
+  return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false>(c, a, s)
+                     : launch_op64_mfma_v<MODE, P, false, false>(c, a, s);
 }
 
-template <int MODE, bool VOCE>
+template <int MODE, bool VOCE, bool MB>
 pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;
-    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -274,13 +301,16 @@ pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE>
 pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
-  return c->has_voce ? launch_op64_q4_v<MODE, true>(c, a, s) : launch_op64_q4_v<MODE, false>(c, a, s);
+  if (c->n_extra > 0) return launch_op64_q4_v<MODE, true, true>(c, a, s);
+  return c->has_voce ? launch_op64_q4_v<MODE, true, false>(c, a, s) : launch_op64_q4_v<MODE, false, false>(c, a, s);
 }
 
 template <int MODE>
 pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   switch (c->mesh.p) {
-    case 1: return launch_op64<MODE, 2, 2>(c, a, s);
+    case 1:
+      if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
+      return launch_op64<MODE, 2, 2>(c, a, s);
     case 2: return launch_op64_mfma<MODE, 3>(c, a, s);
     case 3: return launch_op64_mfma<MODE, 4>(c, a, s);
     case 4: return launch_op64_q4<MODE>(c, a, s);
@@ -308,6 +338,9 @@ OpArgs op_args(pf_ctx* c) {
   a.ebuf = nullptr;
   a.brick_base = 0;
   a.flag = c->d_flag;
+  a.xb = c->d_xb;
+  a.xstate = c->xstate;
+  a.n_extra = c->n_extra;
   return a;
 }
 
@@ -394,6 +427,48 @@ pf_status pf_sizes(const pf_ctx* c, int64_t* n_nodes, int64_t* n_q, int64_t* n_d
   if (n_nodes) *n_nodes = c->n_nodes;
   if (n_q) *n_q = c->n_q;
   if (n_dof) *n_dof = 4 * c->n_nodes;
+  return PF_OK;
+}
+
+pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, const double* xstate) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if (n_extra < 0 || n_extra > PF_MAX_EXTRA_BRANCHES)
+    return fail(PF_EINVAL, "n_extra=%d outside 0..%d", n_extra, PF_MAX_EXTRA_BRANCHES);
+  if (n_extra > 0 && (!branches || !xstate)) return fail(PF_EINVAL, "null branches or xstate");
+  if (n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
+  const int nph = (int)c->phases.size();
+  std::vector<XBranch> xb((size_t)nph * (n_extra > 0 ? n_extra : 1));
+  for (int i = 0; i < nph * n_extra; ++i) {
+    const pf_branch& b = branches[i];
+    if (b.kind < PF_BRANCH_NONE || b.kind > PF_BRANCH_PRANDTL) return fail(PF_EINVAL, "branch %d: bad kind %d", i, b.kind);
+    xb[i].kind = b.kind;
+    xb[i].m = MatParams<double>{};
+    if (b.kind == PF_BRANCH_NONE) continue;
+    if (!(b.E > 0) || !(b.nu > -1.0 && b.nu < 0.5)) return fail(PF_EINVAL, "branch %d: bad E or nu", i);
+    if (b.kind == PF_BRANCH_MAXWELL && !(b.eta_d > 0)) return fail(PF_EINVAL, "branch %d: Maxwell needs eta_d > 0", i);
+    if (b.kind == PF_BRANCH_PRANDTL) {
+      if (!(b.sigma0 > 0 && b.H >= 0 && b.visc >= 0 && b.voce_beta >= 0))
+        return fail(PF_EINVAL, "branch %d: bad Prandtl parameters", i);
+      if (b.voce_beta > 0 && !(b.sigma_inf >= b.sigma0))
+        return fail(PF_EINVAL, "branch %d: Voce needs sigma_inf >= sigma0", i);
+    }
+    xb[i].m = branch_params(b, c->fr, c->phases[i / n_extra].Gc);
+  }
+  HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old table
+  (void)hipFree(c->d_xb);
+  c->d_xb = nullptr;
+  c->n_extra = 0;
+  c->xstate = nullptr;
+  if (n_extra > 0) {
+    if (hipMalloc(&c->d_xb, xb.size() * sizeof(XBranch)) != hipSuccess)
+      return fail(PF_ENOMEM, "branch table allocation failed");
+    HIPCHK(hipMemcpy(c->d_xb, xb.data(), xb.size() * sizeof(XBranch), hipMemcpyHostToDevice));
+    c->n_extra = n_extra;
+    c->xstate = xstate;
+  }
+  c->mg.linearized = false;  // the linearisation covers the single block
+  c->mg.lin64_valid = false;
   return PF_OK;
 }
 
@@ -516,6 +591,7 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_gpart);
   (void)hipFree(c->d_ebuf);
   (void)hipFree(c->d_flag);
+  (void)hipFree(c->d_xb);
   delete c;
 }
 

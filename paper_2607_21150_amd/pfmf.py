@@ -23,7 +23,7 @@ EXPORTED = [
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
-    "pf_apply_jacobian_lin",
+    "pf_apply_jacobian_lin", "pf_set_branches",
 ]
 
 # pf_set_option
@@ -51,6 +51,17 @@ class PhaseDesc(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("Gc", C.c_double), ("sigma0", C.c_double),
                 ("H", C.c_double), ("visc", C.c_double), ("plastic", C.c_int),
                 ("sigma_inf", C.c_double), ("voce_beta", C.c_double)]
+
+
+class BranchDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("E", C.c_double), ("nu", C.c_double), ("eta_d", C.c_double),
+                ("sigma0", C.c_double), ("H", C.c_double), ("visc", C.c_double), ("sigma_inf", C.c_double),
+                ("voce_beta", C.c_double)]
+
+
+# pf_branch kinds
+PF_BRANCH_NONE, PF_BRANCH_HOOKE, PF_BRANCH_MAXWELL, PF_BRANCH_PRANDTL = 0, 1, 2, 3
+PF_MAX_EXTRA_BRANCHES = 2
 
 
 class FractureDesc(C.Structure):
@@ -110,6 +121,7 @@ def load():
     L.pf_newton_step.argtypes = [vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp]
     L.pf_set_option.argtypes = [vp, C.c_int, C.c_int]
     L.pf_apply_jacobian_lin.argtypes = [vp, vp, vp, vp]
+    L.pf_set_branches.argtypes = [vp, vp, C.c_int, vp]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -172,8 +184,11 @@ class Context:
     @classmethod
     def from_inputs(cls, d, device="cuda"):
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
-        return cls(d["mesh"], d["phases"], d["fracture"], t(d["phase"], torch.uint8),
-                   t(d["state"], torch.float64), t(d["phi_n"], torch.float64))
+        ctx = cls(d["mesh"], d["phases"], d["fracture"], t(d["phase"], torch.uint8),
+                  t(d["state"], torch.float64), t(d["phi_n"], torch.float64))
+        if d.get("branches"):
+            ctx.set_branches(d["branches"], t(d["xstate"], torch.float64))
+        return ctx
 
     def close(self):
         if getattr(self, "_h", None):
@@ -191,6 +206,23 @@ class Context:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         _check(load().pf_sizes(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
+
+    def set_branches(self, branches, xstate):
+        """pf_set_branches: branches = per phase a list of n_extra branch descriptions
+        (kind, E, nu, eta_d, sigma0, H, visc, sigma_inf, voce_beta); xstate = device
+        float64 [7*n_extra][n_q], kept referenced. branches = None detaches."""
+        if not branches:
+            _check(load().pf_set_branches(self._h, None, 0, None))
+            self.xstate = None
+            return
+        n_extra = len(branches[0])
+        if len(branches) != self.n_phases or any(len(b) != n_extra for b in branches):
+            raise PfError(PF_EINVAL, "branches: one list of equal length per phase")
+        flat = [b for row in branches for b in row]
+        arr = (BranchDesc * len(flat))(*[BranchDesc(int(b.kind), b.E, b.nu, b.eta_d, b.sigma0, b.H, b.visc,
+                                                    b.sigma_inf, b.voce_beta) for b in flat])
+        self.xstate = _req(xstate, torch.float64, (7 * n_extra, self.n_q), "xstate")
+        _check(load().pf_set_branches(self._h, arr, n_extra, _ptr(self.xstate)))
 
     def set_params(self, params):
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.n_phases, 3))
