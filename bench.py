@@ -185,6 +185,71 @@ def secondary_leg(torch, I, pfmf, config):
             "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
 
 
+def branch_state_bytes(d):
+    """Algorithmic bytes of the extra branches' state per apply: D (6 doubles) of every
+    inelastic extra branch at the points of its phase, plus the accumulated plastic strain
+    of a Prandtl branch (a Hooke branch reads none)."""
+    total = 0
+    for pid, row in enumerate(d["branches"]):
+        npts = int(np.count_nonzero(d["phase"] == pid))
+        for b in row:
+            if b.kind == 2:
+                total += 48 * npts
+            elif b.kind == 3:
+                total += 56 * npts
+    return total
+
+
+def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
+    """FP64 applies with the third example's matrix (perfectly plastic Prandtl block in
+    parallel with a Hooke spring and a Maxwell branch; Hooke particles) on a workload of the
+    headline's size: median device time of each apply (HIP events around every launch)."""
+    d = I.make_inputs(config, "ex3")
+    mesh = d["mesh"]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64)
+    ctx = pfmf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_top"])
+    r, y, g = torch.empty_like(z), torch.empty_like(z), torch.empty_like(z)
+    gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
+    ops = {"residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
+           "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp)}
+    for _ in range(warmup):
+        for f in ops.values():
+            f()
+    torch.cuda.synchronize()
+    ev = {k: [] for k in ops}
+    for _ in range(steps):
+        for k, f in ops.items():
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            f()
+            b.record()
+            ev[k].append((a, b))
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
+    xb = branch_state_bytes(d)
+    alg = {k: alg_bytes(mesh, k) + xb for k in ms}
+    errs = {}
+    try:
+        from oracle import pyoracle
+        pyoracle.build(force=False)
+        orc = pyoracle.Oracle.from_inputs(d)
+        rng = np.random.default_rng(0)
+        errs["jacobian"] = sampled_rel_err(orc, mesh, y.cpu().numpy(),
+                                           lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        errs["adjoint"] = sampled_rel_err(orc, mesh, g.cpu().numpy(),
+                                          lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
+    except Exception as exc:
+        errs["error"] = str(exc)
+    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, matrix = perfectly plastic Prandtl "
+                      f"|| Hooke || Maxwell, particle = Hooke (particle fraction {d['vol_frac']:.3f}, e0={d['e0']})",
+            "ms_median": ms, "dofs_per_s": {k: mesh.n_dof / (t * 1e-3) for k, t in ms.items()},
+            "alg_bytes_per_apply": alg,
+            "gbs_alg": {k: alg[k] / (t * 1e-3) / 1e9 for k, t in ms.items()},
+            "rel_err_vs_oracle_sampled": errs}
+
+
 def newton_leg(torch, I, pfmf, config):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
@@ -258,6 +323,9 @@ def main():
     ap.add_argument("--newton-config", default="C5")
     ap.add_argument("--secondary", default="C2",
                     help="second workload whose applies are timed and reported beside the headline ('' = none)")
+    ap.add_argument("--branches", default="C3",
+                    help="workload on which the applies with the third example's branches in parallel are timed "
+                         "('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
@@ -356,11 +424,11 @@ def main():
     achieved = bj / t_jac / 1e9
     counters = measured_counters(args.config + "/" + args.variant)
     traffic = counters.get("hbm_bytes_per_apply")
-    kname = {2: "pfmf::k_op64_q2<1, true, false> + pfmf::k_gather_bricks<double, 3>: one launch over all "
+    kname = {2: "pfmf::k_op64_q2<1, true, false, false> + pfmf::k_gather_bricks<double, 3>: one launch over all "
                 "bricks, then the node gather",
-             3: "pfmf::k_op64_q3<1, true, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
+             3: "pfmf::k_op64_q3<1, true, false, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
                 "bricks, then the node gather",
-             4: "pfmf::k_op64_q4<1, false>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
+             4: "pfmf::k_op64_q4<1, false, false>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(d, args.cpu_seconds)
@@ -428,8 +496,12 @@ def main():
         "fp32_over_fp64_apply_speedup": ms_med["jacobian"] / ms_med["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
-    if args.secondary or args.newton:
+    if args.secondary or args.newton or args.branches:
         del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32, ys
+        torch.cuda.empty_cache()
+    if args.branches:
+        out["branches"] = branches_leg(torch, I, pfmf, args.branches)
+        print(f"[bench] branches {out['branches']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if args.secondary:
         out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)

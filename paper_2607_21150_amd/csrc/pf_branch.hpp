@@ -10,6 +10,23 @@
 
 namespace pfmf {
 
+// Nine values of one thread in LDS at a stride (the point's G, or its direction or
+// cotangent): the branch loops read them back with volatile loads at every branch, so
+// that they are not held in registers across the branch states (which otherwise spill).
+struct Slot9 {
+  double* p;
+  int stride;
+  __device__ void put(const double* v) const {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) p[k * stride] = v[k];
+  }
+  __device__ void get(double* v) const {
+    const volatile double* q = p;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = q[k * stride];
+  }
+};
+
 // Point state of extra branch j of the phase (Box 1 steps 1-3 with the branch's
 // material); a Hooke branch reads no state (Cin^-1 = I), and neither does a lane
 // without a point (valid = false: gq may lie past the state arrays).
@@ -44,14 +61,16 @@ __device__ inline void mb_fracture(const OpArgs& a, const MatParams<double>& m0,
 // returns L of the total psi^+.
 template <bool VOCE>
 __device__ inline double mb_residual(const OpArgs& a, const MatParams<double>& m0, int pid, int64_t gq,
-                                     bool valid, const double* G, double phi, double phin, double Hn, double psi0,
+                                     bool valid, Slot9 sG, double phi, double phin, double Hn, double psi0,
                                      double gp, double* P, bool& bad) {
   double psi = psi0;
 #pragma unroll 1
   for (int j = 0; j < a.n_extra; ++j) {
-    const XBranch b = a.xb[pid * a.n_extra + j];
+    const XBranch& b = a.xb[pid * a.n_extra + j];
     if (b.kind == XB_NONE) continue;
     QPState<double> s;
+    double G[9];
+    sG.get(G);
     xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
     bad |= s.bad;
     double Pj[9];
@@ -70,21 +89,26 @@ __device__ inline double mb_residual(const OpArgs& a, const MatParams<double>& m
 // dH = sum of the branches' dpsi^+ when the total switch is on. Returns dL.
 template <bool VOCE>
 __device__ inline double mb_jacobian(const OpArgs& a, const MatParams<double>& m0, const QPState<double>& s0,
-                                     int pid, int64_t gq, bool valid, const double* G, double phi, double phin,
-                                     double Hn, const double* W, double wphi, double* dP, bool& bad) {
+                                     int pid, int64_t gq, bool valid, Slot9 sG, double phi, double phin,
+                                     double Hn, const double* W, Slot9 sW, double wphi, double* dP, bool& bad) {
   double dpsi;
   qp_tangent_psi<double>(m0, s0, W, wphi, dP, dpsi);
   double psi = s0.psi;
   const double gp = s0.gp;
 #pragma unroll 1
   for (int j = 0; j < a.n_extra; ++j) {
-    const XBranch b = a.xb[pid * a.n_extra + j];
+    const XBranch& b = a.xb[pid * a.n_extra + j];
     if (b.kind == XB_NONE) continue;
     QPState<double> s;
-    xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
+    {
+      double G[9];
+      sG.get(G);
+      xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
+    }
     bad |= s.bad;
-    double dPj[9], dpj;
-    qp_tangent_psi<double>(b.m, s, W, wphi, dPj, dpj);
+    double dPj[9], dpj, Wj[9];
+    sW.get(Wj);
+    qp_tangent_psi<double>(b.m, s, Wj, wphi, dPj, dpj);
 #pragma unroll
     for (int k = 0; k < 9; ++k) dP[k] += dPj[k];
     dpsi += dpj;
@@ -99,14 +123,16 @@ __device__ inline double mb_jacobian(const OpArgs& a, const MatParams<double>& m
 // psi^+ of the extra branches (the adjoint needs the total switch before the
 // transposed branches).
 template <bool VOCE>
-__device__ inline double mb_psi_extra(const OpArgs& a, int pid, int64_t gq, bool valid, const double* G,
+__device__ inline double mb_psi_extra(const OpArgs& a, int pid, int64_t gq, bool valid, Slot9 sG,
                                       double phi, bool& bad) {
   double psi = 0.0;
 #pragma unroll 1
   for (int j = 0; j < a.n_extra; ++j) {
-    const XBranch b = a.xb[pid * a.n_extra + j];
+    const XBranch& b = a.xb[pid * a.n_extra + j];
     if (b.kind == XB_NONE) continue;
     QPState<double> s;
+    double G[9];
+    sG.get(G);
     xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
     bad |= s.bad;
     psi += s.psi;
@@ -130,15 +156,20 @@ __device__ inline double mb_adjoint_block(const OpArgs& a, const MatParams<doubl
 
 // Adjoint, extra branches: adds their transposed tangents (same Pb, Hb) to Gb, phib.
 template <bool VOCE>
-__device__ inline void mb_adjoint_extra(const OpArgs& a, int pid, int64_t gq, bool valid, const double* G,
-                                        double phi, const double* Pb, double Hb, double* Gb, double& phib) {
+__device__ inline void mb_adjoint_extra(const OpArgs& a, int pid, int64_t gq, bool valid, Slot9 sG,
+                                        double phi, Slot9 sPb, double Hb, double* Gb, double& phib) {
 #pragma unroll 1
   for (int j = 0; j < a.n_extra; ++j) {
-    const XBranch b = a.xb[pid * a.n_extra + j];
+    const XBranch& b = a.xb[pid * a.n_extra + j];
     if (b.kind == XB_NONE) continue;
     QPState<double> s;
-    xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
-    double Gj[9], pj, Xj[3];
+    {
+      double G[9];
+      sG.get(G);
+      xbranch_state<VOCE>(a, b, j, gq, valid, G, phi, s);
+    }
+    double Gj[9], pj, Xj[3], Pb[9];
+    sPb.get(Pb);
     qp_tangent_T_psi<double>(b.m, s, Pb, Hb, 0.0, Gj, pj, Xj);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Gb[k] += Gj[k];

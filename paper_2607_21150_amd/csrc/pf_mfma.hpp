@@ -303,6 +303,8 @@ template <int MODE, bool BB, bool VOCE, bool MB>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
+  __shared__ double mbs[MB ? 18 * NT : 1];  // branches in parallel: G and W (or Pb) per thread
+  const Slot9 sG{mbs + threadIdx.x, NT}, sW{mbs + 9 * NT + threadIdx.x, NT};
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
@@ -369,7 +371,8 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     const MatParams<double> mp = a.mats[pidc];
     // branches in parallel, adjoint: the extra branches' psi^+ decides the switch
     double psi_x = 0.0;
-    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, true, G, phi, any_bad);
+    if (MB) sG.put(G);
+    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, true, sG, phi, any_bad);
     QPState<double> s;
     qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= s.bad;
@@ -392,7 +395,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     if (MODE == M_RES) {
       piola<double>(s, Fu);
       double L = s.L;
-      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, true, G, phi, phin, st[7], s.psi, s.gp, Fu, any_bad);
+      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, true, sG, phi, phin, st[7], s.psi, s.gp, Fu, any_bad);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
       f0 = wdet * a.fr.s_phi * L;
@@ -400,9 +403,10 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
     } else if (MODE == M_JAC) {
       double dL;
-      if (MB)
-        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, true, G, phi, phi, st[7], W, wphi, Fu, any_bad);
-      else
+      if (MB) {
+        sW.put(W);
+        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, true, sG, phi, phi, st[7], W, sW, wphi, Fu, any_bad);
+      } else
         qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
@@ -435,7 +439,10 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
         gsum[1] += -w3q * s.ddg_s0 * base;
         gsum[2] += -w3q * s.ddg_visc * base;
       }
-      if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, true, G, phi, Pb, Hb, Fu, phib);
+      if (MB) {
+        sW.put(Pb);
+        mb_adjoint_extra<VOCE>(a, pidc, gq, true, sG, phi, sW, Hb, Fu, phib);
+      }
       f0 = phib;
       gpid[slot * 64 + l] = (unsigned char)pid;
 #pragma unroll
@@ -520,6 +527,8 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
                                                                               DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
+  __shared__ double mbs[MB ? 18 * NT : 1];  // branches in parallel: G and W (or Pb) per thread
+  const Slot9 sG{mbs + threadIdx.x, NT}, sW{mbs + 9 * NT + threadIdx.x, NT};
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
@@ -594,7 +603,8 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
     // branches in parallel (flags of lanes without a point are dropped)
     bool xbad = false;
     double psi_x = 0.0;
-    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, valid, G, phi, xbad);
+    if (MB) sG.put(G);
+    if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, valid, sG, phi, xbad);
     QPState<double> s;
     qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
     any_bad |= valid && s.bad;
@@ -634,7 +644,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
     if (MODE == M_RES) {
       piola<double>(s, Fu);
       double L = s.L;
-      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, valid, G, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
+      if (MB) L = mb_residual<VOCE>(a, mp, pidc, gq, valid, sG, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
       f0 = wdet * a.fr.s_phi * L;
@@ -642,9 +652,10 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
       for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
     } else if (MODE == M_JAC) {
       double dL;
-      if (MB)
-        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, valid, G, phi, phi, st[7], W, wphi, Fu, xbad);
-      else
+      if (MB) {
+        sW.put(W);
+        dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, valid, sG, phi, phi, st[7], W, sW, wphi, Fu, xbad);
+      } else
         qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
       for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
@@ -676,7 +687,10 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
         gsum[1] = -w3q * s.ddg_s0 * base;
         gsum[2] = -w3q * s.ddg_visc * base;
       }
-      if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, valid, G, phi, Pb, Hb, Fu, phib);
+      if (MB) {
+        sW.put(Pb);
+        mb_adjoint_extra<VOCE>(a, pidc, gq, valid, sG, phi, sW, Hb, Fu, phib);
+      }
       f0 = phib;
       if (!valid) gsum[0] = gsum[1] = gsum[2] = 0.0;
     }

@@ -260,6 +260,8 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   __shared__ double bufA[L::A];
   __shared__ double bufB[L::B];
   __shared__ double red[2 * 3 * 8];
+  __shared__ double mbs[MB ? 18 * NT5 : 1];  // branches in parallel: G and W (or Pb) per thread
+  const Slot9 sG{mbs + threadIdx.x, NT5}, sW{mbs + 9 * NT5 + threadIdx.x, NT5};
   ElemGeom g;
   if (!xcd_elem(a.m, colour, blockIdx.x, g)) return;  // padding workgroup (uniform)
   const int t = threadIdx.x;
@@ -300,7 +302,8 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   // branches in parallel (flags of threads without a point are dropped)
   bool xbad = false;
   double psi_x = 0.0;
-  if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, pt, G, phi, xbad);
+  if (MB) sG.put(G);
+  if (MB && MODE == M_ADJ) psi_x = mb_psi_extra<VOCE>(a, pidc, gq, pt, sG, phi, xbad);
   QPState<double> s;
   qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
   bool bad = pt && s.bad;
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   if (MODE == M_RES) {
     piola<double>(s, Fu);
     double Lr = s.L;
-    if (MB) Lr = mb_residual<VOCE>(a, mp, pidc, gq, pt, G, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
+    if (MB) Lr = mb_residual<VOCE>(a, mp, pidc, gq, pt, sG, phi, phin, st[7], s.psi, s.gp, Fu, xbad);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
     f0 = wdet * a.fr.s_phi * Lr;
@@ -332,9 +335,10 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
   } else if (MODE == M_JAC) {
     double dL;
-    if (MB)
-      dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, pt, G, phi, phi, st[7], W, wphi, Fu, xbad);
-    else
+    if (MB) {
+      sW.put(W);
+      dL = mb_jacobian<VOCE>(a, mp, s, pidc, gq, pt, sG, phi, phi, st[7], W, sW, wphi, Fu, xbad);
+    } else
       qp_tangent<double>(mp, s, W, wphi, Fu, dL);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
@@ -366,7 +370,10 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
       gsum[1] = -w3q * s.ddg_s0 * base;
       gsum[2] = -w3q * s.ddg_visc * base;
     }
-    if (MB) mb_adjoint_extra<VOCE>(a, pidc, gq, pt, G, phi, Pb, Hb, Fu, phib);
+    if (MB) {
+      sW.put(Pb);
+      mb_adjoint_extra<VOCE>(a, pidc, gq, pt, sG, phi, sW, Hb, Fu, phib);
+    }
     f0 = phib;
   }
   if (MB) bad |= pt && xbad;

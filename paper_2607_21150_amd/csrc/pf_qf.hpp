@@ -688,9 +688,10 @@ __device__ inline void piola(const QPState<T>& s, T* P) {
 // increments on the diagonal and the divided-difference terms off it, and the second
 // term is the geometric part -tau_degr dl^T expressed in the frame.
 // The phase-field gradient term is linear and handled by the caller.
+// dpsi: this branch's psi^+ increment, evaluated only when `want` (else 0).
 template <typename T>
 __device__ inline void qp_tangent_psi(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
-                                      T* dP, T& dpsi) {
+                                      T* dP, T& dpsi, bool want = true) {
   const T* N = s.N;
   // FiN = F^-1 N serves both ends: dl N = dG FiN and F^-T at the output
   T FiN[9];
@@ -763,8 +764,11 @@ __device__ inline void qp_tangent_psi(const MatParams<T>& m, const QPState<T>& s
     for (int J = 0; J < 3; ++J)
       dP[3 * i + J] = NZ[3 * i] * FiN[3 * J] + NZ[3 * i + 1] * FiN[3 * J + 1] + NZ[3 * i + 2] * FiN[3 * J + 2];
   // psi^+ increment of this branch (eq:energy-displacement-linearization)
-  dpsi = tm2 * s.c * (s.e[0] * dce[0] + s.e[1] * dce[1] + s.e[2] * dce[2]);
-  if (s.tension) dpsi += m.kappa * s.theta * dth;
+  dpsi = T(0);
+  if (want) {
+    dpsi = tm2 * s.c * (s.e[0] * dce[0] + s.e[1] * dce[1] + s.e[2] * dce[2]);
+    if (s.tension) dpsi += m.kappa * s.theta * dth;
+  }
 }
 
 // The tangent of a single block: dP and the local phase-field increment
@@ -773,9 +777,9 @@ __device__ inline void qp_tangent_psi(const MatParams<T>& m, const QPState<T>& s
 template <typename T>
 __device__ inline void qp_tangent(const MatParams<T>& m, const QPState<T>& s, const T* dG, T dphi,
                                   T* dP, T& dL) {
-  T dpsi;
-  qp_tangent_psi<T>(m, s, dG, dphi, dP, dpsi);
-  dL = s.dLcoef * dphi + s.gp * (s.hactive ? dpsi : T(0));
+  T dH;
+  qp_tangent_psi<T>(m, s, dG, dphi, dP, dH, s.hactive);
+  dL = s.dLcoef * dphi + s.gp * dH;
 }
 
 // Reverse (transpose) of qp_tangent: cotangents (Pb = dP-bar, Lb = dL-bar) ->
