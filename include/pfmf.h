@@ -137,9 +137,12 @@ pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n
  * extra branch j, row 7j+6 its accumulated plastic strain (a Hooke branch reads none of
  * them). n_extra = 0 detaches (branches and xstate may then be NULL). Orders 2-4; the
  * FP64 residual, Jacobian and adjoint (with the block's parameter partials) include the
- * branches. The linearisation-based calls (pf_linearize and what needs it: the FP32
- * levels, the V-cycle, pf_apply_jacobian_lin, pf_newton_step) and pf_commit_state cover
- * the single block only and return PF_EUNSUPPORTED while branches are attached.
+ * branches, and so does the linearisation: pf_linearize stores one record layer per
+ * branch (the block's layer holds the switch and dL/dphi of the total psi^+), which the
+ * FP32 levels, the V-cycle, pf_apply_jacobian_lin and pf_newton_step sum over; the
+ * record grows to (1 + n_extra) layers. The call invalidates the linearisation.
+ * pf_commit_state covers the single block only and returns PF_EUNSUPPORTED while
+ * branches are attached.
  * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
  * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
  * p = 1, PF_ENOMEM / PF_EHIP from the device copy. */
@@ -165,7 +168,8 @@ pf_status pf_apply_adjoint(pf_ctx* ctx, const double* z, const double* v, double
 /* Linearise at z for the FP32 multigrid: the return-mapping, split and history
  * decisions, their scalars, the principal frame of b_tr (a unit quaternion, its three
  * smallest components), the principal trial log strains and the off-diagonal tangent
- * factors are taken in FP64 and stored per point as an FP32 record of 15 values and a
+ * factors are taken in FP64 and stored per point (and per branch, see pf_set_branches)
+ * as an FP32 record of 15 values and a
  * flag byte (Appendices A-C evaluated once), with an FP32 mirror of u; assembles an
  * order-1 coarsest level into a block stencil; builds every level's point-Jacobi
  * diagonal and Chebyshev bounds (power iteration on the device). Synchronises the

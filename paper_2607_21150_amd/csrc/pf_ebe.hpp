@@ -27,12 +27,14 @@ struct EbeArgs {
   int nph;
   FracParams<float> fr;
   float* K;             // [n_elem][32][32]
+  const MatParams<float>* xmats;  // extra branches [nph][n_extra] (record layers 1..n_extra)
+  int n_extra;
 };
 
 // One workgroup per element. The threads evaluate the tangent of the points on the
 // 10 unit directions (dG_ij, dphi) into LDS; the element matrix is then the
 // point sum of (test basis) x tangent x (trial basis), contracted in two steps.
-template <int PF>
+template <int PF, bool MB>
 __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __restrict__ tabs) {
   constexpr int Q = PF, Q3 = Q * Q * Q, P3 = PF * PF * PF;
   __shared__ float ub[3 * P3];      // fine u of the element
@@ -93,14 +95,15 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
     rc.flags = a.rec.flags[gq];
     const int pid = a.phase[gq];
-    const MatParams<float> mp = a.mats[pid < a.nph ? pid : 0];
+    const int pidc = pid < a.nph ? pid : 0;
+    const MatParams<float> mp = a.mats[pidc];
     QPState<float> s;
     qp_state_lin<float>(mp, G, rc, s);
     for (int in = grp; in < 10; in += NG) {
       float dG[9], dP[9], dL;
 #pragma unroll
       for (int k = 0; k < 9; ++k) dG[k] = (k == in) ? 1.f : 0.f;
-      qp_tangent<float>(mp, s, dG, in == 9 ? 1.f : 0.f, dP, dL);
+      lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, true, G, dG, in == 9 ? 1.f : 0.f, dP, dL);
 #pragma unroll
       for (int o = 0; o < 9; ++o) Cq[q][o * 10 + in] = dP[o];
       Cq[q][90 + in] = dL;

@@ -777,7 +777,7 @@ namespace pfmf {
 // nodes PC <= 3, 3 Gauss points): the packing of k_op64_q2 (sum factorisation per
 // element on the padded 4 x 4 layout, the pointwise JVP once for both elements of the
 // wave on lanes 0-26 and 32-58) with the FP32 record path of k_a32_q3.
-template <typename V, int PC, bool BB>
+template <typename V, int PC, bool BB, bool MB>
 __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
   __shared__ V ev[8 * 4 * 64];
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
@@ -852,11 +852,12 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
     for (int k = 0; k < REC_N; ++k) rc.v[k] = valid ? a.rec.rec[k * a.n_q + gq] : V(0);
     rc.flags = valid ? a.rec.flags[gq] : 0;
     const int pid = valid ? a.phase[gq] : 0;
-    const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+    const int pidc = pid < a.nph ? pid : 0;
+    const MatParams<V> mp = a.mats[pidc];
     QPState<V> s;
     qp_state_lin<V>(mp, G, rc, s);
     V Fu[9], dL;
-    qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+    lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, valid, G, W, wphi, Fu, dL);
     const V kfg = a.fr.kf * mp.Gc;
     double b1p[4][3], b0p3;
 #pragma unroll
@@ -901,7 +902,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
 // FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
 // level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
 // contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).
-template <typename V, int PC, bool BB>
+template <typename V, int PC, bool BB, bool MB>
 __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
   __shared__ V ev[8 * 4 * 64];
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
@@ -954,11 +955,12 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour,
 #pragma unroll
       for (int J = 0; J < 3; ++J) gw[J] = (V)d[3][J] * ih[J];
     }
-    const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+    const int pidc = pid < a.nph ? pid : 0;
+    const MatParams<V> mp = a.mats[pidc];
     QPState<V> s;
     qp_state_lin<V>(mp, G, rc, s);
     V Fu[9], dL;
-    qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+    lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, true, G, W, wphi, Fu, dL);
     const V kfg = a.fr.kf * mp.Gc;
     double b0[4], b1[4][3], r[4];
 #pragma unroll

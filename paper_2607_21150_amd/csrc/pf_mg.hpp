@@ -49,15 +49,16 @@ struct MGState {
   int n_levels = 0;
   MGLevel lv[5];
   float* z32 = nullptr;  // FP32 mirror of u on the fine level [3][n_nodes]
-  RecordSoA rec{nullptr, nullptr};
+  RecordSoA rec{nullptr, nullptr};  // [rec_layers][REC_N][n_q] and flags [rec_layers][n_q]
   float* tmpA = nullptr;
   float* tmpB = nullptr;
   double* red = nullptr;  // reduction scratch
   float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
   float* stencil = nullptr;  // the same level as a block stencil [27][4][4][n_nodes]
   float* ebuf32 = nullptr;   // brick-buffer scatter of the FP32 level applies
-  double* rec64 = nullptr;   // stored FP64 linearisation [REC_N][n_q] (flags in rec.flags)
+  double* rec64 = nullptr;   // stored FP64 linearisation [rec_layers][REC_N][n_q] (flags in rec.flags)
   double* u64 = nullptr;     // u at the linearisation point [3][n_nodes]
+  int rec_layers = 0;        // record layers allocated (1 + extra branches)
   int ebe_level = -1;
   bool linearized = false;
   bool lin64_valid = false;  // rec64 / u64 hold the current linearisation
@@ -96,6 +97,13 @@ inline void mg_free(MGState& mg) {
 // ---------------------------------------------------------------------------
 
 // MODE 0: linearisation record; MODE 1: state commit into state_out.
+// Records of a point with extra branches in parallel: layer 0 is the block's record,
+// whose flags carry the point's history switch and whose dL slot its dL/dphi (both
+// from the total psi^+); layer 1 + j that of extra branch j, or flags REC_EMPTY where
+// the point's phase has no branch in slot j. Layer l of a record array sits at
+// rec + l * REC_N * n_q and flags + l * n_q.
+constexpr uint8_t REC_EMPTY = 0x80;
+
 struct LinArgs {
   MeshDev m;
   int nx1, ny1;
@@ -111,8 +119,12 @@ struct LinArgs {
   double* rec64;         // MODE 0: the same record in FP64 [REC_N][n_q] (flags shared), or null
   double* state_out;
   int* flag;
+  const XBranch* xb;     // extra branches [nph][n_extra] and their states [7*n_extra][n_q]
+  const double* xstate;
+  int n_extra;
 };
 
+// MODE 0: record; MODE 2: record with the extra branches' layers; MODE 1: state commit.
 template <int P, int Q, int MODE>
 __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTables* __restrict__ tabs) {
   using S = OpShape<P, Q>;
@@ -172,7 +184,45 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
       QPState<double> s;
       qp_state<double>(mp, a.fr, G, phi, 0.0, st, s);
       any_bad |= s.bad;
-      if (MODE == 0) {
+      if (MODE == 2) {
+        // extra branches: one record layer each; the block's layer takes the point's
+        // history switch and dL/dphi from the total psi^+
+        double psi = s.psi;
+        const int pidc = pid < a.nph ? pid : 0;
+#pragma unroll 1
+        for (int j = 0; j < a.n_extra; ++j) {
+          const int64_t lj = 1 + j;
+          const XBranch& b = a.xb[pidc * a.n_extra + j];
+          if (b.kind == XB_NONE) {
+            a.rec.flags[lj * a.n_q + gq] = REC_EMPTY;
+            continue;
+          }
+          double xs[8];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) xs[k] = b.kind == XB_HOOKE ? 0.0 : a.xstate[(int64_t)(7 * j + k) * a.n_q + gq];
+          xs[7] = 0.0;
+          QPState<double> sj;
+          qp_state<double, true, true>(b.m, a.fr, G, phi, 0.0, xs, sj);
+          any_bad |= sj.bad;
+          psi += sj.psi;
+          LinRecord rj;
+          record_from_state(sj, rj);
+#pragma unroll
+          for (int k = 0; k < REC_N; ++k) a.rec.rec[(lj * REC_N + k) * a.n_q + gq] = rj.v[k];
+          a.rec.flags[lj * a.n_q + gq] = rj.flags;
+          if (a.rec64) {
+            LinRecordT<double> r64;
+            record_from_state(sj, r64);
+#pragma unroll
+            for (int k = 0; k < REC_N; ++k) a.rec64[(lj * REC_N + k) * a.n_q + gq] = r64.v[k];
+          }
+        }
+        s.hactive = psi > st[7];
+        const double H = s.hactive ? psi : st[7];
+        const double alpha_pp = (a.fr.at == 2) ? 2.0 : 0.0;
+        s.dLcoef = 2.0 * H + mp.Gc * a.fr.inv_c0l0 * alpha_pp + a.fr.zeta * a.fr.inv_dt;
+      }
+      if (MODE != 1) {
         LinRecord rc;
         record_from_state(s, rc);
 #pragma unroll
@@ -215,7 +265,44 @@ template <typename V> struct LinApplyArgs {
   FracParams<V> fr;
   V* out;
   V* ebuf;               // brick-buffer scatter (extended node grid)
+  const MatParams<V>* xmats;  // extra branches [nph][n_extra] (record layers 1..n_extra)
+  int n_extra;
 };
+
+// Record-based tangent of one point: the block's layer, plus (n_extra > 0) the extra
+// branches' layers, their dP and dpsi^+ summed and the switch applied to the total.
+// valid = false (a lane without a point) reads no layer.
+// MB = false compiles the block's tangent only (kernels launched without branches).
+template <typename V, bool MB>
+__device__ inline void lin_tangent(const RecordSoAT<V>& rec, int64_t n_q, const MatParams<V>* xmats, int n_extra,
+                                   const MatParams<V>& mp, const QPState<V>& s, int pid, int64_t gq, bool valid,
+                                   const V* G, const V* dG, V dphi, V* dP, V& dL) {
+  if (!MB || n_extra == 0) {
+    qp_tangent<V>(mp, s, dG, dphi, dP, dL);
+    return;
+  }
+  V dpsi;
+  qp_tangent_psi<V>(mp, s, dG, dphi, dP, dpsi, true);
+#pragma unroll 1
+  for (int j = 0; j < n_extra; ++j) {
+    const int64_t lj = 1 + j;
+    const uint8_t fl = valid ? rec.flags[lj * n_q + gq] : REC_EMPTY;
+    if (fl & REC_EMPTY) continue;
+    LinRecordT<V> r;
+#pragma unroll
+    for (int k = 0; k < REC_N; ++k) r.v[k] = rec.rec[(lj * REC_N + k) * n_q + gq];
+    r.flags = fl;
+    const MatParams<V>& bm = xmats[pid * n_extra + j];
+    QPState<V> sj;
+    qp_state_lin<V>(bm, G, r, sj);
+    V dPj[9], dpj;
+    qp_tangent_psi<V>(bm, sj, dG, dphi, dPj, dpj, true);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dP[k] += dPj[k];
+    dpsi += dpj;
+  }
+  dL = s.dLcoef * dphi + s.gp * (s.hactive ? dpsi : V(0));
+}
 using A32Args = LinApplyArgs<float>;
 
 template <int PF, int PC, int Q> struct A32Shape {
@@ -236,7 +323,7 @@ template <int PF, int PC, int Q> struct A32Shape {
   static constexpr size_t lds_bytes = lds_floats * sizeof(float);
 };
 
-template <int MODE, int PF, int PC, int Q>
+template <int MODE, int PF, int PC, int Q, bool MB>
 __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTablesF* __restrict__ tabs) {
   using S = A32Shape<PF, PC, Q>;
   constexpr int NBF3 = S::NBF3, NBC3 = S::NBC3, PC3 = S::PC3, Q3 = S::Q3, ER = S::ER, PM = S::PM;
@@ -321,6 +408,8 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
     QPState<float> s;
     MatParams<float> mp;
     float wdet = 0.f;
+    int pidc = 0;
+    int64_t gqa = 0;
     if (active) {
       const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
       const int64_t gq = e * Q3 + ql;
@@ -329,12 +418,14 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
       for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
       rc.flags = a.rec.flags[gq];
       const int pid = a.phase[gq];
-      mp = a.mats[pid < a.nph ? pid : 0];
+      pidc = pid < a.nph ? pid : 0;
+      gqa = gq;
+      mp = a.mats[pidc];
       qp_state_lin<float>(mp, G, rc, s);
       wdet = wq[qx] * wq[qy] * wq[qz] * jdet;
       if (MODE == 0) {
         float dL;
-        qp_tangent<float>(mp, s, W, wphi, Fu, dL);
+        lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, true, G, W, wphi, Fu, dL);
 #pragma unroll
         for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
         f0 = wdet * a.fr.s_phi * dL;
@@ -381,7 +472,7 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
 #pragma unroll
               for (int k = 0; k < 9; ++k) dG[k] = 0.f;
               dG[3 * i + K] = 1.f;
-              qp_tangent<float>(mp, s, dG, 0.f, dP, dL);
+              lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gqa, true, G, dG, 0.f, dP, dL);
 #pragma unroll
               for (int J = 0; J < 3; ++J) C[J][K] = dP[3 * i + J];
             }
@@ -396,7 +487,7 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
           float dG[9], dP[9], dL;
 #pragma unroll
           for (int k = 0; k < 9; ++k) dG[k] = 0.f;
-          qp_tangent<float>(mp, s, dG, 1.f, dP, dL);
+          lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gqa, true, G, dG, 1.f, dP, dL);
           c22[18] = wdet * a.fr.s_phi * dL;
           const float kfg = wdet * a.fr.kf * mp.Gc;
           c22[19] = kfg * ih[0] * ih[0];

@@ -104,11 +104,28 @@ pf_status mg_alloc(pf_ctx* c) {
   }
   const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
   if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
-      hipMalloc(&mg.rec.rec, REC_N * c->n_q * sizeof(float)) != hipSuccess ||
-      hipMalloc(&mg.rec.flags, c->n_q) != hipSuccess ||
       hipMalloc(&mg.tmpA, nfine) != hipSuccess || hipMalloc(&mg.tmpB, nfine) != hipSuccess ||
       hipMalloc(&mg.red, (VEC_BLOCKS + 16) * sizeof(double)) != hipSuccess)
     return fail(PF_ENOMEM, "multigrid allocation failed");
+  return PF_OK;
+}
+
+// Record arrays with one layer per branch (the block and the extra branches),
+// reallocated when the number of layers changes.
+pf_status ensure_records(pf_ctx* c) {
+  MGState& mg = c->mg;
+  const int layers = 1 + c->n_extra;
+  if (mg.rec.rec && mg.rec_layers == layers) return PF_OK;
+  (void)hipFree(mg.rec.rec);
+  (void)hipFree(mg.rec.flags);
+  (void)hipFree(mg.rec64);
+  mg.rec = RecordSoA{nullptr, nullptr};
+  mg.rec64 = nullptr;
+  mg.rec_layers = 0;
+  if (hipMalloc(&mg.rec.rec, (size_t)layers * REC_N * c->n_q * sizeof(float)) != hipSuccess ||
+      hipMalloc(&mg.rec.flags, (size_t)layers * c->n_q) != hipSuccess)
+    return fail(PF_ENOMEM, "linearisation record: allocation failed");
+  mg.rec_layers = layers;
   return PF_OK;
 }
 
@@ -145,25 +162,33 @@ A32Args a32_args(pf_ctx* c, int level, const float* dz, float* out) {
   a.fr = frac_params<float>(c->fr);
   a.out = out;
   a.ebuf = nullptr;
+  a.xmats = c->d_xmatsf;
+  a.n_extra = c->n_extra;
   return a;
 }
 
-template <int MODE, int PF, int PC>
-pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
+template <int MODE, int PF, int PC, bool MB>
+pf_status launch_level32_v(pf_ctx* c, const A32Args& a, hipStream_t s) {
   using S = A32Shape<PF, PC, PF>;
   static bool attr_set = false;
   if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_level32<MODE, PF, PC, PF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)S::lds_bytes));
+    HIPCHK(hipFuncSetAttribute((const void*)k_level32<MODE, PF, PC, PF, MB>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes));
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
+    hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF, MB>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
+}
+
+// kernels with the extra branches' record layers only when branches are attached
+template <int MODE, int PF, int PC>
+pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
+  return a.n_extra > 0 ? launch_level32_v<MODE, PF, PC, true>(c, a, s) : launch_level32_v<MODE, PF, PC, false>(c, a, s);
 }
 
 template <int MODE, int PF>
@@ -182,8 +207,8 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
 // (order-2 mesh, k_a32_q2); V = float for the FP32 levels, V = double for the apply
 // from the stored FP64 linearisation (fine level). The brick buffer of each precision
 // is sized for the fine level and shared by the coarser ones.
-template <typename V, int PF, int PC>
-pf_status launch_lin_mfma(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
+template <typename V, int PF, int PC, bool MB>
+pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
   if (use_brick_buffer(c)) {
     V** buf;
     if constexpr (sizeof(V) == 4) buf = &c->mg.ebuf32;
@@ -194,9 +219,9 @@ pf_status launch_lin_mfma(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
     a.ebuf = *buf;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<V, PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, true, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<V, PC, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, true, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
     hipLaunchKernelGGL((k_gather_bricks<V, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -208,12 +233,17 @@ pf_status launch_lin_mfma(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<V, PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, false, MB>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<V, PC, false>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, false, MB>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
+}
+
+template <typename V, int PF, int PC>
+pf_status launch_lin_mfma(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
+  return a.n_extra > 0 ? launch_lin_mfma_v<V, PF, PC, true>(c, a, s) : launch_lin_mfma_v<V, PF, PC, false>(c, a, s);
 }
 
 template <int PF, int PC>
@@ -221,18 +251,23 @@ pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
   return launch_lin_mfma<float, PF, PC>(c, a, s);
 }
 
-template <typename V, int PC>
-pf_status launch_lin_q4(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
+template <typename V, int PC, bool MB>
+pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;
     if constexpr (sizeof(V) == 4)
-      hipLaunchKernelGGL((k_a32_q4<V, PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
     else
-      hipLaunchKernelGGL((k_a32_q4<V, PC>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
+}
+
+template <typename V, int PC>
+pf_status launch_lin_q4(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
+  return a.n_extra > 0 ? launch_lin_q4_v<V, PC, true>(c, a, s) : launch_lin_q4_v<V, PC, false>(c, a, s);
 }
 
 template <int PC>
@@ -255,17 +290,24 @@ EbeArgs ebe_args(pf_ctx* c) {
   a.nph = (int)c->phases.size();
   a.fr = frac_params<float>(c->fr);
   a.K = c->mg.ebe;
+  a.xmats = c->d_xmatsf;
+  a.n_extra = c->n_extra;
   return a;
 }
 
 pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
   const EbeArgs a = ebe_args(c);
   const int n_elem = c->mesh.nx * c->mesh.ny * c->mesh.nz;
-  switch (c->mg.lv[0].P) {
-    case 2: hipLaunchKernelGGL(k_ebe_assemble<2>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
-    case 3: hipLaunchKernelGGL(k_ebe_assemble<3>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
-    case 4: hipLaunchKernelGGL(k_ebe_assemble<4>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
-    case 5: hipLaunchKernelGGL(k_ebe_assemble<5>, dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+  const bool mb = a.n_extra > 0;
+  switch (c->mg.lv[0].P * 2 + (mb ? 1 : 0)) {
+    case 4: hipLaunchKernelGGL((k_ebe_assemble<2, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 5: hipLaunchKernelGGL((k_ebe_assemble<2, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 6: hipLaunchKernelGGL((k_ebe_assemble<3, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 7: hipLaunchKernelGGL((k_ebe_assemble<3, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 8: hipLaunchKernelGGL((k_ebe_assemble<4, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 9: hipLaunchKernelGGL((k_ebe_assemble<4, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 10: hipLaunchKernelGGL((k_ebe_assemble<5, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+    case 11: hipLaunchKernelGGL((k_ebe_assemble<5, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
     default: return fail(PF_EUNSUPPORTED, "order not built");
   }
   HIPCHK(hipGetLastError());
@@ -476,15 +518,15 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!z) return fail(PF_EINVAL, "null z");
-  if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "the linearisation covers the single block (extra branches attached)");
+  if (c->n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
-  if ((st = mg_alloc(c))) return st;
+  if ((st = mg_alloc(c)) || (st = ensure_records(c))) return st;
   MGState& mg = c->mg;
   hipLaunchKernelGGL(k_mirror_u, dim3(vec_grid(3 * c->n_nodes)), dim3(NT), 0, s, z, mg.z32, c->n_nodes);
   HIPCHK(hipGetLastError());
   if (c->store_lin64) {
-    if ((!mg.rec64 && hipMalloc(&mg.rec64, (size_t)REC_N * c->n_q * sizeof(double)) != hipSuccess) ||
+    if ((!mg.rec64 && hipMalloc(&mg.rec64, (size_t)mg.rec_layers * REC_N * c->n_q * sizeof(double)) != hipSuccess) ||
         (!mg.u64 && hipMalloc(&mg.u64, (size_t)3 * c->n_nodes * sizeof(double)) != hipSuccess))
       return fail(PF_ENOMEM, "stored linearisation: allocation failed");
     HIPCHK(hipMemcpyAsync(mg.u64, z, (size_t)3 * c->n_nodes * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -506,11 +548,15 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.rec64 = c->store_lin64 ? mg.rec64 : nullptr;
   a.state_out = nullptr;
   a.flag = c->d_flag;
+  a.xb = c->d_xb;
+  a.xstate = c->xstate;
+  a.n_extra = c->n_extra;
+  const bool mb = c->n_extra > 0;
   switch (c->mesh.p) {
     case 1: st = launch_linearize<2, 0>(c, a, s); break;
-    case 2: st = launch_linearize<3, 0>(c, a, s); break;
-    case 3: st = launch_linearize<4, 0>(c, a, s); break;
-    case 4: st = launch_linearize<5, 0>(c, a, s); break;
+    case 2: st = mb ? launch_linearize<3, 2>(c, a, s) : launch_linearize<3, 0>(c, a, s); break;
+    case 3: st = mb ? launch_linearize<4, 2>(c, a, s) : launch_linearize<4, 0>(c, a, s); break;
+    case 4: st = mb ? launch_linearize<5, 2>(c, a, s) : launch_linearize<5, 0>(c, a, s); break;
     default: st = fail(PF_EUNSUPPORTED, "order not built");
   }
   if (st) return st;
@@ -669,6 +715,8 @@ pf_status pf_apply_jacobian_lin(pf_ctx* c, const double* dz, double* y, void* st
   a.fr = frac_params<double>(c->fr);
   a.out = y;
   a.ebuf = nullptr;
+  a.xmats = c->d_xmats64;
+  a.n_extra = c->n_extra;
   switch (c->mesh.p) {
     case 2: return launch_lin_mfma<double, 3, 3>(c, a, s);
     case 3: return launch_lin_mfma<double, 4, 4>(c, a, s);

@@ -426,7 +426,7 @@ template <typename V> struct TablesOf;
 template <> struct TablesOf<float> { using type = DevTablesF; };
 template <> struct TablesOf<double> { using type = DevTables; };
 
-template <typename V, int PC>
+template <typename V, int PC, bool MB>
 __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour,
                                                    const typename TablesOf<V>::type* __restrict__ tabs) {
   using Tab = typename TablesOf<V>::type;
@@ -470,11 +470,12 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
 #pragma unroll
   for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
   __syncthreads();
-  const MatParams<V> mp = a.mats[pid < a.nph ? pid : 0];
+  const int pidc = pid < a.nph ? pid : 0;
+  const MatParams<V> mp = a.mats[pidc];
   QPState<V> s;
   qp_state_lin<V>(mp, G, rc, s);
   V Fu[9], dL;
-  qp_tangent<V>(mp, s, W, wphi, Fu, dL);
+  lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, pt, G, W, wphi, Fu, dL);
   const V kfg = a.fr.kf * mp.Gc;
   if (pt) {
 #pragma unroll

@@ -60,6 +60,8 @@ struct pf_ctx {
   // extra branches in parallel (pf_set_branches)
   int n_extra = 0;
   XBranch* d_xb = nullptr;
+  MatParams<double>* d_xmats64 = nullptr;  // the same branches' materials for the record applies
+  MatParams<float>* d_xmatsf = nullptr;
   const double* xstate = nullptr;
   // device buffers
   DevTables* d_tab = nullptr;
@@ -455,15 +457,31 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
     }
     xb[i].m = branch_params(b, c->fr, c->phases[i / n_extra].Gc);
   }
-  HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old table
+  std::vector<MatParams<double>> x64(xb.size());
+  std::vector<MatParams<float>> x32(xb.size());
+  for (size_t i = 0; i < xb.size(); ++i) {
+    const MatParams<double>& m = xb[i].m;
+    x64[i] = m;
+    x32[i] = MatParams<float>{(float)m.mu, (float)m.kappa, (float)m.Gc, (float)m.sigma0, (float)m.H, (float)m.a,
+                              m.plastic, (float)m.sinf, (float)m.bv, (float)m.am};
+  }
+  HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old tables
   (void)hipFree(c->d_xb);
+  (void)hipFree(c->d_xmats64);
+  (void)hipFree(c->d_xmatsf);
   c->d_xb = nullptr;
+  c->d_xmats64 = nullptr;
+  c->d_xmatsf = nullptr;
   c->n_extra = 0;
   c->xstate = nullptr;
   if (n_extra > 0) {
-    if (hipMalloc(&c->d_xb, xb.size() * sizeof(XBranch)) != hipSuccess)
+    if (hipMalloc(&c->d_xb, xb.size() * sizeof(XBranch)) != hipSuccess ||
+        hipMalloc(&c->d_xmats64, x64.size() * sizeof(x64[0])) != hipSuccess ||
+        hipMalloc(&c->d_xmatsf, x32.size() * sizeof(x32[0])) != hipSuccess)
       return fail(PF_ENOMEM, "branch table allocation failed");
     HIPCHK(hipMemcpy(c->d_xb, xb.data(), xb.size() * sizeof(XBranch), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_xmats64, x64.data(), x64.size() * sizeof(x64[0]), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_xmatsf, x32.data(), x32.size() * sizeof(x32[0]), hipMemcpyHostToDevice));
     c->n_extra = n_extra;
     c->xstate = xstate;
   }
@@ -592,6 +610,8 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_ebuf);
   (void)hipFree(c->d_flag);
   (void)hipFree(c->d_xb);
+  (void)hipFree(c->d_xmats64);
+  (void)hipFree(c->d_xmatsf);
   delete c;
 }
 

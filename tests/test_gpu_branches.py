@@ -136,10 +136,7 @@ def test_branch_errors(pf):
     with pytest.raises(pf.PfError) as e:
         ctx.set_branches(bad_eta, xs)
     assert e.value.code == pf.PF_EINVAL
-    # the failed calls left the previous branches attached: linearisation-based calls refuse
-    with pytest.raises(pf.PfError) as e:
-        ctx.linearize(dev(d["z"]))
-    assert e.value.code == pf.PF_EUNSUPPORTED
+    # the failed calls left the previous branches attached: the commit refuses them
     with pytest.raises(pf.PfError) as e:
         ctx.commit_state(dev(d["z"]))
     assert e.value.code == pf.PF_EUNSUPPORTED

@@ -72,7 +72,9 @@ def restrict_np(r, mesh_n, pf_order, pc_order):
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", None, None),
                                               ("C1", "compress", None, None), ("C1", "plastic", 3, 3),
                                               ("C2", "plastic", 2, 6), ("C1", "plastic", 4, 3),
-                                              ("C1", "base", 4, 2), ("C1", "voce", 3, 3)])
+                                              ("C1", "base", 4, 2), ("C1", "voce", 3, 3),
+                                              ("C1", "ex3", None, None), ("C1", "ex3", 3, 3),
+                                              ("C1", "ex3_compress", 3, 2), ("C1", "ex3", 4, 2)])
 @pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
 def test_fp32_fine_apply_vs_fp64_oracle(pf, oracle_lib, name, variant, p, n, scatter):
     print(f"case {name} {variant} p={p} n={n} {scatter}", flush=True)
@@ -138,12 +140,13 @@ def test_restriction_is_prolongation_transpose_and_matches_numpy(pf):
         assert relerr(Rr, refr) <= 1e-6
 
 
-@pytest.mark.parametrize("p,level", [(3, 1), (3, 2), (4, 1), (4, 2)])
-def test_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level):
+@pytest.mark.parametrize("p,level,variant", [(3, 1, "plastic"), (3, 2, "plastic"), (4, 1, "plastic"),
+                                             (4, 2, "plastic"), (3, 2, "ex3"), (4, 1, "ex3")])
+def test_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level, variant):
     """A_c = P^T A_f P (coarse levels share the fine quadrature and record); checked against the
     FP64 oracle's fine Jacobian with a numpy prolongation. Level 2 is the order-1 level, which is
-    assembled from element matrices into a block stencil."""
-    d = I.make_inputs("C1", "plastic", p=p, n=3 if p == 3 else 2)
+    assembled from element matrices into a block stencil. ex3: with branches in parallel."""
+    d = I.make_inputs("C1", variant, p=p, n=3 if p == 3 else 2)
     ctx = lin_ctx(pf, d)
     m = d["mesh"]
     orc = oracle_lib.Oracle.from_inputs(d)
@@ -169,8 +172,9 @@ def test_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level):
     assert relerr(yc, y2) <= FP32_TOL
 
 
-def test_fine_diagonal_matches_oracle_element_matrices(pf, oracle_lib):
-    d = I.make_inputs("C1", "plastic")
+@pytest.mark.parametrize("variant", ["plastic", "ex3"])
+def test_fine_diagonal_matches_oracle_element_matrices(pf, oracle_lib, variant):
+    d = I.make_inputs("C1", variant)
     ctx = lin_ctx(pf, d)
     diag = ctx.level_diagonal(0).cpu().numpy()
     orc = oracle_lib.Oracle.from_inputs(d)

@@ -99,7 +99,8 @@ def test_bitwise_deterministic(pf, p, n, scatter):
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", 2, 5),
                                               ("C1", "plastic", 3, 3), ("C1", "compress", 3, 2),
                                               ("C1", "voce", 3, 3), ("C1", "plastic", 4, 3),
-                                              ("C1", "voce", 4, 2)])
+                                              ("C1", "voce", 4, 2), ("C1", "ex3", 2, 4), ("C1", "ex3", 3, 3),
+                                              ("C1", "ex3_compress", 3, 2), ("C1", "ex3", 4, 2)])
 def test_stored_linearisation_jacobian(pf, oracle_lib, name, variant, p, n, scatter):
     """J dz from the FP64 record stored by pf_linearize equals the oracle's Jacobian (1e-12) and the
     recomputed apply (1e-13): the record holds the FP64 decisions, frame and coefficients."""

@@ -173,7 +173,7 @@ def assembled_jacobian(orc, mesh, z):
     return K
 
 
-@pytest.mark.parametrize("variant", ["base", "plastic"])
+@pytest.mark.parametrize("variant", ["base", "plastic", "ex3"])
 def test_newton_update_matches_dense_solve(pf, oracle_lib, variant):
     """One update dz: FGMRES with the V-cycle reaches 1e-11; dz agrees with the dense solve of the
     oracle's assembled constrained Jacobian, and its residual in that system is small."""
