@@ -211,8 +211,13 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
     z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_top"])
     r, y, g = torch.empty_like(z), torch.empty_like(z), torch.empty_like(z)
     gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
-    ops = {"residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
-           "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp)}
+    ctx.linearize(z)
+    dz32 = dz.float()
+    y32, b32, x32, ys = torch.empty_like(dz32), torch.empty_like(dz32), torch.empty_like(dz32), torch.empty_like(z)
+    ctx.apply_jacobian_f32(0, dz32, b32)
+    ops = {"vcycle": lambda: ctx.pmg_vcycle(b32, x32), "fp32_apply": lambda: ctx.apply_jacobian_f32(0, dz32, y32),
+           "residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
+           "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp), "jacobian_stored": lambda: ctx.apply_jacobian_lin(dz, ys)}
     for _ in range(warmup):
         for f in ops.values():
             f()
@@ -228,8 +233,16 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
     torch.cuda.synchronize()
     ctx.check()
     ms = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
+    t0 = time.perf_counter()
+    ctx.linearize(z)
+    ms["linearize"] = (time.perf_counter() - t0) * 1e3  # host wall time (the call synchronises)
     xb = branch_state_bytes(d)
-    alg = {k: alg_bytes(mesh, k) + xb for k in ms}
+    n_layers = 1 + len(d["branches"][0])
+    alg = {k: alg_bytes(mesh, k) + xb for k in ("residual", "jacobian", "adjoint")}
+    # record applies: every layer's record is read (61 B per point and layer for FP32, 121 B
+    # for the stored FP64 linearisation), on top of the block-only bytes
+    alg["fp32_apply"] = alg_bytes(mesh, "fp32_apply") + 61 * (n_layers - 1) * mesh.n_q
+    alg["jacobian_stored"] = alg_bytes(mesh, "jacobian_stored") + 121 * (n_layers - 1) * mesh.n_q
     errs = {}
     try:
         from oracle import pyoracle
@@ -240,25 +253,30 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
                                            lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
         errs["adjoint"] = sampled_rel_err(orc, mesh, g.cpu().numpy(),
                                           lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
+        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32.double().cpu().numpy(),
+                                             lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        errs["jacobian_stored"] = sampled_rel_err(orc, mesh, ys.cpu().numpy(),
+                                                  lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
     except Exception as exc:
         errs["error"] = str(exc)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, matrix = perfectly plastic Prandtl "
                       f"|| Hooke || Maxwell, particle = Hooke (particle fraction {d['vol_frac']:.3f}, e0={d['e0']})",
-            "ms_median": ms, "dofs_per_s": {k: mesh.n_dof / (t * 1e-3) for k, t in ms.items()},
+            "ms_median": ms, "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in alg},
             "alg_bytes_per_apply": alg,
-            "gbs_alg": {k: alg[k] / (t * 1e-3) / 1e9 for k, t in ms.items()},
+            "gbs_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in alg},
+            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
             "rel_err_vs_oracle_sampled": errs}
 
 
-def newton_leg(torch, I, pfmf, config):
+def newton_leg(torch, I, pfmf, config, variant="base"):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
     (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1; Chebyshev(3); 32 sweeps on the order-1
     level, assembled as a block stencil), FP64 Jacobian as the operator."""
     t_gen = time.perf_counter()
-    d = I.make_inputs(config, "base")
+    d = I.make_inputs(config, variant)
     mesh = d["mesh"]
-    print(f"[bench] newton inputs {config}: {mesh.n_dof} DoFs, generated in {time.perf_counter() - t_gen:.1f} s",
+    print(f"[bench] newton inputs {config}/{variant}: {mesh.n_dof} DoFs, generated in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
     nx1, ny1, nz1 = mesh.node_dims
     i = np.arange(mesh.n_nodes)
@@ -300,7 +318,8 @@ def newton_leg(torch, I, pfmf, config):
                           raise_on_noconv=False)
     t_step = time.perf_counter() - t0
     print(f"[bench] newton step {rep} in {t_step:.2f} s", file=sys.stderr, flush=True)
-    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}",
+    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}"
+                      + (f", materials '{variant}'" if variant != "base" else ""),
             "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
             "gram_schmidt_refinements": rep["refinements"],
             "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
@@ -508,6 +527,9 @@ def main():
         print(f"[bench] secondary {out['secondary']}", file=sys.stderr, flush=True)
     if args.newton:
         out["newton"] = newton_leg(torch, I, pfmf, args.newton_config)
+        if args.branches:
+            torch.cuda.empty_cache()
+            out["newton_branches"] = newton_leg(torch, I, pfmf, args.branches, "ex3")
     print(json.dumps(out), flush=True)
 
 

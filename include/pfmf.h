@@ -240,8 +240,9 @@ typedef struct {
  * pf_set_dirichlet: M J(z) dz = -M R(z) (M zeroes constrained entries, which z must
  * already hold at their prescribed values), solved by restarted flexible GMRES with
  * the FP64 Jacobian apply (from the stored FP64 linearisation when PF_OPT_STORE_LIN64
- * is on and p >= 2, else recomputed; the reported true residual always uses the
- * recomputed one) and one FP32 p-multigrid V-cycle per iteration as right
+ * is on, p >= 2 and no extra branch is attached, else recomputed; the reported true
+ * residual always uses the recomputed one) and one FP32 p-multigrid V-cycle per
+ * iteration as right
  * preconditioner (re-linearised at z; the paper's solver is GMRES with p-multigrid,
  * Section 5). Allocates its Krylov workspace ((2 restart + 4) vectors of 4 n_nodes
  * doubles) on first use and keeps it. Synchronises the stream. Returns PF_ENOCONV when

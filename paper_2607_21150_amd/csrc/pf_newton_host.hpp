@@ -74,11 +74,13 @@ pf_status precondition(pf_ctx* c, const double* v, double* x, const pf_pmg_opts&
 
 // y = M J x on the unconstrained subspace (x vanishes on constrained entries)
 // M J(z) x: from the stored FP64 linearisation when the step linearised with it (the
-// same operator, without recomputing the point state), else recomputed
+// same operator, without recomputing the point state), else recomputed; with extra
+// branches the recompute apply is the faster of the two (the layered FP64 record apply
+// spills), so it is used
 pf_status masked_jacobian(pf_ctx* c, const double* z, const double* x, double* y, hipStream_t s,
                           bool stored = true) {
   pf_status st;
-  if (stored && c->mg.lin64_valid && c->mesh.p >= 2) {
+  if (stored && c->mg.lin64_valid && c->mesh.p >= 2 && c->n_extra == 0) {
     st = pf_apply_jacobian_lin(c, x, y, s);
   } else {
     OpArgs a = op_args(c);
