@@ -768,11 +768,8 @@ void or_qf_jacobian_mb(const or_phase* ph, const or_branch* xb, int n_extra, con
  * and the history field becomes max(H_n, psi^+). The decisions and c, dgamma, psi^+
  * come from the same pointwise evaluation as the residual; the frame, the
  * exponential and the products are taken in long double. */
-void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], double phi,
-                  const double st[8], double st_new[8]) {
-  mat_t m = make_mat(ph, fr);
-  qp_state s;
-  qp_eval(&m, fr, G, phi, phi, st, &s);
+/* D_new = F^-1 b^e F^-T - I for one branch with state D (Voigt) and return factor c. */
+static void commit_exp_map(const double G[9], const double* st, double c, double D_new[6]) {
   long double F[3][3], A[3][3], D[3][3];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) F[i][j] = (i == j ? 1.0L : 0.0L) + (long double)G[i * 3 + j];
@@ -795,7 +792,7 @@ void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], doub
     th += eps[i];
   }
   long double be[3][3] = {{0}}, bev[3];
-  for (int i = 0; i < 3; i++) bev[i] = expl(2.0L * ((long double)s.c * (eps[i] - th / 3.0L) + th / 3.0L));
+  for (int i = 0; i < 3; i++) bev[i] = expl(2.0L * ((long double)c * (eps[i] - th / 3.0L) + th / 3.0L));
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++)
       for (int k = 0; k < 3; k++) be[i][j] += bev[k] * N[i][k] * N[j][k];
@@ -821,10 +818,41 @@ void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], doub
         for (int l = 0; l < 3; l++) sum += Fi[i][k] * be[k][l] * Fi[j][l];
       C[i][j] = sum - (i == j ? 1.0L : 0.0L);
     }
-  st_new[0] = (double)C[0][0]; st_new[1] = (double)C[1][1]; st_new[2] = (double)C[2][2];
-  st_new[3] = (double)C[1][2]; st_new[4] = (double)C[0][2]; st_new[5] = (double)C[0][1];
+  D_new[0] = (double)C[0][0]; D_new[1] = (double)C[1][1]; D_new[2] = (double)C[2][2];
+  D_new[3] = (double)C[1][2]; D_new[4] = (double)C[0][2]; D_new[5] = (double)C[0][1];
+}
+
+void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], double phi,
+                  const double st[8], double st_new[8]) {
+  mat_t m = make_mat(ph, fr);
+  qp_state s;
+  qp_eval(&m, fr, G, phi, phi, st, &s);
+  commit_exp_map(G, st, s.c, st_new);
   st_new[6] = st[6] + s.dgamma;
   st_new[7] = s.H;
+}
+
+/* With extra branches (Box 1 step 4 for every branch): the block as or_qf_commit with the
+ * history field of the point's total psi^+; each Maxwell or Prandtl branch's D by the same
+ * exponential map with its own factor c, and its ebar_p + dgamma; the rows of Hooke
+ * branches and empty slots are copied. */
+void or_qf_commit_mb(const or_phase* ph, const or_branch* xb, int n_extra, const or_frac* fr,
+                     const double G[9], double phi, const double st[8], const double* xs, double st_new[8],
+                     double* xs_new) {
+  mb_point p;
+  mb_eval(ph, xb, n_extra, fr, G, phi, phi, st, xs, &p);
+  commit_exp_map(G, st, p.s[0].c, st_new);
+  st_new[6] = st[6] + p.s[0].dgamma;
+  st_new[7] = p.s[0].H;
+  for (int j = 0, k = 1; j < n_extra; j++) {
+    const int kind = xb[j].kind;
+    for (int r = 0; r < 7; r++) xs_new[7 * j + r] = xs[7 * j + r];
+    if (kind == OR_BR_NONE) continue;
+    const qp_state* sj = &p.s[k++];
+    if (kind == OR_BR_HOOKE) continue;
+    commit_exp_map(G, xs + 7 * j, sj->c, xs_new + 7 * j);
+    xs_new[7 * j + 6] = xs[7 * j + 6] + sj->dgamma;
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1117,9 +1145,12 @@ int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_
   return bad;
 }
 
-/* Commit over all points of the mesh: state_new[8][n_q] from z (see or_qf_commit). */
-int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
-                    const double* state, const double* z, double* state_new) {
+/* Commit over all points of the mesh: state_new[8][n_q] from z (see or_qf_commit); with
+ * extra branches also xstate_new[7*n_extra][n_q] (see or_qf_commit_mb). */
+int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+                       const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+                       const double* z, double* state_new, double* xstate_new) {
+  if (n_extra < 0 || n_extra > OR_MAX_EXTRA || (n_extra > 0 && (!xbr || !xstate || !xstate_new))) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
   int nP = t.nP, nQ = t.nQ;
@@ -1140,10 +1171,16 @@ int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac
         int64_t gq = e * nQ + qq;
         int pid = phase[gq];
         if (pid >= nph) { err = 1; continue; }
-        double G[9], phi, gphi[3], st[8], sn[8];
+        double G[9], phi, gphi[3], st[8], sn[8], xs[7 * OR_MAX_EXTRA], xn[7 * OR_MAX_EXTRA];
         interp_qp(&t, qq, ze, G, &phi, gphi);
         for (int k = 0; k < 8; k++) st[k] = state[k * n_q + gq];
-        or_qf_commit(&ph[pid], fr, G, phi, st, sn);
+        if (n_extra == 0) {
+          or_qf_commit(&ph[pid], fr, G, phi, st, sn);
+        } else {
+          for (int k = 0; k < 7 * n_extra; k++) xs[k] = xstate[k * n_q + gq];
+          or_qf_commit_mb(&ph[pid], xbr + (size_t)pid * n_extra, n_extra, fr, G, phi, st, xs, sn, xn);
+          for (int k = 0; k < 7 * n_extra; k++) xstate_new[k * n_q + gq] = xn[k];
+        }
         for (int k = 0; k < 8; k++) state_new[k * n_q + gq] = sn[k];
       }
     }
@@ -1151,4 +1188,9 @@ int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac
   }
   free_tab(&t);
   return err ? -1 : 0;
+}
+
+int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr, const uint8_t* phase,
+                    const double* state, const double* z, double* state_new) {
+  return or_commit_state_mb(m, ph, nph, NULL, 0, fr, phase, state, NULL, z, state_new, NULL);
 }

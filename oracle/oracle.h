@@ -136,6 +136,15 @@ void or_qf_commit(const or_phase* ph, const or_frac* fr, const double G[9], doub
                   const double st[8], double st_new[8]);
 int or_commit_state(const or_mesh* m, const or_phase* ph, int nph, const or_frac* fr,
                     const uint8_t* phase, const double* state, const double* z, double* state_new);
+/* With extra branches (Box 1 step 4 for every branch): the block's history field takes the
+ * point's total psi^+; each Maxwell or Prandtl branch gets its own exponential-map update
+ * and ebar_p + dgamma in xs_new / xstate_new; Hooke rows and empty slots are copied. */
+void or_qf_commit_mb(const or_phase* ph, const or_branch* xb, int n_extra, const or_frac* fr,
+                     const double G[9], double phi, const double st[8], const double* xs, double st_new[8],
+                     double* xs_new);
+int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_branch* xbr, int n_extra,
+                       const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
+                       const double* z, double* state_new, double* xstate_new);
 
 /* Number of OpenMP threads the applies use (1 when built without OpenMP). */
 int or_num_threads(void);

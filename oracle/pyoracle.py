@@ -91,6 +91,11 @@ def lib():
         L.or_commit_state.argtypes = [C.POINTER(OrMesh), C.POINTER(OrPhase), C.c_int, C.POINTER(OrFrac),
                                       C.c_void_p, _D, _D, _D]
         L.or_commit_state.restype = C.c_int
+        L.or_qf_commit_mb.argtypes = [C.POINTER(OrPhase), C.POINTER(OrBranch), C.c_int, C.POINTER(OrFrac), _D,
+                                      C.c_double, _D, _D, _D, _D]
+        L.or_commit_state_mb.argtypes = [C.POINTER(OrMesh), C.POINTER(OrPhase), C.c_int, C.POINTER(OrBranch),
+                                         C.c_int, C.POINTER(OrFrac), C.c_void_p, _D, _D, _D, _D, _D]
+        L.or_commit_state_mb.restype = C.c_int
         for f in ("or_residual", "or_jacobian", "or_adjoint", "or_element_jacobian"):
             getattr(L, f).restype = C.c_int
         L.or_num_threads.restype = C.c_int
@@ -213,6 +218,16 @@ def qf_commit(ph, fr, G, phi, st):
     return out
 
 
+def qf_commit_mb(ph, xb, fr, G, phi, st, xs):
+    """Commit of a point with extra branches: (new block state[8], new extra states[7*n_extra])."""
+    arr, n_extra = branches_array([xb])
+    G = _f64(np.reshape(G, 9)); st = _f64(st); xs = _f64(np.reshape(xs, -1))
+    out = np.zeros(8); xout = np.zeros(max(7 * n_extra, 1))
+    lib().or_qf_commit_mb(C.byref(phase_struct(ph)), arr, n_extra, C.byref(frac_struct(fr)), _p(G), float(phi),
+                          _p(st), _p(xs), _p(out), _p(xout))
+    return out, xout[:7 * n_extra]
+
+
 class Oracle:
     """Oracle bound to one set of inputs (as produced by ``inputs.make_inputs``)."""
 
@@ -286,16 +301,23 @@ class Oracle:
         return g, gp.reshape(self._nph, 3)
 
     def commit_state(self, z):
-        """State [8][n_q] after a converged step at z (exponential-map update; single block)."""
-        if self._nx:
-            raise ValueError("state commit covers the single block only")
+        """State [8][n_q] after a converged step at z (exponential-map update); with extra
+        branches the pair (state, xstate)."""
         z = _f64(z)
         out = np.zeros_like(self.state)
-        rc = lib().or_commit_state(C.byref(self._m), self._ph, self._nph, C.byref(self._fr),
-                                   self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(z), _p(out))
+        if not self._nx:
+            rc = lib().or_commit_state(C.byref(self._m), self._ph, self._nph, C.byref(self._fr),
+                                       self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(z), _p(out))
+            if rc < 0:
+                raise RuntimeError("oracle commit failed")
+            return out
+        xout = np.zeros_like(self.xstate)
+        rc = lib().or_commit_state_mb(C.byref(self._m), self._ph, self._nph, self._xbr, self._nx, C.byref(self._fr),
+                                      self.phase.ctypes.data_as(C.c_void_p), _p(self.state), _p(self.xstate), _p(z),
+                                      _p(out), _p(xout))
         if rc < 0:
             raise RuntimeError("oracle commit failed")
-        return out
+        return out, xout
 
     def element_jacobian(self, z, e):
         z = _f64(z)

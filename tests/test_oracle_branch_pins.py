@@ -331,3 +331,80 @@ def test_ex3_parameter_gradients_match_finite_differences(O, ex3):
         orc.set_phases(d["phases"])
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - gp[0, k]) <= 1e-6 * max(abs(fd), 1e-12), (name, fd, gp[0, k])
+
+
+# ------------------------------------------------------------------ state commit (Box 1 step 4)
+
+def test_commit_with_empty_slots_equals_the_block_commit(O):
+    """Empty slots leave the block's commit bit for bit."""
+    rng = np.random.default_rng(29)
+    ph = I.Phase(E=1000.0, nu=0.45, Gc=0.2, sigma0=10.0, H=100.0, visc=1e-2, plastic=True)
+    G = point(rng, 1, amp=4e-2)
+    st = st8(iso_D(rng), 1e-3, 0.0)
+    a = O.qf_commit(ph, FR, G, 0.3, st)
+    b, xb_new = O.qf_commit_mb(ph, [NONE, NONE], FR, G, 0.3, st, np.zeros(14))
+    assert np.array_equal(a, b) and np.array_equal(xb_new, np.zeros(14))
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_maxwell_commit_stores_the_relaxed_elastic_strain(O, sign):
+    """After the commit, F (I + D_new) F^T = exp(2 eps^e) with eps^e = c dev(eps^tr) + vol(eps^tr)
+    (Box 1 step 4, eq:inelasticity-deviatoric-strain-update-2/-3): its log (numpy eigh) equals
+    the trial log strain (numpy) with the deviator scaled by the branch's factor, c read from the
+    transmitted stress; the volume is kept (det(I + D_new) = det(I + D))."""
+    rng = np.random.default_rng(31)
+    D = iso_D(rng)
+    G = point(rng, sign)
+    phi = 0.3
+    a, b, xb, st = maxwell_pair(O, G, phi, D)
+    mu, _ = moduli(MAXW["E"], MAXW["nu"])
+    epsd_tr, th = trial_dev_log_strain(G, D)
+    c = np.linalg.norm(dev(tau_of(a, G) - tau_of(b, G))) / (2 * a.g * mu * np.linalg.norm(epsd_tr))
+    _, xs_new = O.qf_commit_mb(BASE, xb, FR, G, phi, st, xs_of(D))
+    F = np.eye(3) + G
+    be = F @ (np.eye(3) + mat(xs_new[:6])) @ F.T
+    lam, V = np.linalg.eigh(be)
+    eps_e = V @ np.diag(0.5 * np.log(lam)) @ V.T
+    expect = c * epsd_tr + th / 3 * np.eye(3)
+    assert np.abs(eps_e - expect).max() <= 1e-12 * np.abs(expect).max()
+    assert abs(np.linalg.det(np.eye(3) + mat(xs_new[:6])) - np.linalg.det(np.eye(3) + mat(D))) <= 1e-13
+    assert xs_new[6] == 0.0  # no plastic strain in a Maxwell branch
+
+
+def test_perfect_plastic_branch_commit(O):
+    """A perfectly plastic extra branch accumulates dgamma = (g q_tr - sigma0) / (3 g mu)
+    (degraded Box 2 with H = 0 and no overstress) and stores the elastic strain with
+    c = sigma0 / (g q_tr) (eq:principal-directions-format-1); the history field takes the
+    point's total psi^+."""
+    rng = np.random.default_rng(37)
+    G = 2e-2 * rng.standard_normal((3, 3)) * 0.5 + 1e-3 * np.eye(3)
+    phi = 0.2
+    st = st8(Hn=0.0)
+    xs = np.zeros(14)
+    xs[6] = 3e-3
+    out = O.qf_residual_mb(BASE, [PERF, NONE], FR, G, phi, [0, 0, 0], phi, st, xs)
+    st_new, xs_new = O.qf_commit_mb(BASE, [PERF, NONE], FR, G, phi, st, xs)
+    mu, _ = moduli(PERF.E, PERF.nu)
+    epsd_tr, th = trial_dev_log_strain(G, np.zeros(6))
+    g = out.g
+    q = 2 * mu * np.sqrt(1.5) * np.linalg.norm(epsd_tr)
+    assert g * q > PERF.sigma0
+    dgamma = (g * q - PERF.sigma0) / (3 * g * mu)
+    assert abs(xs_new[6] - (3e-3 + dgamma)) <= 1e-12 * dgamma
+    F = np.eye(3) + G
+    lam, V = np.linalg.eigh(F @ (np.eye(3) + mat(xs_new[:6])) @ F.T)
+    eps_e = V @ np.diag(0.5 * np.log(lam)) @ V.T
+    expect = PERF.sigma0 / (g * q) * epsd_tr + th / 3 * np.eye(3)
+    assert np.abs(eps_e - expect).max() <= 1e-11 * np.abs(expect).max()
+    assert st_new[7] == out.psi_plus  # H_{n+1} = total psi^+ (H_n = 0)
+
+
+def test_ex3_global_commit(O, ex3):
+    """Mesh-level commit with branches: the matrix's Maxwell states relax, the particles' rows
+    are copied, the history is at least H_n."""
+    d, orc = ex3
+    st_new, xs_new = orc.commit_state(d["z"])
+    part = d["phase"] != 0
+    assert np.array_equal(xs_new[:, part], d["xstate"][:, part])
+    assert np.all(st_new[7] >= d["state"][7])
+    assert np.abs(xs_new[7:13, ~part] - d["xstate"][7:13, ~part]).max() > 0
