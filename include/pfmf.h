@@ -141,8 +141,7 @@ pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n
  * branch (the block's layer holds the switch and dL/dphi of the total psi^+), which the
  * FP32 levels, the V-cycle, pf_apply_jacobian_lin and pf_newton_step sum over; the
  * record grows to (1 + n_extra) layers. The call invalidates the linearisation.
- * pf_commit_state covers the single block only and returns PF_EUNSUPPORTED while
- * branches are attached.
+ * The state commit with branches is pf_commit_state_branches.
  * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
  * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
  * p = 1, PF_ENOMEM / PF_EHIP from the device copy. */
@@ -215,6 +214,16 @@ pf_status pf_set_dirichlet(pf_ctx* ctx, const uint32_t face_fields[6]);
  * state_out must not alias the context's state or z. To advance a step, copy it into
  * the state buffer given to pf_setup_mesh (and phi into phi_n) once the stream is done. */
 pf_status pf_commit_state(pf_ctx* ctx, const double* z, double* state_out, void* stream);
+
+/* The same with extra branches attached (Box 1 step 4 for every branch): state_out as
+ * above, with the history field of the point's total psi^+; xstate_out (device double,
+ * the layout of the xstate given to pf_set_branches) gets each Maxwell or Prandtl branch's
+ * D_{n+1} by the same exponential map with its own return factor and its ebar_p + dgamma;
+ * the rows of Hooke branches and empty slots are copied. xstate_out must not alias the
+ * context's states, state_out or z. pf_commit_state returns PF_EUNSUPPORTED while
+ * branches are attached, this call PF_EINVAL while none is. */
+pf_status pf_commit_state_branches(pf_ctx* ctx, const double* z, double* state_out, double* xstate_out,
+                                   void* stream);
 
 /* Newton step options: relative tolerance of the linear solve (default 1e-8),
  * FGMRES restart length (30, at most 60), iteration limit (300), and the V-cycle

@@ -122,9 +122,11 @@ struct LinArgs {
   const XBranch* xb;     // extra branches [nph][n_extra] and their states [7*n_extra][n_q]
   const double* xstate;
   int n_extra;
+  double* xstate_out;    // MODE 3: the extra branches' committed states
 };
 
-// MODE 0: record; MODE 2: record with the extra branches' layers; MODE 1: state commit.
+// MODE 0: record; MODE 2: record with the extra branches' layers; MODE 1: state commit;
+// MODE 3: state commit with the extra branches.
 template <int P, int Q, int MODE>
 __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTables* __restrict__ tabs) {
   using S = OpShape<P, Q>;
@@ -222,7 +224,43 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
         const double alpha_pp = (a.fr.at == 2) ? 2.0 : 0.0;
         s.dLcoef = 2.0 * H + mp.Gc * a.fr.inv_c0l0 * alpha_pp + a.fr.zeta * a.fr.inv_dt;
       }
-      if (MODE != 1) {
+      if (MODE == 3) {
+        // every branch's state (Box 1 step 4); the block's history takes the total psi^+
+        double psi = s.psi;
+        const int pidc = pid < a.nph ? pid : 0;
+#pragma unroll 1
+        for (int j = 0; j < a.n_extra; ++j) {
+          const XBranch& b = a.xb[pidc * a.n_extra + j];
+          double xs[8];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) xs[k] = a.xstate[(int64_t)(7 * j + k) * a.n_q + gq];
+          xs[7] = 0.0;
+          if (b.kind == XB_NONE) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) a.xstate_out[(int64_t)(7 * j + k) * a.n_q + gq] = xs[k];
+            continue;
+          }
+          double xk[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) xk[k] = b.kind == XB_HOOKE ? 0.0 : xs[k];
+          QPState<double> sj;
+          qp_state<double, true, true>(b.m, a.fr, G, phi, 0.0, xk, sj);
+          any_bad |= sj.bad;
+          psi += sj.psi;
+          double nj[8];
+          if (b.kind == XB_HOOKE) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) nj[k] = xs[k];
+          } else {
+            commit_from_state(sj, G, xk, nj);
+          }
+#pragma unroll
+          for (int k = 0; k < 7; ++k) a.xstate_out[(int64_t)(7 * j + k) * a.n_q + gq] = nj[k];
+        }
+        s.hactive = psi > st[7];
+        s.H = s.hactive ? psi : st[7];
+      }
+      if (MODE == 0 || MODE == 2) {
         LinRecord rc;
         record_from_state(s, rc);
 #pragma unroll

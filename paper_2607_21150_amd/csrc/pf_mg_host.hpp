@@ -551,6 +551,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.xb = c->d_xb;
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
+  a.xstate_out = nullptr;
   const bool mb = c->n_extra > 0;
   switch (c->mesh.p) {
     case 1: st = launch_linearize<2, 0>(c, a, s); break;
@@ -598,15 +599,25 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   return PF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
 // New per-point state after a converged step (see commit_from_state).
-pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
+pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xstate_out, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!z || !state_out) return fail(PF_EINVAL, "null argument");
-  if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "the state commit covers the single block (extra branches attached)");
   const size_t ns = 8 * c->n_q * sizeof(double);
+  const size_t nz = 4 * c->n_nodes * sizeof(double);
   if (overlaps(state_out, ns, c->qp_state, ns)) return fail(PF_EINVAL, "state_out aliases the context's state");
-  if (overlaps(state_out, ns, z, 4 * c->n_nodes * sizeof(double))) return fail(PF_EINVAL, "state_out aliases z");
+  if (overlaps(state_out, ns, z, nz)) return fail(PF_EINVAL, "state_out aliases z");
+  if (xstate_out) {
+    const size_t nx = (size_t)7 * c->n_extra * c->n_q * sizeof(double);
+    if (overlaps(xstate_out, nx, c->xstate, nx) || overlaps(xstate_out, nx, c->qp_state, ns) ||
+        overlaps(xstate_out, nx, state_out, ns) || overlaps(xstate_out, nx, z, nz))
+      return fail(PF_EINVAL, "xstate_out aliases an input or state_out");
+  }
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   LinArgs a;
@@ -623,15 +634,38 @@ pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* s
   a.nph = (int)c->phases.size();
   a.fr = frac_params<double>(c->fr);
   a.rec = RecordSoA{nullptr, nullptr};
+  a.rec64 = nullptr;
   a.state_out = state_out;
   a.flag = c->d_flag;
+  a.xb = c->d_xb;
+  a.xstate = c->xstate;
+  a.n_extra = c->n_extra;
+  a.xstate_out = xstate_out;
+  const bool mb = c->n_extra > 0;
   switch (c->mesh.p) {
     case 1: return launch_linearize<2, 1>(c, a, s);
-    case 2: return launch_linearize<3, 1>(c, a, s);
-    case 3: return launch_linearize<4, 1>(c, a, s);
-    case 4: return launch_linearize<5, 1>(c, a, s);
+    case 2: return mb ? launch_linearize<3, 3>(c, a, s) : launch_linearize<3, 1>(c, a, s);
+    case 3: return mb ? launch_linearize<4, 3>(c, a, s) : launch_linearize<4, 1>(c, a, s);
+    case 4: return mb ? launch_linearize<5, 3>(c, a, s) : launch_linearize<5, 1>(c, a, s);
     default: return fail(PF_EUNSUPPORTED, "order not built");
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
+  if (c && c->n_extra > 0)
+    return fail(PF_EUNSUPPORTED, "extra branches attached: use pf_commit_state_branches");
+  return commit_state(c, z, state_out, nullptr, stream);
+}
+
+pf_status pf_commit_state_branches(pf_ctx* c, const double* z, double* state_out, double* xstate_out,
+                                   void* stream) {
+  if (c && c->n_extra == 0) return fail(PF_EINVAL, "no extra branch attached: use pf_commit_state");
+  if (!xstate_out) return fail(PF_EINVAL, "null xstate_out");
+  return commit_state(c, z, state_out, xstate_out, stream);
 }
 
 pf_status pf_set_pmg_levels(pf_ctx* c, const int* orders, int n_levels) {

@@ -23,7 +23,7 @@ EXPORTED = [
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
-    "pf_apply_jacobian_lin", "pf_set_branches",
+    "pf_apply_jacobian_lin", "pf_set_branches", "pf_commit_state_branches",
 ]
 
 # pf_set_option
@@ -122,6 +122,7 @@ def load():
     L.pf_set_option.argtypes = [vp, C.c_int, C.c_int]
     L.pf_apply_jacobian_lin.argtypes = [vp, vp, vp, vp]
     L.pf_set_branches.argtypes = [vp, vp, C.c_int, vp]
+    L.pf_commit_state_branches.argtypes = [vp, vp, vp, vp, vp]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -180,6 +181,7 @@ class Context:
                                _ptr(self.qp_state), _ptr(self.phi_n), _stream(stream), C.byref(h)))
         self._h = h
         self.n_phases = len(phases)
+        self.xstate = None
 
     @classmethod
     def from_inputs(cls, d, device="cuda"):
@@ -329,6 +331,20 @@ class Context:
         _req(out, torch.float64, (8, self.n_q), "state_out")
         _check(load().pf_commit_state(self._h, _ptr(z), _ptr(out), _stream(stream)))
         return out
+
+    def commit_state_branches(self, z, out=None, xout=None, stream=None):
+        """pf_commit_state_branches: (state [8][n_q], extra branches' states [7*n_extra][n_q])."""
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        if self.xstate is None:
+            raise PfError(PF_EINVAL, "no extra branch attached")
+        if out is None:
+            out = torch.empty((8, self.n_q), dtype=torch.float64, device=z.device)
+        if xout is None:
+            xout = torch.empty_like(self.xstate)
+        _req(out, torch.float64, (8, self.n_q), "state_out")
+        _req(xout, torch.float64, tuple(self.xstate.shape), "xstate_out")
+        _check(load().pf_commit_state_branches(self._h, _ptr(z), _ptr(out), _ptr(xout), _stream(stream)))
+        return out, xout
 
     def newton_step(self, z, rtol=1e-8, restart=30, max_iters=300, cheb_degree=3, coarse_sweeps=32,
                     stream=None, raise_on_noconv=True):

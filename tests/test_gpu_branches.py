@@ -136,7 +136,7 @@ def test_branch_errors(pf):
     with pytest.raises(pf.PfError) as e:
         ctx.set_branches(bad_eta, xs)
     assert e.value.code == pf.PF_EINVAL
-    # the failed calls left the previous branches attached: the commit refuses them
+    # the failed calls left the previous branches attached: the single-block commit refuses them
     with pytest.raises(pf.PfError) as e:
         ctx.commit_state(dev(d["z"]))
     assert e.value.code == pf.PF_EUNSUPPORTED
@@ -173,3 +173,40 @@ def test_branches_full_size_sampled(pf, oracle_lib):
     for got, ref in ((r, orc.residual(d["z"], elems=els)), (y, orc.jacobian(d["z"], d["dz"], elems=els)),
                      (gz, orc.adjoint(d["z"], d["v_rand"], elems=els)[0])):
         assert relerr(got[:, nodes], ref[:, nodes]) <= FP64_TOL, relerr(got[:, nodes], ref[:, nodes])
+
+
+@pytest.mark.parametrize("variant,p,n", [("ex3", 2, 4), ("ex3", 3, 3), ("ex3_compress", 3, 2), ("ex3", 4, 2)])
+def test_commit_with_branches(pf, oracle_lib, variant, p, n):
+    """pf_commit_state_branches against the oracle: the block's state (history from the total
+    psi^+) and every branch's state; bars as the block's commit (D to 1e-12 of its largest entry,
+    ebar_p and H to 1e-13)."""
+    print(f"case commit branches {variant} p={p} n={n}", flush=True)
+    d = I.make_inputs("C1", variant, p=p, n=n)
+    ctx = pf.Context.from_inputs(d)
+    st, xs = ctx.commit_state_branches(dev(d["z"]))
+    st, xs = st.cpu().numpy(), xs.cpu().numpy()
+    ctx.check()
+    ref, xref = oracle_lib.Oracle.from_inputs(d).commit_state(d["z"])
+    sD = np.abs(ref[:6]).max()
+    assert np.abs(st[:6] - ref[:6]).max() <= 1e-12 * sD
+    assert np.abs(st[6] - ref[6]).max() <= 1e-13 * max(np.abs(ref[6]).max(), 1e-300)
+    assert np.abs(st[7] - ref[7]).max() <= 1e-13 * np.abs(ref[7]).max()
+    for j in range(xref.shape[0] // 7):
+        rows = slice(7 * j, 7 * j + 6)
+        sx = max(np.abs(xref[rows]).max(), 1e-300)
+        assert np.abs(xs[rows] - xref[rows]).max() <= 1e-12 * sx, (j, np.abs(xs[rows] - xref[rows]).max() / sx)
+        assert np.abs(xs[7 * j + 6] - xref[7 * j + 6]).max() <= 1e-13 * max(np.abs(xref[7 * j + 6]).max(), 1e-300)
+
+
+def test_commit_entry_points_check_branches(pf):
+    d = I.make_inputs("C1", "ex3", p=2, n=2)
+    ctx = pf.Context.from_inputs(d)
+    with pytest.raises(pf.PfError) as e:
+        ctx.commit_state(dev(d["z"]))
+    assert e.value.code == pf.PF_EUNSUPPORTED
+    with pytest.raises(pf.PfError) as e:
+        ctx.commit_state_branches(dev(d["z"]), xout=ctx.xstate)  # aliases the context's state
+    assert e.value.code == pf.PF_EINVAL
+    ctx.set_branches(None, None)
+    with pytest.raises(pf.PfError):
+        ctx.commit_state_branches(dev(d["z"]))
