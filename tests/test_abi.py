@@ -36,3 +36,10 @@ def test_null_context_is_rejected_without_gpu():
     assert b"null" in L.pf_last_error()
     rc = L.pf_setup_mesh(None, None, 0, None, None, None, None, None, None)
     assert rc == pfmf.PF_EINVAL
+
+
+def test_branch_calls_reject_a_null_context_without_gpu():
+    from paper_2607_21150_amd import pfmf
+    L = pfmf.load()
+    assert L.pf_set_branches(None, None, 0, None) == pfmf.PF_EINVAL
+    assert L.pf_commit_state_branches(None, None, None, None, None) == pfmf.PF_EINVAL
