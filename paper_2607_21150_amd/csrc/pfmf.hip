@@ -59,6 +59,7 @@ struct pf_ctx {
   const double* phi_n = nullptr;
   // extra branches in parallel (pf_set_branches)
   int n_extra = 0;
+  bool xvoce = false;  // some extra Prandtl branch hardens by the Voce law
   XBranch* d_xb = nullptr;
   MatParams<double>* d_xmats64 = nullptr;  // the same branches' materials for the record applies
   MatParams<float>* d_xmatsf = nullptr;
@@ -285,7 +286,9 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 // attached, the branch variant (which carries the Voce iteration for any branch)
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if (c->n_extra > 0) return launch_op64_mfma_v<MODE, P, true, true>(c, a, s);
+  if (c->n_extra > 0)
+    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true>(c, a, s)
+                                     : launch_op64_mfma_v<MODE, P, false, true>(c, a, s);
   return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false>(c, a, s)
                      : launch_op64_mfma_v<MODE, P, false, false>(c, a, s);
 }
@@ -303,7 +306,9 @@ pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE>
 pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if (c->n_extra > 0) return launch_op64_q4_v<MODE, true, true>(c, a, s);
+  if (c->n_extra > 0)
+    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true>(c, a, s)
+                                     : launch_op64_q4_v<MODE, false, true>(c, a, s);
   return c->has_voce ? launch_op64_q4_v<MODE, true, false>(c, a, s) : launch_op64_q4_v<MODE, false, false>(c, a, s);
 }
 
@@ -473,6 +478,7 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
   c->d_xmats64 = nullptr;
   c->d_xmatsf = nullptr;
   c->n_extra = 0;
+  c->xvoce = false;
   c->xstate = nullptr;
   if (n_extra > 0) {
     if (hipMalloc(&c->d_xb, xb.size() * sizeof(XBranch)) != hipSuccess ||
@@ -484,6 +490,8 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
     HIPCHK(hipMemcpy(c->d_xmatsf, x32.data(), x32.size() * sizeof(x32[0]), hipMemcpyHostToDevice));
     c->n_extra = n_extra;
     c->xstate = xstate;
+    for (int i = 0; i < nph * n_extra; ++i)
+      c->xvoce |= branches[i].kind == PF_BRANCH_PRANDTL && branches[i].voce_beta > 0;
   }
   c->mg.linearized = false;  // the linearisation covers the single block
   c->mg.lin64_valid = false;
