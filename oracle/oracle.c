@@ -864,6 +864,8 @@ typedef struct {
   double* N;                 /* [nQ][nP] basis values */
   double* dN;                /* [nQ][nP][3] physical gradients */
   double* wdet;              /* [nQ] quadrature weight times det J */
+  double* dNr;               /* [nQ][nP][3] reference gradients (d/dxi) */
+  double* wq3;               /* [nQ] quadrature weights on the reference cube */
   int nx1, ny1;
 } elem_tab;
 
@@ -879,12 +881,15 @@ static int make_tab(const or_mesh* m, elem_tab* t) {
   t->N = (double*)malloc(sizeof(double) * t->nQ * t->nP);
   t->dN = (double*)malloc(sizeof(double) * t->nQ * t->nP * 3);
   t->wdet = (double*)malloc(sizeof(double) * t->nQ);
-  if (!t->N || !t->dN || !t->wdet) return -1;
+  t->dNr = (double*)malloc(sizeof(double) * t->nQ * t->nP * 3);
+  t->wq3 = (double*)malloc(sizeof(double) * t->nQ);
+  if (!t->N || !t->dN || !t->wdet || !t->dNr || !t->wq3) return -1;
   for (int qz = 0; qz < Q; qz++)
     for (int qy = 0; qy < Q; qy++)
       for (int qx = 0; qx < Q; qx++) {
         int qq = qx + Q * (qy + Q * qz);
         t->wdet[qq] = wq[qx] * wq[qy] * wq[qz] * (hx * hy * hz / 8.0);
+        t->wq3[qq] = wq[qx] * wq[qy] * wq[qz];
         for (int az = 0; az < P; az++)
           for (int ay = 0; ay < P; ay++)
             for (int ax = 0; ax < P; ax++) {
@@ -893,6 +898,9 @@ static int make_tab(const or_mesh* m, elem_tab* t) {
               t->dN[(qq * t->nP + a) * 3 + 0] = (2.0 / hx) * D1[qx][ax] * B1[qy][ay] * B1[qz][az];
               t->dN[(qq * t->nP + a) * 3 + 1] = (2.0 / hy) * B1[qx][ax] * D1[qy][ay] * B1[qz][az];
               t->dN[(qq * t->nP + a) * 3 + 2] = (2.0 / hz) * B1[qx][ax] * B1[qy][ay] * D1[qz][az];
+              t->dNr[(qq * t->nP + a) * 3 + 0] = D1[qx][ax] * B1[qy][ay] * B1[qz][az];
+              t->dNr[(qq * t->nP + a) * 3 + 1] = B1[qx][ax] * D1[qy][ay] * B1[qz][az];
+              t->dNr[(qq * t->nP + a) * 3 + 2] = B1[qx][ax] * B1[qy][ay] * D1[qz][az];
             }
       }
   t->nx1 = m->p * m->nx + 1;
@@ -900,7 +908,33 @@ static int make_tab(const or_mesh* m, elem_tab* t) {
   return 0;
 }
 
-static void free_tab(elem_tab* t) { free(t->N); free(t->dN); free(t->wdet); }
+static void free_tab(elem_tab* t) { free(t->N); free(t->dN); free(t->wdet); free(t->dNr); free(t->wq3); }
+
+/* Mapped element (Section 4's isoparametric geometry): with node positions X [3][n_nodes]
+ * the map x(xi) = sum_a X_a N_a(xi) has J_iK = sum_a X_a,i dN_a/dxi_K at each point; the
+ * physical gradients are dN/dx_J = sum_K dN/dxi_K (J^-1)_KJ and the weight w det J.
+ * Returns 1 if some det J <= 0. */
+static int elem_geometry(const or_mesh* m, const elem_tab* t, const int64_t* idx, double* dNe, double* wde) {
+  int64_t n_nodes = (int64_t)t->nx1 * t->ny1 * (m->p * m->nz + 1);
+  int bad = 0;
+  for (int qq = 0; qq < t->nQ; qq++) {
+    double J[3][3] = {{0}}, Ji[3][3];
+    for (int a = 0; a < t->nP; a++) {
+      const double* dr = t->dNr + ((size_t)qq * t->nP + a) * 3;
+      for (int i = 0; i < 3; i++)
+        for (int K = 0; K < 3; K++) J[i][K] += m->X[i * n_nodes + idx[a]] * dr[K];
+    }
+    double det = inv3(J, Ji);
+    if (!(det > 0.0)) bad = 1;
+    wde[qq] = t->wq3[qq] * det;
+    for (int a = 0; a < t->nP; a++) {
+      const double* dr = t->dNr + ((size_t)qq * t->nP + a) * 3;
+      double* dp = dNe + ((size_t)qq * t->nP + a) * 3;
+      for (int Jc = 0; Jc < 3; Jc++) dp[Jc] = dr[0] * Ji[0][Jc] + dr[1] * Ji[1][Jc] + dr[2] * Ji[2][Jc];
+    }
+  }
+  return bad;
+}
 
 static void elem_nodes(const or_mesh* m, const elem_tab* t, int64_t e, int64_t* idx) {
   int64_t ex = e % m->nx, ey = (e / m->nx) % m->ny, ez = e / ((int64_t)m->nx * m->ny);
@@ -970,11 +1004,23 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
       ze[f * nP + a] = A->z[f * n_nodes + idx[a]];
       we[f * nP + a] = A->w ? A->w[f * n_nodes + idx[a]] : 0.0;
     }
+  /* mapped geometry: the element's own gradients and weights in a copy of the table */
+  elem_tab te;
+  double* geo = NULL;
+  if (m->X) {
+    geo = (double*)malloc(sizeof(double) * ((size_t)nQ * nP * 3 + nQ));
+    if (!geo) return -1;
+    te = *t;
+    te.dN = geo;
+    te.wdet = geo + (size_t)nQ * nP * 3;
+    bad |= elem_geometry(m, t, idx, te.dN, te.wdet);
+    t = &te;
+  }
   for (int k = 0; k < 4 * nP; k++) out[k] = 0.0;
   for (int qq = 0; qq < nQ; qq++) {
     int64_t gq = e * nQ + qq;
     int pid = A->phase[gq];
-    if (pid >= A->nph) return -1;
+    if (pid >= A->nph) { free(geo); return -1; }
     double G[9], phi, gphi[3], st[8], xs[7 * OR_MAX_EXTRA];
     interp_qp(t, qq, ze, G, &phi, gphi);
     double phin = 0.0;
@@ -1031,6 +1077,7 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
       }
     }
   }
+  free(geo);
   return bad;
 }
 
@@ -1162,17 +1209,24 @@ int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_b
   {
     int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * nP);
     double* ze = (double*)malloc(sizeof(double) * 4 * nP);
+    double* geo = (double*)malloc(sizeof(double) * ((size_t)nQ * nP * 3 + nQ));
 #pragma omp for schedule(static)
     for (int64_t e = 0; e < n_el; e++) {
       elem_nodes(m, &t, e, idx);
       for (int f = 0; f < 4; f++)
         for (int a = 0; a < nP; a++) ze[f * nP + a] = z[f * n_nodes + idx[a]];
+      elem_tab te = t;
+      if (m->X) {
+        te.dN = geo;
+        te.wdet = geo + (size_t)nQ * nP * 3;
+        elem_geometry(m, &t, idx, te.dN, te.wdet);
+      }
       for (int qq = 0; qq < nQ; qq++) {
         int64_t gq = e * nQ + qq;
         int pid = phase[gq];
         if (pid >= nph) { err = 1; continue; }
         double G[9], phi, gphi[3], st[8], sn[8], xs[7 * OR_MAX_EXTRA], xn[7 * OR_MAX_EXTRA];
-        interp_qp(&t, qq, ze, G, &phi, gphi);
+        interp_qp(&te, qq, ze, G, &phi, gphi);
         for (int k = 0; k < 8; k++) st[k] = state[k * n_q + gq];
         if (n_extra == 0) {
           or_qf_commit(&ph[pid], fr, G, phi, st, sn);
@@ -1184,7 +1238,7 @@ int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_b
         for (int k = 0; k < 8; k++) state_new[k * n_q + gq] = sn[k];
       }
     }
-    free(idx); free(ze);
+    free(idx); free(ze); free(geo);
   }
   free_tab(&t);
   return err ? -1 : 0;

@@ -35,7 +35,9 @@
 extern "C" {
 #endif
 
-typedef struct { int p, q, nx, ny, nz; double lx, ly, lz; } or_mesh;
+/* X: optional positions of the nodes [3][n_nodes] (an isoparametric map of every element,
+ * Section 4); NULL = the box [0,lx]x[0,ly]x[0,lz] with affine elements. */
+typedef struct { int p, q, nx, ny, nz; double lx, ly, lz; const double* X; } or_mesh;
 /* sigma_inf, voce_beta: Voce term (sigma_inf - sigma0)(1 - exp(-voce_beta ebar_p)) of the
  * hardening law; voce_beta = 0 is linear hardening. */
 typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; double sigma_inf, voce_beta; } or_phase;

@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
 
 class OrMesh(C.Structure):
     _fields_ = [("p", C.c_int), ("q", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
-                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double)]
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double), ("X", C.c_void_p)]
 
 
 class OrPhase(C.Structure):
@@ -112,8 +112,10 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mesh_struct(mesh, q=None):
-    return OrMesh(mesh.p, q if q is not None else mesh.p + 1, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz)
+def mesh_struct(mesh, q=None, X=None):
+    """X: node positions [3][n_nodes] (float64, C-contiguous, kept alive by the caller) or None."""
+    return OrMesh(mesh.p, q if q is not None else mesh.p + 1, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz,
+                  X.ctypes.data_as(C.c_void_p) if X is not None else None)
 
 
 def phase_struct(ph):
@@ -231,9 +233,15 @@ def qf_commit_mb(ph, xb, fr, G, phi, st, xs):
 class Oracle:
     """Oracle bound to one set of inputs (as produced by ``inputs.make_inputs``)."""
 
-    def __init__(self, mesh, phases, fracture, phase, state, phi_n, branches=None, xstate=None):
+    def __init__(self, mesh, phases, fracture, phase, state, phi_n, branches=None, xstate=None, X=None, q=None):
+        """X: node positions [3][n_nodes] of a mapped mesh (None: the box lattice); q: points
+        per direction of the Gauss rule (None: p + 1; state and phase then hold nx*ny*nz*q^3
+        points)."""
         self.mesh = mesh
-        self._m = mesh_struct(mesh)
+        self.X = _f64(X) if X is not None else None
+        if self.X is not None:
+            assert self.X.shape == (3, mesh.n_nodes)
+        self._m = mesh_struct(mesh, q=q, X=self.X)
         self._ph = phases_array(phases)
         self._nph = len(phases)
         self._fr = frac_struct(fracture)
@@ -245,7 +253,7 @@ class Oracle:
     @classmethod
     def from_inputs(cls, d):
         return cls(d["mesh"], d["phases"], d["fracture"], d["phase"], d["state"], d["phi_n"],
-                   d.get("branches"), d.get("xstate"))
+                   d.get("branches"), d.get("xstate"), d.get("X"))
 
     def set_branches(self, branches, xstate):
         """Extra branches per phase (list over phases of lists of length n_extra) and their

@@ -288,15 +288,40 @@ def _grid_to_qp_order(grid: np.ndarray, mesh: Mesh) -> np.ndarray:
     return np.ascontiguousarray(g).reshape(-1)
 
 
+def curved_nodes(mesh: Mesh, amp: float = 0.2):
+    """Node positions of a curved mesh: the box's GLL lattice moved by
+    amp * h * sin(2 pi x / lam) sin(2 pi y / lam) sin(2 pi z / lam) * (1, 0.7, -0.5) with
+    lam = 4 h, so elements are curved at their own scale while every boundary face stays
+    planar (the field vanishes there when the element count per side is even)."""
+    gll = gll_points(mesh.p)
+    X = _coords_1d(mesh.nx, mesh.p, mesh.lx, gll)
+    Y = _coords_1d(mesh.ny, mesh.p, mesh.ly, gll)
+    Z = _coords_1d(mesh.nz, mesh.p, mesh.lz, gll)
+    h = mesh.lx / mesh.nx
+    lam = 4.0 * h
+    sx = np.sin(2 * math.pi * X / lam)
+    sy = np.sin(2 * math.pi * Y / lam)
+    sz = np.sin(2 * math.pi * Z / lam)
+    bump = amp * h * sz[:, None, None] * sy[None, :, None] * sx[None, None, :]
+    nz1, ny1, nx1 = len(Z), len(Y), len(X)
+    out = np.empty((3, nz1, ny1, nx1))
+    out[0] = X[None, None, :] + 1.0 * bump
+    out[1] = Y[None, :, None] + 0.7 * bump
+    out[2] = Z[:, None, None] - 0.5 * bump
+    return out.reshape(3, -1)
+
+
 def make_inputs(name: str = "C1", variant: str = "base", p: Optional[int] = None,
-                n: Optional[int] = None, phases=None, at: int = 1, with_dir: bool = True):
+                n: Optional[int] = None, phases=None, at: int = 1, with_dir: bool = True,
+                geometry: str = "box"):
     """Draw every input of one configuration.
 
     Returns a dict with ``mesh``, ``phases``, ``fracture``, ``z`` [4][n_nodes],
     ``phi_n`` [n_nodes], ``state`` [8][n_q], ``phase`` uint8[n_q],
     ``dz`` [4][n_nodes] (unit l2 norm), ``v_top`` (top-face u_z indicator) and
     ``v_rand`` [4][n_nodes] (unit l2 norm). The ``ex3`` variants add ``branches``
-    (per phase, the extra branches) and ``xstate`` [7*n_extra][n_q].
+    (per phase, the extra branches) and ``xstate`` [7*n_extra][n_q]. ``geometry="curved"``
+    adds ``X`` [3][n_nodes], the node positions of a curved mesh (see curved_nodes).
     """
     cfg = make_config(name, p, n)
     mesh = Mesh(cfg.p, cfg.n, cfg.n, cfg.n)
@@ -385,6 +410,10 @@ def make_inputs(name: str = "C1", variant: str = "base", p: Optional[int] = None
     out = dict(mesh=mesh, phases=list(phases), fracture=frac, z=z, phi_n=phi_n,
                state=state, phase=phase, cfg=cfg, variant=variant, e0=e0,
                sphere_scale=scale, vol_frac=float(phase.mean()))
+    if geometry == "curved":
+        out["X"] = curved_nodes(mesh)
+    elif geometry != "box":
+        raise ValueError(f"geometry {geometry!r}")
     if branches is not None:
         # extra branches' states: an isochoric D per inelastic branch drawn like the
         # block's (accumulated plastic strain 0), zero in the particles
