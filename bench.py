@@ -268,6 +268,66 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
             "rel_err_vs_oracle_sampled": errs}
 
 
+def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3):
+    """FP64 applies on mapped (curved) Q3 elements: the headline's plastic workload with its
+    node lattice moved by a smooth bump of 0.2 h, the per-point J^-1 and weight read from
+    the stored geometry record (80 B per point on top of the box's bytes). Median device
+    time of each apply (HIP events around every launch), and the same applies on the box
+    for the ratio."""
+    d = I.make_inputs(config, "plastic", geometry="curved")
+    mesh = d["mesh"]
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64)
+    ctx = pfmf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_top"])
+    r, y, g = torch.empty_like(z), torch.empty_like(z), torch.empty_like(z)
+    gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    ctx.set_geometry(dev(d["X"]))
+    setup_ms = (time.perf_counter() - t0) * 1e3  # host wall time of the setup call (it synchronises)
+    ops = {"residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
+           "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp)}
+
+    def timed():
+        for _ in range(warmup):
+            for f in ops.values():
+                f()
+        torch.cuda.synchronize()
+        ev = {k: [] for k in ops}
+        for _ in range(steps):
+            for k, f in ops.items():
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                f()
+                b.record()
+                ev[k].append((a, b))
+        torch.cuda.synchronize()
+        ctx.check()
+        return {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
+
+    ms = timed()
+    y_cur, g_cur = y.cpu().numpy(), g.cpu().numpy()
+    ctx.set_geometry(None)
+    ms_box = timed()
+    alg = {k: alg_bytes(mesh, k) + 80 * mesh.n_q for k in ops}
+    errs = {}
+    try:
+        from oracle import pyoracle
+        pyoracle.build(force=False)
+        orc = pyoracle.Oracle.from_inputs(d)
+        rng = np.random.default_rng(0)
+        errs["jacobian"] = sampled_rel_err(orc, mesh, y_cur, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        errs["adjoint"] = sampled_rel_err(orc, mesh, g_cur, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
+    except Exception as exc:
+        errs["error"] = str(exc)
+    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3 curved (bump 0.2 h), {mesh.n_dof} DoFs, plastic matrix",
+            "ms_median": ms, "ms_median_box": ms_box, "setup_ms": setup_ms,
+            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ms},
+            "alg_bytes_per_apply": alg,
+            "gbs_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in alg},
+            "curved_over_box_time": {k: ms[k] / ms_box[k] for k in ms},
+            "rel_err_vs_oracle_sampled": errs}
+
+
 def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
@@ -348,6 +408,8 @@ def main():
     ap.add_argument("--branches", default="C3",
                     help="workload on which the applies with the third example's branches in parallel are timed "
                          "('' = none)")
+    ap.add_argument("--geometry", default="C3",
+                    help="workload on which the applies on curved (mapped) Q3 elements are timed ('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
@@ -448,7 +510,7 @@ def main():
     traffic = counters.get("hbm_bytes_per_apply")
     kname = {2: "pfmf::k_op64_q2<1, true, false, false> + pfmf::k_gather_bricks<double, 3>: one launch over all "
                 "bricks, then the node gather",
-             3: "pfmf::k_op64_q3<1, true, false, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
+             3: "pfmf::k_op64_q3<1, true, false, false, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
                 "bricks, then the node gather",
              4: "pfmf::k_op64_q4<1, false, false>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
@@ -518,12 +580,16 @@ def main():
         "fp32_over_fp64_apply_speedup": ms_med["jacobian"] / ms_med["fp32_apply"],
         "rel_err_vs_oracle_sampled": errs,
     }
-    if args.secondary or args.newton or args.branches:
+    if args.secondary or args.newton or args.branches or args.geometry:
         del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32, ys
         torch.cuda.empty_cache()
     if args.branches:
         out["branches"] = branches_leg(torch, I, pfmf, args.branches)
         print(f"[bench] branches {out['branches']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if args.geometry:
+        out["geometry"] = geometry_leg(torch, I, pfmf, args.geometry)
+        print(f"[bench] geometry {out['geometry']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if args.secondary:
         out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)

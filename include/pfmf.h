@@ -141,11 +141,24 @@ pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n
  * branch (the block's layer holds the switch and dL/dphi of the total psi^+), which the
  * FP32 levels, the V-cycle, pf_apply_jacobian_lin and pf_newton_step sum over; the
  * record grows to (1 + n_extra) layers. The call invalidates the linearisation.
+ * PF_EUNSUPPORTED with a mapped geometry attached (pf_set_geometry).
  * The state commit with branches is pf_commit_state_branches.
  * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
  * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
  * p = 1, PF_ENOMEM / PF_EHIP from the device copy. */
 pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, const double* xstate);
+
+/* Mapped (curved) elements, the isoparametric map of Section 4: X is a device pointer to
+ * double[3][n_nodes], the position of every node (rows x, y, z; node order as z). The call
+ * computes, once, a per-point geometry record of 10 doubles (J^-1 and the weight times
+ * det J, 80 bytes per point, owned by the context) from which the FP64 residual, Jacobian
+ * and adjoint take their gradients and weights; X itself is not kept. X = NULL returns to
+ * the box. Order 3 only. The call invalidates the linearisation and synchronises the
+ * stream. With a geometry attached pf_linearize, pf_commit_state and pf_newton_step
+ * return PF_EUNSUPPORTED (they are built for the box).
+ * Errors: PF_EINVAL when some point has det J <= 0 (the geometry stays detached),
+ * PF_EUNSUPPORTED for p != 3 or with extra branches attached, PF_ENOMEM, PF_EHIP. */
+pf_status pf_set_geometry(pf_ctx* ctx, const double* X, void* stream);
 
 /* Replace the per-phase parameters (Gc, sigma0, visc) from host memory
  * params[n_phases][3]. Takes effect for applies enqueued after the call. */

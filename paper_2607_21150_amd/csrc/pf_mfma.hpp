@@ -20,6 +20,7 @@
 #include "pf_mg.hpp"
 #include "pf_ops.hpp"
 #include "pf_branch.hpp"
+#include "pf_geom.hpp"
 #include "pf_qf.hpp"
 
 namespace pfmf {
@@ -299,7 +300,8 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
 }
 
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
-template <int MODE, bool BB, bool VOCE, bool MB>
+// GEO: mapped elements, each point's J^-1 and weight read from the geometry record a.qd.
+template <int MODE, bool BB, bool VOCE, bool MB, bool GEO>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
   const int ql = qx + 4 * qy + 16 * qz;
   const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
-  const double wdet = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet;
+  const double wbox = tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet;
   // adjoint: parameter partials and phase id of every point of the brick (slot, lane)
   __shared__ double gpq[MODE == M_ADJ ? 8 * 3 * 64 : 1];
   __shared__ unsigned char gpid[MODE == M_ADJ ? 8 * 64 : 1];
@@ -346,20 +348,23 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
 #pragma unroll
     for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];
     const int pid = a.phase[gq];
+    // mapped elements: the point's J^-1 and weight
+    double gA[GEO ? 9 : 1];
+    double wdet = wbox;
+    if (GEO) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+      wdet = a.qd[9 * a.n_q + gq];
+    }
     // forward sum factorisation
     double G[9], phi = 0.0, gphi[3] = {0.0, 0.0, 0.0}, phin = 0.0;
     {
       double v[4], d[4][3];
       sf4_fwd_n<4>(zu, bs, 0x8u, MODE == M_JAC ? 0x7u : 0xFu, v, d);
 #pragma unroll
-      for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int J = 0; J < 3; ++J) G[3 * f + J] = d[f][J] * ih[J];
+      for (int f = 0; f < 3; ++f) ref_to_phys<GEO>(d[f], ih, gA, G + 3 * f);
       phi = v[3];
-      if (MODE != M_JAC) {
-#pragma unroll
-        for (int J = 0; J < 3; ++J) gphi[J] = d[3][J] * ih[J];
-      }
+      if (MODE != M_JAC) ref_to_phys<GEO>(d[3], ih, gA, gphi);
     }
     if (MODE == M_RES) {
       double v[1], d[1][3];
@@ -383,12 +388,9 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       double v[4], d[4][3];
       sf4_fwd_n<4>(wu, bs, 0x8u, 0xFu, v, d);
 #pragma unroll
-      for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int J = 0; J < 3; ++J) W[3 * f + J] = d[f][J] * ih[J];
+      for (int f = 0; f < 3; ++f) ref_to_phys<GEO>(d[f], ih, gA, W + 3 * f);
       wphi = v[3];
-#pragma unroll
-      for (int J = 0; J < 3; ++J) gw[J] = d[3][J] * ih[J];
+      ref_to_phys<GEO>(d[3], ih, gA, gw);
     }
     const double kfg = a.fr.kf * mp.Gc;
     double Fu[9], f0, f1[3];
@@ -454,12 +456,10 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
         b0[f] = 0.0;
-#pragma unroll
-        for (int J = 0; J < 3; ++J) b1[f][J] = Fu[3 * f + J] * ih[J];
+        phys_to_ref<GEO>(Fu + 3 * f, ih, gA, b1[f]);
       }
       b0[3] = f0;
-#pragma unroll
-      for (int J = 0; J < 3; ++J) b1[3][J] = f1[J] * ih[J];
+      phys_to_ref<GEO>(f1, ih, gA, b1[3]);
       sf4_bwd_n<4>(b0, b1, 0x8u, bs, r);
 #pragma unroll
       for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];

@@ -519,6 +519,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   if (st) return st;
   if (!z) return fail(PF_EINVAL, "null z");
   if (c->n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
+  if (c->d_qd) return fail(PF_EUNSUPPORTED, "the linearisation on mapped elements is not built");
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   if ((st = mg_alloc(c)) || (st = ensure_records(c))) return st;
@@ -656,6 +657,7 @@ pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xs
 extern "C" {
 
 pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
+  if (c && c->d_qd) return fail(PF_EUNSUPPORTED, "the commit on mapped elements is not built");
   if (c && c->n_extra > 0)
     return fail(PF_EUNSUPPORTED, "extra branches attached: use pf_commit_state_branches");
   return commit_state(c, z, state_out, nullptr, stream);

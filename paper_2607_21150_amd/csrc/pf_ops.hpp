@@ -37,6 +37,7 @@ struct OpArgs {
   const XBranch* xb;    // extra branches [nph][n_extra] (n_extra = 0: none)
   const double* xstate; // their states [7*n_extra][n_q]: D[6], ebar_p per branch
   int n_extra;
+  const double* qd;     // mapped elements: per-point geometry [10][n_q] (null: the box)
 };
 
 template <int P, int Q> struct OpShape {

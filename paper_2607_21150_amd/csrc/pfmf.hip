@@ -64,6 +64,8 @@ struct pf_ctx {
   MatParams<double>* d_xmats64 = nullptr;  // the same branches' materials for the record applies
   MatParams<float>* d_xmatsf = nullptr;
   const double* xstate = nullptr;
+  // mapped elements (pf_set_geometry): per-point J^-1 and weights [10][n_q]
+  double* d_qd = nullptr;
   // device buffers
   DevTables* d_tab = nullptr;
   DevTablesF* d_tabf = nullptr;
@@ -247,8 +249,9 @@ inline bool use_brick_buffer(const pf_ctx* c) {
   return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
 }
 
-template <int MODE, int P, bool VOCE, bool MB>
+template <int MODE, int P, bool VOCE, bool MB, bool GEO>
 pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
+  static_assert(!GEO || P == 4, "mapped elements on Q3 only");
   const bool bb = use_brick_buffer(c);
   if (bb) {
     constexpr int NB = 2 * P - 1;
@@ -258,8 +261,8 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     a.ebuf = c->d_ebuf;
     a.brick_base = 0;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
-    if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    if constexpr (P == 4)
+      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
       hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
@@ -273,8 +276,8 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     const int ng = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (ng == 0) continue;
     a.brick_base = c->colour_base[col];
-    if (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+    if constexpr (P == 4)
+      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     else
       hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
@@ -283,14 +286,20 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 }
 
 // kernels without the Voce iteration unless a phase uses it; with extra branches
-// attached, the branch variant (which carries the Voce iteration for any branch)
+// attached, the branch variant (which carries the Voce iteration for any branch); with
+// mapped elements (Q3, no extra branch: pf_set_geometry checks both) the geometry variant
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if constexpr (P == 4) {
+    if (c->d_qd)
+      return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, true>(c, a, s)
+                         : launch_op64_mfma_v<MODE, P, false, false, true>(c, a, s);
+  }
   if (c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true>(c, a, s)
-                                     : launch_op64_mfma_v<MODE, P, false, true>(c, a, s);
-  return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false>(c, a, s)
-                     : launch_op64_mfma_v<MODE, P, false, false>(c, a, s);
+    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true, false>(c, a, s)
+                                     : launch_op64_mfma_v<MODE, P, false, true, false>(c, a, s);
+  return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, false>(c, a, s)
+                     : launch_op64_mfma_v<MODE, P, false, false, false>(c, a, s);
 }
 
 template <int MODE, bool VOCE, bool MB>
@@ -348,6 +357,7 @@ OpArgs op_args(pf_ctx* c) {
   a.xb = c->d_xb;
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
+  a.qd = c->d_qd;
   return a;
 }
 
@@ -444,6 +454,7 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
     return fail(PF_EINVAL, "n_extra=%d outside 0..%d", n_extra, PF_MAX_EXTRA_BRANCHES);
   if (n_extra > 0 && (!branches || !xstate)) return fail(PF_EINVAL, "null branches or xstate");
   if (n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
+  if (n_extra > 0 && c->d_qd) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
   const int nph = (int)c->phases.size();
   std::vector<XBranch> xb((size_t)nph * (n_extra > 0 ? n_extra : 1));
   for (int i = 0; i < nph * n_extra; ++i) {
@@ -602,6 +613,47 @@ pf_status pf_check(pf_ctx* c) {
   return PF_OK;
 }
 
+pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (X && c->mesh.p != 3) return fail(PF_EUNSUPPORTED, "mapped elements are built for p = 3 (p=%d)", c->mesh.p);
+  if (X && c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
+  HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old record
+  (void)hipFree(c->d_qd);
+  c->d_qd = nullptr;
+  c->mg.linearized = false;  // a linearisation belongs to the geometry it was taken on
+  c->mg.lin64_valid = false;
+  if (!X) return PF_OK;
+  double* qd = nullptr;
+  int* flag = nullptr;
+  if (hipMalloc(&qd, (size_t)GEO_N * c->n_q * sizeof(double)) != hipSuccess) return fail(PF_ENOMEM, "geometry record: allocation failed");
+  if (hipMalloc(&flag, sizeof(int)) != hipSuccess) {
+    (void)hipFree(qd);
+    return fail(PF_ENOMEM, "geometry flag: allocation failed");
+  }
+  int bad = 0;
+  hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((k_geometry<4, 4>), dim3((unsigned)((c->n_q + NT - 1) / NT)), dim3(NT), 0, s, X, c->n_nodes,
+                       c->nx1, c->ny1, c->mesh.nx, c->mesh.ny, c->n_q, (const DevTables*)c->d_tab, qd, flag);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(flag);
+  if (e != hipSuccess) {
+    (void)hipFree(qd);
+    return fail(PF_EHIP, "geometry setup: %s", hipGetErrorString(e));
+  }
+  if (bad) {
+    (void)hipFree(qd);
+    return fail(PF_EINVAL, "node positions give an element with det J <= 0 at some quadrature point");
+  }
+  c->d_qd = qd;
+  return PF_OK;
+}
+
 void pf_destroy(pf_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
@@ -620,6 +672,7 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_xb);
   (void)hipFree(c->d_xmats64);
   (void)hipFree(c->d_xmatsf);
+  (void)hipFree(c->d_qd);
   delete c;
 }
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "pf_apply_adjoint", "pf_linearize", "pf_level_info", "pf_apply_jacobian_f32", "pf_prolong",
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
-    "pf_apply_jacobian_lin", "pf_set_branches", "pf_commit_state_branches",
+    "pf_apply_jacobian_lin", "pf_set_branches", "pf_commit_state_branches", "pf_set_geometry",
 ]
 
 # pf_set_option
@@ -123,6 +123,7 @@ def load():
     L.pf_apply_jacobian_lin.argtypes = [vp, vp, vp, vp]
     L.pf_set_branches.argtypes = [vp, vp, C.c_int, vp]
     L.pf_commit_state_branches.argtypes = [vp, vp, vp, vp, vp]
+    L.pf_set_geometry.argtypes = [vp, vp, vp]
     L.pf_check.argtypes = [vp]
     L.pf_destroy.argtypes = [vp]
     L.pf_destroy.restype = None
@@ -190,6 +191,8 @@ class Context:
                   t(d["state"], torch.float64), t(d["phi_n"], torch.float64))
         if d.get("branches"):
             ctx.set_branches(d["branches"], t(d["xstate"], torch.float64))
+        if d.get("X") is not None:
+            ctx.set_geometry(t(d["X"], torch.float64))
         return ctx
 
     def close(self):
@@ -225,6 +228,15 @@ class Context:
                                                     b.sigma_inf, b.voce_beta) for b in flat])
         self.xstate = _req(xstate, torch.float64, (7 * n_extra, self.n_q), "xstate")
         _check(load().pf_set_branches(self._h, arr, n_extra, _ptr(self.xstate)))
+
+    def set_geometry(self, X, stream=None):
+        """pf_set_geometry: X = device float64 [3][n_nodes] node positions of a mapped mesh
+        (read once, not kept); None returns to the box."""
+        if X is None:
+            _check(load().pf_set_geometry(self._h, None, _stream(stream)))
+            return
+        X = _req(X, torch.float64, (3, self.n_nodes), "X")
+        _check(load().pf_set_geometry(self._h, _ptr(X), _stream(stream)))
 
     def set_params(self, params):
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.n_phases, 3))

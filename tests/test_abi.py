@@ -43,3 +43,9 @@ def test_branch_calls_reject_a_null_context_without_gpu():
     L = pfmf.load()
     assert L.pf_set_branches(None, None, 0, None) == pfmf.PF_EINVAL
     assert L.pf_commit_state_branches(None, None, None, None, None) == pfmf.PF_EINVAL
+
+
+def test_geometry_call_rejects_a_null_context_without_gpu():
+    from paper_2607_21150_amd import pfmf
+    L = pfmf.load()
+    assert L.pf_set_geometry(None, None, None) == pfmf.PF_EINVAL

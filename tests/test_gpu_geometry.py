@@ -1,0 +1,142 @@
+"""HIP library on mapped (curved) Q3 hexahedra (Section 4's isoparametric map) against the
+oracle: FP64 residual, Jacobian and adjoint with parameter partials, both scatter modes,
+the full-size mesh on sampled nodes, and the boundary's error paths.
+
+Bar: relative L2 error <= 1e-12 for every FP64 output (and per field block).
+"""
+import numpy as np
+import pytest
+
+from paper_2607_21150_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pf():
+    from paper_2607_21150_amd import pfmf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pfmf.load()
+    return pfmf
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def dev(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+def check_blocks(gpu, ref, tol, what):
+    assert relerr(gpu, ref) <= tol, (what, relerr(gpu, ref))
+    for f in range(4):
+        if np.linalg.norm(ref[f]) > 1e-10 * np.linalg.norm(ref):
+            assert relerr(gpu[f], ref[f]) <= tol * 10, (what, f, relerr(gpu[f], ref[f]))
+
+
+CASES = [
+    ("plastic", 3, 1), ("plastic", 2, 1), ("base", 3, 1), ("compress", 2, 1), ("voce", 3, 1),
+    ("plastic", 3, 2),  # AT2
+]
+
+
+@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
+@pytest.mark.parametrize("variant,n,at", CASES)
+def test_curved_q3_fp64(pf, oracle_lib, variant, n, at, scatter):
+    print(f"case curved Q3 {variant} n={n} at={at} {scatter}", flush=True)
+    d = I.make_inputs("C1", variant, p=3, n=n, at=at, geometry="curved")
+    orc = oracle_lib.Oracle.from_inputs(d)
+    ctx = pf.Context.from_inputs(d)
+    ctx.set_scatter(scatter)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r = ctx.apply_residual(z).cpu().numpy()
+    y = ctx.apply_jacobian(z, dz).cpu().numpy()
+    gz, gp = ctx.apply_adjoint(z, v)
+    ctx.check()
+    check_blocks(r, orc.residual(d["z"]), FP64_TOL, "residual")
+    check_blocks(y, orc.jacobian(d["z"], d["dz"]), FP64_TOL, "jacobian")
+    gref, gpref = orc.adjoint(d["z"], d["v_rand"])
+    check_blocks(gz.cpu().numpy(), gref, FP64_TOL, "adjoint")
+    gp = gp.cpu().numpy()
+    for k in range(3):
+        scale = max(np.abs(gpref[:, k]).max(), 1e-300)
+        assert np.abs(gp[:, k] - gpref[:, k]).max() <= 1e-11 * scale, (k, gp[:, k], gpref[:, k])
+
+
+def test_detach_returns_to_the_box(pf, oracle_lib):
+    d = I.make_inputs("C1", "plastic", p=3, n=3, geometry="curved")
+    ctx = pf.Context.from_inputs(d)
+    z = dev(d["z"])
+    curved = ctx.apply_residual(z).cpu().numpy()
+    ctx.set_geometry(None)
+    box = ctx.apply_residual(z).cpu().numpy()
+    ctx.check()
+    single = dict(d)
+    single.pop("X")
+    check_blocks(box, oracle_lib.Oracle.from_inputs(single).residual(d["z"]), FP64_TOL, "box")
+    assert relerr(curved, box) > 1e-3
+
+
+def test_geometry_errors(pf):
+    d = I.make_inputs("C1", "plastic", p=3, n=2)
+    ctx = pf.Context.from_inputs(d)
+    X = I.curved_nodes(d["mesh"], amp=0.0)
+    bad = X.copy()
+    bad[0, 1 + 7 * (1 + 7 * 1)] += 0.6  # an interior node of element 0 pushed through its face
+    with pytest.raises(pf.PfError) as e:
+        ctx.set_geometry(dev(bad))
+    assert e.value.code == pf.PF_EINVAL
+    ctx.set_geometry(dev(I.curved_nodes(d["mesh"])))
+    z = dev(d["z"])
+    for call in (lambda: ctx.linearize(z), lambda: ctx.commit_state(z)):
+        with pytest.raises(pf.PfError) as e:
+            call()
+        assert e.value.code == pf.PF_EUNSUPPORTED
+    # extra branches on mapped elements are not built (either order of attaching)
+    dx = I.make_inputs("C1", "ex3", p=3, n=2)
+    with pytest.raises(pf.PfError) as e:
+        ctx.set_branches(dx["branches"], dev(dx["xstate"]))
+    assert e.value.code == pf.PF_EUNSUPPORTED
+    with pytest.raises(pf.PfError) as e:
+        pf.Context.from_inputs(dict(dx, X=I.curved_nodes(dx["mesh"])))
+    assert e.value.code == pf.PF_EUNSUPPORTED
+    with pytest.raises(pf.PfError) as e:
+        ctx.set_geometry(torch.zeros((3, 5), dtype=torch.float64, device="cuda"))
+    assert e.value.code == pf.PF_EINVAL
+    # orders other than 3 are not built
+    d2 = I.make_inputs("C1", "plastic", p=2, n=2)
+    ctx2 = pf.Context.from_inputs(d2)
+    with pytest.raises(pf.PfError) as e:
+        ctx2.set_geometry(dev(I.curved_nodes(d2["mesh"])))
+    assert e.value.code == pf.PF_EUNSUPPORTED
+    ctx.check()
+
+
+def test_curved_full_size_sampled(pf, oracle_lib):
+    """Q3 48^3 curved, launched as the bench times it: sampled nodes against the oracle
+    (elements around them recomputed), and <v, J dz> = <J^T v, dz>."""
+    print("case curved C3 full size, sampled nodes", flush=True)
+    d = I.make_inputs("C3", "plastic", geometry="curved")
+    mesh = d["mesh"]
+    ctx = pf.Context.from_inputs(d)
+    orc = oracle_lib.Oracle.from_inputs(d)
+    rng = np.random.default_rng(9)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r = ctx.apply_residual(z).cpu().numpy()
+    y_t = ctx.apply_jacobian(z, dz)
+    gz_t, _ = ctx.apply_adjoint(z, v)
+    ctx.check()
+    a = float(torch.sum(v * y_t))
+    b = float(torch.sum(gz_t * dz))
+    assert abs(a - b) <= 1e-12 * float(torch.linalg.norm(gz_t) * torch.linalg.norm(dz)), (a, b)
+    y, gz = y_t.cpu().numpy(), gz_t.cpu().numpy()
+    nodes = np.unique(rng.choice(mesh.n_nodes, size=64, replace=False))
+    els = I.elements_touching_nodes(mesh, nodes)
+    for got, ref in ((r, orc.residual(d["z"], elems=els)), (y, orc.jacobian(d["z"], d["dz"], elems=els)),
+                     (gz, orc.adjoint(d["z"], d["v_rand"], elems=els)[0])):
+        assert relerr(got[:, nodes], ref[:, nodes]) <= FP64_TOL, relerr(got[:, nodes], ref[:, nodes])
