@@ -521,9 +521,9 @@ namespace pfmf {
 // 4 x 4 (one element per pass, 27 of 64 lanes carry points); the pointwise function
 // then runs on a packed layout holding both elements of the wave (lanes 0-26 and
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
-// two elements.
-template <int MODE, bool BB, bool VOCE, bool MB>
-__global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
+// two elements. GEO: mapped elements (J^-1 and weight per point from a.qd).
+template <int MODE, bool BB, bool VOCE, bool MB, bool GEO>
+__global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
                                                                               DevTables* __restrict__ tabs) {
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
   const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
   const int pq = pqx + 3 * pqy + 9 * pqz;
   const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
-  const double wdet = tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz] *
+  const double wbox = tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz] *
                       a.m.jdet;
   bool any_bad = false;
   int pid = 255;
@@ -573,7 +573,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
 #pragma unroll
         for (int J = 0; J < 3; ++J) {
           const double r = lane_read(d[f][J], src_fwd);
-          if (mine) G[3 * f + J] = r * ih[J];
+          if (mine) G[3 * f + J] = GEO ? r : r * ih[J];  // GEO: reference derivatives, mapped below
         }
       const double rp = lane_read(v[3], src_fwd);
       if (mine) phi = rp;
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
 #pragma unroll
         for (int J = 0; J < 3; ++J) {
           const double r = lane_read(d[3][J], src_fwd);
-          if (mine) gphi[J] = r * ih[J];
+          if (mine) gphi[J] = GEO ? r : r * ih[J];
         }
       }
       if (MODE == M_RES) {
@@ -598,6 +598,21 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
 #pragma unroll
     for (int k = 0; k < 8; ++k) st[k] = valid ? a.state[k * a.n_q + gq] : 0.0;
     pid = valid ? a.phase[gq] : 255;
+    // mapped elements: the point's J^-1 and weight; gradients to physical coordinates
+    double gA[GEO ? 9 : 1];
+    double wdet = wbox;
+    if (GEO) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = valid ? a.qd[k * a.n_q + gq] : 0.0;
+      wdet = valid ? a.qd[9 * a.n_q + gq] : 0.0;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const double dr[3] = {G[3 * f], G[3 * f + 1], G[3 * f + 2]};
+        ref_to_phys<true>(dr, ih, gA, G + 3 * f);
+      }
+      const double dp[3] = {gphi[0], gphi[1], gphi[2]};
+      ref_to_phys<true>(dp, ih, gA, gphi);
+    }
     const int pidc = pid < a.nph ? pid : 0;
     const MatParams<double> mp = a.mats[pidc];
     // branches in parallel (flags of lanes without a point are dropped)
@@ -627,15 +642,24 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
 #pragma unroll
           for (int J = 0; J < 3; ++J) {
             const double r = lane_read(d[f][J], src_fwd);
-            if (mine) W[3 * f + J] = r * ih[J];
+            if (mine) W[3 * f + J] = GEO ? r : r * ih[J];
           }
         const double rp = lane_read(v[3], src_fwd);
         if (mine) wphi = rp;
 #pragma unroll
         for (int J = 0; J < 3; ++J) {
           const double r = lane_read(d[3][J], src_fwd);
-          if (mine) gw[J] = r * ih[J];
+          if (mine) gw[J] = GEO ? r : r * ih[J];
         }
+      }
+      if (GEO) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const double dr[3] = {W[3 * f], W[3 * f + 1], W[3 * f + 2]};
+          ref_to_phys<true>(dr, ih, gA, W + 3 * f);
+        }
+        const double dw[3] = {gw[0], gw[1], gw[2]};
+        ref_to_phys<true>(dw, ih, gA, gw);
       }
     }
     // ---- pointwise function (packed layout)
@@ -699,11 +723,8 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB) ? 2 : 3) void k_op64_q2(O
     double b1p[4][3];
     double b0p[4];
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-      for (int J = 0; J < 3; ++J) b1p[f][J] = Fu[3 * f + J] * ih[J];
-#pragma unroll
-    for (int J = 0; J < 3; ++J) b1p[3][J] = f1[J] * ih[J];
+    for (int f = 0; f < 3; ++f) phys_to_ref<GEO>(Fu + 3 * f, ih, gA, b1p[f]);
+    phys_to_ref<GEO>(f1, ih, gA, b1p[3]);
     b0p[3] = f0;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {

@@ -21,6 +21,7 @@
 #include "pf_mg.hpp"
 #include "pf_ops.hpp"
 #include "pf_branch.hpp"
+#include "pf_geom.hpp"
 #include "pf_qf.hpp"
 
 namespace pfmf {
@@ -253,7 +254,8 @@ template <int P, int Q> struct Q5Lds {
 };
 
 // FP64 residual / Jacobian / adjoint on order-4 elements.
-template <int MODE, bool VOCE, bool MB>
+// GEO: mapped elements (J^-1 and weight per point from a.qd).
+template <int MODE, bool VOCE, bool MB, bool GEO>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   constexpr int P = 5, Q = 5, Q3 = 125;
   using L = Q5Lds<P, Q>;
@@ -276,18 +278,24 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   for (int k = 0; k < 8; ++k) st[k] = pt ? a.state[k * a.n_q + gq] : 0.0;
   const int pid = pt ? a.phase[gq] : 0;
   const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
-  const double wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * a.m.jdet;
+  double wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * a.m.jdet;
+  // mapped elements: the point's J^-1 and weight
+  double gA[GEO ? 9 : 1];
+  if (GEO) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gA[k] = pt ? a.qd[k * a.n_q + gq] : 0.0;
+    wdet = pt ? a.qd[9 * a.n_q + gq] : 0.0;
+  }
   gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
   __syncthreads();
   sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
   double G[9], phi, gphi[3];
 #pragma unroll
-  for (int f = 0; f < 3; ++f)
-#pragma unroll
-    for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  for (int f = 0; f < 4; ++f) {
+    const double dr[3] = {bufB[(4 * f + 1) * Q3 + ql], bufB[(4 * f + 2) * Q3 + ql], bufB[(4 * f + 3) * Q3 + ql]};
+    ref_to_phys<GEO>(dr, ih, gA, f < 3 ? G + 3 * f : gphi);
+  }
   phi = bufB[12 * Q3 + ql];
-#pragma unroll
-  for (int J = 0; J < 3; ++J) gphi[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
   double phin = 0.0;
   __syncthreads();
   if (MODE == M_RES) {
@@ -313,12 +321,11 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     __syncthreads();
     sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-      for (int J = 0; J < 3; ++J) W[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+    for (int f = 0; f < 4; ++f) {
+      const double dr[3] = {bufB[(4 * f + 1) * Q3 + ql], bufB[(4 * f + 2) * Q3 + ql], bufB[(4 * f + 3) * Q3 + ql]};
+      ref_to_phys<GEO>(dr, ih, gA, f < 3 ? W + 3 * f : gw);
+    }
     wphi = bufB[12 * Q3 + ql];
-#pragma unroll
-    for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
     __syncthreads();
   }
   const double kfg = a.fr.kf * mp.Gc;
@@ -380,14 +387,14 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   // point coefficients into Qi[f][c][q] (bufB is free: every thread has read its values)
   if (pt) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      bufB[(4 * f) * Q3 + ql] = 0.0;
+    for (int f = 0; f < 4; ++f) {
+      double b[3];
+      phys_to_ref<GEO>(f < 3 ? Fu + 3 * f : f1, ih, gA, b);
+      if (f < 3) bufB[(4 * f) * Q3 + ql] = 0.0;
 #pragma unroll
-      for (int J = 0; J < 3; ++J) bufB[(4 * f + 1 + J) * Q3 + ql] = Fu[3 * f + J] * ih[J];
+      for (int K = 0; K < 3; ++K) bufB[(4 * f + 1 + K) * Q3 + ql] = b[K];
     }
     bufB[12 * Q3 + ql] = f0;
-#pragma unroll
-    for (int J = 0; J < 3; ++J) bufB[(13 + J) * Q3 + ql] = f1[J] * ih[J];
   }
   __syncthreads();
   sf5_bwd<double, DevTables, P, Q, 4>(bufB, bufA, tabs);

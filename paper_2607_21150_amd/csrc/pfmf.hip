@@ -251,7 +251,6 @@ inline bool use_brick_buffer(const pf_ctx* c) {
 
 template <int MODE, int P, bool VOCE, bool MB, bool GEO>
 pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
-  static_assert(!GEO || P == 4, "mapped elements on Q3 only");
   const bool bb = use_brick_buffer(c);
   if (bb) {
     constexpr int NB = 2 * P - 1;
@@ -264,7 +263,7 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     if constexpr (P == 4)
       hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = c->ny1 * c->nz1;
     hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -279,7 +278,7 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     if constexpr (P == 4)
       hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, MB>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -287,14 +286,13 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 // kernels without the Voce iteration unless a phase uses it; with extra branches
 // attached, the branch variant (which carries the Voce iteration for any branch); with
-// mapped elements (Q3, no extra branch: pf_set_geometry checks both) the geometry variant
+// mapped elements (no extra branch: pf_set_geometry and pf_set_branches check it) the
+// geometry variant
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if constexpr (P == 4) {
-    if (c->d_qd)
-      return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, true>(c, a, s)
-                         : launch_op64_mfma_v<MODE, P, false, false, true>(c, a, s);
-  }
+  if (c->d_qd)
+    return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, true>(c, a, s)
+                       : launch_op64_mfma_v<MODE, P, false, false, true>(c, a, s);
   if (c->n_extra > 0)
     return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true, false>(c, a, s)
                                      : launch_op64_mfma_v<MODE, P, false, true, false>(c, a, s);
@@ -302,12 +300,12 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
                      : launch_op64_mfma_v<MODE, P, false, false, false>(c, a, s);
 }
 
-template <int MODE, bool VOCE, bool MB>
+template <int MODE, bool VOCE, bool MB, bool GEO>
 pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;
-    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB, GEO>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -315,10 +313,14 @@ pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE>
 pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if (c->d_qd)
+    return c->has_voce ? launch_op64_q4_v<MODE, true, false, true>(c, a, s)
+                       : launch_op64_q4_v<MODE, false, false, true>(c, a, s);
   if (c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true>(c, a, s)
-                                     : launch_op64_q4_v<MODE, false, true>(c, a, s);
-  return c->has_voce ? launch_op64_q4_v<MODE, true, false>(c, a, s) : launch_op64_q4_v<MODE, false, false>(c, a, s);
+    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true, false>(c, a, s)
+                                     : launch_op64_q4_v<MODE, false, true, false>(c, a, s);
+  return c->has_voce ? launch_op64_q4_v<MODE, true, false, false>(c, a, s)
+                     : launch_op64_q4_v<MODE, false, false, false>(c, a, s);
 }
 
 template <int MODE>
@@ -617,7 +619,8 @@ pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (X && c->mesh.p != 3) return fail(PF_EUNSUPPORTED, "mapped elements are built for p = 3 (p=%d)", c->mesh.p);
+  if (X && (c->mesh.p < 2 || c->mesh.p > 4))
+    return fail(PF_EUNSUPPORTED, "mapped elements are built for p = 2..4 (p=%d)", c->mesh.p);
   if (X && c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
   HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old record
   (void)hipFree(c->d_qd);
@@ -635,8 +638,17 @@ pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
   int bad = 0;
   hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_geometry<4, 4>), dim3((unsigned)((c->n_q + NT - 1) / NT)), dim3(NT), 0, s, X, c->n_nodes,
-                       c->nx1, c->ny1, c->mesh.nx, c->mesh.ny, c->n_q, (const DevTables*)c->d_tab, qd, flag);
+    const dim3 grid((unsigned)((c->n_q + NT - 1) / NT));
+    const DevTables* tab = c->d_tab;
+    if (c->mesh.p == 2)
+      hipLaunchKernelGGL((k_geometry<3, 3>), grid, dim3(NT), 0, s, X, c->n_nodes, c->nx1, c->ny1, c->mesh.nx,
+                         c->mesh.ny, c->n_q, tab, qd, flag);
+    else if (c->mesh.p == 3)
+      hipLaunchKernelGGL((k_geometry<4, 4>), grid, dim3(NT), 0, s, X, c->n_nodes, c->nx1, c->ny1, c->mesh.nx,
+                         c->mesh.ny, c->n_q, tab, qd, flag);
+    else
+      hipLaunchKernelGGL((k_geometry<5, 5>), grid, dim3(NT), 0, s, X, c->n_nodes, c->nx1, c->ny1, c->mesh.nx,
+                         c->mesh.ny, c->n_q, tab, qd, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s);
