@@ -14,6 +14,7 @@
 #include "pf_brick.hpp"
 #include "pf_ops.hpp"
 #include "pf_qf.hpp"
+#include "pf_geom.hpp"
 
 namespace pfmf {
 
@@ -123,11 +124,13 @@ struct LinArgs {
   const double* xstate;
   int n_extra;
   double* xstate_out;    // MODE 3: the extra branches' committed states
+  const double* qd;      // GEO: mapped elements' geometry record [10][n_q] (J^-1, w det J)
 };
 
 // MODE 0: record; MODE 2: record with the extra branches' layers; MODE 1: state commit;
-// MODE 3: state commit with the extra branches.
-template <int P, int Q, int MODE>
+// MODE 3: state commit with the extra branches. GEO: mapped elements (gradients through
+// each point's J^-1 from a.qd).
+template <int P, int Q, int MODE, bool GEO = false>
 __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTables* __restrict__ tabs) {
   using S = OpShape<P, Q>;
   constexpr int NB3 = S::NB3, Q3 = S::Q3, ER = S::ER;
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
         fwd_z<double, P, Q>(ybb, ydb, ybd, el, qx, qy, qz, tb, f < 3, v, d);
         if (f < 3) {
 #pragma unroll
-          for (int J = 0; J < 3; ++J) G[3 * f + J] = d[J] * ih[J];
+          for (int J = 0; J < 3; ++J) G[3 * f + J] = GEO ? d[J] : d[J] * ih[J];  // GEO: mapped below
         } else {
           phi = v;
         }
@@ -178,6 +181,16 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
     if (active) {
       const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
       const int64_t gq = e * Q3 + ql;
+      if (GEO) {
+        double gA[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const double dr[3] = {G[3 * f], G[3 * f + 1], G[3 * f + 2]};
+          ref_to_phys<true>(dr, ih, gA, G + 3 * f);
+        }
+      }
       double st[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];

@@ -377,20 +377,20 @@ pf_status level_op(pf_ctx* c, int level, const float* dz, float* out, hipStream_
   return mask_level(c, level, out, s);
 }
 
-template <int P, int MODE>
+template <int P, int MODE, bool GEO = false>
 pf_status launch_linearize(pf_ctx* c, const LinArgs& a, hipStream_t s) {
   using S = OpShape<P, P>;
   const size_t lds = (4 * S::NB3 + S::TMP + S::TAB) * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_linearize<P, P, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    HIPCHK(hipFuncSetAttribute((const void*)k_linearize<P, P, MODE, GEO>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds));
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_linearize<P, P, MODE>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
+    hipLaunchKernelGGL((k_linearize<P, P, MODE, GEO>), dim3(nb), dim3(NT), lds, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -553,6 +553,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
   a.xstate_out = nullptr;
+  a.qd = nullptr;  // the linearisation is built for the box (pf_linearize refuses mapped elements)
   const bool mb = c->n_extra > 0;
   switch (c->mesh.p) {
     case 1: st = launch_linearize<2, 0>(c, a, s); break;
@@ -642,7 +643,16 @@ pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xs
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
   a.xstate_out = xstate_out;
+  a.qd = c->d_qd;
   const bool mb = c->n_extra > 0;
+  if (c->d_qd) {  // mapped elements (orders 2-4, no extra branch: pf_set_geometry checks both)
+    switch (c->mesh.p) {
+      case 2: return launch_linearize<3, 1, true>(c, a, s);
+      case 3: return launch_linearize<4, 1, true>(c, a, s);
+      case 4: return launch_linearize<5, 1, true>(c, a, s);
+      default: return fail(PF_EUNSUPPORTED, "order not built");
+    }
+  }
   switch (c->mesh.p) {
     case 1: return launch_linearize<2, 1>(c, a, s);
     case 2: return mb ? launch_linearize<3, 3>(c, a, s) : launch_linearize<3, 1>(c, a, s);
@@ -657,7 +667,6 @@ pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xs
 extern "C" {
 
 pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
-  if (c && c->d_qd) return fail(PF_EUNSUPPORTED, "the commit on mapped elements is not built");
   if (c && c->n_extra > 0)
     return fail(PF_EUNSUPPORTED, "extra branches attached: use pf_commit_state_branches");
   return commit_state(c, z, state_out, nullptr, stream);
