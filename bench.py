@@ -269,12 +269,13 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
 
 
 def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
-    """FP64 applies on mapped (curved) Q3 elements: the headline's plastic workload with its
-    node lattice moved by a smooth bump of 0.2 h, the per-point J^-1 and weight read from
-    the stored geometry record (80 B per point on top of the box's bytes). Median device
-    time of each apply (HIP events around every launch); with_box: the same applies on the
-    box mesh too, for the ratio (they launch the headline's kernels on other inputs, so a
-    profiled run leaves them out)."""
+    """Applies on mapped (curved) Q3 elements: the headline's plastic workload with its node
+    lattice moved by a smooth bump of 0.2 h, the per-point J^-1 and weight read from the
+    stored geometry record (80 B per point on top of the box's bytes): the FP64 residual,
+    Jacobian and adjoint, and the FP32 multigrid (linearisation, fine apply, stored FP64
+    apply, V-cycle). Median device time of each (HIP events around every launch); with_box:
+    the same on the box mesh too, for the ratio (they launch the headline's kernels on other
+    inputs, so a profiled run leaves them out)."""
     d = I.make_inputs(config, "plastic", geometry="curved")
     mesh = d["mesh"]
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64)
@@ -287,6 +288,15 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
     setup_ms = (time.perf_counter() - t0) * 1e3  # host wall time of the setup call (it synchronises)
     ops = {"residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
            "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp)}
+    # the FP32 multigrid on the same mesh: linearisation, fine apply, stored FP64 apply, V-cycle
+    t0 = time.perf_counter()
+    ctx.linearize(z)
+    lin_ms = (time.perf_counter() - t0) * 1e3  # host wall time (the call synchronises)
+    dz32 = dz.float()
+    y32, b32, x32, ys = torch.empty_like(dz32), torch.empty_like(dz32), torch.empty_like(dz32), torch.empty_like(z)
+    ctx.apply_jacobian_f32(0, dz32, b32)
+    ops.update({"fp32_apply": lambda: ctx.apply_jacobian_f32(0, dz32, y32),
+                "jacobian_stored": lambda: ctx.apply_jacobian_lin(dz, ys), "vcycle": lambda: ctx.pmg_vcycle(b32, x32)})
 
     def timed():
         for _ in range(warmup):
@@ -306,12 +316,16 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
         return {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
 
     ms = timed()
-    y_cur, g_cur = y.cpu().numpy(), g.cpu().numpy()
+    ms["linearize"] = lin_ms
+    y_cur, g_cur, y32_cur = y.cpu().numpy(), g.cpu().numpy(), y32.double().cpu().numpy()
     ms_box = None
     if with_box:
         ctx.set_geometry(None)
+        ctx.linearize(z)
         ms_box = timed()
-    alg = {k: alg_bytes(mesh, k) + 80 * mesh.n_q for k in ops}
+    # algorithmic bytes: the box's plus the geometry record (80 B per point) for the applies
+    # that read it (the V-cycle is timed only)
+    alg = {k: alg_bytes(mesh, k) + 80 * mesh.n_q for k in ops if k != "vcycle"}
     errs = {}
     try:
         from oracle import pyoracle
@@ -320,14 +334,16 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
         rng = np.random.default_rng(0)
         errs["jacobian"] = sampled_rel_err(orc, mesh, y_cur, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
         errs["adjoint"] = sampled_rel_err(orc, mesh, g_cur, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
+        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32_cur, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
     except Exception as exc:
         errs["error"] = str(exc)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3 curved (bump 0.2 h), {mesh.n_dof} DoFs, plastic matrix",
             "ms_median": ms, "setup_ms": setup_ms,
-            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ms},
+            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in alg},
             "alg_bytes_per_apply": alg,
             "gbs_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in alg},
-            **({"ms_median_box": ms_box, "curved_over_box_time": {k: ms[k] / ms_box[k] for k in ms}}
+            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
+            **({"ms_median_box": ms_box, "curved_over_box_time": {k: ms[k] / ms_box[k] for k in ms_box}}
                if ms_box else {}),
             "rel_err_vs_oracle_sampled": errs}
 

@@ -154,9 +154,10 @@ pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, c
  * det J, 80 bytes per point, owned by the context) from which the FP64 residual, Jacobian
  * and adjoint take their gradients and weights; X itself is not kept. X = NULL returns to
  * the box. Orders 2-4. The call invalidates the linearisation and synchronises the
- * stream. The state commit (pf_commit_state) follows the geometry too. With a geometry
- * attached pf_linearize and pf_newton_step return PF_EUNSUPPORTED (the FP32 multigrid
- * is built for the box).
+ * stream. Everything else follows the geometry too: the state commit, the linearisation
+ * (records, FP32 levels evaluated at the fine points with the fine J^-1, their Jacobi
+ * diagonals, the order-1 element matrices), pf_apply_jacobian_lin, the V-cycle and
+ * pf_newton_step.
  * Errors: PF_EINVAL when some point has det J <= 0 (the geometry stays detached),
  * PF_EUNSUPPORTED at p = 1 or with extra branches attached, PF_ENOMEM, PF_EHIP. */
 pf_status pf_set_geometry(pf_ctx* ctx, const double* X, void* stream);

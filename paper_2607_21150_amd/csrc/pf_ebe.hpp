@@ -29,12 +29,14 @@ struct EbeArgs {
   float* K;             // [n_elem][32][32]
   const MatParams<float>* xmats;  // extra branches [nph][n_extra] (record layers 1..n_extra)
   int n_extra;
+  const double* qd;     // GEO: mapped elements' geometry record [10][n_q] (J^-1, w det J)
 };
 
 // One workgroup per element. The threads evaluate the tangent of the points on the
 // 10 unit directions (dG_ij, dphi) into LDS; the element matrix is then the
 // point sum of (test basis) x tangent x (trial basis), contracted in two steps.
-template <int PF, bool MB>
+// GEO: mapped elements (gradients and weights from the points' geometry record).
+template <int PF, bool MB, bool GEO = false>
 __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __restrict__ tabs) {
   constexpr int Q = PF, Q3 = Q * Q * Q, P3 = PF * PF * PF;
   __shared__ float ub[3 * P3];      // fine u of the element
@@ -78,9 +80,10 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     for (int n = 0; n < P3; ++n) {
       const int ax = n % PF, ay = (n / PF) % PF, az = n / (PF * PF);
       const float bx = Bf[qx * PF + ax], by = Bf[qy * PF + ay], bz = Bf[qz * PF + az];
-      const float gx = Df[qx * PF + ax] * by * bz * ih[0];
-      const float gy = bx * Df[qy * PF + ay] * bz * ih[1];
-      const float gz = bx * by * Df[qz * PF + az] * ih[2];
+      // GEO: reference derivatives here, mapped below
+      const float gx = Df[qx * PF + ax] * by * bz * (GEO ? 1.f : ih[0]);
+      const float gy = bx * Df[qy * PF + ay] * bz * (GEO ? 1.f : ih[1]);
+      const float gz = bx * by * Df[qz * PF + az] * (GEO ? 1.f : ih[2]);
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
         const float u = ub[f * P3 + n];
@@ -90,6 +93,13 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
       }
     }
     const int64_t gq = e * Q3 + q;
+    if (GEO) {
+      double gA[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+#pragma unroll
+      for (int f = 0; f < 3; ++f) map_grad<float>(G[3 * f], G[3 * f + 1], G[3 * f + 2], gA, G + 3 * f);
+    }
     LinRecord rc;
 #pragma unroll
     for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
       for (int o = 0; o < 9; ++o) Cq[q][o * 10 + in] = dP[o];
       Cq[q][90 + in] = dL;
     }
-    if (grp == 0) Cq[q][100] = wq[qx] * wq[qy] * wq[qz] * jdet;
+    if (grp == 0) Cq[q][100] = GEO ? (float)a.qd[9 * a.n_q + gq] : wq[qx] * wq[qy] * wq[qz] * jdet;
   }
   // order-1 basis at the points (values and physical gradients) and the fracture
   // gradient coefficient of each point's phase
@@ -118,9 +128,21 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     const int bx = nb & 1, by = (nb >> 1) & 1, bz = nb >> 2;
     const float vx = B1[qx * 2 + bx], vy = B1[qy * 2 + by], vz = B1[qz * 2 + bz];
     Nq[q][nb] = vx * vy * vz;
-    Gq[q][nb][0] = D1[qx * 2 + bx] * vy * vz * ih[0];
-    Gq[q][nb][1] = vx * D1[qy * 2 + by] * vz * ih[1];
-    Gq[q][nb][2] = vx * vy * D1[qz * 2 + bz] * ih[2];
+    if (GEO) {
+      const int64_t gq = e * Q3 + q;
+      double gA[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+      float gr[3];
+      map_grad<float>(D1[qx * 2 + bx] * vy * vz, vx * D1[qy * 2 + by] * vz, vx * vy * D1[qz * 2 + bz], gA, gr);
+      Gq[q][nb][0] = gr[0];
+      Gq[q][nb][1] = gr[1];
+      Gq[q][nb][2] = gr[2];
+    } else {
+      Gq[q][nb][0] = D1[qx * 2 + bx] * vy * vz * ih[0];
+      Gq[q][nb][1] = vx * D1[qy * 2 + by] * vz * ih[1];
+      Gq[q][nb][2] = vx * vy * D1[qz * 2 + bz] * ih[2];
+    }
   }
   for (int q = t; q < Q3; q += NT) {
     const int pid = a.phase[e * Q3 + q];

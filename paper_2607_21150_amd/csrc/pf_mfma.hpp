@@ -798,7 +798,7 @@ namespace pfmf {
 // nodes PC <= 3, 3 Gauss points): the packing of k_op64_q2 (sum factorisation per
 // element on the padded 4 x 4 layout, the pointwise JVP once for both elements of the
 // wave on lanes 0-26 and 32-58) with the FP32 record path of k_a32_q3.
-template <typename V, int PC, bool BB, bool MB>
+template <typename V, int PC, bool BB, bool MB, bool GEO = false>
 __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
   __shared__ V ev[8 * 4 * 64];
   const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
   const bool pvalid = pqx < 3 && pqy < 3 && pqz < 3;
   const int pq = pqx + 3 * pqy + 9 * pqz;
   const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
-  const V wdet = (V)(tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz < 3 ? cqz : 0] *
+  const V wbox = (V)(tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz < 3 ? cqz : 0] *
                              a.m.jdet);
   if (hasA) {
     V G[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
 #pragma unroll
           for (int J = 0; J < 3; ++J) {
             const double r = lane_read(d[f][J], src_fwd);
-            if (mine) G[3 * f + J] = (V)r * ih[J];
+            if (mine) G[3 * f + J] = GEO ? (V)r : (V)r * ih[J];  // GEO: reference derivatives, mapped below
           }
       }
       {
@@ -854,20 +854,34 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
 #pragma unroll
           for (int J = 0; J < 3; ++J) {
             const double r = lane_read(d[f][J], src_fwd);
-            if (mine) W[3 * f + J] = (V)r * ih[J];
+            if (mine) W[3 * f + J] = GEO ? (V)r : (V)r * ih[J];
           }
         const double rp = lane_read(v[3], src_fwd);
         if (mine) wphi = (V)rp;
 #pragma unroll
         for (int J = 0; J < 3; ++J) {
           const double r = lane_read(d[3][J], src_fwd);
-          if (mine) gw[J] = (V)r * ih[J];
+          if (mine) gw[J] = GEO ? (V)r : (V)r * ih[J];
         }
       }
     }
     // pointwise JVP from the record (packed layout)
     const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
     const int64_t gq = e * 27 + q;
+    // mapped elements: the point's J^-1 and weight; gradients to physical coordinates
+    double gA[GEO ? 9 : 1];
+    V wdet = wbox;
+    if (GEO) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = valid ? a.qd[k * a.n_q + gq] : 0.0;
+      wdet = valid ? (V)a.qd[9 * a.n_q + gq] : V(0);
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        map_grad<V>((double)G[3 * f], (double)G[3 * f + 1], (double)G[3 * f + 2], gA, G + 3 * f);
+        map_grad<V>((double)W[3 * f], (double)W[3 * f + 1], (double)W[3 * f + 2], gA, W + 3 * f);
+      }
+      map_grad<V>((double)gw[0], (double)gw[1], (double)gw[2], gA, gw);
+    }
     LinRecordT<V> rc;
 #pragma unroll
     for (int k = 0; k < REC_N; ++k) rc.v[k] = valid ? a.rec.rec[k * a.n_q + gq] : V(0);
@@ -881,12 +895,22 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
     lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, valid, G, W, wphi, Fu, dL);
     const V kfg = a.fr.kf * mp.Gc;
     double b1p[4][3], b0p3;
+    if (GEO) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+      for (int f = 0; f < 4; ++f) {
+        double fl[3];
 #pragma unroll
-      for (int J = 0; J < 3; ++J) b1p[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+        for (int J = 0; J < 3; ++J) fl[J] = f < 3 ? (double)(wdet * Fu[3 * f + J]) : (double)(wdet * kfg * gw[J]);
+        phys_to_ref<true>(fl, nullptr, gA, b1p[f]);
+      }
+    } else {
 #pragma unroll
-    for (int J = 0; J < 3; ++J) b1p[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
+      for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) b1p[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1p[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
+    }
     b0p3 = (double)(wdet * a.fr.s_phi * dL);
     // back to each element's padded layout, transposed interpolation
 #pragma unroll
@@ -923,7 +947,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2(LinApplyArgs<V> a, int colour,
 // FP32 linearised level apply on a Q3 fine mesh (fine kinematics on P = 4 nodes,
 // level nodes PC <= 4, 4 Gauss points): FP32 storage and pointwise arithmetic,
 // contractions on the FP64 matrix cores (at the FP32 vector rate on this chip).
-template <typename V, int PC, bool BB, bool MB>
+template <typename V, int PC, bool BB, bool MB, bool GEO = false>
 __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour, DevTables* __restrict__ tabs) {
   __shared__ V ev[8 * 4 * 64];
   // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
@@ -936,7 +960,7 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour,
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
   const int ql = qx + 4 * qy + 16 * qz;
   const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
-  const V wdet = (V)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet);
+  const V wbox = (V)(tabs->w[4][qx] * tabs->w[4][qy] * tabs->w[4][qz] * a.m.jdet);
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
     const int slot = wv + 4 * half;
@@ -956,25 +980,44 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour,
     for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
     rc.flags = a.rec.flags[gq];
     const int pid = a.phase[gq];
+    // mapped elements: the point's J^-1 and weight
+    double gA[GEO ? 9 : 1];
+    V wdet = wbox;
+    if (GEO) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+      wdet = (V)a.qd[9 * a.n_q + gq];
+    }
     V G[9], W[9], wphi, gw[3];
     {
       double v[3], d[3][3];
       sf4_fwd_n<3>(zu, bf, 0x0u, 0x7u, v, d);
 #pragma unroll
-      for (int f = 0; f < 3; ++f)
+      for (int f = 0; f < 3; ++f) {
+        if (GEO)
+          map_grad<V>(d[f][0], d[f][1], d[f][2], gA, G + 3 * f);
+        else
 #pragma unroll
-        for (int J = 0; J < 3; ++J) G[3 * f + J] = (V)d[f][J] * ih[J];
+          for (int J = 0; J < 3; ++J) G[3 * f + J] = (V)d[f][J] * ih[J];
+      }
     }
     {
       double v[4], d[4][3];
       sf4_fwd_n<4>(wu, bc, 0x8u, 0xFu, v, d);
 #pragma unroll
-      for (int f = 0; f < 3; ++f)
+      for (int f = 0; f < 3; ++f) {
+        if (GEO)
+          map_grad<V>(d[f][0], d[f][1], d[f][2], gA, W + 3 * f);
+        else
 #pragma unroll
-        for (int J = 0; J < 3; ++J) W[3 * f + J] = (V)d[f][J] * ih[J];
+          for (int J = 0; J < 3; ++J) W[3 * f + J] = (V)d[f][J] * ih[J];
+      }
       wphi = (V)v[3];
+      if (GEO)
+        map_grad<V>(d[3][0], d[3][1], d[3][2], gA, gw);
+      else
 #pragma unroll
-      for (int J = 0; J < 3; ++J) gw[J] = (V)d[3][J] * ih[J];
+        for (int J = 0; J < 3; ++J) gw[J] = (V)d[3][J] * ih[J];
     }
     const int pidc = pid < a.nph ? pid : 0;
     const MatParams<V> mp = a.mats[pidc];
@@ -984,15 +1027,26 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q3(LinApplyArgs<V> a, int colour,
     lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, true, G, W, wphi, Fu, dL);
     const V kfg = a.fr.kf * mp.Gc;
     double b0[4], b1[4][3], r[4];
+    if (GEO) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      b0[f] = 0.0;
+      for (int f = 0; f < 4; ++f) {
+        double fl[3];
 #pragma unroll
-      for (int J = 0; J < 3; ++J) b1[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+        for (int J = 0; J < 3; ++J) fl[J] = f < 3 ? (double)(wdet * Fu[3 * f + J]) : (double)(wdet * kfg * gw[J]);
+        phys_to_ref<true>(fl, nullptr, gA, b1[f]);
+        b0[f] = 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        b0[f] = 0.0;
+#pragma unroll
+        for (int J = 0; J < 3; ++J) b1[f][J] = (double)(wdet * Fu[3 * f + J] * ih[J]);
+      }
+#pragma unroll
+      for (int J = 0; J < 3; ++J) b1[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
     }
     b0[3] = (double)(wdet * a.fr.s_phi * dL);
-#pragma unroll
-    for (int J = 0; J < 3; ++J) b1[3][J] = (double)(wdet * kfg * gw[J] * ih[J]);
     sf4_bwd_n<4>(b0, b1, 0x8u, bc, r);
 #pragma unroll
     for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = (V)r[f];

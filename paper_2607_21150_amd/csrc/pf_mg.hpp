@@ -318,7 +318,16 @@ template <typename V> struct LinApplyArgs {
   V* ebuf;               // brick-buffer scatter (extended node grid)
   const MatParams<V>* xmats;  // extra branches [nph][n_extra] (record layers 1..n_extra)
   int n_extra;
+  const double* qd;      // GEO: mapped elements' geometry record [10][n_q] (J^-1, w det J)
 };
+
+// Mapped elements in the record applies: reference derivatives (FP64) to a physical
+// gradient in the working precision through the point's J^-1 (FP64).
+template <typename V>
+__device__ inline void map_grad(double d0, double d1, double d2, const double* A, V* out) {
+#pragma unroll
+  for (int J = 0; J < 3; ++J) out[J] = (V)(d0 * A[J] + d1 * A[3 + J] + d2 * A[6 + J]);
+}
 
 // Record-based tangent of one point: the block's layer, plus (n_extra > 0) the extra
 // branches' layers, their dP and dpsi^+ summed and the switch applied to the total.
@@ -365,7 +374,7 @@ template <int PF, int PC, int Q> struct A32Shape {
   static constexpr int ROUNDS = (8 + ER - 1) / ER;
   static constexpr int FWD = 2 * ER * PM * PM * Q + 3 * ER * PM * Q * Q;
   static constexpr int BWD = 4 * ER * Q3 + 3 * ER * PM * Q * Q + 2 * ER * PM * PM * Q;
-  static constexpr int DIAG = 22 * ER * Q3;
+  static constexpr int DIAG = 25 * ER * Q3;  // 22 coefficients on the box, 25 on mapped elements
   static constexpr int TMP0 = FWD > BWD ? FWD : BWD;
   static constexpr int TMP = TMP0 > DIAG ? TMP0 : DIAG;
   static constexpr int EV = 8 * 4 * PC3;
@@ -374,7 +383,8 @@ template <int PF, int PC, int Q> struct A32Shape {
   static constexpr size_t lds_bytes = lds_floats * sizeof(float);
 };
 
-template <int MODE, int PF, int PC, int Q, bool MB>
+// GEO: mapped elements (gradients and weights from the point's geometry record).
+template <int MODE, int PF, int PC, int Q, bool MB, bool GEO = false>
 __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTablesF* __restrict__ tabs) {
   using S = A32Shape<PF, PC, Q>;
   constexpr int NBF3 = S::NBF3, NBC3 = S::NBC3, PC3 = S::PC3, Q3 = S::Q3, ER = S::ER, PM = S::PM;
@@ -422,6 +432,16 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
     const int slot0 = r * ER, slot = slot0 + el;
     const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
     const bool active = (t < ER * Q3) && (slot < 8) && sx < g.nex && sy < g.ney && sz < g.nez;
+    // mapped elements: the point's J^-1 (FP64) and weight
+    double gA[GEO ? 9 : 1];
+    float wgeo = 0.f;
+    if (GEO) {
+      const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+      const int64_t gq = e * Q3 + ql;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = active ? a.qd[k * a.n_q + gq] : 0.0;
+      wgeo = active ? (float)a.qd[9 * a.n_q + gq] : 0.f;
+    }
     float G[9], W[9], wphi = 0.f, gw[3] = {0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int f = 0; f < 3; ++f) {
@@ -429,8 +449,11 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
       if (t < ER * Q3) {
         float v, d[3];
         fwd_z<float, PF, Q>(ybb, ydb, ybd, el, qx, qy, qz, tf, true, v, d);
+        if (GEO)
+          map_grad<float>(d[0], d[1], d[2], gA, G + 3 * f);
+        else
 #pragma unroll
-        for (int J = 0; J < 3; ++J) G[3 * f + J] = d[J] * ih[J];
+          for (int J = 0; J < 3; ++J) G[3 * f + J] = d[J] * ih[J];
       }
       __syncthreads();
     }
@@ -441,13 +464,19 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
         if (t < ER * Q3) {
           float v, d[3];
           fwd_z<float, PC, Q>(ybb, ydb, ybd, el, qx, qy, qz, tc, true, v, d);
+          float m[3];
+          if (GEO)
+            map_grad<float>(d[0], d[1], d[2], gA, m);
+          else
+#pragma unroll
+            for (int J = 0; J < 3; ++J) m[J] = d[J] * ih[J];
           if (f < 3) {
 #pragma unroll
-            for (int J = 0; J < 3; ++J) W[3 * f + J] = d[J] * ih[J];
+            for (int J = 0; J < 3; ++J) W[3 * f + J] = m[J];
           } else {
             wphi = v;
 #pragma unroll
-            for (int J = 0; J < 3; ++J) gw[J] = d[J] * ih[J];
+            for (int J = 0; J < 3; ++J) gw[J] = m[J];
           }
         }
         __syncthreads();
@@ -473,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
       gqa = gq;
       mp = a.mats[pidc];
       qp_state_lin<float>(mp, G, rc, s);
-      wdet = wq[qx] * wq[qy] * wq[qz] * jdet;
+      wdet = GEO ? wgeo : wq[qx] * wq[qy] * wq[qz] * jdet;
       if (MODE == 0) {
         float dL;
         lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, true, G, W, wphi, Fu, dL);
@@ -489,17 +518,20 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
 #pragma unroll 1
       for (int f = 0; f < 4; ++f) {
         if (t < ER * Q3) {
+          float fl[3];
           if (f < 3) {
             q0[t] = 0.f;
-            q0[ER * Q3 + t] = Fu[3 * f + 0] * ih[0];
-            q0[2 * ER * Q3 + t] = Fu[3 * f + 1] * ih[1];
-            q0[3 * ER * Q3 + t] = Fu[3 * f + 2] * ih[2];
+#pragma unroll
+            for (int J = 0; J < 3; ++J) fl[J] = Fu[3 * f + J];
           } else {
             q0[t] = f0;
-            q0[ER * Q3 + t] = f1[0] * ih[0];
-            q0[2 * ER * Q3 + t] = f1[1] * ih[1];
-            q0[3 * ER * Q3 + t] = f1[2] * ih[2];
+#pragma unroll
+            for (int J = 0; J < 3; ++J) fl[J] = f1[J];
           }
+#pragma unroll
+          for (int K = 0; K < 3; ++K)
+            q0[(1 + K) * ER * Q3 + t] =
+                GEO ? (float)(fl[0] * gA[3 * K] + fl[1] * gA[3 * K + 1] + fl[2] * gA[3 * K + 2]) : fl[K] * ih[K];
         }
         __syncthreads();
         bwd_field<float, PC, Q, ER>(q0, q0 + ER * Q3, q0 + 2 * ER * Q3, q0 + 3 * ER * Q3, f == 3, slot0, ER, tc,
@@ -508,11 +540,12 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
     } else {
       // diagonal: quadratic-form coefficients per point in reference coordinates,
       // then every (element, node) pair sums over the points with the 1-D tables
-      float* cf = tmp;  // [22][ER*Q3]
+      constexpr int NCF = GEO ? 25 : 22;
+      float* cf = tmp;  // [NCF][ER*Q3]
       if (t < ER * Q3) {
-        float c22[22];
+        float c22[NCF];
 #pragma unroll
-        for (int k = 0; k < 22; ++k) c22[k] = 0.f;
+        for (int k = 0; k < NCF; ++k) c22[k] = 0.f;
         if (active) {
 #pragma unroll 1
           for (int i = 0; i < 3; ++i) {
@@ -527,13 +560,30 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
 #pragma unroll
               for (int J = 0; J < 3; ++J) C[J][K] = dP[3 * i + J];
             }
+            // in reference coordinates, Ch = A C A^T (A = J^-1; the box: A = diag(ih));
             // xx, yy, zz, xy, xz, yz
-            c22[6 * i + 0] = wdet * ih[0] * ih[0] * C[0][0];
-            c22[6 * i + 1] = wdet * ih[1] * ih[1] * C[1][1];
-            c22[6 * i + 2] = wdet * ih[2] * ih[2] * C[2][2];
-            c22[6 * i + 3] = wdet * ih[0] * ih[1] * (C[0][1] + C[1][0]);
-            c22[6 * i + 4] = wdet * ih[0] * ih[2] * (C[0][2] + C[2][0]);
-            c22[6 * i + 5] = wdet * ih[1] * ih[2] * (C[1][2] + C[2][1]);
+            float Ch[3][3];
+#pragma unroll
+            for (int K = 0; K < 3; ++K)
+#pragma unroll
+              for (int L = 0; L < 3; ++L) {
+                if (GEO) {
+                  double acc = 0.0;
+#pragma unroll
+                  for (int J = 0; J < 3; ++J)
+#pragma unroll
+                    for (int J2 = 0; J2 < 3; ++J2) acc += gA[3 * K + J] * (double)C[J][J2] * gA[3 * L + J2];
+                  Ch[K][L] = (float)acc;
+                } else {
+                  Ch[K][L] = ih[K] * ih[L] * C[K][L];
+                }
+              }
+            c22[6 * i + 0] = wdet * Ch[0][0];
+            c22[6 * i + 1] = wdet * Ch[1][1];
+            c22[6 * i + 2] = wdet * Ch[2][2];
+            c22[6 * i + 3] = wdet * (Ch[0][1] + Ch[1][0]);
+            c22[6 * i + 4] = wdet * (Ch[0][2] + Ch[2][0]);
+            c22[6 * i + 5] = wdet * (Ch[1][2] + Ch[2][1]);
           }
           float dG[9], dP[9], dL;
 #pragma unroll
@@ -541,12 +591,27 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
           lin_tangent<float, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gqa, true, G, dG, 1.f, dP, dL);
           c22[18] = wdet * a.fr.s_phi * dL;
           const float kfg = wdet * a.fr.kf * mp.Gc;
-          c22[19] = kfg * ih[0] * ih[0];
-          c22[20] = kfg * ih[1] * ih[1];
-          c22[21] = kfg * ih[2] * ih[2];
+          if (GEO) {
+            // kfg A A^T: diagonal in 19..21, xy, xz, yz (doubled) in 22..24
+            double M[3][3];
+#pragma unroll
+            for (int K = 0; K < 3; ++K)
+#pragma unroll
+              for (int L = 0; L < 3; ++L) M[K][L] = gA[3 * K] * gA[3 * L] + gA[3 * K + 1] * gA[3 * L + 1] + gA[3 * K + 2] * gA[3 * L + 2];
+            c22[19] = kfg * (float)M[0][0];
+            c22[20] = kfg * (float)M[1][1];
+            c22[21] = kfg * (float)M[2][2];
+            c22[NCF - 3] = kfg * (float)(2.0 * M[0][1]);
+            c22[NCF - 2] = kfg * (float)(2.0 * M[0][2]);
+            c22[NCF - 1] = kfg * (float)(2.0 * M[1][2]);
+          } else {
+            c22[19] = kfg * ih[0] * ih[0];
+            c22[20] = kfg * ih[1] * ih[1];
+            c22[21] = kfg * ih[2] * ih[2];
+          }
         }
 #pragma unroll
-        for (int k = 0; k < 22; ++k) cf[k * ER * Q3 + t] = c22[k];
+        for (int k = 0; k < NCF; ++k) cf[k * ER * Q3 + t] = c22[k];
       }
       __syncthreads();
       for (int o = t; o < ER * PC3; o += NT) {
@@ -568,6 +633,8 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
           }
           acc[3] += nn * nn * cq[18 * ER * Q3] + gx * gx * cq[19 * ER * Q3] + gy * gy * cq[20 * ER * Q3] +
                     gz * gz * cq[21 * ER * Q3];
+          if (GEO) acc[3] += gx * gy * cq[(NCF - 3) * ER * Q3] + gx * gz * cq[(NCF - 2) * ER * Q3] +
+                             gy * gz * cq[(NCF - 1) * ER * Q3];
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) ev[((slot0 + e2) * 4 + f) * PC3 + a2] = acc[f];

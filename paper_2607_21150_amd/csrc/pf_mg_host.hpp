@@ -164,31 +164,35 @@ A32Args a32_args(pf_ctx* c, int level, const float* dz, float* out) {
   a.ebuf = nullptr;
   a.xmats = c->d_xmatsf;
   a.n_extra = c->n_extra;
+  a.qd = c->d_qd;
   return a;
 }
 
-template <int MODE, int PF, int PC, bool MB>
+template <int MODE, int PF, int PC, bool MB, bool GEO>
 pf_status launch_level32_v(pf_ctx* c, const A32Args& a, hipStream_t s) {
   using S = A32Shape<PF, PC, PF>;
   static bool attr_set = false;
   if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_level32<MODE, PF, PC, PF, MB>,
+    HIPCHK(hipFuncSetAttribute((const void*)k_level32<MODE, PF, PC, PF, MB, GEO>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::lds_bytes));
     attr_set = true;
   }
   for (int col = 0; col < 8; ++col) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
-    hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF, MB>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
+    hipLaunchKernelGGL((k_level32<MODE, PF, PC, PF, MB, GEO>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tabf);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
 }
 
-// kernels with the extra branches' record layers only when branches are attached
+// kernels with the extra branches' record layers only when branches are attached, with
+// the geometry record only on mapped elements (never both: pf_set_geometry checks it)
 template <int MODE, int PF, int PC>
 pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
-  return a.n_extra > 0 ? launch_level32_v<MODE, PF, PC, true>(c, a, s) : launch_level32_v<MODE, PF, PC, false>(c, a, s);
+  if (a.qd) return launch_level32_v<MODE, PF, PC, false, true>(c, a, s);
+  return a.n_extra > 0 ? launch_level32_v<MODE, PF, PC, true, false>(c, a, s)
+                       : launch_level32_v<MODE, PF, PC, false, false>(c, a, s);
 }
 
 template <int MODE, int PF>
@@ -207,7 +211,7 @@ pf_status dispatch_pc(pf_ctx* c, int PC, const A32Args& a, hipStream_t s) {
 // (order-2 mesh, k_a32_q2); V = float for the FP32 levels, V = double for the apply
 // from the stored FP64 linearisation (fine level). The brick buffer of each precision
 // is sized for the fine level and shared by the coarser ones.
-template <typename V, int PF, int PC, bool MB>
+template <typename V, int PF, int PC, bool MB, bool GEO>
 pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
   if (use_brick_buffer(c)) {
     V** buf;
@@ -219,9 +223,9 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
     a.ebuf = *buf;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<V, PC, true, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, true, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<V, PC, true, MB>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, true, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
     hipLaunchKernelGGL((k_gather_bricks<V, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
@@ -233,9 +237,9 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
     const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
     if (nb == 0) continue;
     if constexpr (PF == 4)
-      hipLaunchKernelGGL((k_a32_q3<V, PC, false, MB>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q3<V, PC, false, MB, GEO>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     else
-      hipLaunchKernelGGL((k_a32_q2<V, PC, false, MB>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q2<V, PC, false, MB, GEO>), dim3(nb), dim3(NT), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -243,7 +247,9 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
 
 template <typename V, int PF, int PC>
 pf_status launch_lin_mfma(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
-  return a.n_extra > 0 ? launch_lin_mfma_v<V, PF, PC, true>(c, a, s) : launch_lin_mfma_v<V, PF, PC, false>(c, a, s);
+  if (a.qd) return launch_lin_mfma_v<V, PF, PC, false, true>(c, a, s);
+  return a.n_extra > 0 ? launch_lin_mfma_v<V, PF, PC, true, false>(c, a, s)
+                       : launch_lin_mfma_v<V, PF, PC, false, false>(c, a, s);
 }
 
 template <int PF, int PC>
@@ -251,15 +257,15 @@ pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
   return launch_lin_mfma<float, PF, PC>(c, a, s);
 }
 
-template <typename V, int PC, bool MB>
+template <typename V, int PC, bool MB, bool GEO>
 pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;
     if constexpr (sizeof(V) == 4)
-      hipLaunchKernelGGL((k_a32_q4<V, PC, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB, GEO>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tabf);
     else
-      hipLaunchKernelGGL((k_a32_q4<V, PC, MB>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB, GEO>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
     HIPCHK(hipGetLastError());
   }
   return PF_OK;
@@ -267,7 +273,8 @@ pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
 
 template <typename V, int PC>
 pf_status launch_lin_q4(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
-  return a.n_extra > 0 ? launch_lin_q4_v<V, PC, true>(c, a, s) : launch_lin_q4_v<V, PC, false>(c, a, s);
+  if (a.qd) return launch_lin_q4_v<V, PC, false, true>(c, a, s);
+  return a.n_extra > 0 ? launch_lin_q4_v<V, PC, true, false>(c, a, s) : launch_lin_q4_v<V, PC, false, false>(c, a, s);
 }
 
 template <int PC>
@@ -292,6 +299,7 @@ EbeArgs ebe_args(pf_ctx* c) {
   a.K = c->mg.ebe;
   a.xmats = c->d_xmatsf;
   a.n_extra = c->n_extra;
+  a.qd = c->d_qd;
   return a;
 }
 
@@ -299,7 +307,14 @@ pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
   const EbeArgs a = ebe_args(c);
   const int n_elem = c->mesh.nx * c->mesh.ny * c->mesh.nz;
   const bool mb = a.n_extra > 0;
-  switch (c->mg.lv[0].P * 2 + (mb ? 1 : 0)) {
+  if (a.qd) {  // mapped elements (no extra branch)
+    switch (c->mg.lv[0].P) {
+      case 3: hipLaunchKernelGGL((k_ebe_assemble<3, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 4: hipLaunchKernelGGL((k_ebe_assemble<4, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 5: hipLaunchKernelGGL((k_ebe_assemble<5, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      default: return fail(PF_EUNSUPPORTED, "order not built");
+    }
+  } else switch (c->mg.lv[0].P * 2 + (mb ? 1 : 0)) {
     case 4: hipLaunchKernelGGL((k_ebe_assemble<2, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
     case 5: hipLaunchKernelGGL((k_ebe_assemble<2, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
     case 6: hipLaunchKernelGGL((k_ebe_assemble<3, false>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
@@ -519,7 +534,6 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   if (st) return st;
   if (!z) return fail(PF_EINVAL, "null z");
   if (c->n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
-  if (c->d_qd) return fail(PF_EUNSUPPORTED, "the linearisation on mapped elements is not built");
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   if ((st = mg_alloc(c)) || (st = ensure_records(c))) return st;
@@ -553,9 +567,16 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
   a.xstate_out = nullptr;
-  a.qd = nullptr;  // the linearisation is built for the box (pf_linearize refuses mapped elements)
+  a.qd = c->d_qd;
   const bool mb = c->n_extra > 0;
-  switch (c->mesh.p) {
+  if (c->d_qd) {  // mapped elements (orders 2-4, no extra branch: pf_set_geometry checks both)
+    switch (c->mesh.p) {
+      case 2: st = launch_linearize<3, 0, true>(c, a, s); break;
+      case 3: st = launch_linearize<4, 0, true>(c, a, s); break;
+      case 4: st = launch_linearize<5, 0, true>(c, a, s); break;
+      default: st = fail(PF_EUNSUPPORTED, "order not built");
+    }
+  } else switch (c->mesh.p) {
     case 1: st = launch_linearize<2, 0>(c, a, s); break;
     case 2: st = mb ? launch_linearize<3, 2>(c, a, s) : launch_linearize<3, 0>(c, a, s); break;
     case 3: st = mb ? launch_linearize<4, 2>(c, a, s) : launch_linearize<4, 0>(c, a, s); break;
@@ -762,6 +783,7 @@ pf_status pf_apply_jacobian_lin(pf_ctx* c, const double* dz, double* y, void* st
   a.ebuf = nullptr;
   a.xmats = c->d_xmats64;
   a.n_extra = c->n_extra;
+  a.qd = c->d_qd;
   switch (c->mesh.p) {
     case 2: return launch_lin_mfma<double, 3, 3>(c, a, s);
     case 3: return launch_lin_mfma<double, 4, 4>(c, a, s);

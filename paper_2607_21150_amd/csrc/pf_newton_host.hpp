@@ -105,7 +105,6 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!z) return fail(PF_EINVAL, "null z");
-  if (c->d_qd) return fail(PF_EUNSUPPORTED, "the Newton step on mapped elements is not built");
   // 32 coarsest-level sweeps: cheap with the element-matrix coarse level, and they
   // cut the FGMRES iterations by 2.5x against 4 sweeps on the Q4 box
   pf_newton_opts opt{1e-8, 30, 300, 3, 32, {0, 0, 0}};

@@ -433,7 +433,7 @@ template <typename V> struct TablesOf;
 template <> struct TablesOf<float> { using type = DevTablesF; };
 template <> struct TablesOf<double> { using type = DevTables; };
 
-template <typename V, int PC, bool MB>
+template <typename V, int PC, bool MB, bool GEO = false>
 __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour,
                                                    const typename TablesOf<V>::type* __restrict__ tabs) {
   using Tab = typename TablesOf<V>::type;
@@ -455,27 +455,43 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
   rc.flags = pt ? a.rec.flags[gq] : 0;
   const int pid = pt ? a.phase[gq] : 0;
   const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
-  const V wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (V)a.m.jdet;
+  V wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (V)a.m.jdet;
+  // mapped elements: the point's J^-1 and weight
+  double gA[GEO ? 9 : 1];
+  if (GEO) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gA[k] = pt ? a.qd[k * a.n_q + gq] : 0.0;
+    wdet = pt ? (V)a.qd[9 * a.n_q + gq] : V(0);
+  }
   gather_elem<V, V, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, bufA);
   __syncthreads();
   sf5_fwd<V, Tab, PF, Q, 3>(bufA, bufB, tabs);
   V G[9];
 #pragma unroll
-  for (int f = 0; f < 3; ++f)
+  for (int f = 0; f < 3; ++f) {
+    if (GEO)
+      map_grad<V>((double)bufB[(4 * f + 1) * Q3 + ql], (double)bufB[(4 * f + 2) * Q3 + ql],
+                  (double)bufB[(4 * f + 3) * Q3 + ql], gA, G + 3 * f);
+    else
 #pragma unroll
-    for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+      for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  }
   __syncthreads();
   gather_elem<V, V, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
   __syncthreads();
   sf5_fwd<V, Tab, PC, Q, 4>(bufA, bufB, tabs);
   V W[9], wphi, gw[3];
 #pragma unroll
-  for (int f = 0; f < 3; ++f)
+  for (int f = 0; f < 4; ++f) {
+    V* out = f < 3 ? W + 3 * f : gw;
+    if (GEO)
+      map_grad<V>((double)bufB[(4 * f + 1) * Q3 + ql], (double)bufB[(4 * f + 2) * Q3 + ql],
+                  (double)bufB[(4 * f + 3) * Q3 + ql], gA, out);
+    else
 #pragma unroll
-    for (int J = 0; J < 3; ++J) W[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+      for (int J = 0; J < 3; ++J) out[J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  }
   wphi = bufB[12 * Q3 + ql];
-#pragma unroll
-  for (int J = 0; J < 3; ++J) gw[J] = bufB[(13 + J) * Q3 + ql] * ih[J];
   __syncthreads();
   const int pidc = pid < a.nph ? pid : 0;
   const MatParams<V> mp = a.mats[pidc];
@@ -484,7 +500,19 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
   V Fu[9], dL;
   lin_tangent<V, MB>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, pt, G, W, wphi, Fu, dL);
   const V kfg = a.fr.kf * mp.Gc;
-  if (pt) {
+  if (pt && GEO) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      double fl[3], b[3];
+#pragma unroll
+      for (int J = 0; J < 3; ++J) fl[J] = f < 3 ? (double)(wdet * Fu[3 * f + J]) : (double)(wdet * kfg * gw[J]);
+      phys_to_ref<true>(fl, nullptr, gA, b);
+      if (f < 3) bufB[(4 * f) * Q3 + ql] = V(0);
+#pragma unroll
+      for (int K = 0; K < 3; ++K) bufB[(4 * f + 1 + K) * Q3 + ql] = (V)b[K];
+    }
+    bufB[12 * Q3 + ql] = wdet * a.fr.s_phi * dL;
+  } else if (pt) {
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
       bufB[(4 * f) * Q3 + ql] = V(0);

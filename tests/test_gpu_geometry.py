@@ -117,10 +117,6 @@ def test_geometry_errors(pf):
         ctx.set_geometry(dev(bad))
     assert e.value.code == pf.PF_EINVAL
     ctx.set_geometry(dev(I.curved_nodes(d["mesh"])))
-    z = dev(d["z"])
-    with pytest.raises(pf.PfError) as e:
-        ctx.linearize(z)
-    assert e.value.code == pf.PF_EUNSUPPORTED
     # extra branches on mapped elements are not built (either order of attaching)
     dx = I.make_inputs("C1", "ex3", p=3, n=2)
     with pytest.raises(pf.PfError) as e:
