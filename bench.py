@@ -323,9 +323,9 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
         ctx.set_geometry(None)
         ctx.linearize(z)
         ms_box = timed()
-    # algorithmic bytes: the box's plus the geometry record (80 B per point) for the applies
-    # that read it (the V-cycle is timed only)
-    alg = {k: alg_bytes(mesh, k) + 80 * mesh.n_q for k in ops if k != "vcycle"}
+    # algorithmic bytes: the box's plus the geometry record (80 B per point in FP64, 40 B in
+    # the FP32 copy the FP32 levels read) for the applies that read it (the V-cycle is timed only)
+    alg = {k: alg_bytes(mesh, k) + (40 if k == "fp32_apply" else 80) * mesh.n_q for k in ops if k != "vcycle"}
     errs = {}
     try:
         from oracle import pyoracle

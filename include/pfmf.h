@@ -151,8 +151,9 @@ pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, c
 /* Mapped (curved) elements, the isoparametric map of Section 4: X is a device pointer to
  * double[3][n_nodes], the position of every node (rows x, y, z; node order as z). The call
  * computes, once, a per-point geometry record of 10 doubles (J^-1 and the weight times
- * det J, 80 bytes per point, owned by the context) from which the FP64 residual, Jacobian
- * and adjoint take their gradients and weights; X itself is not kept. X = NULL returns to
+ * det J, 80 bytes per point, owned by the context, plus an FP32 copy of 40 bytes per point
+ * for the FP32 levels) from which the applies take their gradients and weights; X itself
+ * is not kept. X = NULL returns to
  * the box. Orders 2-4. The call invalidates the linearisation and synchronises the
  * stream. Everything else follows the geometry too: the state commit, the linearisation
  * (records, FP32 levels evaluated at the fine points with the fine J^-1, their Jacobi

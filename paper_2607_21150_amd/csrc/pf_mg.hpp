@@ -318,7 +318,8 @@ template <typename V> struct LinApplyArgs {
   V* ebuf;               // brick-buffer scatter (extended node grid)
   const MatParams<V>* xmats;  // extra branches [nph][n_extra] (record layers 1..n_extra)
   int n_extra;
-  const double* qd;      // GEO: mapped elements' geometry record [10][n_q] (J^-1, w det J)
+  const V* qd;           // GEO: mapped elements' geometry record [10][n_q] (J^-1, w det J),
+                         // in the working precision
 };
 
 // Mapped elements in the record applies: reference derivatives (FP64) to a physical
@@ -759,6 +760,11 @@ __global__ void k_vec_axs(const float* __restrict__ a, float* __restrict__ b, fl
 }
 
 // FP64 -> FP32 mirror of the displacement rows of z
+__global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
 __global__ void k_mirror_u(const double* __restrict__ z, float* __restrict__ z32, int64_t n_nodes) {
   const int64_t n = 3 * n_nodes;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

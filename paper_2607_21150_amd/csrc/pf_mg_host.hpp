@@ -164,7 +164,7 @@ A32Args a32_args(pf_ctx* c, int level, const float* dz, float* out) {
   a.ebuf = nullptr;
   a.xmats = c->d_xmatsf;
   a.n_extra = c->n_extra;
-  a.qd = c->d_qd;
+  a.qd = c->d_qd32;
   return a;
 }
 

@@ -66,6 +66,7 @@ struct pf_ctx {
   const double* xstate = nullptr;
   // mapped elements (pf_set_geometry): per-point J^-1 and weights [10][n_q]
   double* d_qd = nullptr;
+  float* d_qd32 = nullptr;  // the same record in FP32 for the FP32 levels
   // device buffers
   DevTables* d_tab = nullptr;
   DevTablesF* d_tabf = nullptr;
@@ -624,7 +625,9 @@ pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
   if (X && c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
   HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old record
   (void)hipFree(c->d_qd);
+  (void)hipFree(c->d_qd32);
   c->d_qd = nullptr;
+  c->d_qd32 = nullptr;
   c->mg.linearized = false;  // a linearisation belongs to the geometry it was taken on
   c->mg.lin64_valid = false;
   if (!X) return PF_OK;
@@ -662,7 +665,22 @@ pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
     (void)hipFree(qd);
     return fail(PF_EINVAL, "node positions give an element with det J <= 0 at some quadrature point");
   }
+  float* qd32 = nullptr;
+  if (hipMalloc(&qd32, (size_t)GEO_N * c->n_q * sizeof(float)) != hipSuccess) {
+    (void)hipFree(qd);
+    return fail(PF_ENOMEM, "geometry record (FP32): allocation failed");
+  }
+  const int64_t nr = (int64_t)GEO_N * c->n_q;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<int64_t>((nr + NT - 1) / NT, 65536)), dim3(NT), 0, s, qd, qd32, nr);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(qd);
+    (void)hipFree(qd32);
+    return fail(PF_EHIP, "geometry setup: %s", hipGetErrorString(e));
+  }
   c->d_qd = qd;
+  c->d_qd32 = qd32;
   return PF_OK;
 }
 
@@ -685,6 +703,7 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_xmats64);
   (void)hipFree(c->d_xmatsf);
   (void)hipFree(c->d_qd);
+  (void)hipFree(c->d_qd32);
   delete c;
 }
 
