@@ -348,13 +348,15 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
             "rel_err_vs_oracle_sampled": errs}
 
 
-def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30):
+def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30,
+               geometry="box"):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
     (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1; Chebyshev(3); 32 sweeps on the order-1
-    level, assembled as a block stencil), FP64 Jacobian as the operator."""
+    level, assembled as a block stencil), FP64 Jacobian as the operator. geometry="curved":
+    the same on the curved mesh (planar boundary faces, so the same faces are constrained)."""
     t_gen = time.perf_counter()
-    d = I.make_inputs(config, variant)
+    d = I.make_inputs(config, variant, geometry=geometry)
     mesh = d["mesh"]
     print(f"[bench] newton inputs {config}/{variant}: {mesh.n_dof} DoFs, generated in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
@@ -400,6 +402,7 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
     print(f"[bench] newton step {rep} in {t_step:.2f} s", file=sys.stderr, flush=True)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}"
                       + (f", materials '{variant}'" if variant != "base" else "")
+                      + (", curved elements (bump 0.2 h)" if geometry != "box" else "")
                       + f", FGMRES({restart}), Chebyshev({cheb_degree}), {coarse_sweeps} coarse sweeps",
             "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
             "gram_schmidt_refinements": rep["refinements"],
@@ -430,6 +433,8 @@ def main():
                          "('' = none)")
     ap.add_argument("--geometry", default="C3",
                     help="workload on which the applies on curved (mapped) Q3 elements are timed ('' = none)")
+    ap.add_argument("--newton-curved-config", default="C5",
+                    help="workload of the Newton step on the curved mesh (with --newton; '' = none)")
     ap.add_argument("--geometry-box", action="store_true",
                     help="also time the geometry leg's applies on the box mesh (the curved / box ratio)")
     args = ap.parse_args()
@@ -623,6 +628,12 @@ def main():
             # the third example's matrix needs a stronger smoother than the defaults
             out["newton_branches"] = newton_leg(torch, I, pfmf, args.newton_branches_config, "ex3", cheb_degree=12,
                                                 coarse_sweeps=64, restart=60)
+        if args.newton_curved_config:
+            torch.cuda.empty_cache()
+            # the curved mesh, like the third example's matrix, needs a stronger smoother than the
+            # defaults (which stall near 2e-7 of the initial residual at C5)
+            out["newton_curved"] = newton_leg(torch, I, pfmf, args.newton_curved_config, geometry="curved",
+                                              cheb_degree=6, coarse_sweeps=64, restart=60)
     print(json.dumps(out), flush=True)
 
 
