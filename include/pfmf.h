@@ -141,7 +141,6 @@ pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n
  * branch (the block's layer holds the switch and dL/dphi of the total psi^+), which the
  * FP32 levels, the V-cycle, pf_apply_jacobian_lin and pf_newton_step sum over; the
  * record grows to (1 + n_extra) layers. The call invalidates the linearisation.
- * PF_EUNSUPPORTED with a mapped geometry attached (pf_set_geometry).
  * The state commit with branches is pf_commit_state_branches.
  * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
  * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
@@ -159,8 +158,9 @@ pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, c
  * (records, FP32 levels evaluated at the fine points with the fine J^-1, their Jacobi
  * diagonals, the order-1 element matrices), pf_apply_jacobian_lin, the V-cycle and
  * pf_newton_step.
+ * Extra branches in parallel (pf_set_branches) combine with it.
  * Errors: PF_EINVAL when some point has det J <= 0 (the geometry stays detached),
- * PF_EUNSUPPORTED at p = 1 or with extra branches attached, PF_ENOMEM, PF_EHIP. */
+ * PF_EUNSUPPORTED at p = 1, PF_ENOMEM, PF_EHIP. */
 pf_status pf_set_geometry(pf_ctx* ctx, const double* X, void* stream);
 
 /* Replace the per-phase parameters (Gc, sigma0, visc) from host memory

@@ -190,7 +190,9 @@ pf_status launch_level32_v(pf_ctx* c, const A32Args& a, hipStream_t s) {
 // the geometry record only on mapped elements (never both: pf_set_geometry checks it)
 template <int MODE, int PF, int PC>
 pf_status launch_level32(pf_ctx* c, const A32Args& a, hipStream_t s) {
-  if (a.qd) return launch_level32_v<MODE, PF, PC, false, true>(c, a, s);
+  if (a.qd)
+    return a.n_extra > 0 ? launch_level32_v<MODE, PF, PC, true, true>(c, a, s)
+                         : launch_level32_v<MODE, PF, PC, false, true>(c, a, s);
   return a.n_extra > 0 ? launch_level32_v<MODE, PF, PC, true, false>(c, a, s)
                        : launch_level32_v<MODE, PF, PC, false, false>(c, a, s);
 }
@@ -247,7 +249,9 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
 
 template <typename V, int PF, int PC>
 pf_status launch_lin_mfma(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
-  if (a.qd) return launch_lin_mfma_v<V, PF, PC, false, true>(c, a, s);
+  if (a.qd)
+    return a.n_extra > 0 ? launch_lin_mfma_v<V, PF, PC, true, true>(c, a, s)
+                         : launch_lin_mfma_v<V, PF, PC, false, true>(c, a, s);
   return a.n_extra > 0 ? launch_lin_mfma_v<V, PF, PC, true, false>(c, a, s)
                        : launch_lin_mfma_v<V, PF, PC, false, false>(c, a, s);
 }
@@ -273,7 +277,8 @@ pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
 
 template <typename V, int PC>
 pf_status launch_lin_q4(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
-  if (a.qd) return launch_lin_q4_v<V, PC, false, true>(c, a, s);
+  if (a.qd)
+    return a.n_extra > 0 ? launch_lin_q4_v<V, PC, true, true>(c, a, s) : launch_lin_q4_v<V, PC, false, true>(c, a, s);
   return a.n_extra > 0 ? launch_lin_q4_v<V, PC, true, false>(c, a, s) : launch_lin_q4_v<V, PC, false, false>(c, a, s);
 }
 
@@ -307,11 +312,14 @@ pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
   const EbeArgs a = ebe_args(c);
   const int n_elem = c->mesh.nx * c->mesh.ny * c->mesh.nz;
   const bool mb = a.n_extra > 0;
-  if (a.qd) {  // mapped elements (no extra branch)
-    switch (c->mg.lv[0].P) {
-      case 3: hipLaunchKernelGGL((k_ebe_assemble<3, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
-      case 4: hipLaunchKernelGGL((k_ebe_assemble<4, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
-      case 5: hipLaunchKernelGGL((k_ebe_assemble<5, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+  if (a.qd) {  // mapped elements
+    switch (c->mg.lv[0].P * 2 + (mb ? 1 : 0)) {
+      case 6: hipLaunchKernelGGL((k_ebe_assemble<3, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 7: hipLaunchKernelGGL((k_ebe_assemble<3, true, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 8: hipLaunchKernelGGL((k_ebe_assemble<4, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 9: hipLaunchKernelGGL((k_ebe_assemble<4, true, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 10: hipLaunchKernelGGL((k_ebe_assemble<5, false, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
+      case 11: hipLaunchKernelGGL((k_ebe_assemble<5, true, true>), dim3(n_elem), dim3(NT), 0, s, a, c->d_tabf); break;
       default: return fail(PF_EUNSUPPORTED, "order not built");
     }
   } else switch (c->mg.lv[0].P * 2 + (mb ? 1 : 0)) {
@@ -569,11 +577,11 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   a.xstate_out = nullptr;
   a.qd = c->d_qd;
   const bool mb = c->n_extra > 0;
-  if (c->d_qd) {  // mapped elements (orders 2-4, no extra branch: pf_set_geometry checks both)
+  if (c->d_qd) {  // mapped elements (orders 2-4: pf_set_geometry checks it)
     switch (c->mesh.p) {
-      case 2: st = launch_linearize<3, 0, true>(c, a, s); break;
-      case 3: st = launch_linearize<4, 0, true>(c, a, s); break;
-      case 4: st = launch_linearize<5, 0, true>(c, a, s); break;
+      case 2: st = mb ? launch_linearize<3, 2, true>(c, a, s) : launch_linearize<3, 0, true>(c, a, s); break;
+      case 3: st = mb ? launch_linearize<4, 2, true>(c, a, s) : launch_linearize<4, 0, true>(c, a, s); break;
+      case 4: st = mb ? launch_linearize<5, 2, true>(c, a, s) : launch_linearize<5, 0, true>(c, a, s); break;
       default: st = fail(PF_EUNSUPPORTED, "order not built");
     }
   } else switch (c->mesh.p) {
@@ -666,11 +674,11 @@ pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xs
   a.xstate_out = xstate_out;
   a.qd = c->d_qd;
   const bool mb = c->n_extra > 0;
-  if (c->d_qd) {  // mapped elements (orders 2-4, no extra branch: pf_set_geometry checks both)
+  if (c->d_qd) {  // mapped elements (orders 2-4: pf_set_geometry checks it)
     switch (c->mesh.p) {
-      case 2: return launch_linearize<3, 1, true>(c, a, s);
-      case 3: return launch_linearize<4, 1, true>(c, a, s);
-      case 4: return launch_linearize<5, 1, true>(c, a, s);
+      case 2: return mb ? launch_linearize<3, 3, true>(c, a, s) : launch_linearize<3, 1, true>(c, a, s);
+      case 3: return mb ? launch_linearize<4, 3, true>(c, a, s) : launch_linearize<4, 1, true>(c, a, s);
+      case 4: return mb ? launch_linearize<5, 3, true>(c, a, s) : launch_linearize<5, 1, true>(c, a, s);
       default: return fail(PF_EUNSUPPORTED, "order not built");
     }
   }

@@ -287,10 +287,12 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 // kernels without the Voce iteration unless a phase uses it; with extra branches
 // attached, the branch variant (which carries the Voce iteration for any branch); with
-// mapped elements (no extra branch: pf_set_geometry and pf_set_branches check it) the
-// geometry variant
+// mapped elements the geometry variant (with or without branches)
 template <int MODE, int P>
 pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if (c->d_qd && c->n_extra > 0)
+    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true, true>(c, a, s)
+                                     : launch_op64_mfma_v<MODE, P, false, true, true>(c, a, s);
   if (c->d_qd)
     return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, true>(c, a, s)
                        : launch_op64_mfma_v<MODE, P, false, false, true>(c, a, s);
@@ -314,6 +316,9 @@ pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE>
 pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if (c->d_qd && c->n_extra > 0)
+    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true, true>(c, a, s)
+                                     : launch_op64_q4_v<MODE, false, true, true>(c, a, s);
   if (c->d_qd)
     return c->has_voce ? launch_op64_q4_v<MODE, true, false, true>(c, a, s)
                        : launch_op64_q4_v<MODE, false, false, true>(c, a, s);
@@ -457,7 +462,6 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
     return fail(PF_EINVAL, "n_extra=%d outside 0..%d", n_extra, PF_MAX_EXTRA_BRANCHES);
   if (n_extra > 0 && (!branches || !xstate)) return fail(PF_EINVAL, "null branches or xstate");
   if (n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
-  if (n_extra > 0 && c->d_qd) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
   const int nph = (int)c->phases.size();
   std::vector<XBranch> xb((size_t)nph * (n_extra > 0 ? n_extra : 1));
   for (int i = 0; i < nph * n_extra; ++i) {
@@ -622,7 +626,6 @@ pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   if (X && (c->mesh.p < 2 || c->mesh.p > 4))
     return fail(PF_EUNSUPPORTED, "mapped elements are built for p = 2..4 (p=%d)", c->mesh.p);
-  if (X && c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches on mapped elements are not built");
   HIPCHK(hipDeviceSynchronize());  // applies in flight may still read the old record
   (void)hipFree(c->d_qd);
   (void)hipFree(c->d_qd32);

@@ -117,14 +117,6 @@ def test_geometry_errors(pf):
         ctx.set_geometry(dev(bad))
     assert e.value.code == pf.PF_EINVAL
     ctx.set_geometry(dev(I.curved_nodes(d["mesh"])))
-    # extra branches on mapped elements are not built (either order of attaching)
-    dx = I.make_inputs("C1", "ex3", p=3, n=2)
-    with pytest.raises(pf.PfError) as e:
-        ctx.set_branches(dx["branches"], dev(dx["xstate"]))
-    assert e.value.code == pf.PF_EUNSUPPORTED
-    with pytest.raises(pf.PfError) as e:
-        pf.Context.from_inputs(dict(dx, X=I.curved_nodes(dx["mesh"])))
-    assert e.value.code == pf.PF_EUNSUPPORTED
     with pytest.raises(pf.PfError) as e:
         ctx.set_geometry(torch.zeros((3, 5), dtype=torch.float64, device="cuda"))
     assert e.value.code == pf.PF_EINVAL
@@ -160,3 +152,52 @@ def test_curved_full_size_sampled(pf, oracle_lib):
     for got, ref in ((r, orc.residual(d["z"], elems=els)), (y, orc.jacobian(d["z"], d["dz"], elems=els)),
                      (gz, orc.adjoint(d["z"], d["v_rand"], elems=els)[0])):
         assert relerr(got[:, nodes], ref[:, nodes]) <= FP64_TOL, relerr(got[:, nodes], ref[:, nodes])
+
+
+def compare_fp64(pf, oracle_lib, d):
+    orc = oracle_lib.Oracle.from_inputs(d)
+    ctx = pf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r = ctx.apply_residual(z).cpu().numpy()
+    y = ctx.apply_jacobian(z, dz).cpu().numpy()
+    gz, gp = ctx.apply_adjoint(z, v)
+    ctx.check()
+    check_blocks(r, orc.residual(d["z"]), FP64_TOL, "residual")
+    check_blocks(y, orc.jacobian(d["z"], d["dz"]), FP64_TOL, "jacobian")
+    gref, gpref = orc.adjoint(d["z"], d["v_rand"])
+    check_blocks(gz.cpu().numpy(), gref, FP64_TOL, "adjoint")
+    gp = gp.cpu().numpy()
+    for k in range(3):
+        scale = max(np.abs(gpref[:, k]).max(), 1e-300)
+        assert np.abs(gp[:, k] - gpref[:, k]).max() <= 1e-11 * scale, (k, gp[:, k], gpref[:, k])
+    return ctx
+
+
+@pytest.mark.parametrize("variant,p,n", [("ex3", 2, 4), ("ex3", 3, 2), ("ex3_compress", 3, 3), ("ex3", 4, 2)])
+def test_curved_with_branches_fp64(pf, oracle_lib, variant, p, n):
+    """Extra branches in parallel on a curved mesh: FP64 applies, then the branch commit."""
+    print(f"case curved branches Q{p} {variant} n={n}", flush=True)
+    d = I.make_inputs("C1", variant, p=p, n=n, geometry="curved")
+    ctx = compare_fp64(pf, oracle_lib, d)
+    st, xs = ctx.commit_state_branches(dev(d["z"]))
+    st, xs = st.cpu().numpy(), xs.cpu().numpy()
+    ctx.check()
+    ref, xref = oracle_lib.Oracle.from_inputs(d).commit_state(d["z"])
+    assert np.abs(st[:6] - ref[:6]).max() <= 1e-12 * np.abs(ref[:6]).max()
+    assert np.abs(st[7] - ref[7]).max() <= 1e-13 * np.abs(ref[7]).max()
+    for j in range(xref.shape[0] // 7):
+        rows = slice(7 * j, 7 * j + 6)
+        sx = max(np.abs(xref[rows]).max(), 1e-300)
+        assert np.abs(xs[rows] - xref[rows]).max() <= 1e-12 * sx
+
+
+def test_branches_then_geometry_in_either_order(pf, oracle_lib):
+    d = I.make_inputs("C1", "ex3", p=3, n=2, geometry="curved")
+    orc = oracle_lib.Oracle.from_inputs(d)
+    box = dict(d)
+    box.pop("X")
+    ctx = pf.Context.from_inputs(box)  # branches first
+    ctx.set_geometry(dev(d["X"]))
+    r = ctx.apply_residual(dev(d["z"])).cpu().numpy()
+    ctx.check()
+    check_blocks(r, orc.residual(d["z"]), FP64_TOL, "residual")

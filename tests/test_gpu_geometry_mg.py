@@ -40,7 +40,8 @@ def dev(a, dt=torch.float64):
 
 @pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
 @pytest.mark.parametrize("variant,p,n", [("plastic", 2, 4), ("plastic", 3, 2), ("base", 3, 3), ("compress", 3, 2),
-                                         ("voce", 2, 3), ("plastic", 4, 2)])
+                                         ("voce", 2, 3), ("plastic", 4, 2), ("ex3", 2, 4), ("ex3", 3, 2),
+                                         ("ex3", 4, 2)])
 def test_curved_fp32_and_stored_apply(pf, oracle_lib, variant, p, n, scatter):
     if p == 4 and scatter == "brick_buffer":
         pytest.skip("order 4 scatters by element colours only")
@@ -57,11 +58,13 @@ def test_curved_fp32_and_stored_apply(pf, oracle_lib, variant, p, n, scatter):
     assert relerr(ylin, ref) <= FP64_TOL, relerr(ylin, ref)
 
 
-@pytest.mark.parametrize("p,level", [(2, 1), (3, 1), (3, 2), (4, 1), (4, 2), (4, 3)])
-def test_curved_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level):
+@pytest.mark.parametrize("p,level,variant", [(2, 1, "plastic"), (3, 1, "plastic"), (3, 2, "plastic"),
+                                             (4, 1, "plastic"), (4, 2, "plastic"), (4, 3, "plastic"),
+                                             (3, 2, "ex3"), (4, 1, "ex3")])
+def test_curved_coarse_operator_is_galerkin_product(pf, oracle_lib, p, level, variant):
     """A_c = P^T A_f P on the curved mesh (the order-1 level, the last of each list, assembled
-    from element matrices)."""
-    d = I.make_inputs("C1", "plastic", p=p, n=2, geometry="curved")
+    from element matrices); ex3: with branches in parallel."""
+    d = I.make_inputs("C1", variant, p=p, n=2, geometry="curved")
     ctx = lin_ctx(pf, d)
     m = d["mesh"]
     orc = oracle_lib.Oracle.from_inputs(d)
@@ -128,7 +131,7 @@ def test_curved_vcycle_preconditioned_gmres(pf):
     assert len(h_prec) < len(h_none) or h_none[-1] > 1e-5
 
 
-@pytest.mark.parametrize("variant", ["base", "plastic"])
+@pytest.mark.parametrize("variant", ["base", "plastic", "ex3"])
 def test_curved_newton_update_matches_dense_solve(pf, oracle_lib, variant):
     """One Newton update on the curved mesh (planar boundary faces, so the box's uniaxial
     faces apply): FGMRES with the V-cycle reaches 1e-11 and the update agrees with the dense
