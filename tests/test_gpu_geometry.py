@@ -49,11 +49,12 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
-@pytest.mark.parametrize("variant,p,n,at", CASES)
+# order 4 scatters by element colours only: one scatter mode there
+SCATTER_CASES = [c + (sc,) for c in CASES for sc in (("colour",) if c[1] == 4 else ("colour", "brick_buffer"))]
+
+
+@pytest.mark.parametrize("variant,p,n,at,scatter", SCATTER_CASES)
 def test_curved_fp64(pf, oracle_lib, variant, p, n, at, scatter):
-    if p == 4 and scatter == "brick_buffer":
-        pytest.skip("order 4 scatters by element colours only")
     print(f"case curved Q{p} {variant} n={n} at={at} {scatter}", flush=True)
     d = I.make_inputs("C1", variant, p=p, n=n, at=at, geometry="curved")
     orc = oracle_lib.Oracle.from_inputs(d)

@@ -38,13 +38,14 @@ def dev(a, dt=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
 
 
-@pytest.mark.parametrize("scatter", ["colour", "brick_buffer"])
-@pytest.mark.parametrize("variant,p,n", [("plastic", 2, 4), ("plastic", 3, 2), ("base", 3, 3), ("compress", 3, 2),
-                                         ("voce", 2, 3), ("plastic", 4, 2), ("ex3", 2, 4), ("ex3", 3, 2),
-                                         ("ex3", 4, 2)])
+RECORD_CASES = [("plastic", 2, 4), ("plastic", 3, 2), ("base", 3, 3), ("compress", 3, 2), ("voce", 2, 3),
+                ("plastic", 4, 2), ("ex3", 2, 4), ("ex3", 3, 2), ("ex3", 4, 2)]
+# order 4 scatters by element colours only: one scatter mode there
+RECORD_SCATTER = [c + (sc,) for c in RECORD_CASES for sc in (("colour",) if c[1] == 4 else ("colour", "brick_buffer"))]
+
+
+@pytest.mark.parametrize("variant,p,n,scatter", RECORD_SCATTER)
 def test_curved_fp32_and_stored_apply(pf, oracle_lib, variant, p, n, scatter):
-    if p == 4 and scatter == "brick_buffer":
-        pytest.skip("order 4 scatters by element colours only")
     print(f"case curved record applies Q{p} {variant} n={n} {scatter}", flush=True)
     d = I.make_inputs("C1", variant, p=p, n=n, geometry="curved")
     ctx = pf.Context.from_inputs(d)
