@@ -223,3 +223,22 @@ def test_inverted_element_is_reported(O):
     orc = O.Oracle.from_inputs(dict(d, X=X))
     with pytest.raises(RuntimeError):
         orc.residual(d["z"])
+
+
+@pytest.mark.parametrize("p,n", [(2, 4), (3, 2), (4, 6)])
+def test_curved_input_keeps_boundary_faces_planar(p, n):
+    """The curved-mesh recipe moves interior nodes by up to 0.2 h and leaves every node of the
+    six boundary faces on its face (even element counts), so the box's Dirichlet faces and the
+    domain volume stay those of the box."""
+    mesh = I.Mesh(p, n, n, n)
+    Xb = I.curved_nodes(mesh, amp=0.0)
+    Xc = I.curved_nodes(mesh, amp=0.2)
+    nx1, ny1, nz1 = mesh.node_dims
+    i = np.arange(mesh.n_nodes)
+    ix, iy, iz = i % nx1, (i // nx1) % ny1, i // (nx1 * ny1)
+    h = mesh.lx / mesh.nx
+    for comp, idx, n1 in ((0, ix, nx1), (1, iy, ny1), (2, iz, nz1)):
+        for face in (0, n1 - 1):
+            on = idx == face
+            assert np.abs(Xc[comp, on] - Xb[comp, on]).max() <= 1e-15
+    assert 0.1 * h < np.abs(Xc - Xb).max() <= 0.2 * h * 1.0 + 1e-15
