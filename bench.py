@@ -5,7 +5,10 @@ FP64 Jacobian apply, FP64 adjoint apply (with parameter gradient) and, when the
 multigrid is built, the FP32 linearised apply and one FP32 p-multigrid V-cycle.
 Inputs are generated once and resident in HBM before the timed region.
 
-value = Jacobian-apply DoFs/s (FP64) = 4 n_nodes / mean Jacobian-apply time.
+value = Jacobian-apply DoFs/s (FP64) = 4 n_nodes / median Jacobian-apply time.
+Beside the headline the line carries side legs on other workloads: the third
+example's branches in parallel, curved (mapped) elements, the order-2 mesh and,
+with --newton, Newton steps on the box, with branches and on the curved mesh.
 Prints one JSON line.
 """
 from __future__ import annotations
