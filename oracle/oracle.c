@@ -876,7 +876,8 @@ static int make_tab(const or_mesh* m, elem_tab* t) {
   or_gll(P, xn);
   or_gauss(Q, xq, wq);
   for (int q = 0; q < Q; q++) lagrange(P, xn, xq[q], B1[q], D1[q]);
-  double hx = m->lx / m->nx, hy = m->ly / m->ny, hz = m->lz / m->nz;
+  /* affine box factors (a table-restricted mesh is always mapped: these are then unused) */
+  double hx = m->conn ? 2.0 : m->lx / m->nx, hy = m->conn ? 2.0 : m->ly / m->ny, hz = m->conn ? 2.0 : m->lz / m->nz;
   t->P = P; t->Q = Q; t->nP = P * P * P; t->nQ = Q * Q * Q;
   t->N = (double*)malloc(sizeof(double) * t->nQ * t->nP);
   t->dN = (double*)malloc(sizeof(double) * t->nQ * t->nP * 3);
@@ -914,8 +915,9 @@ static void free_tab(elem_tab* t) { free(t->N); free(t->dN); free(t->wdet); free
  * the map x(xi) = sum_a X_a N_a(xi) has J_iK = sum_a X_a,i dN_a/dxi_K at each point; the
  * physical gradients are dN/dx_J = sum_K dN/dxi_K (J^-1)_KJ and the weight w det J.
  * Returns 1 if some det J <= 0. */
+static int64_t mesh_nodes(const or_mesh* m, const elem_tab* t);
 static int elem_geometry(const or_mesh* m, const elem_tab* t, const int64_t* idx, double* dNe, double* wde) {
-  int64_t n_nodes = (int64_t)t->nx1 * t->ny1 * (m->p * m->nz + 1);
+  int64_t n_nodes = mesh_nodes(m, t);
   int bad = 0;
   for (int qq = 0; qq < t->nQ; qq++) {
     double J[3][3] = {{0}}, Ji[3][3];
@@ -936,7 +938,20 @@ static int elem_geometry(const or_mesh* m, const elem_tab* t, const int64_t* idx
   return bad;
 }
 
+/* Number of nodes and elements: the table's when the restriction is a table, else the lattice's. */
+static int64_t mesh_nodes(const or_mesh* m, const elem_tab* t) {
+  return m->conn ? m->n_nodes : (int64_t)t->nx1 * t->ny1 * (m->p * m->nz + 1);
+}
+static int64_t mesh_elems(const or_mesh* m) {
+  return m->conn ? m->n_elem : (int64_t)m->nx * m->ny * m->nz;
+}
+
+/* Global nodes of element e (the restriction E_e): the table's row, or lattice arithmetic. */
 static void elem_nodes(const or_mesh* m, const elem_tab* t, int64_t e, int64_t* idx) {
+  if (m->conn) {
+    for (int a = 0; a < t->nP; a++) idx[a] = m->conn[e * t->nP + a];
+    return;
+  }
   int64_t ex = e % m->nx, ey = (e / m->nx) % m->ny, ez = e / ((int64_t)m->nx * m->ny);
   int P = t->P;
   for (int az = 0; az < P; az++)
@@ -995,8 +1010,8 @@ static int elem_apply(const apply_args* A, const elem_tab* t, int kind, int64_t 
                       double* gp, int64_t* idx, double* ze, double* we) {
   const or_mesh* m = A->m;
   int nP = t->nP, nQ = t->nQ;
-  int64_t n_nodes = (int64_t)t->nx1 * t->ny1 * (m->p * m->nz + 1);
-  int64_t n_q = (int64_t)m->nx * m->ny * m->nz * nQ;
+  int64_t n_nodes = mesh_nodes(m, t);
+  int64_t n_q = mesh_elems(m) * nQ;
   int bad = 0;
   elem_nodes(m, t, e, idx);
   for (int f = 0; f < 4; f++)
@@ -1086,11 +1101,16 @@ static int run_apply(const apply_args* A, int kind, double* outv, double* gparam
   const or_mesh* m = A->m;
   if (!m || !A->ph || A->nph < 1 || !A->fr || !A->phase || !A->state || !A->z || !outv) return -1;
   if (A->n_extra < 0 || A->n_extra > OR_MAX_EXTRA || (A->n_extra > 0 && (!A->xbr || !A->xstate))) return -1;
+  if (m->conn && (!m->X || m->n_elem < 0 || m->n_nodes < 1)) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
-  int64_t ne_all = (int64_t)m->nx * m->ny * m->nz;
+  int64_t ne_all = mesh_elems(m);
   int64_t n = elems ? n_elems : ne_all;
-  int64_t n_nodes = (int64_t)t.nx1 * t.ny1 * (m->p * m->nz + 1);
+  int64_t n_nodes = mesh_nodes(m, &t);
+  if (m->conn) {
+    for (int64_t k = 0; k < ne_all * t.nP; k++)
+      if (m->conn[k] < 0 || m->conn[k] >= n_nodes) { free_tab(&t); return -1; }
+  }
   int nP = t.nP;
   double* eres = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * 4 * nP);
   /* per-element parameter partials, summed serially afterwards (deterministic) */
@@ -1165,10 +1185,11 @@ int or_element_jacobian(const or_mesh* m, const or_phase* ph, int nph, const or_
                         const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
                         const double* phi_n, const double* z, int64_t e, double* Ke) {
   if (n_extra < 0 || n_extra > OR_MAX_EXTRA || (n_extra > 0 && (!xbr || !xstate))) return -1;
+  if (m->conn && !m->X) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
   int nP = t.nP, nd = 4 * nP;
-  int64_t n_nodes = (int64_t)t.nx1 * t.ny1 * (m->p * m->nz + 1);
+  int64_t n_nodes = mesh_nodes(m, &t);
   /* column j = element apply of the unit element vector e_j; a unit vector
    * placed in a private global-size buffer keeps the same gather path */
   double* unit = (double*)calloc((size_t)4 * n_nodes, sizeof(double));
@@ -1198,11 +1219,12 @@ int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_b
                        const or_frac* fr, const uint8_t* phase, const double* state, const double* xstate,
                        const double* z, double* state_new, double* xstate_new) {
   if (n_extra < 0 || n_extra > OR_MAX_EXTRA || (n_extra > 0 && (!xbr || !xstate || !xstate_new))) return -1;
+  if (m->conn && !m->X) return -1;
   elem_tab t;
   if (make_tab(m, &t)) return -1;
   int nP = t.nP, nQ = t.nQ;
-  int64_t n_nodes = (int64_t)t.nx1 * t.ny1 * (m->p * m->nz + 1);
-  int64_t n_el = (int64_t)m->nx * m->ny * m->nz;
+  int64_t n_nodes = mesh_nodes(m, &t);
+  int64_t n_el = mesh_elems(m);
   int64_t n_q = n_el * nQ;
   int err = 0;
 #pragma omp parallel

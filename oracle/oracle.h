@@ -36,8 +36,19 @@ extern "C" {
 #endif
 
 /* X: optional positions of the nodes [3][n_nodes] (an isoparametric map of every element,
- * Section 4); NULL = the box [0,lx]x[0,ly]x[0,lz] with affine elements. */
-typedef struct { int p, q, nx, ny, nz; double lx, ly, lz; const double* X; } or_mesh;
+ * Section 4); NULL = the box [0,lx]x[0,ly]x[0,lz] with affine elements.
+ * conn: optional element restriction as a table (the general E and P of Section 4's
+ * compact residual): conn[e*(p+1)^3 + a] is the global node of local node
+ * a = ax + (p+1)(ay + (p+1) az) of element e, for e < n_elem, nodes < n_nodes; it needs X
+ * (every element is mapped) and then replaces the lattice numbering (nx, ny, nz, lx, ly,
+ * lz are ignored). NULL = the box lattice (n_elem, n_nodes ignored). */
+typedef struct {
+  int p, q, nx, ny, nz;
+  double lx, ly, lz;
+  const double* X;
+  const int32_t* conn;
+  int64_t n_elem, n_nodes;
+} or_mesh;
 /* sigma_inf, voce_beta: Voce term (sigma_inf - sigma0)(1 - exp(-voce_beta ebar_p)) of the
  * hardening law; voce_beta = 0 is linear hardening. */
 typedef struct { double E, nu, Gc, sigma0, H, visc; int plastic; double sigma_inf, voce_beta; } or_phase;

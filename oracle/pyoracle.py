@@ -29,7 +29,8 @@ def build(force: bool = True) -> str:
 
 class OrMesh(C.Structure):
     _fields_ = [("p", C.c_int), ("q", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
-                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double), ("X", C.c_void_p)]
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double), ("X", C.c_void_p),
+                ("conn", C.c_void_p), ("n_elem", C.c_int64), ("n_nodes", C.c_int64)]
 
 
 class OrPhase(C.Structure):
@@ -112,10 +113,16 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mesh_struct(mesh, q=None, X=None):
-    """X: node positions [3][n_nodes] (float64, C-contiguous, kept alive by the caller) or None."""
-    return OrMesh(mesh.p, q if q is not None else mesh.p + 1, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz,
-                  X.ctypes.data_as(C.c_void_p) if X is not None else None)
+def mesh_struct(mesh, q=None, X=None, conn=None):
+    """X: node positions [3][n_nodes] (float64, C-contiguous, kept alive by the caller) or None.
+    conn: element-to-node table int32 [n_elem][(p+1)^3] (kept alive by the caller) of a mesh
+    with a table restriction (needs X), or None for the box lattice."""
+    q = q if q is not None else mesh.p + 1
+    Xp = X.ctypes.data_as(C.c_void_p) if X is not None else None
+    if conn is not None:
+        return OrMesh(mesh.p, q, 1, 1, 1, 1.0, 1.0, 1.0, Xp, conn.ctypes.data_as(C.c_void_p),
+                      int(conn.shape[0]), int(mesh.n_nodes))
+    return OrMesh(mesh.p, q, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz, Xp, None, 0, 0)
 
 
 def phase_struct(ph):
@@ -233,15 +240,20 @@ def qf_commit_mb(ph, xb, fr, G, phi, st, xs):
 class Oracle:
     """Oracle bound to one set of inputs (as produced by ``inputs.make_inputs``)."""
 
-    def __init__(self, mesh, phases, fracture, phase, state, phi_n, branches=None, xstate=None, X=None, q=None):
+    def __init__(self, mesh, phases, fracture, phase, state, phi_n, branches=None, xstate=None, X=None, q=None,
+                 conn=None):
         """X: node positions [3][n_nodes] of a mapped mesh (None: the box lattice); q: points
-        per direction of the Gauss rule (None: p + 1; state and phase then hold nx*ny*nz*q^3
-        points)."""
+        per direction of the Gauss rule (None: p + 1; state and phase then hold n_elem*q^3
+        points); conn: element-to-node table [n_elem][(p+1)^3] of a mesh with a table
+        restriction (needs X)."""
         self.mesh = mesh
         self.X = _f64(X) if X is not None else None
         if self.X is not None:
             assert self.X.shape == (3, mesh.n_nodes)
-        self._m = mesh_struct(mesh, q=q, X=self.X)
+        self.conn = np.ascontiguousarray(conn, dtype=np.int32) if conn is not None else None
+        if self.conn is not None:
+            assert self.X is not None and self.conn.shape[1] == (mesh.p + 1) ** 3
+        self._m = mesh_struct(mesh, q=q, X=self.X, conn=self.conn)
         self._ph = phases_array(phases)
         self._nph = len(phases)
         self._fr = frac_struct(fracture)
@@ -253,7 +265,7 @@ class Oracle:
     @classmethod
     def from_inputs(cls, d):
         return cls(d["mesh"], d["phases"], d["fracture"], d["phase"], d["state"], d["phi_n"],
-                   d.get("branches"), d.get("xstate"), d.get("X"))
+                   d.get("branches"), d.get("xstate"), d.get("X"), conn=d.get("conn"))
 
     def set_branches(self, branches, xstate):
         """Extra branches per phase (list over phases of lists of length n_extra) and their
@@ -337,6 +349,8 @@ class Oracle:
         return K
 
     def element_nodes(self, e):
+        if self.conn is not None:
+            return self.conn[e].astype(np.int64)
         m = self.mesh
         P = m.p + 1
         nx1, ny1, _ = m.node_dims

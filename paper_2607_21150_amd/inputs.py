@@ -46,14 +46,15 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Mesh", "Phase", "Branch", "Fracture", "Config", "CONFIGS", "make_config",
-    "make_inputs", "gll_points", "gauss_points", "default_phases",
+    "Mesh", "UMesh", "Phase", "Branch", "Fracture", "Config", "CONFIGS", "make_config",
+    "make_inputs", "unstructured", "gll_points", "gauss_points", "default_phases",
     "default_fracture",
 ]
 
 SEED_BASE = 21150
 # one independent random stream per purpose
-STREAM_SPHERES, STREAM_PHI, STREAM_SINES, STREAM_STATE, STREAM_DIR, STREAM_COT, STREAM_XSTATE = range(7)
+(STREAM_SPHERES, STREAM_PHI, STREAM_SINES, STREAM_STATE, STREAM_DIR, STREAM_COT, STREAM_XSTATE,
+ STREAM_UNSTRUCT) = range(8)
 
 # kinds of extra branches in parallel with a phase's block
 BRANCH_NONE, BRANCH_HOOKE, BRANCH_MAXWELL, BRANCH_PRANDTL = 0, 1, 2, 3
@@ -93,6 +94,36 @@ class Mesh:
     @property
     def n_dof(self) -> int:
         return 4 * self.n_nodes
+
+
+@dataclasses.dataclass(frozen=True)
+class UMesh:
+    """Hexahedral mesh given by a table restriction: ``n_elem`` elements of order ``p``
+    whose ``(p+1)^3`` nodes are listed, per element, in the element's own reference
+    coordinates (local node ``a = ax + P*(ay + P*az)``), over ``n_nodes`` nodes with
+    arbitrary numbering. Quadrature points stay element-major with ``Q = p+1`` Gauss
+    points per direction in the element's reference coordinates. ``box`` is the lattice
+    mesh the synthetic table was cut from (its size and extent)."""
+    p: int
+    n_elem: int
+    n_nodes: int
+    box: Mesh
+
+    @property
+    def q(self) -> int:
+        return self.p + 1
+
+    @property
+    def n_q(self) -> int:
+        return self.n_elem * self.q ** 3
+
+    @property
+    def n_dof(self) -> int:
+        return 4 * self.n_nodes
+
+    @property
+    def lx(self) -> float:
+        return self.box.lx
 
 
 @dataclasses.dataclass(frozen=True)
@@ -478,3 +509,113 @@ def elements_touching_nodes(mesh: Mesh, nodes) -> np.ndarray:
                 for ez in ezs:
                     out.add(ex + mesh.nx * (ey + mesh.ny * ez))
     return np.array(sorted(out), dtype=np.int32)
+
+
+def lattice_connectivity(mesh: Mesh) -> np.ndarray:
+    """Element-to-node table [n_elem][P^3] of the box lattice (the numbering of this module)."""
+    P = mesh.p + 1
+    nx1, ny1, _ = mesh.node_dims
+    e = np.arange(mesh.n_elem)
+    ex, ey, ez = e % mesh.nx, (e // mesh.nx) % mesh.ny, e // (mesh.nx * mesh.ny)
+    a = np.arange(P)
+    az, ay, ax = np.meshgrid(a, a, a, indexing="ij")
+    ax, ay, az = ax.reshape(-1), ay.reshape(-1), az.reshape(-1)
+    gx = ex[:, None] * mesh.p + ax[None, :]
+    gy = ey[:, None] * mesh.p + ay[None, :]
+    gz = ez[:, None] * mesh.p + az[None, :]
+    return (gx + nx1 * (gy + ny1 * gz)).astype(np.int64)
+
+
+def cube_rotations():
+    """The 24 proper rotations of the reference cube, as signed 3x3 permutation matrices."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), dtype=np.int64)
+            for i in range(3):
+                R[i, perm[i]] = signs[i]
+            if round(np.linalg.det(R)) == 1:
+                out.append(R)
+    return out
+
+
+def rotated_local_index(R: np.ndarray, n: int) -> np.ndarray:
+    """For a grid of n points per direction, symmetric about the cube's centre (GLL nodes,
+    Gauss points): idx[a'] = the lattice-local index of the point R xi(a') (x fastest)."""
+    c = 2 * np.arange(n) - (n - 1)
+    cz, cy, cx = np.meshgrid(c, c, c, indexing="ij")
+    C = np.stack([cx.reshape(-1), cy.reshape(-1), cz.reshape(-1)])
+    il = (R @ C + (n - 1)) // 2
+    return il[0] + n * (il[1] + n * il[2])
+
+
+def unstructured(d, hole_radius: float = 0.0, node_order: str = "random", shuffle_elements: bool = True,
+                 rotate: bool = True):
+    """The inputs ``d`` of a box (or curved) lattice re-expressed on a mesh given by a table
+    restriction (UMesh): elements whose centre lies within ``hole_radius`` of the axis
+    x = lx/2, z = lz/2 are removed (a cylindrical hole, so node valences vary), every kept
+    element gets one of the 24 proper cube rotations as its own local orientation (``rotate``),
+    the elements are shuffled (``shuffle_elements``), and the nodes in use are renumbered:
+    ``node_order`` "random" (a random permutation) or "first_touch" (order of first appearance
+    in the element table, as a mesh generator's renumbering would give). Fields, state and
+    phase ids are carried over unchanged by index maps (the physics is the same; only the
+    numbering and the element orientation change). Adds ``conn`` int32 [n_elem][P^3], ``X``
+    [3][n_nodes] (node positions), and the maps ``node_map`` (new node -> lattice node),
+    ``elem_map`` (new element -> lattice element) and ``qp_map`` (new point -> lattice point)."""
+    box = d["mesh"]
+    assert isinstance(box, Mesh)
+    rng = _rng(d["cfg"].cfg_id, STREAM_UNSTRUCT)
+    P, Q = box.p + 1, box.q
+    conn_l = lattice_connectivity(box)
+    # element removal: a cylindrical hole along y
+    e = np.arange(box.n_elem)
+    ex, ez = e % box.nx, e // (box.nx * box.ny)
+    cx = (ex + 0.5) * box.lx / box.nx - 0.5 * box.lx
+    cz = (ez + 0.5) * box.lz / box.nz - 0.5 * box.lz
+    keep = np.nonzero(cx * cx + cz * cz >= hole_radius * hole_radius)[0]
+    elem_map = rng.permutation(keep) if shuffle_elements else keep
+    ne = len(elem_map)
+    rots = cube_rotations()
+    rid = rng.integers(0, len(rots), size=ne) if rotate else np.zeros(ne, dtype=np.int64)
+    if not rotate:
+        rots = [np.eye(3, dtype=np.int64)]
+    nidx = np.stack([rotated_local_index(R, P) for R in rots])  # [24][P^3]
+    qidx = np.stack([rotated_local_index(R, Q) for R in rots])  # [24][Q^3]
+    conn_old = conn_l[elem_map[:, None], nidx[rid]]  # lattice node ids, rotated local order
+    used, first = np.unique(conn_old.reshape(-1), return_index=True)
+    if node_order == "random":
+        node_map = rng.permutation(used)
+    elif node_order == "first_touch":
+        node_map = used[np.argsort(first, kind="stable")]
+    else:
+        raise ValueError(node_order)
+    new_of_old = np.full(box.n_nodes, -1, dtype=np.int64)
+    new_of_old[node_map] = np.arange(len(node_map))
+    conn = new_of_old[conn_old].astype(np.int32)
+    qp_map = (elem_map[:, None] * Q ** 3 + qidx[rid]).reshape(-1)
+    mesh = UMesh(box.p, ne, len(node_map), box)
+    if d.get("X") is not None:
+        X = d["X"][:, node_map]
+    else:
+        gll = gll_points(box.p)
+        xs = _coords_1d(box.nx, box.p, box.lx, gll)
+        ys = _coords_1d(box.ny, box.p, box.ly, gll)
+        zs = _coords_1d(box.nz, box.p, box.lz, gll)
+        nx1, ny1, _ = box.node_dims
+        X = np.stack([xs[node_map % nx1], ys[(node_map // nx1) % ny1], zs[node_map // (nx1 * ny1)]])
+    out = dict(d, mesh=mesh, conn=conn, X=np.ascontiguousarray(X), node_map=node_map, elem_map=elem_map,
+               qp_map=qp_map, hole_radius=hole_radius)
+    for k in ("z", "dz", "v_rand", "v_top"):
+        if k in d:
+            out[k] = np.ascontiguousarray(d[k][:, node_map])
+    for k in ("dz", "v_rand"):
+        if k in out:
+            out[k] /= np.linalg.norm(out[k])
+    out["phi_n"] = np.ascontiguousarray(d["phi_n"][node_map])
+    out["state"] = np.ascontiguousarray(d["state"][:, qp_map])
+    out["phase"] = np.ascontiguousarray(d["phase"][qp_map])
+    if "xstate" in d:
+        out["xstate"] = np.ascontiguousarray(d["xstate"][:, qp_map])
+    out["vol_frac"] = float(out["phase"].mean())
+    return out
