@@ -6,9 +6,12 @@ multigrid is built, the FP32 linearised apply and one FP32 p-multigrid V-cycle.
 Inputs are generated once and resident in HBM before the timed region.
 
 value = Jacobian-apply DoFs/s (FP64) = 4 n_nodes / median Jacobian-apply time.
+The headline's outputs are compared with the oracle on every node (rel-L2 and, per field,
+the largest entry error over the largest reference entry).
 Beside the headline the line carries side legs on other workloads: the third
-example's branches in parallel, curved (mapped) elements, the order-2 mesh and,
-with --newton, Newton steps on the box, with branches and on the curved mesh.
+example's branches in parallel, curved (mapped) elements, the order-2 mesh and one
+Newton step on the Q4 box (FGMRES, and the conjugate-gradient variant beside it);
+with --newton-all also Newton steps with branches and on the curved mesh.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -94,11 +97,36 @@ def alg_bytes(mesh, kind):
         return 72 * nodes + 65 * qps
     if kind in ("jacobian", "adjoint"):  # z, dz read, y written
         return 96 * nodes + 65 * qps
-    if kind == "fp32_apply":    # FP32 u mirror (12), dz (16), y (16) per node; record 60 + flags 1 + phase 1 per point
-        return 44 * nodes + 62 * qps
-    if kind == "jacobian_stored":  # FP64 u copy (24), dz (32), y (32) per node; record 120 + flags 1 + phase 1
-        return 88 * nodes + 122 * qps
+    if kind == "fp32_apply":    # design C: FP32 z, dz, y (48 B per node); 46 B record per point
+        return 48 * nodes + 46 * qps
+    if kind == "jacobian_stored":  # the same operator as the recompute Jacobian: priced on its bytes
+        return 96 * nodes + 65 * qps
     raise ValueError(kind)
+
+
+def stored_bytes(mesh, kind):
+    """Bytes the record applies actually read and write (larger than the algorithmic bytes,
+    which do not grow with what is stored): FP32 apply: u mirror (12), dz (16), y (16) per
+    node, record 60 + flags 1 + phase 1 per point; stored FP64 Jacobian: u copy (24), dz (32),
+    y (32) per node, record 120 + flags 1 + phase 1 per point."""
+    if kind == "fp32_apply":
+        return 44 * mesh.n_nodes + 62 * mesh.n_q
+    if kind == "jacobian_stored":
+        return 88 * mesh.n_nodes + 122 * mesh.n_q
+    raise ValueError(kind)
+
+
+def whole_mesh_err(gpu_vec, ref):
+    """Error of a [4][n_nodes] GPU result against the oracle on every node: rel-L2 and, per
+    field, max |gpu - ref| / max |ref| (the largest over the four fields)."""
+    gpu_vec = np.asarray(gpu_vec, dtype=np.float64)
+    rel = float(np.linalg.norm(gpu_vec - ref) / max(np.linalg.norm(ref), 1e-300))
+    worst = 0.0
+    for f in range(ref.shape[0]):
+        s = float(np.max(np.abs(ref[f])))
+        if s > 0.0:
+            worst = max(worst, float(np.max(np.abs(gpu_vec[f] - ref[f]))) / s)
+    return {"rel_l2": rel, "max_entry": worst}
 
 
 def sampled_rel_err(orc, mesh, gpu_vec, fn, rng, n_nodes=48):
@@ -138,18 +166,41 @@ def cpu_baseline(d, seconds=10.0):
     orc.jacobian(d["z"], d["dz"], elems=np.arange(n1, dtype=np.int32), check=False)
     t1 = time.perf_counter() - t0
     pyoracle.set_num_threads(cores)
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), model)
-    except OSError:
-        pass
+    model = cpu_description()
     return {"value": dofs_per_s, "unit": "DoF/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 Jacobian apply on elements 0..{n - 1} ({n} of {mesh.n_elem}, {frac:.3f} of the work) "
                       f"took {t:.2f} s on {cores} threads; scaled to the full apply",
             "value_1core": mesh.n_dof / (t1 * mesh.n_elem / n1),
             "sample_1core": f"elements 0..{n1 - 1} on 1 thread took {t1:.2f} s",
             "cpu_model": model, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_description():
+    """Host CPU as /proc/cpuinfo names it (model name, family/model/stepping, sockets, cores
+    per socket) and the CPUs this process may run on."""
+    info, sockets, cores = {}, set(), {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("model name", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                    info[k] = v
+                if k == "physical id":
+                    sockets.add(v)
+                if k == "cpu cores":
+                    cores[len(sockets)] = v
+    except OSError:
+        return "unknown"
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = os.cpu_count()
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, model "
+            f"{info.get('model', '?')}, stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz; "
+            f"{len(sockets) or '?'} socket(s), {next(iter(cores.values()), '?')} cores per socket; "
+            f"{os.cpu_count()} logical CPUs, {avail} available to this process)")
 
 
 def secondary_leg(torch, I, pfmf, config):
@@ -185,7 +236,9 @@ def secondary_leg(torch, I, pfmf, config):
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs", "ms": ms,
             "dofs_per_s": {k: mesh.n_dof / (t * 1e-3) for k, t in ms.items()},
             "gbs_alg": {k: alg_bytes(mesh, k) / (t * 1e-3) / 1e9 for k, t in ms.items()},
-            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
+            "hbm_frac_alg": {k: alg_bytes(mesh, k) / (t * 1e-3) / 1e9 / HBM_PEAK_GBS for k, t in ms.items()},
+            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
+            "fp32_over_stored_fp64_speedup": ms["jacobian_stored"] / ms["fp32_apply"]}
 
 
 def branch_state_bytes(d):
@@ -352,12 +405,14 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
 
 
 def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30,
-               geometry="box"):
+               geometry="box", with_cg=False):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
     (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1; Chebyshev(3); 32 sweeps on the order-1
     level, assembled as a block stencil), FP64 Jacobian as the operator. geometry="curved":
-    the same on the curved mesh (planar boundary faces, so the same faces are constrained)."""
+    the same on the curved mesh (planar boundary faces, so the same faces are constrained).
+    with_cg: the same step again from the same start with preconditioned conjugate gradients
+    (the same V-cycle, at most 300 iterations), its outcome reported beside FGMRES."""
     t_gen = time.perf_counter()
     d = I.make_inputs(config, variant, geometry=geometry)
     mesh = d["mesh"]
@@ -403,16 +458,33 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
                           coarse_sweeps=coarse_sweeps, raise_on_noconv=False)
     t_step = time.perf_counter() - t0
     print(f"[bench] newton step {rep} in {t_step:.2f} s", file=sys.stderr, flush=True)
-    return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}"
-                      + (f", materials '{variant}'" if variant != "base" else "")
-                      + (", curved elements (bump 0.2 h)" if geometry != "box" else "")
-                      + f", FGMRES({restart}), Chebyshev({cheb_degree}), {coarse_sweeps} coarse sweeps",
-            "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
-            "gram_schmidt_refinements": rep["refinements"],
-            "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
-            "t_linearize_ms": rep["t_linearize_ms"], "ms": ms,
-            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "jacobian_stored", "fp32_apply")},
-            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"]}
+    out = {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, uniaxial faces, levels {levels}"
+                     + (f", materials '{variant}'" if variant != "base" else "")
+                     + (", curved elements (bump 0.2 h)" if geometry != "box" else "")
+                     + f", FGMRES({restart}), Chebyshev({cheb_degree}), {coarse_sweeps} coarse sweeps",
+           "time_to_solution_s": t_step, "fgmres_iterations": rep["iterations"],
+           "gram_schmidt_refinements": rep["refinements"],
+           "converged": bool(rep["converged"]), "rel_res_true": rep["res_true"] / max(rep["res0"], 1e-300),
+           "t_linearize_ms": rep["t_linearize_ms"], "ms": ms,
+           "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "jacobian_stored", "fp32_apply")},
+           "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
+           "fp32_over_stored_fp64_speedup": ms["jacobian_stored"] / ms["fp32_apply"]}
+    if with_cg:
+        zc = torch.as_tensor(z0).to("cuda", torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cg = ctx.newton_step(zc, rtol=1e-8, restart=restart, max_iters=300, cheb_degree=cheb_degree,
+                             coarse_sweeps=coarse_sweeps, raise_on_noconv=False, krylov="cg")
+        t_cg = time.perf_counter() - t0
+        print(f"[bench] newton step (CG) {cg} in {t_cg:.2f} s", file=sys.stderr, flush=True)
+        out["cg"] = {"time_s": t_cg, "iterations": cg["iterations"], "converged": bool(cg["converged"]),
+                     "breakdown": bool(cg["breakdown"]),
+                     "rel_res_true": cg["res_true"] / max(cg["res0"], 1e-300),
+                     "rel_res_cg": cg["res_lin"] / max(cg["res0"], 1e-300),
+                     "update_rel_diff_vs_fgmres": float(torch.linalg.norm((zc - z)) /
+                                                         max(float(torch.linalg.norm(z - torch.as_tensor(z0).to(
+                                                             "cuda", torch.float64))), 1e-300))}
+    return out
 
 
 def main():
@@ -424,20 +496,23 @@ def main():
     ap.add_argument("--variant", default="base")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--newton", action="store_true",
-                    help="also time one Newton step (FGMRES + FP32 p-MG) on --newton-config")
+    ap.add_argument("--no-newton", action="store_true",
+                    help="skip the Newton step (FGMRES + FP32 p-MG, and the CG variant) on --newton-config")
+    ap.add_argument("--newton-all", action="store_true",
+                    help="also the Newton steps with the third example's branches and on the curved mesh")
     ap.add_argument("--newton-config", default="C5")
     ap.add_argument("--secondary", default="C2",
                     help="second workload whose applies are timed and reported beside the headline ('' = none)")
     ap.add_argument("--newton-branches-config", default="C2",
-                    help="workload of the Newton step with the third example's branches (with --newton; '' = none)")
+                    help="workload of the Newton step with the third example's branches (with --newton-all; "
+                         "'' = none)")
     ap.add_argument("--branches", default="C3",
                     help="workload on which the applies with the third example's branches in parallel are timed "
                          "('' = none)")
     ap.add_argument("--geometry", default="C3",
                     help="workload on which the applies on curved (mapped) Q3 elements are timed ('' = none)")
     ap.add_argument("--newton-curved-config", default="C5",
-                    help="workload of the Newton step on the curved mesh (with --newton; '' = none)")
+                    help="workload of the Newton step on the curved mesh (with --newton-all; '' = none)")
     ap.add_argument("--geometry-box", action="store_true",
                     help="also time the geometry leg's applies on the box mesh (the curved / box ratio)")
     args = ap.parse_args()
@@ -510,21 +585,23 @@ def main():
     ms_med = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
     print(f"[bench] timed {args.steps} steps in {wall:.2f} s: {ms}", file=sys.stderr, flush=True)
 
-    # errors against the oracle on sampled nodes (FP64 bar 1e-12)
+    # errors against the oracle on every node of the mesh (FP64 bar 1e-12, FP32 1e-5)
     errs = {}
     try:
         from oracle import pyoracle
         pyoracle.build(force=False)
         orc = pyoracle.Oracle.from_inputs(d)
-        rng = np.random.default_rng(0)
-        rr, yy, gg = r.cpu().numpy(), y.cpu().numpy(), gz.cpu().numpy()
-        errs["residual"] = sampled_rel_err(orc, mesh, rr, lambda e: orc.residual(d["z"], elems=e), rng)
-        errs["jacobian"] = sampled_rel_err(orc, mesh, yy, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
-        errs["adjoint"] = sampled_rel_err(orc, mesh, gg, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
-        y32h = y32.double().cpu().numpy()
-        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32h, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
-        errs["jacobian_stored"] = sampled_rel_err(orc, mesh, ys.cpu().numpy(),
-                                                  lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        t_or = time.perf_counter()
+        errs["residual"] = whole_mesh_err(r.cpu().numpy(), orc.residual(d["z"]))
+        jref = orc.jacobian(d["z"], d["dz"])
+        errs["jacobian"] = whole_mesh_err(y.cpu().numpy(), jref)
+        errs["fp32_apply"] = whole_mesh_err(y32.double().cpu().numpy(), jref)
+        errs["jacobian_stored"] = whole_mesh_err(ys.cpu().numpy(), jref)
+        del jref
+        errs["adjoint"] = whole_mesh_err(gz.cpu().numpy(), orc.adjoint(d["z"], d["v_top"])[0])
+        errs["nodes_compared"] = mesh.n_nodes
+        print(f"[bench] whole-mesh oracle comparison in {time.perf_counter() - t_or:.1f} s: {errs}",
+              file=sys.stderr, flush=True)
     except Exception as exc:  # the oracle is a checker; its absence does not stop the benchmark
         errs["error"] = str(exc)
 
@@ -606,11 +683,23 @@ def main():
             "unit": "GB/s",
             "frac": alg_bytes(mesh, "jacobian_stored") / (ms_med["jacobian_stored"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "alg_bytes_per_apply": alg_bytes(mesh, "jacobian_stored"),
+            "bytes_read_and_written": stored_bytes(mesh, "jacobian_stored"),
+        },
+        "roofline_fp32_apply": {
+            "bound": "hbm",
+            "achieved": alg_bytes(mesh, "fp32_apply") / (ms_med["fp32_apply"] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": alg_bytes(mesh, "fp32_apply") / (ms_med["fp32_apply"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "alg_bytes_per_apply": alg_bytes(mesh, "fp32_apply"),
+            "bytes_read_and_written": stored_bytes(mesh, "fp32_apply"),
         },
         "fp32_over_fp64_apply_speedup": ms_med["jacobian"] / ms_med["fp32_apply"],
-        "rel_err_vs_oracle_sampled": errs,
+        "fp32_over_stored_fp64_speedup": ms_med["jacobian_stored"] / ms_med["fp32_apply"],
+        "rel_err_vs_oracle": errs,
     }
-    if args.secondary or args.newton or args.branches or args.geometry:
+    newton = not args.no_newton
+    if args.secondary or newton or args.branches or args.geometry:
         del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32, ys
         torch.cuda.empty_cache()
     if args.branches:
@@ -624,8 +713,10 @@ def main():
     if args.secondary:
         out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)
         print(f"[bench] secondary {out['secondary']}", file=sys.stderr, flush=True)
-    if args.newton:
-        out["newton"] = newton_leg(torch, I, pfmf, args.newton_config)
+    if newton:
+        torch.cuda.empty_cache()
+        out["newton"] = newton_leg(torch, I, pfmf, args.newton_config, with_cg=True)
+    if newton and args.newton_all:
         if args.newton_branches_config:
             torch.cuda.empty_cache()
             # the third example's matrix needs a stronger smoother than the defaults

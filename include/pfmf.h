@@ -128,6 +128,35 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
                         const double* qp_state, const double* phi_n, void* stream,
                         pf_ctx** out);
 
+/* Hexahedral mesh given by a table restriction (the general element restriction E and
+ * P of Section 4's compact residual, eq:matrix-free-residual-compact, as on the paper's
+ * unstructured meshes): n_elem elements of order p (2 or 3) over n_nodes nodes. */
+typedef struct { int p; int64_t n_elem, n_nodes; } pf_table_mesh_desc;
+
+/* Create a context on a mesh given by its element-to-node table. conn: device
+ * int32[n_elem][(p+1)^3], conn[e (p+1)^3 + a] = global node of local node
+ * a = ax + (p+1)(ay + (p+1) az) of element e in the element's own reference coordinates
+ * (any orientation, any node numbering); X: device double[3][n_nodes], node positions
+ * (every element is mapped, Section 4's isoparametric map; X is read once, not kept).
+ * Quadrature points stay element-major, qp = e (p+1)^3 + qx + (p+1)(qy + (p+1) qz) in
+ * the element's reference coordinates; qp_phase, qp_state, phi_n and the nodal vectors are
+ * as for pf_setup_mesh with n_nodes and n_q = n_elem (p+1)^3. conn is kept by the context
+ * (valid and unchanged for its lifetime). The call reads the table once (host copy,
+ * synchronising `stream`) to build the node-to-(element, local node) map of its
+ * transpose, computes the geometry record (80 bytes per point) and allocates the element
+ * vectors (n_elem x 4 (p+1)^3 doubles). The FP64 residual, Jacobian and adjoint then
+ * gather through the table and scatter deterministically: each element vector is stored,
+ * and every node sums its entries in element order (no atomics). The multigrid, the
+ * Newton step, the state commit, extra branches, pf_set_geometry and
+ * pf_apply_adjoint_noalloc need the box lattice and return PF_EUNSUPPORTED on such a
+ * context. Errors: PF_EINVAL for a node id outside 0..n_nodes-1, an inverted element
+ * (det J <= 0), a phase id >= n_phases or sizes beyond 32-bit indices;
+ * PF_EUNSUPPORTED for p other than 2, 3; PF_ENOMEM, PF_EHIP. */
+pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* conn, const double* X,
+                              const pf_phase* phases, int n_phases, const pf_fracture* fracture,
+                              const uint8_t* qp_phase, const double* qp_state, const double* phi_n,
+                              void* stream, pf_ctx** out);
+
 /* Sizes of the fine level. Any output pointer may be NULL. */
 pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n_dof);
 
@@ -164,8 +193,15 @@ pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, c
 pf_status pf_set_geometry(pf_ctx* ctx, const double* X, void* stream);
 
 /* Replace the per-phase parameters (Gc, sigma0, visc) from host memory
- * params[n_phases][3]. Takes effect for applies enqueued after the call. */
-pf_status pf_set_params(pf_ctx* ctx, const double* params);
+ * params[n_phases][3] (the material of the residual, Sections 2-3; the parameters the
+ * adjoint differentiates). Stream-ordered and asynchronous: the tables are staged in
+ * pinned host memory owned by the context and copied on `stream`, so applies enqueued
+ * on that stream before the call use the old values and later ones the new; params may
+ * be reused as soon as the call returns. The host waits only when four earlier uploads
+ * are still queued. Values equal to the current ones upload nothing and keep the
+ * linearisation; other values invalidate it. Errors: PF_EINVAL for a negative value,
+ * sigma0 = 0 in a plastic phase or sigma0 above a Voce phase's sigma_inf. */
+pf_status pf_set_params(pf_ctx* ctx, const double* params, void* stream);
 
 /* r = R(z). z, r: device double[4][n_nodes]. */
 pf_status pf_apply_residual(pf_ctx* ctx, const double* z, double* r, void* stream);
@@ -242,23 +278,33 @@ pf_status pf_commit_state_branches(pf_ctx* ctx, const double* z, double* state_o
                                    void* stream);
 
 /* Newton step options: relative tolerance of the linear solve (default 1e-8),
- * FGMRES restart length (30, at most 60), iteration limit (300), and the V-cycle
- * smoother (Chebyshev degree 3, 32 coarsest sweeps). Zero fields take defaults. */
+ * FGMRES restart length (30, at most 60), iteration limit (300), the V-cycle
+ * smoother (Chebyshev degree 3, 32 coarsest sweeps), and the Krylov method:
+ * PF_KRYLOV_FGMRES (0, default; the GMRES of Section 5 with the V-cycle as flexible
+ * right preconditioner) or PF_KRYLOV_CG (1; preconditioned conjugate gradients with
+ * the same V-cycle, which assume a symmetric positive definite system: the coupled
+ * Jacobian is not one in general, so CG stops at the first breakdown, p^T J p <= 0
+ * or r^T M r <= 0, and reports it). Zero fields take defaults. */
+#define PF_KRYLOV_FGMRES 0
+#define PF_KRYLOV_CG 1
 typedef struct {
   double rtol;
   int restart, max_iters, cheb_degree, coarse_sweeps;
-  int reserved[3];
+  int krylov;
+  int reserved[2];
 } pf_newton_opts;
 
-/* Newton step report: FGMRES iterations, convergence flag, ||b|| with b = -M R(z),
- * the FGMRES residual estimate, the true residual ||b - M J dz||, host wall times
- * (linearisation, whole step) in milliseconds, and the number of iterations whose
- * Gram-Schmidt needed the second (refinement) pass. */
+/* Newton step report: Krylov iterations, convergence flag, ||b|| with b = -M R(z),
+ * the solver's residual (FGMRES estimate, CG recurrence), the true residual
+ * ||b - M J dz||, host wall times (linearisation, whole step) in milliseconds, the
+ * number of FGMRES iterations whose Gram-Schmidt needed the second (refinement) pass,
+ * the Krylov method used, and whether CG broke down. */
 typedef struct {
   int iterations, converged;
   double res0, res_lin, res_true;
   double t_linearize_ms, t_total_ms;
   int refinements;
+  int krylov, breakdown;
 } pf_newton_stats;
 
 /* One Newton update z += dz of the coupled problem with the Dirichlet faces of

@@ -115,6 +115,16 @@ __device__ inline BrickGeom decode_brick_lin(const MeshDev& m, int b) {
   return g;
 }
 
+// Table restriction: groups of 8 consecutive elements, XCD-aware. Workgroup id w runs on
+// XCD w % 8; group (w % 8) * per + w / 8 gives every XCD one contiguous range of groups,
+// processed in order, so elements that are neighbours in the element order share its L2.
+__host__ __device__ inline int xcd_grid_groups(int n_groups) { return ((n_groups + 7) / 8) * 8; }
+__device__ inline int xcd_group(int n_groups, int id) {
+  const int per = (n_groups + 7) / 8;
+  const int gr = (id & 7) * per + (id >> 3);
+  return gr < n_groups ? gr : -1;
+}
+
 __host__ __device__ inline int bricks_in_colour(int nbx, int nby, int nbz, int colour) {
   const int cx = colour & 1, cy = (colour >> 1) & 1, cz = (colour >> 2) & 1;
   return ((nbx - cx + 1) / 2) * ((nby - cy + 1) / 2) * ((nbz - cz + 1) / 2);

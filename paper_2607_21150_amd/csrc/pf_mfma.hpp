@@ -299,18 +299,33 @@ __device__ inline int64_t lane_node(const BrickGeom& g, int sx, int sy, int sz, 
   return (int64_t)((g.ex0 + sx) * p + x) + (int64_t)nx1 * (((g.ey0 + sy) * p + y) + (int64_t)ny1 * ((g.ez0 + sz) * p + z));
 }
 
+// Table restriction: global node of lane (x, y, z) of element e, -1 outside its P^3 nodes.
+template <int P>
+__device__ inline int64_t tab_lane_node(const OpArgs& a, int64_t e) {
+  const int l = threadIdx.x & 63;
+  const int x = l & 3, y = (l >> 2) & 3, z = l >> 4;
+  if (x >= P || y >= P || z >= P) return -1;
+  return a.conn[e * (P * P * P) + x + P * (y + P * z)];
+}
+
 // FP64 residual / Jacobian / adjoint on Q3 elements with matrix-core sum factorisation.
 // GEO: mapped elements, each point's J^-1 and weight read from the geometry record a.qd.
-template <int MODE, bool BB, bool VOCE, bool MB, bool GEO>
+// TAB: table restriction (with GEO): the workgroup takes a group of 8 consecutive elements,
+// lane l of an element reads global node a.conn[e * 64 + l], and the element vector goes
+// straight to a.evec (summed per node afterwards by k_gather_csr).
+template <int MODE, bool BB, bool VOCE, bool MB, bool GEO, bool TAB = false>
 __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+  static_assert(!TAB || (GEO && !MB), "the table restriction runs on mapped elements without branches");
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
   __shared__ double mbs[MB ? 18 * NT : 1];  // branches in parallel: G and W (or Pb) per thread
   const Slot9 sG{mbs + threadIdx.x, NT}, sW{mbs + 9 * NT + threadIdx.x, NT};
-  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
-  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
+  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4); TAB: the
+  // workgroup's group of 8 elements
+  const int brick = TAB ? xcd_group(a.n_groups, blockIdx.x)
+                        : (BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x));
   if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
+  const BrickGeom g = TAB ? BrickGeom{} : (BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick));
   const Basis4 bs = load_basis4<4>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qx = l & 3, qz = (l >> 2) & 3, qy = l >> 4;
@@ -324,13 +339,15 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     gpid[wv * 64 + l] = 255;
     gpid[(wv + 4) * 64 + l] = 255;
   }
-  bool any_bad = false;
+  bool any_bad = false, bad_pid = false;
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
     const int slot = wv + 4 * half;
     const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
-    if (!(sx < g.nex && sy < g.ney && sz < g.nez)) continue;  // uniform per wave
-    const int64_t gn = lane_node<4>(g, sx, sy, sz, a.nx1, a.ny1);
+    if (TAB ? (int64_t)brick * 8 + slot >= a.n_elem : !(sx < g.nex && sy < g.ney && sz < g.nez)) continue;  // uniform per wave
+    const int64_t e = TAB ? (int64_t)brick * 8 + slot
+                          : (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
+    const int64_t gn = TAB ? tab_lane_node<4>(a, e) : lane_node<4>(g, sx, sy, sz, a.nx1, a.ny1);
     // gather the element's nodal values (lane = node)
     double zu[4], wu[4], pn = 0.0;
 #pragma unroll
@@ -342,7 +359,6 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       pn = a.phin[gn];
     }
     // per-point state, issued early
-    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + sz));
     const int64_t gq = e * 64 + ql;
     double st[8];
 #pragma unroll
@@ -371,7 +387,8 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       sf4_fwd_n<1>(&pn, bs, 0x1u, 0x0u, v, d);
       phin = v[0];
     }
-    // pointwise function
+    // pointwise function (an id outside the phase table raises the phase flag)
+    bad_pid |= pid >= a.nph;
     const int pidc = pid < a.nph ? pid : 0;
     const MatParams<double> mp = a.mats[pidc];
     // branches in parallel, adjoint: the extra branches' psi^+ decides the switch
@@ -462,7 +479,12 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
       phys_to_ref<GEO>(f1, ih, gA, b1[3]);
       sf4_bwd_n<4>(b0, b1, 0x8u, bs, r);
 #pragma unroll
-      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];
+      for (int f = 0; f < 4; ++f) {
+        if (TAB)
+          a.evec[(e * 4 + f) * 64 + l] = r[f];
+        else
+          ev[(slot * 4 + f) * 64 + l] = r[f];
+      }
     }
   }
   if (MODE == M_ADJ) {
@@ -505,11 +527,14 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
     }
   }
   __syncthreads();
-  if (BB)
+  if (TAB) {
+  } else if (BB) {
     store_brick4<double, 4, 4>(ev, a.m, g, a.ebuf);
-  else
+  } else {
     scatter_brick4<double, 4, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  }
   if (any_bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
 }
 
 }  // namespace pfmf
@@ -521,24 +546,30 @@ namespace pfmf {
 // 4 x 4 (one element per pass, 27 of 64 lanes carry points); the pointwise function
 // then runs on a packed layout holding both elements of the wave (lanes 0-26 and
 // 32-58), moved there and back by lane permutes, so that it is evaluated once for
-// two elements. GEO: mapped elements (J^-1 and weight per point from a.qd).
-template <int MODE, bool BB, bool VOCE, bool MB, bool GEO>
+// two elements. GEO: mapped elements (J^-1 and weight per point from a.qd). TAB: table
+// restriction (with GEO): a group of 8 consecutive elements per workgroup (wave w: elements
+// w and w + 4), nodes from a.conn, element vectors straight to a.evec [n_elem][4][27].
+template <int MODE, bool BB, bool VOCE, bool MB, bool GEO, bool TAB = false>
 __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
                                                                               DevTables* __restrict__ tabs) {
+  static_assert(!TAB || (GEO && !MB), "the table restriction runs on mapped elements without branches");
   __shared__ double ev[8 * 4 * 64];
   __shared__ double red[NT];
   __shared__ double mbs[MB ? 18 * NT : 1];  // branches in parallel: G and W (or Pb) per thread
   const Slot9 sG{mbs + threadIdx.x, NT}, sW{mbs + 9 * NT + threadIdx.x, NT};
-  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4)
-  const int brick = BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x);
+  // BB: all bricks in one launch, brick sums to a buffer (see store_brick4); TAB: the
+  // workgroup's group of 8 elements
+  const int brick = TAB ? xcd_group(a.n_groups, blockIdx.x)
+                        : (BB ? xcd_brick_all(a.m, blockIdx.x) : xcd_brick(a.m, colour, blockIdx.x));
   if (brick < 0) return;  // padding workgroup (uniform)
-  const BrickGeom g = BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick);
+  const BrickGeom g = TAB ? BrickGeom{} : (BB ? decode_brick_lin(a.m, brick) : decode_brick(a.m, colour, brick));
   const Basis4 bs = load_basis_pq<3, 3>(tabs);
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // the wave's two elements: slot wv (sz = 0) and slot wv + 4 (sz = 1)
   const int sx = wv & 1, sy = wv >> 1;
-  const bool hasA = sx < g.nex && sy < g.ney;  // uniform per wave
-  const bool hasB = hasA && g.nez > 1;
+  const int64_t e0 = (int64_t)brick * 8 + wv;  // TAB: elements e0 (half 0) and e0 + 4 (half 1)
+  const bool hasA = TAB ? e0 < a.n_elem : sx < g.nex && sy < g.ney;  // uniform per wave
+  const bool hasB = TAB ? e0 + 4 < a.n_elem : hasA && g.nez > 1;
   // packed layout: lane l holds point q = l & 31 (q < 27) of element E = l >> 5
   const int E = l >> 5, q = l & 31;
   const int cqx = q % 3, cqy = (q / 3) % 3, cqz = q / 9;
@@ -551,7 +582,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
   const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
   const double wbox = tabs->w[3][cqx < 3 ? cqx : 0] * tabs->w[3][cqy] * tabs->w[3][cqz] *
                       a.m.jdet;
-  bool any_bad = false;
+  bool any_bad = false, bad_pid = false;
   int pid = 255;
   double gsum[3] = {0.0, 0.0, 0.0};
   if (hasA) {
@@ -561,7 +592,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       if (half == 1 && !hasB) break;  // uniform
-      const int64_t gn = lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
+      const int64_t gn = TAB ? tab_lane_node<3>(a, e0 + 4 * half) : lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
       double zu[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) zu[f] = gn >= 0 ? a.z[f * a.n_nodes + gn] : 0.0;
@@ -592,7 +623,8 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
       }
     }
     // ---- per-point state (packed layout)
-    const int64_t e = (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
+    const int64_t e = TAB ? e0 + 4 * E
+                          : (int64_t)(g.ex0 + sx) + (int64_t)a.m.nx * ((g.ey0 + sy) + (int64_t)a.m.ny * (g.ez0 + E));
     const int64_t gq = e * 27 + q;
     double st[8];
 #pragma unroll
@@ -613,6 +645,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
       const double dp[3] = {gphi[0], gphi[1], gphi[2]};
       ref_to_phys<true>(dp, ih, gA, gphi);
     }
+    bad_pid |= valid && pid >= a.nph;
     const int pidc = pid < a.nph ? pid : 0;
     const MatParams<double> mp = a.mats[pidc];
     // branches in parallel (flags of lanes without a point are dropped)
@@ -630,7 +663,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         if (half == 1 && !hasB) break;
-        const int64_t gn = lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
+        const int64_t gn = TAB ? tab_lane_node<3>(a, e0 + 4 * half) : lane_node<3>(g, sx, sy, half, a.nx1, a.ny1);
         double wu[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) wu[f] = gn >= 0 ? a.w[f * a.n_nodes + gn] : 0.0;
@@ -746,8 +779,18 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
       }
       sf4_bwd_n<4>(b0, b1, 0x8u, bs, r);
       const int slot = wv + 4 * half;
+      if (TAB) {
+        // nodal layout (x, y, z) = lane bits (0-1, 2-3, 4-5); 27 of 64 lanes hold a node
+        const int nx_ = l & 3, ny_ = (l >> 2) & 3, nz_ = l >> 4;
+        if (nx_ < 3 && ny_ < 3 && nz_ < 3) {
+          const int64_t eh = e0 + 4 * half;
 #pragma unroll
-      for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];
+          for (int f = 0; f < 4; ++f) a.evec[(eh * 4 + f) * 27 + nx_ + 3 * ny_ + 9 * nz_] = r[f];
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + l] = r[f];
+      }
     }
   }
   if (MODE == M_ADJ) {
@@ -783,11 +826,14 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
     }
   }
   __syncthreads();
-  if (BB)
+  if (TAB) {
+  } else if (BB) {
     store_brick4<double, 3, 4>(ev, a.m, g, a.ebuf);
-  else
+  } else {
     scatter_brick4<double, 3, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
+  }
   if (any_bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
 }
 
 }  // namespace pfmf

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
   const int t = threadIdx.x;
   const int el = t / Q3, ql = t % Q3;
   const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
-  bool any_bad = false;
+  bool any_bad = false, bad_pid = false;
   for (int r = 0; r < S::ROUNDS; ++r) {
     const int slot0 = r * ER, slot = slot0 + el;
     const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
@@ -195,6 +195,7 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
 #pragma unroll
       for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];
       const int pid = a.phase[gq];
+      bad_pid |= pid >= a.nph;  // an id outside the phase table raises the phase flag
       const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
       QPState<double> s;
       qp_state<double>(mp, a.fr, G, phi, 0.0, st, s);
@@ -294,6 +295,7 @@ __global__ __launch_bounds__(NT) void k_linearize(LinArgs a, int colour, DevTabl
     }
   }
   if (any_bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
 }
 
 // ---------------------------------------------------------------------------

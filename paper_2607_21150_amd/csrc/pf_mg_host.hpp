@@ -58,20 +58,36 @@ pf_status upload(T** dst, const std::vector<T>& v) {
   return PF_OK;
 }
 
+pf_status mg_alloc_levels(pf_ctx* c, const int* orders, int nl);
+
 pf_status mg_alloc(pf_ctx* c) {
   MGState& mg = c->mg;
   if (mg.n_levels > 0) return PF_OK;
   const int p = c->mesh.p;
   int orders[5];
+  int nl;
   if (c->n_orders > 0) {
-    mg.n_levels = c->n_orders;
+    nl = c->n_orders;
     for (int l = 0; l < c->n_orders; ++l) orders[l] = c->orders[l];
   } else {
-    mg.n_levels = p;
+    nl = p;
     for (int l = 0; l < p; ++l) orders[l] = p - l;
   }
+  // n_levels becomes nl only once every buffer exists; on a failure the partial
+  // hierarchy is freed (mg_free) and n_levels stays 0, so a later call starts over
+  pf_status st = mg_alloc_levels(c, orders, nl);
+  if (st != PF_OK) {
+    mg_free(mg);
+    return st;
+  }
+  mg.n_levels = nl;
+  return PF_OK;
+}
+
+pf_status mg_alloc_levels(pf_ctx* c, const int* orders, int nl) {
+  MGState& mg = c->mg;
   const int N[3] = {c->mesh.nx, c->mesh.ny, c->mesh.nz};
-  for (int l = 0; l < mg.n_levels; ++l) {
+  for (int l = 0; l < nl; ++l) {
     MGLevel& L = mg.lv[l];
     L.p = orders[l];
     L.P = L.p + 1;
@@ -83,7 +99,7 @@ pf_status mg_alloc(pf_ctx* c) {
     float** bufs[] = {&L.x, &L.r, &L.d, &L.t, &L.b, &L.diag, &L.dinv};
     for (float** b : bufs)
       if (hipMalloc(b, nb) != hipSuccess) return fail(PF_ENOMEM, "multigrid level allocation failed");
-    if (l + 1 < mg.n_levels) {
+    if (l + 1 < nl) {
       for (int k = 0; k < 3; ++k) {
         std::vector<int> pb, rb;
         std::vector<float> pw, rw;
@@ -95,12 +111,12 @@ pf_status mg_alloc(pf_ctx* c) {
       }
     }
   }
-  if (mg.lv[mg.n_levels - 1].p == 1) {
+  if (mg.lv[nl - 1].p == 1) {
     const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
     if (hipMalloc(&mg.ebe, (size_t)n_elem * 1024 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&mg.stencil, (size_t)27 * 16 * mg.lv[mg.n_levels - 1].n_nodes * sizeof(float)) != hipSuccess)
+        hipMalloc(&mg.stencil, (size_t)27 * 16 * mg.lv[nl - 1].n_nodes * sizeof(float)) != hipSuccess)
       return fail(PF_ENOMEM, "coarse element matrices: allocation failed");
-    mg.ebe_level = mg.n_levels - 1;
+    mg.ebe_level = nl - 1;
   }
   const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
   if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
@@ -540,6 +556,7 @@ extern "C" {
 pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_linearize"))) return st;
   if (!z) return fail(PF_EINVAL, "null z");
   if (c->n_extra > 0 && c->mesh.p < 2) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
   hipStream_t s = (hipStream_t)stream;
@@ -638,6 +655,7 @@ namespace {
 pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xstate_out, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "the state commit"))) return st;
   if (!z || !state_out) return fail(PF_EINVAL, "null argument");
   const size_t ns = 8 * c->n_q * sizeof(double);
   const size_t nz = 4 * c->n_nodes * sizeof(double);
@@ -696,6 +714,7 @@ pf_status commit_state(pf_ctx* c, const double* z, double* state_out, double* xs
 extern "C" {
 
 pf_status pf_commit_state(pf_ctx* c, const double* z, double* state_out, void* stream) {
+  if (c && c->table) return fail(PF_EUNSUPPORTED, "the state commit needs the box lattice");
   if (c && c->n_extra > 0)
     return fail(PF_EUNSUPPORTED, "extra branches attached: use pf_commit_state_branches");
   return commit_state(c, z, state_out, nullptr, stream);
@@ -711,6 +730,7 @@ pf_status pf_commit_state_branches(pf_ctx* c, const double* z, double* state_out
 pf_status pf_set_pmg_levels(pf_ctx* c, const int* orders, int n_levels) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_set_pmg_levels"))) return st;
   if (n_levels < 0 || n_levels > 5) return fail(PF_EINVAL, "n_levels=%d outside 0..5", n_levels);
   if (n_levels > 0 && !orders) return fail(PF_EINVAL, "null orders");
   if (n_levels > 0) {
@@ -729,6 +749,7 @@ pf_status pf_set_pmg_levels(pf_ctx* c, const int* orders, int n_levels) {
 pf_status pf_set_dirichlet(pf_ctx* c, const uint32_t* face_fields) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_set_dirichlet"))) return st;
   if (!face_fields) return fail(PF_EINVAL, "null face_fields");
   bool any = false;
   for (int k = 0; k < 6; ++k) {

@@ -1,9 +1,11 @@
 // Host side of the Newton step (included at the end of pfmf.hip): one Newton update
-// of the coupled residual with flexible GMRES (right preconditioning, restarted),
-// the FP64 Jacobian apply as the Krylov operator and one FP32 p-multigrid V-cycle
-// at the FP64 linearisation as the preconditioner. Every vector operation runs in
+// of the coupled residual with flexible GMRES (right preconditioning, restarted) or,
+// on request, preconditioned conjugate gradients, the FP64 Jacobian apply as the
+// Krylov operator and one FP32 p-multigrid V-cycle at the FP64 linearisation as the
+// preconditioner. Every vector operation runs in
 // the kernels of pf_step.hpp; the host holds only the small Hessenberg system.
 #pragma once
+#include <algorithm>
 #include <chrono>
 
 namespace {
@@ -104,23 +106,27 @@ extern "C" {
 pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newton_stats* out, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_newton_step"))) return st;
   if (!z) return fail(PF_EINVAL, "null z");
   // 32 coarsest-level sweeps: cheap with the element-matrix coarse level, and they
   // cut the FGMRES iterations by 2.5x against 4 sweeps on the Q4 box
-  pf_newton_opts opt{1e-8, 30, 300, 3, 32, {0, 0, 0}};
+  pf_newton_opts opt{1e-8, 30, 300, 3, 32, PF_KRYLOV_FGMRES, {0, 0}};
   if (o) {
     if (o->rtol > 0) opt.rtol = o->rtol;
     if (o->restart > 0) opt.restart = o->restart;
     if (o->max_iters > 0) opt.max_iters = o->max_iters;
     if (o->cheb_degree > 0) opt.cheb_degree = o->cheb_degree;
     if (o->coarse_sweeps > 0) opt.coarse_sweeps = o->coarse_sweeps;
+    opt.krylov = o->krylov;
   }
+  if (opt.krylov != PF_KRYLOV_FGMRES && opt.krylov != PF_KRYLOV_CG)
+    return fail(PF_EINVAL, "krylov %d is neither PF_KRYLOV_FGMRES nor PF_KRYLOV_CG", opt.krylov);
   if (opt.restart > 60) return fail(PF_EINVAL, "restart %d above 60", opt.restart);
   if (opt.cheb_degree > 32 || opt.coarse_sweeps > 64) return fail(PF_EINVAL, "smoother degree too large");
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const double t0 = now_ms();
-  const int m = opt.restart;
+  const int m = std::max(opt.restart, 2);  // CG takes r, p, q from V and its z from Z
   if ((st = newton_alloc(c, m))) return st;
   const int64_t n = 4 * c->n_nodes;
   const int g = vec_grid(n);
@@ -149,10 +155,51 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
   const double t2 = now_ms();
   const pf_pmg_opts po{opt.cheb_degree, c->mg.lv[c->mg.n_levels - 1].p, opt.coarse_sweeps, 0};
   int its = 0, refinements = 0;
-  bool conv = bnorm == 0.0;
+  bool conv = bnorm == 0.0, breakdown = false;
   double res = bnorm;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), h(m + 1), h2(m + 1), y(m);
-  while (!conv && its < opt.max_iters) {
+  if (opt.krylov == PF_KRYLOV_CG && !conv) {
+    // preconditioned conjugate gradients on M J dz = b with the same V-cycle. CG assumes a
+    // symmetric positive definite operator and preconditioner; the coupled Jacobian is
+    // neither in general (s_phi-scaled damage rows, history switch, softening), so the
+    // iteration stops at the first p^T J p <= 0 or r^T M r <= 0 (breakdown) or at the limit.
+    double* r = V;
+    double* p = V + n;
+    double* q = V + 2 * n;
+    double* zc = Z;
+    hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, rhs, r, n, 0);
+    if ((st = precondition(c, r, zc, po, s))) return st;
+    hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, zc, p, n, 0);
+    HIPCHK(hipGetLastError());
+    double rz;
+    if ((st = mdot(c, r, n, 1, zc, n, s, &rz))) return st;
+    breakdown = !(rz > 0.0);
+    while (!breakdown && its < opt.max_iters) {
+      if ((st = masked_jacobian(c, z, p, q, s))) return st;
+      double pq;
+      if ((st = mdot(c, p, n, 1, q, n, s, &pq))) return st;
+      if (!(pq > 0.0)) { breakdown = true; break; }
+      const double alpha = rz / pq;
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, alpha, p, dz, n, 1);
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, -alpha, q, r, n, 1);
+      HIPCHK(hipGetLastError());
+      ++its;
+      double rr;
+      if ((st = mdot(c, r, n, 1, r, n, s, &rr))) return st;
+      res = std::sqrt(rr);
+      if (res <= opt.rtol * bnorm) { conv = true; break; }
+      if ((st = precondition(c, r, zc, po, s))) return st;
+      double rz1;
+      if ((st = mdot(c, r, n, 1, zc, n, s, &rz1))) return st;
+      if (!(rz1 > 0.0)) { breakdown = true; break; }
+      const double beta = rz1 / rz;
+      rz = rz1;
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, beta, p, p, n, 0);
+      hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0, zc, p, n, 1);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  while (opt.krylov == PF_KRYLOV_FGMRES && !conv && its < opt.max_iters) {
     // r = b - J dz (dz = 0 on the first cycle)
     double beta;
     if (its == 0) {
@@ -170,7 +217,7 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int k = 0;
-    for (; k < m && its < opt.max_iters; ++k, ++its) {
+    for (; k < opt.restart && its < opt.max_iters; ++k, ++its) {
       double* Vk = V + (int64_t)k * n;
       double* Zk = Z + (int64_t)k * n;
       double* Vn = V + (int64_t)(k + 1) * n;
@@ -252,9 +299,12 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
     out->t_linearize_ms = t2 - t1;
     out->t_total_ms = t3 - t0;
     out->refinements = refinements;
+    out->krylov = opt.krylov;
+    out->breakdown = breakdown ? 1 : 0;
   }
-  return conv ? PF_OK : fail(PF_ENOCONV, "FGMRES did not reach rtol %.1e in %d iterations (%.3e)", opt.rtol,
-                             its, bnorm > 0 ? res / bnorm : 0.0);
+  return conv ? PF_OK : fail(PF_ENOCONV, "%s did not reach rtol %.1e in %d iterations (%.3e%s)",
+                             opt.krylov == PF_KRYLOV_CG ? "CG" : "FGMRES", opt.rtol, its,
+                             bnorm > 0 ? res / bnorm : 0.0, breakdown ? ", breakdown" : "");
 }
 
 }  // extern "C"

@@ -38,6 +38,13 @@ struct OpArgs {
   const double* xstate; // their states [7*n_extra][n_q]: D[6], ebar_p per branch
   int n_extra;
   const double* qd;     // mapped elements: per-point geometry [10][n_q] (null: the box)
+  // table restriction (pf_setup_mesh_table): element e's local node a is global node
+  // conn[e * P^3 + a]; element vectors go to evec [n_elem][4][P^3], summed per node by
+  // k_gather_csr; elements are taken in groups of 8 per workgroup
+  const int32_t* conn;
+  int64_t n_elem;
+  double* evec;
+  int n_groups;
 };
 
 template <int P, int Q> struct OpShape {
@@ -87,7 +94,7 @@ __global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colou
   const double jdet = a.m.jdet;
   double gsum[3] = {0.0, 0.0, 0.0};   // adjoint parameter partials of this thread
   int my_pid = -1;
-  bool any_bad = false;
+  bool any_bad = false, bad_pid = false;
 
   // tmp sub-arrays
   double* xb = tmp;
@@ -172,6 +179,7 @@ __global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colou
 #pragma unroll
       for (int k = 0; k < 8; ++k) st[k] = a.state[k * a.n_q + gq];
       const int pid = a.phase[gq];
+      bad_pid |= pid >= a.nph;  // an id outside the phase table raises the phase flag
       const MatParams<double> mp = a.mats[pid < a.nph ? pid : 0];
       QPState<double> s;
       qp_state<double>(mp, a.fr, G, phi, phin, st, s);
@@ -274,6 +282,15 @@ __global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colou
   }
   scatter_brick<double, P, 4>(ev, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (any_bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
+}
+
+// flag[1] = 1 when some phase id is outside the phase table [0, nph).
+__global__ void k_check_phase(const uint8_t* __restrict__ ph, int64_t n, int nph, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= ph[i] >= nph;
+  if (bad) flag[1] = 1;
 }
 
 // Deterministic final sum of per-brick parameter partials: out[ph*3+k] = sum_b gpart[b][ph][k].

@@ -315,6 +315,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   QPState<double> s;
   qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
   bool bad = pt && s.bad;
+  const bool bad_pid = pt && pid >= a.nph;  // an id outside the phase table raises the phase flag
   double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
   if (MODE != M_RES) {
     gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
@@ -425,6 +426,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     }
   }
   if (bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
 }
 
 // FP32 level apply (direction on a level with PC nodes per direction, kinematics on the

@@ -24,6 +24,7 @@ namespace {
 
 thread_local std::string g_err;
 
+
 pf_status fail(pf_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -76,8 +77,26 @@ struct pf_ctx {
   double* d_ebuf = nullptr;  // brick-buffer scatter (allocated on first use)
   int scatter_mode = 0;      // PF_OPT_SCATTER
   bool store_lin64 = true;   // PF_OPT_STORE_LIN64
-  int* d_flag = nullptr;
+  // table restriction (pf_setup_mesh_table): element-to-node table (caller's), the node ->
+  // (element, local node) CSR map of its transpose, the element vectors, element groups
+  bool table = false;
+  const int32_t* conn = nullptr;
+  int64_t n_elem = 0;
+  int n_groups = 0;
+  int32_t* d_csr_off = nullptr;
+  int32_t* d_csr_ent = nullptr;
+  double* d_evec = nullptr;
+  int* d_flag = nullptr;      // [0] non-physical point, [1] phase id outside the table
   hipStream_t last_stream = nullptr;
+  // pf_set_params: pinned staging slots, each reused once its last copy has run
+  static constexpr int PARAM_RING = 4;
+  struct ParamSlot {
+    MatParams<double>* h64 = nullptr;
+    MatParams<float>* h32 = nullptr;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+  } pslot[PARAM_RING];
+  int pnext = 0;
   MGState mg;
   // multigrid level orders (fine first); n_orders = 0 means p, p-1, ..., 1
   int orders[5] = {0, 0, 0, 0, 0};
@@ -174,6 +193,33 @@ pf_status upload_mats(pf_ctx* c) {
   }
   HIPCHK(hipMemcpy(c->d_mats, md.data(), md.size() * sizeof(md[0]), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_matsf, mf.data(), mf.size() * sizeof(mf[0]), hipMemcpyHostToDevice));
+  return PF_OK;
+}
+
+// Stream-ordered upload of the material tables: the tables are written into a pinned
+// staging slot and copied on stream s, so applies enqueued before the call on s read the
+// old values and later ones the new. A slot is rewritten only after its previous copy
+// ran (an event per slot; the host waits only when PARAM_RING uploads are still queued).
+pf_status upload_mats_async(pf_ctx* c, hipStream_t s) {
+  const size_t nph = c->phases.size();
+  pf_ctx::ParamSlot& ps = c->pslot[c->pnext];
+  if (!ps.h64) {
+    if (hipHostMalloc((void**)&ps.h64, nph * sizeof(MatParams<double>), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ps.h32, nph * sizeof(MatParams<float>), hipHostMallocDefault) != hipSuccess)
+      return fail(PF_ENOMEM, "pinned parameter staging: allocation failed");
+    HIPCHK(hipEventCreateWithFlags(&ps.ev, hipEventDisableTiming));
+  } else if (ps.used) {
+    HIPCHK(hipEventSynchronize(ps.ev));
+  }
+  for (size_t i = 0; i < nph; ++i) {
+    ps.h64[i] = mat_params<double>(c->phases[i], c->fr);
+    ps.h32[i] = mat_params<float>(c->phases[i], c->fr);
+  }
+  HIPCHK(hipMemcpyAsync(c->d_mats, ps.h64, nph * sizeof(MatParams<double>), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_matsf, ps.h32, nph * sizeof(MatParams<float>), hipMemcpyHostToDevice, s));
+  HIPCHK(hipEventRecord(ps.ev, s));
+  ps.used = true;
+  c->pnext = (c->pnext + 1) % pf_ctx::PARAM_RING;
   return PF_OK;
 }
 
@@ -329,8 +375,30 @@ pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
                      : launch_op64_q4_v<MODE, false, false, false>(c, a, s);
 }
 
+// Table restriction: one launch over the element groups (element vectors to c->d_evec),
+// then the node-owner gather into the output.
+template <int MODE, int P, bool VOCE>
+pf_status launch_op64_tab_v(pf_ctx* c, OpArgs a, hipStream_t s) {
+  const int ng = xcd_grid_groups(c->n_groups);
+  if constexpr (P == 4)
+    hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+  else
+    hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+  HIPCHK(hipGetLastError());
+  const int gb = (int)std::min<int64_t>((c->n_nodes + NT - 1) / NT, 1 << 16);
+  hipLaunchKernelGGL(k_gather_csr, dim3(gb), dim3(NT), 0, s, (const double*)c->d_evec, (const int32_t*)c->d_csr_off,
+                     (const int32_t*)c->d_csr_ent, c->n_nodes, P * P * P, a.out);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
 template <int MODE>
 pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if (c->table) {
+    if (c->mesh.p == 2)
+      return c->has_voce ? launch_op64_tab_v<MODE, 3, true>(c, a, s) : launch_op64_tab_v<MODE, 3, false>(c, a, s);
+    return c->has_voce ? launch_op64_tab_v<MODE, 4, true>(c, a, s) : launch_op64_tab_v<MODE, 4, false>(c, a, s);
+  }
   switch (c->mesh.p) {
     case 1:
       if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
@@ -366,7 +434,17 @@ OpArgs op_args(pf_ctx* c) {
   a.xstate = c->xstate;
   a.n_extra = c->n_extra;
   a.qd = c->d_qd;
+  a.conn = c->conn;
+  a.n_elem = c->n_elem;
+  a.evec = c->d_evec;
+  a.n_groups = c->n_groups;
   return a;
+}
+
+// Calls that need the box lattice refuse a table-restriction context.
+pf_status box_only(const pf_ctx* c, const char* what) {
+  if (c->table) return fail(PF_EUNSUPPORTED, "%s needs the box lattice (the context has a table restriction)", what);
+  return PF_OK;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -381,6 +459,63 @@ extern "C" {
 
 const char* pf_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both setup calls: phases, fracture parameters.
+pf_status check_materials(const pf_phase* phases, int n_phases, const pf_fracture* fr) {
+  if (n_phases < 1 || n_phases > 255) return fail(PF_EINVAL, "n_phases=%d outside 1..255", n_phases);
+  if (!(fr->l0 > 0 && fr->dt > 0 && fr->eta >= 0 && fr->s_phi > 0) || (fr->at != 1 && fr->at != 2))
+    return fail(PF_EINVAL, "bad fracture parameters");
+  for (int i = 0; i < n_phases; ++i) {
+    const pf_phase& p = phases[i];
+    if (!(p.E > 0 && p.nu > -1 && p.nu < 0.5 && p.Gc >= 0 && p.sigma0 >= 0 && p.H >= 0 && p.visc >= 0))
+      return fail(PF_EINVAL, "bad parameters for phase %d", i);
+    if (p.plastic && !(p.sigma0 > 0)) return fail(PF_EINVAL, "plastic phase %d needs sigma0 > 0", i);
+    if (!(p.voce_beta >= 0) || (p.voce_beta > 0 && !(p.sigma_inf >= p.sigma0)))
+      return fail(PF_EINVAL, "phase %d: Voce needs voce_beta >= 0 and sigma_inf >= sigma0", i);
+  }
+  return PF_OK;
+}
+
+// The rest of a context once its sizes are set: tables, materials, partials, flags and
+// the check of the phase ids (stream-ordered after the caller's writes; synchronises).
+pf_status setup_common(pf_ctx* c, const pf_phase* phases, int n_phases, const pf_fracture* fr,
+                       const uint8_t* qp_phase, const double* qp_state, const double* phi_n, void* stream) {
+  c->phases.assign(phases, phases + n_phases);
+  for (int i = 0; i < n_phases; ++i) c->has_voce |= phases[i].plastic && phases[i].voce_beta > 0;
+  c->fr = *fr;
+  c->qp_phase = qp_phase;
+  c->qp_state = qp_state;
+  c->phi_n = phi_n;
+  c->last_stream = (hipStream_t)stream;
+  pf_status st = build_tables(c);
+  if (st != PF_OK) return st;
+  if (hipMalloc(&c->d_mats, n_phases * sizeof(MatParams<double>)) != hipSuccess ||
+      hipMalloc(&c->d_matsf, n_phases * sizeof(MatParams<float>)) != hipSuccess ||
+      hipMalloc(&c->d_gpart, (size_t)c->n_parts * n_phases * 3 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_flag, 2 * sizeof(int)) != hipSuccess)
+    return fail(PF_ENOMEM, "context allocation failed");
+  if (hipMemset(c->d_flag, 0, 2 * sizeof(int)) != hipSuccess) return fail(PF_EHIP, "memset failed");
+  st = upload_mats(c);
+  if (st != PF_OK) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  int bad = 0;
+  hipLaunchKernelGGL(k_check_phase, dim3((unsigned)std::min<int64_t>((c->n_q + NT - 1) / NT, 4096)), dim3(NT), 0, s,
+                     qp_phase, c->n_q, n_phases, c->d_flag);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(PF_EHIP, "phase check: %s", hipGetErrorString(e));
+  if (bad) return fail(PF_EINVAL, "qp_phase holds an id >= n_phases (%d)", n_phases);
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_phases, const pf_fracture* fr,
                         const uint8_t* qp_phase, const double* qp_state, const double* phi_n, void* stream,
                         pf_ctx** out) {
@@ -391,20 +526,11 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
   if (mesh->p < 1 || mesh->p > 4) return fail(PF_EUNSUPPORTED, "order p=%d outside 1..4", mesh->p);
   if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(PF_EINVAL, "empty mesh");
   if (!(mesh->lx > 0 && mesh->ly > 0 && mesh->lz > 0)) return fail(PF_EINVAL, "box lengths must be positive");
-  if (n_phases < 1 || n_phases > 255) return fail(PF_EINVAL, "n_phases=%d outside 1..255", n_phases);
-  if (!(fr->l0 > 0 && fr->dt > 0 && fr->eta >= 0 && fr->s_phi > 0) || (fr->at != 1 && fr->at != 2))
-    return fail(PF_EINVAL, "bad fracture parameters");
+  pf_status st0 = check_materials(phases, n_phases, fr);
+  if (st0) return st0;
   const int64_t nx1 = (int64_t)mesh->p * mesh->nx + 1, ny1 = (int64_t)mesh->p * mesh->ny + 1,
                 nz1 = (int64_t)mesh->p * mesh->nz + 1;
   if (nx1 * ny1 * nz1 >= (int64_t)1 << 31) return fail(PF_EINVAL, "mesh too large for 32-bit node ids");
-  for (int i = 0; i < n_phases; ++i) {
-    const pf_phase& p = phases[i];
-    if (!(p.E > 0 && p.nu > -1 && p.nu < 0.5 && p.Gc >= 0 && p.sigma0 >= 0 && p.H >= 0 && p.visc >= 0))
-      return fail(PF_EINVAL, "bad parameters for phase %d", i);
-    if (p.plastic && !(p.sigma0 > 0)) return fail(PF_EINVAL, "plastic phase %d needs sigma0 > 0", i);
-    if (!(p.voce_beta >= 0) || (p.voce_beta > 0 && !(p.sigma_inf >= p.sigma0)))
-      return fail(PF_EINVAL, "phase %d: Voce needs voce_beta >= 0 and sigma_inf >= sigma0", i);
-  }
   auto* c = new pf_ctx;
   (void)hipGetDevice(&c->device);
   c->mesh = *mesh;
@@ -424,25 +550,93 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
   c->colour_base[0] = 0;
   for (int col = 0; col < 8; ++col)
     c->colour_base[col + 1] = c->colour_base[col] + bricks_in_colour(c->nbx, c->nby, c->nbz, col);
-  c->phases.assign(phases, phases + n_phases);
-  for (int i = 0; i < n_phases; ++i) c->has_voce |= phases[i].plastic && phases[i].voce_beta > 0;
-  c->fr = *fr;
-  c->qp_phase = qp_phase;
-  c->qp_state = qp_state;
-  c->phi_n = phi_n;
-  c->last_stream = (hipStream_t)stream;
-  pf_status st = build_tables(c);
+  pf_status st = setup_common(c, phases, n_phases, fr, qp_phase, qp_state, phi_n, stream);
   if (st != PF_OK) { pf_destroy(c); return st; }
-  if (hipMalloc(&c->d_mats, n_phases * sizeof(MatParams<double>)) != hipSuccess ||
-      hipMalloc(&c->d_matsf, n_phases * sizeof(MatParams<float>)) != hipSuccess ||
-      hipMalloc(&c->d_gpart, (size_t)c->n_parts * n_phases * 3 * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
-    pf_destroy(c);
-    return fail(PF_ENOMEM, "context allocation failed");
+  *out = c;
+  return PF_OK;
+}
+
+pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* conn, const double* X,
+                              const pf_phase* phases, int n_phases, const pf_fracture* fr, const uint8_t* qp_phase,
+                              const double* qp_state, const double* phi_n, void* stream, pf_ctx** out) {
+  g_err.clear();
+  if (!out) return fail(PF_EINVAL, "out is null");
+  *out = nullptr;
+  if (!mesh || !conn || !X || !phases || !fr || !qp_phase || !qp_state || !phi_n) return fail(PF_EINVAL, "null argument");
+  if (mesh->p != 2 && mesh->p != 3) return fail(PF_EUNSUPPORTED, "table restriction built for p = 2, 3 (p=%d)", mesh->p);
+  const int P = mesh->p + 1, P3 = P * P * P;
+  if (mesh->n_elem < 1 || mesh->n_nodes < 1) return fail(PF_EINVAL, "empty mesh");
+  if (mesh->n_nodes >= ((int64_t)1 << 31) - 1 || mesh->n_elem * 4 * P3 >= ((int64_t)1 << 31))
+    return fail(PF_EINVAL, "mesh too large for 32-bit node and element-vector indices");
+  pf_status st0 = check_materials(phases, n_phases, fr);
+  if (st0) return st0;
+  const hipStream_t s = (hipStream_t)stream;
+  // the table on the host: range check and the CSR map of its transpose (node -> entries
+  // e 4 P^3 + a in element order), built once here
+  std::vector<int32_t> h((size_t)mesh->n_elem * P3);
+  {
+    hipError_t e = hipMemcpyAsync(h.data(), conn, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(PF_EHIP, "reading the element table: %s", hipGetErrorString(e));
   }
-  if (hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess) { pf_destroy(c); return fail(PF_EHIP, "memset failed"); }
-  st = upload_mats(c);
+  std::vector<int32_t> off((size_t)mesh->n_nodes + 1, 0), ent(h.size());
+  for (size_t k = 0; k < h.size(); ++k) {
+    if (h[k] < 0 || h[k] >= mesh->n_nodes)
+      return fail(PF_EINVAL, "element %lld, local node %d: node %d outside 0..%lld", (long long)(k / P3), (int)(k % P3),
+                  h[k], (long long)mesh->n_nodes - 1);
+    ++off[(size_t)h[k] + 1];
+  }
+  for (int64_t i = 0; i < mesh->n_nodes; ++i) off[i + 1] += off[i];
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (size_t k = 0; k < h.size(); ++k) {
+      const int64_t e = (int64_t)(k / P3), a = (int64_t)(k % P3);
+      ent[fill[h[k]]++] = (int32_t)(e * 4 * P3 + a);
+    }
+  }
+  auto* c = new pf_ctx;
+  (void)hipGetDevice(&c->device);
+  c->table = true;
+  c->mesh = pf_mesh_desc{mesh->p, 0, 0, 0, 1.0, 1.0, 1.0};
+  c->P = P;
+  c->Q = P;
+  c->n_nodes = mesh->n_nodes;
+  c->n_elem = mesh->n_elem;
+  c->n_q = mesh->n_elem * P3;
+  c->n_groups = (int)((mesh->n_elem + 7) / 8);
+  c->n_parts = c->n_groups;
+  c->conn = conn;
+  pf_status st = setup_common(c, phases, n_phases, fr, qp_phase, qp_state, phi_n, stream);
   if (st != PF_OK) { pf_destroy(c); return st; }
+  if (hipMalloc(&c->d_csr_off, off.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_csr_ent, ent.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->d_evec, (size_t)c->n_elem * 4 * P3 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_qd, (size_t)GEO_N * c->n_q * sizeof(double)) != hipSuccess) {
+    pf_destroy(c);
+    return fail(PF_ENOMEM, "table restriction: allocation failed");
+  }
+  hipError_t e = hipMemcpyAsync(c->d_csr_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_csr_ent, ent.data(), ent.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_flag, 0, 2 * sizeof(int), s);
+  if (e == hipSuccess) {
+    const dim3 grid((unsigned)((c->n_q + NT - 1) / NT));
+    if (mesh->p == 2)
+      hipLaunchKernelGGL((k_geometry_tab<3, 3>), grid, dim3(NT), 0, s, X, c->n_nodes, conn, c->n_q, c->d_tab, c->d_qd,
+                         c->d_flag);
+    else
+      hipLaunchKernelGGL((k_geometry_tab<4, 4>), grid, dim3(NT), 0, s, X, c->n_nodes, conn, c->n_q, c->d_tab, c->d_qd,
+                         c->d_flag);
+    e = hipGetLastError();
+  }
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // also keeps off / ent alive until copied
+  if (e != hipSuccess) { pf_destroy(c); return fail(PF_EHIP, "table setup: %s", hipGetErrorString(e)); }
+  if (bad) {
+    (void)hipMemset(c->d_flag, 0, 2 * sizeof(int));
+    pf_destroy(c);
+    return fail(PF_EINVAL, "node positions give an element with det J <= 0 at some quadrature point");
+  }
   *out = c;
   return PF_OK;
 }
@@ -458,6 +652,7 @@ pf_status pf_sizes(const pf_ctx* c, int64_t* n_nodes, int64_t* n_q, int64_t* n_d
 pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, const double* xstate) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_set_branches"))) return st;
   if (n_extra < 0 || n_extra > PF_MAX_EXTRA_BRANCHES)
     return fail(PF_EINVAL, "n_extra=%d outside 0..%d", n_extra, PF_MAX_EXTRA_BRANCHES);
   if (n_extra > 0 && (!branches || !xstate)) return fail(PF_EINVAL, "null branches or xstate");
@@ -516,7 +711,7 @@ pf_status pf_set_branches(pf_ctx* c, const pf_branch* branches, int n_extra, con
   return PF_OK;
 }
 
-pf_status pf_set_params(pf_ctx* c, const double* params) {
+pf_status pf_set_params(pf_ctx* c, const double* params, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
   if (!params) return fail(PF_EINVAL, "null params");
@@ -527,6 +722,11 @@ pf_status pf_set_params(pf_ctx* c, const double* params) {
     if (c->phases[i].voce_beta > 0 && !(c->phases[i].sigma_inf >= s0))
       return fail(PF_EINVAL, "phase %zu: Voce needs sigma_inf >= sigma0", i);
   }
+  bool same = true;
+  for (size_t i = 0; i < c->phases.size(); ++i)
+    same = same && c->phases[i].Gc == params[3 * i] && c->phases[i].sigma0 == params[3 * i + 1] &&
+           c->phases[i].visc == params[3 * i + 2];
+  if (same) return PF_OK;  // nothing to upload; the linearisation stays valid
   c->mg.linearized = false;  // the records hold decisions taken with the old parameters
   c->mg.lin64_valid = false;
   for (size_t i = 0; i < c->phases.size(); ++i) {
@@ -534,10 +734,8 @@ pf_status pf_set_params(pf_ctx* c, const double* params) {
     c->phases[i].sigma0 = params[3 * i + 1];
     c->phases[i].visc = params[3 * i + 2];
   }
-  // stream-ordered with respect to the default stream only; the caller
-  // synchronises its own stream before changing parameters
-  HIPCHK(hipDeviceSynchronize());
-  return upload_mats(c);
+  c->last_stream = (hipStream_t)stream;
+  return upload_mats_async(c, (hipStream_t)stream);
 }
 
 pf_status pf_apply_residual(pf_ctx* c, const double* z, double* r, void* stream) {
@@ -611,10 +809,11 @@ pf_status pf_check(pf_ctx* c) {
   pf_status st = check_ctx(c);
   if (st) return st;
   HIPCHK(hipStreamSynchronize(c->last_stream));
-  int flag = 0;
-  HIPCHK(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
-  if (flag) {
-    HIPCHK(hipMemset(c->d_flag, 0, sizeof(int)));
+  int flag[2] = {0, 0};
+  HIPCHK(hipMemcpy(flag, c->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost));
+  if (flag[0] || flag[1]) {
+    HIPCHK(hipMemset(c->d_flag, 0, 2 * sizeof(int)));
+    if (flag[1]) return fail(PF_EINVAL, "a quadrature point holds a phase id >= n_phases");
     return fail(PF_ENONPHYSICAL, "a quadrature point left the physical domain (det F <= 0 or b_i <= 0)");
   }
   return PF_OK;
@@ -623,6 +822,7 @@ pf_status pf_check(pf_ctx* c) {
 pf_status pf_set_geometry(pf_ctx* c, const double* X, void* stream) {
   pf_status st = check_ctx(c);
   if (st) return st;
+  if ((st = box_only(c, "pf_set_geometry"))) return st;
   hipStream_t s = (hipStream_t)stream;
   if (X && (c->mesh.p < 2 || c->mesh.p > 4))
     return fail(PF_EUNSUPPORTED, "mapped elements are built for p = 2..4 (p=%d)", c->mesh.p);
@@ -707,6 +907,14 @@ void pf_destroy(pf_ctx* c) {
   (void)hipFree(c->d_xmatsf);
   (void)hipFree(c->d_qd);
   (void)hipFree(c->d_qd32);
+  (void)hipFree(c->d_csr_off);
+  (void)hipFree(c->d_csr_ent);
+  (void)hipFree(c->d_evec);
+  for (auto& ps : c->pslot) {
+    (void)hipHostFree(ps.h64);
+    (void)hipHostFree(ps.h32);
+    if (ps.ev) (void)hipEventDestroy(ps.ev);
+  }
   delete c;
 }
 

@@ -24,6 +24,7 @@ EXPORTED = [
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
     "pf_apply_jacobian_lin", "pf_set_branches", "pf_commit_state_branches", "pf_set_geometry",
+    "pf_setup_mesh_table",
 ]
 
 # pf_set_option
@@ -45,6 +46,10 @@ class PfError(RuntimeError):
 class MeshDesc(C.Structure):
     _fields_ = [("p", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double)]
+
+
+class TableMeshDesc(C.Structure):
+    _fields_ = [("p", C.c_int), ("n_elem", C.c_int64), ("n_nodes", C.c_int64)]
 
 
 class PhaseDesc(C.Structure):
@@ -74,15 +79,20 @@ class PmgOpts(C.Structure):
                 ("reserved", C.c_int)]
 
 
+# pf_newton_opts.krylov
+PF_KRYLOV_FGMRES, PF_KRYLOV_CG = 0, 1
+KRYLOV = {"fgmres": PF_KRYLOV_FGMRES, "cg": PF_KRYLOV_CG}
+
+
 class NewtonOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int), ("cheb_degree", C.c_int),
-                ("coarse_sweeps", C.c_int), ("reserved", C.c_int * 3)]
+                ("coarse_sweeps", C.c_int), ("krylov", C.c_int), ("reserved", C.c_int * 2)]
 
 
 class NewtonStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("res0", C.c_double), ("res_lin", C.c_double),
                 ("res_true", C.c_double), ("t_linearize_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("refinements", C.c_int)]
+                ("refinements", C.c_int), ("krylov", C.c_int), ("breakdown", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,8 +113,10 @@ def load():
     vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
     L.pf_setup_mesh.argtypes = [C.POINTER(MeshDesc), C.POINTER(PhaseDesc), C.c_int, C.POINTER(FractureDesc),
                                 vp, vp, vp, vp, C.POINTER(vp)]
+    L.pf_setup_mesh_table.argtypes = [C.POINTER(TableMeshDesc), vp, vp, C.POINTER(PhaseDesc), C.c_int,
+                                      C.POINTER(FractureDesc), vp, vp, vp, vp, C.POINTER(vp)]
     L.pf_sizes.argtypes = [vp, i64p, i64p, i64p]
-    L.pf_set_params.argtypes = [vp, vp]
+    L.pf_set_params.argtypes = [vp, vp, vp]
     L.pf_apply_residual.argtypes = [vp, vp, vp, vp]
     L.pf_apply_jacobian.argtypes = [vp, vp, vp, vp, vp]
     L.pf_apply_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -162,10 +174,12 @@ def _req(t, dtype, shape, name):
 class Context:
     """One operator context (pf_ctx). Holds references to the device state tensors."""
 
-    def __init__(self, mesh, phases, fracture, qp_phase, qp_state, phi_n, stream=None):
+    def __init__(self, mesh, phases, fracture, qp_phase, qp_state, phi_n, stream=None, conn=None, X=None):
+        """mesh: a box (pf_setup_mesh), or with ``conn`` (device int32 [n_elem][(p+1)^3], kept
+        referenced) and ``X`` (device float64 [3][n_nodes]) a mesh given by its element table
+        (pf_setup_mesh_table)."""
         L = load()
         self._phases = list(phases)
-        md = MeshDesc(mesh.p, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz)
         arr = (PhaseDesc * len(phases))(*[PhaseDesc(p.E, p.nu, p.Gc, p.sigma0, p.H, p.visc, int(p.plastic),
                                                                  getattr(p, "sigma_inf", 0.0),
                                                                  getattr(p, "voce_beta", 0.0))
@@ -178,8 +192,19 @@ class Context:
         self.qp_state = _req(qp_state, torch.float64, (8, mesh.n_q), "qp_state")
         self.phi_n = _req(phi_n, torch.float64, (mesh.n_nodes,), "phi_n")
         h = C.c_void_p()
-        _check(L.pf_setup_mesh(C.byref(md), arr, len(phases), C.byref(fd), _ptr(self.qp_phase),
-                               _ptr(self.qp_state), _ptr(self.phi_n), _stream(stream), C.byref(h)))
+        if conn is None:
+            md = MeshDesc(mesh.p, mesh.nx, mesh.ny, mesh.nz, mesh.lx, mesh.ly, mesh.lz)
+            _check(L.pf_setup_mesh(C.byref(md), arr, len(phases), C.byref(fd), _ptr(self.qp_phase),
+                                   _ptr(self.qp_state), _ptr(self.phi_n), _stream(stream), C.byref(h)))
+            self.conn = None
+        else:
+            P3 = (mesh.p + 1) ** 3
+            self.conn = _req(conn, torch.int32, (mesh.n_elem, P3), "conn")
+            X = _req(X, torch.float64, (3, mesh.n_nodes), "X")
+            md = TableMeshDesc(mesh.p, mesh.n_elem, mesh.n_nodes)
+            _check(L.pf_setup_mesh_table(C.byref(md), _ptr(self.conn), _ptr(X), arr, len(phases), C.byref(fd),
+                                         _ptr(self.qp_phase), _ptr(self.qp_state), _ptr(self.phi_n),
+                                         _stream(stream), C.byref(h)))
         self._h = h
         self.n_phases = len(phases)
         self.xstate = None
@@ -187,6 +212,10 @@ class Context:
     @classmethod
     def from_inputs(cls, d, device="cuda"):
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        if d.get("conn") is not None:
+            return cls(d["mesh"], d["phases"], d["fracture"], t(d["phase"], torch.uint8),
+                       t(d["state"], torch.float64), t(d["phi_n"], torch.float64),
+                       conn=t(d["conn"], torch.int32), X=t(d["X"], torch.float64))
         ctx = cls(d["mesh"], d["phases"], d["fracture"], t(d["phase"], torch.uint8),
                   t(d["state"], torch.float64), t(d["phi_n"], torch.float64))
         if d.get("branches"):
@@ -238,9 +267,10 @@ class Context:
         X = _req(X, torch.float64, (3, self.n_nodes), "X")
         _check(load().pf_set_geometry(self._h, _ptr(X), _stream(stream)))
 
-    def set_params(self, params):
+    def set_params(self, params, stream=None):
+        """pf_set_params: stream-ordered upload of the per-phase (Gc, sigma0, visc)."""
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.n_phases, 3))
-        _check(load().pf_set_params(self._h, p.ctypes.data_as(C.c_void_p)))
+        _check(load().pf_set_params(self._h, p.ctypes.data_as(C.c_void_p), _stream(stream)))
 
     def apply_residual(self, z, r=None, stream=None):
         _req(z, torch.float64, (4, self.n_nodes), "z")
@@ -359,10 +389,11 @@ class Context:
         return out, xout
 
     def newton_step(self, z, rtol=1e-8, restart=30, max_iters=300, cheb_degree=3, coarse_sweeps=32,
-                    stream=None, raise_on_noconv=True):
-        """One Newton update of z in place; returns the solver report as a dict."""
+                    stream=None, raise_on_noconv=True, krylov="fgmres"):
+        """One Newton update of z in place; returns the solver report as a dict.
+        krylov: 'fgmres' (default) or 'cg'."""
         _req(z, torch.float64, (4, self.n_nodes), "z")
-        o = NewtonOpts(rtol, restart, max_iters, cheb_degree, coarse_sweeps)
+        o = NewtonOpts(rtol, restart, max_iters, cheb_degree, coarse_sweeps, KRYLOV[krylov])
         st = NewtonStats()
         code = load().pf_newton_step(self._h, _ptr(z), C.byref(o), C.byref(st), _stream(stream))
         if code != PF_OK and not (code == PF_ENOCONV and not raise_on_noconv):

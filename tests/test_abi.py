@@ -49,3 +49,14 @@ def test_geometry_call_rejects_a_null_context_without_gpu():
     from paper_2607_21150_amd import pfmf
     L = pfmf.load()
     assert L.pf_set_geometry(None, None, None) == pfmf.PF_EINVAL
+
+
+def test_table_setup_rejects_null_arguments_without_gpu():
+    from paper_2607_21150_amd import pfmf
+    L = pfmf.load()
+    assert L.pf_setup_mesh_table(None, None, None, None, 0, None, None, None, None, None, None) == pfmf.PF_EINVAL
+    out = ctypes.c_void_p()
+    md = pfmf.TableMeshDesc(3, 0, 0)
+    assert L.pf_setup_mesh_table(ctypes.byref(md), None, None, None, 0, None, None, None, None, None,
+                                 ctypes.byref(out)) == pfmf.PF_EINVAL
+    assert not out.value

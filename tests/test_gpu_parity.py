@@ -133,7 +133,10 @@ def test_stored_linearisation_needs_linearize(pf):
     ctx.set_store_lin64(True)
     ctx.linearize(z)
     ctx.apply_jacobian_lin(dz)
-    ctx.set_params(np.array([[ph.Gc, ph.sigma0, ph.visc] for ph in d["phases"]]))
+    same = np.array([[ph.Gc, ph.sigma0, ph.visc] for ph in d["phases"]])
+    ctx.set_params(same)
+    ctx.apply_jacobian_lin(dz)  # unchanged parameters keep the linearisation
+    ctx.set_params(same * np.array([1.0, 1.5, 1.0]))
     with pytest.raises(pf.PfError):
         ctx.apply_jacobian_lin(dz)  # parameters changed since the linearisation
     with pytest.raises(pf.PfError):
@@ -227,3 +230,61 @@ def test_repeated_eigenvalues(pf, oracle_lib, kind, p):
     check_blocks(ctx.apply_jacobian(z, dz).cpu().numpy(), orc.jacobian(d["z"], d["dz"]), FP64_TOL, "jacobian")
     gz, _ = ctx.apply_adjoint(z, v)
     check_blocks(gz.cpu().numpy(), orc.adjoint(d["z"], d["v_rand"])[0], FP64_TOL, "adjoint")
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_phase_ids_outside_the_table(pf, p):
+    """An id >= n_phases is rejected at setup; one written into the phase array afterwards
+    raises the sticky phase flag in every apply that reads it (pf_check: PF_EINVAL), which
+    pf_check clears."""
+    print(f"case bad phase ids p={p}", flush=True)
+    d = I.make_inputs("C1", "plastic", p=p, n=2)
+    bad = d["phase"].copy()
+    bad[5] = len(d["phases"])
+    with pytest.raises(pf.PfError) as e:
+        pf.Context.from_inputs(dict(d, phase=bad))
+    assert e.value.code == pf.PF_EINVAL
+    ctx = pf.Context.from_inputs(d)
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    ctx.apply_residual(z)
+    ctx.check()
+    ctx.qp_phase[17] = 200
+    calls = [lambda: ctx.apply_residual(z), lambda: ctx.apply_jacobian(z, dz), lambda: ctx.apply_adjoint(z, v)]
+    if p >= 2:
+        calls.append(lambda: ctx.linearize(z))
+    for f in calls:
+        try:
+            f()
+        except pf.PfError as exc:  # the linearisation synchronises and may report it itself
+            assert exc.code == pf.PF_EINVAL
+            ctx.check()
+            continue
+        with pytest.raises(pf.PfError) as e:
+            ctx.check()
+        assert e.value.code == pf.PF_EINVAL
+        ctx.check()  # cleared
+
+
+def test_set_params_is_stream_ordered(pf, oracle_lib):
+    """Applies enqueued before pf_set_params on the same stream use the old parameters, those
+    after it the new ones, with no host synchronisation between them."""
+    d = I.make_inputs("C1", "plastic", p=3, n=2)
+    ctx = pf.Context.from_inputs(d)
+    z = dev(d["z"])
+    p0 = np.array([[ph.Gc, ph.sigma0, ph.visc] for ph in d["phases"]])
+    p1 = p0 * np.array([1.3, 0.8, 2.0])
+    s = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(s):
+        for k in range(6):  # several uploads in flight: the staging slots are reused
+            outs.append(ctx.apply_residual(z, stream=s))
+            ctx.set_params(p1 if k % 2 == 0 else p0, stream=s)
+    s.synchronize()
+    ctx.check()
+    import dataclasses
+    for k, r in enumerate(outs):
+        pk = p0 if k % 2 == 0 else p1
+        phases = [dataclasses.replace(ph, Gc=float(pk[i, 0]), sigma0=float(pk[i, 1]), visc=float(pk[i, 2]))
+                  for i, ph in enumerate(d["phases"])]
+        ref = oracle_lib.Oracle.from_inputs(dict(d, phases=phases)).residual(d["z"])
+        assert relerr(r.cpu().numpy(), ref) <= FP64_TOL, k

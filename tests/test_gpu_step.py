@@ -221,3 +221,51 @@ def test_newton_converges_on_small_mesh(pf, oracle_lib):
     print("Newton residual history", hist, flush=True)
     assert hist[-1] <= 1e-8 * hist[0]
     assert hist[-1] < 0.1 * hist[-2]
+
+
+def test_newton_step_at_full_size_q4(pf):
+    """One Newton step on the Q4 40^3 box (16.7 M DoFs), as bench.py runs it: uniaxial faces,
+    FGMRES(30) with one FP32 V-cycle (levels 4 -> 2 -> 1) per iteration. The true linear
+    residual ||b - M J dz||, recomputed with the FP64 Jacobian apply, reaches 1e-8 of ||b||."""
+    print("case newton C5 full size", flush=True)
+    d = I.make_inputs("C5", "base")
+    z0, _ = constrained_start(d)
+    ctx = pf.Context.from_inputs(d)
+    ctx.set_pmg_levels([4, 2, 1])
+    ctx.set_dirichlet(uniaxial_faces())
+    z = dev(z0)
+    rep = ctx.newton_step(z, rtol=1e-8, restart=30, max_iters=300)
+    ctx.check()
+    print(rep, flush=True)
+    assert rep["converged"] == 1 and rep["krylov"] == pf.PF_KRYLOV_FGMRES
+    assert rep["res_true"] <= 1e-8 * rep["res0"] * 1.05  # true residual, recomputed Jacobian
+    assert rep["iterations"] <= 300
+
+
+@pytest.mark.parametrize("variant", ["base", "plastic"])
+def test_newton_step_cg_variant(pf, variant):
+    """The conjugate-gradient variant with the same V-cycle: it either reaches the tolerance
+    or stops at a breakdown (the coupled Jacobian is not symmetric positive definite); the
+    reported true residual is the recomputed one in both cases, and a CG step that claims
+    convergence agrees with the FGMRES update on the same system."""
+    print(f"case newton CG C1 {variant}", flush=True)
+    d = I.make_inputs("C1", variant)
+    z0, M = constrained_start(d)
+    ctx = pf.Context.from_inputs(d)
+    ctx.set_dirichlet(uniaxial_faces())
+    zc = dev(z0)
+    rep = ctx.newton_step(zc, rtol=1e-10, restart=30, max_iters=400, krylov="cg", raise_on_noconv=False)
+    print(rep, flush=True)
+    assert rep["krylov"] == pf.PF_KRYLOV_CG
+    assert rep["converged"] == 1 or rep["breakdown"] == 1 or rep["iterations"] == 400
+    assert np.all((zc.cpu().numpy() - z0)[M] == 0.0)  # constrained entries keep their values
+    if rep["converged"]:
+        assert rep["res_true"] <= 1e-9 * rep["res0"]
+        zg = dev(z0)
+        ctx.newton_step(zg, rtol=1e-11, restart=40, max_iters=400)
+        dzc, dzg = zc - dev(z0), zg - dev(z0)
+        assert float(torch.linalg.norm(dzc - dzg) / torch.linalg.norm(dzg)) <= 1e-6
+    with pytest.raises(pf.PfError) as e:
+        pf._check(pf.load().pf_newton_step(ctx._h, pf._ptr(zc), pf.C.byref(pf.NewtonOpts(1e-8, 30, 10, 3, 32, 7)),
+                                           None, pf._stream()))
+    assert e.value.code == pf.PF_EINVAL
