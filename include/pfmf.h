@@ -216,6 +216,23 @@ pf_status pf_apply_jacobian(pf_ctx* ctx, const double* z, const double* dz, doub
 pf_status pf_apply_adjoint(pf_ctx* ctx, const double* z, const double* v, double* gz,
                            double* gparams, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): pf_apply_adjoint with no allocation of
+ * any kind. Same arguments, results and errors as pf_apply_adjoint (gz and gparams equal
+ * to it up to the order of the final additions); the scatter-add takes the
+ * eight colour launches, which write gz directly, and the per-brick (order 4:
+ * per-element) parameter partials go to a static device array of PF_NOALLOC_PARTIALS
+ * doubles (4 MiB) that each GPU the library runs on holds until the process ends. Every
+ * call overwrites all partials it reads, so nothing carries over between calls; calls
+ * that overlap on one GPU (several streams, threads or contexts at once) race on that
+ * array and must be serialised by the caller. Errors: PF_EINVAL when
+ * 3 n_phases x (number of 2x2x2-element bricks, or of elements at order 4) exceeds
+ * PF_NOALLOC_PARTIALS, PF_EUNSUPPORTED on a table-restriction context, the errors of
+ * pf_apply_adjoint otherwise. */
+#define PF_NOALLOC_PARTIALS (1 << 19)
+pf_status pf_apply_adjoint_noalloc(pf_ctx* ctx, const double* z, const double* v, double* gz,
+                                   double* gparams, void* stream);
+
 /* Linearise at z for the FP32 multigrid: the return-mapping, split and history
  * decisions, their scalars, the principal frame of b_tr (a unit quaternion, its three
  * smallest components), the principal trial log strains and the off-diagonal tangent

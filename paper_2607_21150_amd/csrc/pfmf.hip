@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,9 +21,20 @@
 
 using namespace pfmf;
 
+// Scratch of pf_apply_adjoint_noalloc: the per-brick (order 4: per-element) parameter
+// partials, PF_NOALLOC_PARTIALS doubles. Every GPU the library runs on holds its own copy
+// for the life of the process. In host code `scratch` is only a symbol: its device address
+// is taken with hipGetSymbolAddress once per device (noalloc_scratch below) and used
+// wherever host code hands the array to a kernel.
+static __device__ __align__(256) double scratch[PF_NOALLOC_PARTIALS];
+
 namespace {
 
 thread_local std::string g_err;
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
 
 
 pf_status fail(pf_status s, const char* fmt, ...) {
@@ -87,6 +99,8 @@ struct pf_ctx {
   int32_t* d_csr_ent = nullptr;
   double* d_evec = nullptr;
   int* d_flag = nullptr;      // [0] non-physical point, [1] phase id outside the table
+  double* scratch = nullptr;  // device address of this device's static scratch (pf_apply_adjoint_noalloc)
+  bool colours_only = false;  // set while an allocation-free call runs: no brick buffer
   hipStream_t last_stream = nullptr;
   // pf_set_params: pinned staging slots, each reused once its last copy has run
   static constexpr int PARAM_RING = 4;
@@ -290,8 +304,9 @@ pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
 }
 
 // PF_OPT_SCATTER: brick buffer unless colours were asked for, or the automatic choice
-// meets a buffer above PF_SCATTER_AUTO_BYTES
+// meets a buffer above PF_SCATTER_AUTO_BYTES; never inside an allocation-free call
 inline bool use_brick_buffer(const pf_ctx* c) {
+  if (c->colours_only) return false;
   if (c->scatter_mode != 0) return c->scatter_mode == 2;
   return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
 }
@@ -447,6 +462,20 @@ pf_status box_only(const pf_ctx* c, const char* what) {
   return PF_OK;
 }
 
+// Device address of the static scratch on device dev (current), taken once per device.
+pf_status noalloc_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(PF_EUNSUPPORTED, "device %d outside 0..%d", dev, MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(PF_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PF_OK;
+}
+
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
@@ -499,6 +528,8 @@ pf_status setup_common(pf_ctx* c, const pf_phase* phases, int n_phases, const pf
     return fail(PF_ENOMEM, "context allocation failed");
   if (hipMemset(c->d_flag, 0, 2 * sizeof(int)) != hipSuccess) return fail(PF_EHIP, "memset failed");
   st = upload_mats(c);
+  if (st != PF_OK) return st;
+  st = noalloc_scratch(c->device, &c->scratch);
   if (st != PF_OK) return st;
   const hipStream_t s = (hipStream_t)stream;
   int bad = 0;
@@ -782,6 +813,38 @@ pf_status pf_apply_adjoint(pf_ctx* c, const double* z, const double* v, double* 
   st = dispatch_op64<M_ADJ>(c, a, (hipStream_t)stream);
   if (st) return st;
   hipLaunchKernelGGL(k_sum_params, dim3((int)c->phases.size() * 3), dim3(NT), 0, (hipStream_t)stream, c->d_gpart,
+                     c->n_parts, (int)c->phases.size(), gparams);
+  HIPCHK(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status pf_apply_adjoint_noalloc(pf_ctx* c, const double* z, const double* v, double* gz, double* gparams,
+                                   void* stream) {
+  pf_status st = check_ctx(c);
+  if (st) return st;
+  if ((st = box_only(c, "pf_apply_adjoint_noalloc"))) return st;
+  if (!z || !v || !gz || !gparams) return fail(PF_EINVAL, "null vector");
+  const int64_t nparts = (int64_t)c->n_parts * (int64_t)c->phases.size() * 3;
+  if (nparts > PF_NOALLOC_PARTIALS)
+    return fail(PF_EINVAL, "%lld parameter partials exceed the allocation-free scratch (%d doubles)",
+                (long long)nparts, PF_NOALLOC_PARTIALS);
+  if (!c->scratch) return fail(PF_EHIP, "no scratch address for device %d", c->device);
+  const size_t nb = 4 * c->n_nodes * sizeof(double);
+  const size_t np = c->phases.size() * 3 * sizeof(double);
+  if (overlaps(z, nb, gz, nb) || overlaps(v, nb, gz, nb) || overlaps(gparams, np, gz, nb) ||
+      overlaps(gparams, np, z, nb) || overlaps(gparams, np, v, nb))
+    return fail(PF_EINVAL, "an output aliases an input");
+  OpArgs a = op_args(c);
+  a.z = z;
+  a.w = v;
+  a.out = gz;
+  a.gpart = c->scratch;  // every brick (element) slot is written by the apply: nothing to clear
+  c->last_stream = (hipStream_t)stream;
+  c->colours_only = true;
+  st = dispatch_op64<M_ADJ>(c, a, (hipStream_t)stream);
+  c->colours_only = false;
+  if (st) return st;
+  hipLaunchKernelGGL(k_sum_params, dim3((int)c->phases.size() * 3), dim3(NT), 0, (hipStream_t)stream, c->scratch,
                      c->n_parts, (int)c->phases.size(), gparams);
   HIPCHK(hipGetLastError());
   return PF_OK;

@@ -24,7 +24,7 @@ EXPORTED = [
     "pf_restrict", "pf_level_diagonal", "pf_pmg_vcycle", "pf_check", "pf_destroy", "pf_last_error",
     "pf_set_pmg_levels", "pf_set_dirichlet", "pf_commit_state", "pf_newton_step", "pf_set_option",
     "pf_apply_jacobian_lin", "pf_set_branches", "pf_commit_state_branches", "pf_set_geometry",
-    "pf_setup_mesh_table",
+    "pf_setup_mesh_table", "pf_apply_adjoint_noalloc",
 ]
 
 # pf_set_option
@@ -120,6 +120,7 @@ def load():
     L.pf_apply_residual.argtypes = [vp, vp, vp, vp]
     L.pf_apply_jacobian.argtypes = [vp, vp, vp, vp, vp]
     L.pf_apply_adjoint.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pf_apply_adjoint_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.pf_linearize.argtypes = [vp, vp, vp]
     L.pf_level_info.argtypes = [vp, C.c_int, C.POINTER(C.c_int), i64p]
     L.pf_apply_jacobian_f32.argtypes = [vp, C.c_int, vp, vp, vp]
@@ -293,6 +294,16 @@ class Context:
             gparams = torch.empty((self.n_phases, 3), dtype=torch.float64, device=z.device)
         _req(gparams, torch.float64, (self.n_phases, 3), "gparams")
         _check(load().pf_apply_adjoint(self._h, _ptr(z), _ptr(v), _ptr(gz), _ptr(gparams), _stream(stream)))
+        return gz, gparams
+
+    def apply_adjoint_noalloc(self, z, v, gz, gparams, stream=None):
+        """pf_apply_adjoint_noalloc: the adjoint without any device allocation; gz and gparams
+        must be given (the caller's memory)."""
+        _req(z, torch.float64, (4, self.n_nodes), "z")
+        _req(v, torch.float64, (4, self.n_nodes), "v")
+        _req(gz, torch.float64, (4, self.n_nodes), "gz")
+        _req(gparams, torch.float64, (self.n_phases, 3), "gparams")
+        _check(load().pf_apply_adjoint_noalloc(self._h, _ptr(z), _ptr(v), _ptr(gz), _ptr(gparams), _stream(stream)))
         return gz, gparams
 
     def linearize(self, z, stream=None):
