@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
 // entry sums the matching element-matrix entries over the (up to 8) elements that
 // hold both nodes, in a fixed order, so the result is deterministic. One thread per
 // (offset, node), nodes fastest.
-__global__ __launch_bounds__(NT) void k_stencil_from_ebe(const float* __restrict__ K, int nx, int ny, int nz,
+static __global__ __launch_bounds__(NT) void k_stencil_from_ebe(const float* __restrict__ K, int nx, int ny, int nz,
                                                          int64_t n_nodes, float* __restrict__ S) {
   const int nx1 = nx + 1, ny1 = ny + 1;
   const int64_t n_all = 27 * n_nodes;

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(NT) void k_geometry_tab(const double* __restrict__ 
 // sums the element-vector entries listed for it in a CSR map, ent[off[i] .. off[i+1]), each
 // entry e 4 P3 + a (element e, local node a; the field adds f P3), in the map's fixed order
 // (by element, then local node): deterministic, no atomics. One thread per node.
-__global__ __launch_bounds__(NT) void k_gather_csr(const double* __restrict__ evec, const int32_t* __restrict__ off,
+static __global__ __launch_bounds__(NT) void k_gather_csr(const double* __restrict__ evec, const int32_t* __restrict__ off,
                                                    const int32_t* __restrict__ ent, int64_t n_nodes, int P3,
                                                    double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n_nodes; i += (int64_t)gridDim.x * NT) {

@@ -654,7 +654,7 @@ __global__ __launch_bounds__(NT) void k_level32(A32Args a, int colour, DevTables
 
 // out[f][i2][i1][i0] = sum_k w[c*nw + k] in[f][...][base[c] + k][...] along `axis`,
 // where c is the output coordinate along axis. in dims: (n0i, n1i, n2i).
-__global__ void k_transfer_1d(const float* __restrict__ in, float* __restrict__ out, int n0o, int n1o, int n2o,
+static __global__ void k_transfer_1d(const float* __restrict__ in, float* __restrict__ out, int n0o, int n1o, int n2o,
                               int n0i, int n1i, int n2i, int axis, const int* __restrict__ base,
                               const float* __restrict__ w, int nw) {
   const int64_t no = (int64_t)n0o * n1o * n2o;
@@ -682,30 +682,30 @@ __global__ void k_transfer_1d(const float* __restrict__ in, float* __restrict__ 
   }
 }
 
-__global__ void k_vec_zero(float* __restrict__ x, int64_t n) {
+static __global__ void k_vec_zero(float* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = 0.f;
 }
 
-__global__ void k_vec_copy(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+static __global__ void k_vec_copy(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
 }
 
 // y += x
-__global__ void k_vec_add(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
+static __global__ void k_vec_add(const float* __restrict__ x, float* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] += x[i];
 }
 
 // r = b - t
-__global__ void k_vec_sub(const float* __restrict__ b, const float* __restrict__ t, float* __restrict__ r, int64_t n) {
+static __global__ void k_vec_sub(const float* __restrict__ b, const float* __restrict__ t, float* __restrict__ r, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     r[i] = b[i] - t[i];
 }
 
 // Chebyshev start: d = s * dinv * r ; x = (x_zero ? 0 : x) + d
-__global__ void k_cheb_first(const float* __restrict__ r, const float* __restrict__ dinv, float* __restrict__ d,
+static __global__ void k_cheb_first(const float* __restrict__ r, const float* __restrict__ dinv, float* __restrict__ d,
                              float* __restrict__ x, float s, int x_zero, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float di = s * dinv[i] * r[i];
@@ -715,7 +715,7 @@ __global__ void k_cheb_first(const float* __restrict__ r, const float* __restric
 }
 
 // Chebyshev step: r -= t ; d = a d + b dinv r ; x += d
-__global__ void k_cheb_step(float* __restrict__ r, const float* __restrict__ t, const float* __restrict__ dinv,
+static __global__ void k_cheb_step(float* __restrict__ r, const float* __restrict__ t, const float* __restrict__ dinv,
                             float* __restrict__ d, float* __restrict__ x, float a, float b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float ri = r[i] - t[i];
@@ -727,19 +727,19 @@ __global__ void k_cheb_step(float* __restrict__ r, const float* __restrict__ t, 
 }
 
 // dinv = 1 / diag (0 where the diagonal vanishes)
-__global__ void k_vec_inv(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+static __global__ void k_vec_inv(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i] != 0.f ? 1.f / a[i] : 0.f;
 }
 
 // x = dinv * x
-__global__ void k_vec_scale(const float* __restrict__ dinv, float* __restrict__ x, int64_t n) {
+static __global__ void k_vec_scale(const float* __restrict__ dinv, float* __restrict__ x, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] *= dinv[i];
 }
 
 // double-precision sum of squares, per-block partials (deterministic)
-__global__ void k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+static __global__ void k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
   __shared__ double red[NT];
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -756,18 +756,18 @@ __global__ void k_sumsq(const float* __restrict__ x, int64_t n, double* __restri
 }
 
 // b = a / ||a|| given the squared norm on the host
-__global__ void k_vec_axs(const float* __restrict__ a, float* __restrict__ b, float s, int64_t n) {
+static __global__ void k_vec_axs(const float* __restrict__ a, float* __restrict__ b, float s, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = s * a[i];
 }
 
 // FP64 -> FP32 mirror of the displacement rows of z
-__global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+static __global__ void k_to_f32(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
 }
 
-__global__ void k_mirror_u(const double* __restrict__ z, float* __restrict__ z32, int64_t n_nodes) {
+static __global__ void k_mirror_u(const double* __restrict__ z, float* __restrict__ z32, int64_t n_nodes) {
   const int64_t n = 3 * n_nodes;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     z32[i] = (float)z[i];

@@ -1,0 +1,4 @@
+// One apply mode of the FP64 operator dispatch, compiled as its own unit.
+#include "pf_dispatch.hpp"
+
+template pf_status dispatch_op64<pfmf::M_ADJ>(pf_ctx*, pfmf::OpArgs, hipStream_t);

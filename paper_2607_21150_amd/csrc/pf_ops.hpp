@@ -286,7 +286,7 @@ __global__ __launch_bounds__(NT, P >= 5 ? 1 : 2) void k_op64(OpArgs a, int colou
 }
 
 // flag[1] = 1 when some phase id is outside the phase table [0, nph).
-__global__ void k_check_phase(const uint8_t* __restrict__ ph, int64_t n, int nph, int* __restrict__ flag) {
+static __global__ void k_check_phase(const uint8_t* __restrict__ ph, int64_t n, int nph, int* __restrict__ flag) {
   bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     bad |= ph[i] >= nph;
@@ -294,7 +294,7 @@ __global__ void k_check_phase(const uint8_t* __restrict__ ph, int64_t n, int nph
 }
 
 // Deterministic final sum of per-brick parameter partials: out[ph*3+k] = sum_b gpart[b][ph][k].
-__global__ void k_sum_params(const double* __restrict__ gpart, int n_bricks, int nph, double* __restrict__ out) {
+static __global__ void k_sum_params(const double* __restrict__ gpart, int n_bricks, int nph, double* __restrict__ out) {
   __shared__ double red[NT];
   const int idx = blockIdx.x;  // ph*3 + k
   double s = 0.0;

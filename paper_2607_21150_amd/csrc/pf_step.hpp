@@ -42,7 +42,7 @@ __global__ void k_mask(T* __restrict__ v, int nx1, int ny1, int nz1, DirMask d) 
 
 // Start vector of the power iteration: uniform values in [-1, 1) from a
 // counter-based mix (SplitMix64 finaliser) of (seed, index).
-__global__ void k_hash_fill(float* __restrict__ x, int64_t n, uint64_t seed) {
+static __global__ void k_hash_fill(float* __restrict__ x, int64_t n, uint64_t seed) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -54,7 +54,7 @@ __global__ void k_hash_fill(float* __restrict__ x, int64_t n, uint64_t seed) {
 
 // Sum of the first n partials (one block of NT threads, fixed strided order and a
 // fixed tree): out[0] = sqrt(sum), inv[0] = 1 / sqrt(sum) (0 when the sum vanishes).
-__global__ void k_norm_finish(const double* __restrict__ part, int n, double* __restrict__ out,
+static __global__ void k_norm_finish(const double* __restrict__ part, int n, double* __restrict__ out,
                               float* __restrict__ inv) {
   __shared__ double red[NT];
   double s = 0.0;
@@ -73,7 +73,7 @@ __global__ void k_norm_finish(const double* __restrict__ part, int n, double* __
 }
 
 // b = s[0] * a (scale held in device memory)
-__global__ void k_vec_axs_dev(const float* __restrict__ a, float* __restrict__ b, const float* __restrict__ s,
+static __global__ void k_vec_axs_dev(const float* __restrict__ a, float* __restrict__ b, const float* __restrict__ s,
                               int64_t n) {
   const float f = s[0];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -86,7 +86,7 @@ __global__ void k_vec_axs_dev(const float* __restrict__ a, float* __restrict__ b
 // ---------------------------------------------------------------------------
 
 // part[j * gridDim.x + b] = block b's share of <V_j, w>, j = 0..k-1, V_j = V + j * ld.
-__global__ void k_mdot(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ w, int64_t n,
+static __global__ void k_mdot(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ w, int64_t n,
                        double* __restrict__ part) {
   __shared__ double red[NT];
   const int j = blockIdx.y;
@@ -105,7 +105,7 @@ __global__ void k_mdot(const double* __restrict__ V, int64_t ld, int k, const do
 }
 
 // w += sum_j c[j] V_j  (c in device memory, k <= 64)
-__global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c,
+static __global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ c,
                         double* __restrict__ w, int64_t n) {
   __shared__ double cs[64];
   if ((int)threadIdx.x < k) cs[threadIdx.x] = c[threadIdx.x];
@@ -118,22 +118,22 @@ __global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int k, const d
 }
 
 // y = a x (+ y when accumulate); x may be y
-__global__ void k_daxpy(double a, const double* x, double* y, int64_t n, int accumulate) {
+static __global__ void k_daxpy(double a, const double* x, double* y, int64_t n, int accumulate) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i] + (accumulate ? y[i] : 0.0);
 }
 
-__global__ void k_dzero(double* __restrict__ y, int64_t n) {
+static __global__ void k_dzero(double* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = 0.0;
 }
 
-__global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+static __global__ void k_d2f(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
 }
 
-__global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+static __global__ void k_f2d(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
 }

@@ -10,12 +10,9 @@
 #include <string>
 #include <vector>
 
-#include "pfmf.h"
-#include "pf_ops.hpp"
-#include "pf_mg.hpp"
+#include "pf_host.hpp"
 #include "pf_mfma.hpp"
 #include "pf_q4.hpp"
-#include "pf_step.hpp"
 #include "pf_ebe.hpp"
 #include "pf_tables.hpp"
 
@@ -36,6 +33,7 @@ constexpr int MAX_DEVICES = 64;
 std::mutex g_scratch_mu;
 double* g_scratch_ptr[MAX_DEVICES] = {};
 
+}  // namespace
 
 pf_status fail(pf_status s, const char* fmt, ...) {
   char buf[512];
@@ -46,86 +44,6 @@ pf_status fail(pf_status s, const char* fmt, ...) {
   g_err = buf;
   return s;
 }
-
-#define HIPCHK(call)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess) return fail(PF_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-}  // namespace
-
-struct pf_ctx {
-  int device = 0;
-  pf_mesh_desc mesh{};
-  int P = 0, Q = 0;
-  int nx1 = 0, ny1 = 0, nz1 = 0;
-  int64_t n_nodes = 0, n_q = 0;
-  int nbx = 0, nby = 0, nbz = 0, n_bricks = 0;
-  int n_parts = 0;  // slots of the adjoint's parameter partials
-  bool has_voce = false;  // some plastic phase hardens by the Voce law
-  int colour_base[9] = {0};
-  std::vector<pf_phase> phases;
-  pf_fracture fr{};
-  const uint8_t* qp_phase = nullptr;
-  const double* qp_state = nullptr;
-  const double* phi_n = nullptr;
-  // extra branches in parallel (pf_set_branches)
-  int n_extra = 0;
-  bool xvoce = false;  // some extra Prandtl branch hardens by the Voce law
-  XBranch* d_xb = nullptr;
-  MatParams<double>* d_xmats64 = nullptr;  // the same branches' materials for the record applies
-  MatParams<float>* d_xmatsf = nullptr;
-  const double* xstate = nullptr;
-  // mapped elements (pf_set_geometry): per-point J^-1 and weights [10][n_q]
-  double* d_qd = nullptr;
-  float* d_qd32 = nullptr;  // the same record in FP32 for the FP32 levels
-  // device buffers
-  DevTables* d_tab = nullptr;
-  DevTablesF* d_tabf = nullptr;
-  MatParams<double>* d_mats = nullptr;
-  MatParams<float>* d_matsf = nullptr;
-  double* d_gpart = nullptr;
-  double* d_ebuf = nullptr;  // brick-buffer scatter (allocated on first use)
-  int scatter_mode = 0;      // PF_OPT_SCATTER
-  bool store_lin64 = true;   // PF_OPT_STORE_LIN64
-  // table restriction (pf_setup_mesh_table): element-to-node table (caller's), the node ->
-  // (element, local node) CSR map of its transpose, the element vectors, element groups
-  bool table = false;
-  const int32_t* conn = nullptr;
-  int64_t n_elem = 0;
-  int n_groups = 0;
-  int32_t* d_csr_off = nullptr;
-  int32_t* d_csr_ent = nullptr;
-  double* d_evec = nullptr;
-  int* d_flag = nullptr;      // [0] non-physical point, [1] phase id outside the table
-  double* scratch = nullptr;  // device address of this device's static scratch (pf_apply_adjoint_noalloc)
-  bool colours_only = false;  // set while an allocation-free call runs: no brick buffer
-  hipStream_t last_stream = nullptr;
-  // pf_set_params: pinned staging slots, each reused once its last copy has run
-  static constexpr int PARAM_RING = 4;
-  struct ParamSlot {
-    MatParams<double>* h64 = nullptr;
-    MatParams<float>* h32 = nullptr;
-    hipEvent_t ev = nullptr;
-    bool used = false;
-  } pslot[PARAM_RING];
-  int pnext = 0;
-  MGState mg;
-  // multigrid level orders (fine first); n_orders = 0 means p, p-1, ..., 1
-  int orders[5] = {0, 0, 0, 0, 0};
-  int n_orders = 0;
-  // Dirichlet faces (multigrid and Newton step)
-  DirMask dir{{0, 0, 0, 0, 0, 0}};
-  bool has_dir = false;
-  // Newton step workspace: Krylov basis V[m+1], preconditioned vectors Z[m], residual,
-  // update; reduction partials; coefficients; FP32 right-hand side and correction
-  double* kry = nullptr;
-  int kry_m = 0;
-  double* kpart = nullptr;
-  double* kcoef = nullptr;
-  float* k32 = nullptr;
-};
 
 namespace {
 
@@ -282,147 +200,6 @@ pf_status check_ctx(pf_ctx* c) {
   HIPCHK(hipGetDevice(&dev));
   if (dev != c->device) return fail(PF_EINVAL, "context belongs to device %d, current device is %d", c->device, dev);
   return PF_OK;
-}
-
-template <int MODE, int P, int Q>
-pf_status launch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
-  using S = OpShape<P, Q>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIPCHK(hipFuncSetAttribute((const void*)k_op64<MODE, P, Q>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)S::lds_bytes));
-    attr_set = true;
-  }
-  for (int col = 0; col < 8; ++col) {
-    const int nb = xcd_grid(c->nbx, c->nby, c->nbz, col);
-    if (nb == 0) continue;
-    a.brick_base = c->colour_base[col];
-    hipLaunchKernelGGL((k_op64<MODE, P, Q>), dim3(nb), dim3(NT), S::lds_bytes, s, a, col, c->d_tab);
-    HIPCHK(hipGetLastError());
-  }
-  return PF_OK;
-}
-
-// PF_OPT_SCATTER: brick buffer unless colours were asked for, or the automatic choice
-// meets a buffer above PF_SCATTER_AUTO_BYTES; never inside an allocation-free call
-inline bool use_brick_buffer(const pf_ctx* c) {
-  if (c->colours_only) return false;
-  if (c->scatter_mode != 0) return c->scatter_mode == 2;
-  return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
-}
-
-template <int MODE, int P, bool VOCE, bool MB, bool GEO>
-pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
-  const bool bb = use_brick_buffer(c);
-  if (bb) {
-    constexpr int NB = 2 * P - 1;
-    if (!c->d_ebuf &&
-        hipMalloc(&c->d_ebuf, (size_t)c->n_bricks * 4 * NB * NB * NB * sizeof(double)) != hipSuccess)
-      return fail(PF_ENOMEM, "brick buffer: allocation failed");
-    a.ebuf = c->d_ebuf;
-    a.brick_base = 0;
-    const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
-    if constexpr (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
-    else
-      hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
-    HIPCHK(hipGetLastError());
-    const int n_rows = c->ny1 * c->nz1;
-    hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
-                       (const double*)c->d_ebuf, a.m, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
-    HIPCHK(hipGetLastError());
-    return PF_OK;
-  }
-  for (int col = 0; col < 8; ++col) {
-    const int ng = xcd_grid(c->nbx, c->nby, c->nbz, col);
-    if (ng == 0) continue;
-    a.brick_base = c->colour_base[col];
-    if constexpr (P == 4)
-      hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
-    else
-      hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, col, c->d_tab);
-    HIPCHK(hipGetLastError());
-  }
-  return PF_OK;
-}
-
-// kernels without the Voce iteration unless a phase uses it; with extra branches
-// attached, the branch variant (which carries the Voce iteration for any branch); with
-// mapped elements the geometry variant (with or without branches)
-template <int MODE, int P>
-pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if (c->d_qd && c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true, true>(c, a, s)
-                                     : launch_op64_mfma_v<MODE, P, false, true, true>(c, a, s);
-  if (c->d_qd)
-    return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, true>(c, a, s)
-                       : launch_op64_mfma_v<MODE, P, false, false, true>(c, a, s);
-  if (c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_mfma_v<MODE, P, true, true, false>(c, a, s)
-                                     : launch_op64_mfma_v<MODE, P, false, true, false>(c, a, s);
-  return c->has_voce ? launch_op64_mfma_v<MODE, P, true, false, false>(c, a, s)
-                     : launch_op64_mfma_v<MODE, P, false, false, false>(c, a, s);
-}
-
-template <int MODE, bool VOCE, bool MB, bool GEO>
-pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
-  for (int col = 0; col < 8; ++col) {
-    const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
-    if (ng == 0) continue;
-    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB, GEO>), dim3(ng), dim3(NT5), 0, s, a, col, c->d_tab);
-    HIPCHK(hipGetLastError());
-  }
-  return PF_OK;
-}
-
-template <int MODE>
-pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if (c->d_qd && c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true, true>(c, a, s)
-                                     : launch_op64_q4_v<MODE, false, true, true>(c, a, s);
-  if (c->d_qd)
-    return c->has_voce ? launch_op64_q4_v<MODE, true, false, true>(c, a, s)
-                       : launch_op64_q4_v<MODE, false, false, true>(c, a, s);
-  if (c->n_extra > 0)
-    return (c->has_voce || c->xvoce) ? launch_op64_q4_v<MODE, true, true, false>(c, a, s)
-                                     : launch_op64_q4_v<MODE, false, true, false>(c, a, s);
-  return c->has_voce ? launch_op64_q4_v<MODE, true, false, false>(c, a, s)
-                     : launch_op64_q4_v<MODE, false, false, false>(c, a, s);
-}
-
-// Table restriction: one launch over the element groups (element vectors to c->d_evec),
-// then the node-owner gather into the output.
-template <int MODE, int P, bool VOCE>
-pf_status launch_op64_tab_v(pf_ctx* c, OpArgs a, hipStream_t s) {
-  const int ng = xcd_grid_groups(c->n_groups);
-  if constexpr (P == 4)
-    hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
-  else
-    hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
-  HIPCHK(hipGetLastError());
-  const int gb = (int)std::min<int64_t>((c->n_nodes + NT - 1) / NT, 1 << 16);
-  hipLaunchKernelGGL(k_gather_csr, dim3(gb), dim3(NT), 0, s, (const double*)c->d_evec, (const int32_t*)c->d_csr_off,
-                     (const int32_t*)c->d_csr_ent, c->n_nodes, P * P * P, a.out);
-  HIPCHK(hipGetLastError());
-  return PF_OK;
-}
-
-template <int MODE>
-pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
-  if (c->table) {
-    if (c->mesh.p == 2)
-      return c->has_voce ? launch_op64_tab_v<MODE, 3, true>(c, a, s) : launch_op64_tab_v<MODE, 3, false>(c, a, s);
-    return c->has_voce ? launch_op64_tab_v<MODE, 4, true>(c, a, s) : launch_op64_tab_v<MODE, 4, false>(c, a, s);
-  }
-  switch (c->mesh.p) {
-    case 1:
-      if (c->n_extra > 0) return fail(PF_EUNSUPPORTED, "extra branches need p >= 2");
-      return launch_op64<MODE, 2, 2>(c, a, s);
-    case 2: return launch_op64_mfma<MODE, 3>(c, a, s);
-    case 3: return launch_op64_mfma<MODE, 4>(c, a, s);
-    case 4: return launch_op64_q4<MODE>(c, a, s);
-    default: return fail(PF_EUNSUPPORTED, "order p=%d not built", c->mesh.p);
-  }
 }
 
 OpArgs op_args(pf_ctx* c) {
