@@ -129,17 +129,6 @@ def whole_mesh_err(gpu_vec, ref):
     return {"rel_l2": rel, "max_entry": worst}
 
 
-def sampled_rel_err(orc, mesh, gpu_vec, fn, rng, n_nodes=48):
-    """Relative error on sampled nodes: the oracle recomputes the elements around them."""
-    from paper_2607_21150_amd.inputs import elements_touching_nodes
-    nodes = rng.choice(mesh.n_nodes, size=n_nodes, replace=False)
-    elems = elements_touching_nodes(mesh, nodes)
-    ref = fn(elems)
-    a = gpu_vec[:, nodes]
-    b = ref[:, nodes]
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-
 def cpu_baseline(d, seconds=10.0):
     """The oracle (as it stands) on the host cores, on a bounded sample of elements."""
     from oracle import pyoracle
@@ -304,15 +293,13 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
         from oracle import pyoracle
         pyoracle.build(force=False)
         orc = pyoracle.Oracle.from_inputs(d)
-        rng = np.random.default_rng(0)
-        errs["jacobian"] = sampled_rel_err(orc, mesh, y.cpu().numpy(),
-                                           lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
-        errs["adjoint"] = sampled_rel_err(orc, mesh, g.cpu().numpy(),
-                                          lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
-        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32.double().cpu().numpy(),
-                                             lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
-        errs["jacobian_stored"] = sampled_rel_err(orc, mesh, ys.cpu().numpy(),
-                                                  lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        jref = orc.jacobian(d["z"], d["dz"])
+        errs["jacobian"] = whole_mesh_err(y.cpu().numpy(), jref)
+        errs["fp32_apply"] = whole_mesh_err(y32.double().cpu().numpy(), jref)
+        errs["jacobian_stored"] = whole_mesh_err(ys.cpu().numpy(), jref)
+        del jref
+        errs["adjoint"] = whole_mesh_err(g.cpu().numpy(), orc.adjoint(d["z"], d["v_top"])[0])
+        errs["nodes_compared"] = mesh.n_nodes
     except Exception as exc:
         errs["error"] = str(exc)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3, {mesh.n_dof} DoFs, matrix = perfectly plastic Prandtl "
@@ -321,7 +308,7 @@ def branches_leg(torch, I, pfmf, config, steps=20, warmup=3):
             "alg_bytes_per_apply": alg,
             "gbs_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in alg},
             "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
-            "rel_err_vs_oracle_sampled": errs}
+            "rel_err_vs_oracle": errs}
 
 
 def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
@@ -387,10 +374,12 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
         from oracle import pyoracle
         pyoracle.build(force=False)
         orc = pyoracle.Oracle.from_inputs(d)
-        rng = np.random.default_rng(0)
-        errs["jacobian"] = sampled_rel_err(orc, mesh, y_cur, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
-        errs["adjoint"] = sampled_rel_err(orc, mesh, g_cur, lambda e: orc.adjoint(d["z"], d["v_top"], elems=e)[0], rng)
-        errs["fp32_apply"] = sampled_rel_err(orc, mesh, y32_cur, lambda e: orc.jacobian(d["z"], d["dz"], elems=e), rng)
+        jref = orc.jacobian(d["z"], d["dz"])
+        errs["jacobian"] = whole_mesh_err(y_cur, jref)
+        errs["fp32_apply"] = whole_mesh_err(y32_cur, jref)
+        del jref
+        errs["adjoint"] = whole_mesh_err(g_cur, orc.adjoint(d["z"], d["v_top"])[0])
+        errs["nodes_compared"] = mesh.n_nodes
     except Exception as exc:
         errs["error"] = str(exc)
     return {"config": f"{config} Q{mesh.p} {mesh.nx}^3 curved (bump 0.2 h), {mesh.n_dof} DoFs, plastic matrix",
@@ -401,7 +390,74 @@ def geometry_leg(torch, I, pfmf, config, steps=20, warmup=3, with_box=False):
             "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
             **({"ms_median_box": ms_box, "curved_over_box_time": {k: ms[k] / ms_box[k] for k in ms_box}}
                if ms_box else {}),
-            "rel_err_vs_oracle_sampled": errs}
+            "rel_err_vs_oracle": errs}
+
+
+def table_leg(torch, I, pfmf, config, steps=20, warmup=3, hole=0.15):
+    """FP64 applies on a mesh given by its element-to-node table (pf_setup_mesh_table): the
+    headline's plastic workload with the elements inside a cylindrical hole of radius `hole`
+    mm removed, every element in one of the 24 cube orientations, elements in lattice order
+    and nodes numbered by first touch. Median device time of each apply (HIP events around
+    every launch) and whole-mesh errors against the oracle. Algorithmic bytes add the
+    geometry record (80 B per point) and the table (4 B per element node) to the box's."""
+    t_gen = time.perf_counter()
+    d = I.unstructured(I.make_inputs(config, "plastic"), hole_radius=hole, node_order="first_touch",
+                       shuffle_elements=False)
+    mesh = d["mesh"]
+    print(f"[bench] table inputs {config}: {mesh.n_elem} elements, {mesh.n_dof} DoFs, generated in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float64)
+    t0 = time.perf_counter()
+    ctx = pfmf.Context.from_inputs(d)
+    setup_ms = (time.perf_counter() - t0) * 1e3  # host wall time: table copy, CSR map, geometry record
+    z, dz, v = dev(d["z"]), dev(d["dz"]), dev(d["v_rand"])
+    r, y, g = torch.empty_like(z), torch.empty_like(z), torch.empty_like(z)
+    gp = torch.empty((len(d["phases"]), 3), dtype=torch.float64, device="cuda")
+    ops = {"residual": lambda: ctx.apply_residual(z, r), "jacobian": lambda: ctx.apply_jacobian(z, dz, y),
+           "adjoint": lambda: ctx.apply_adjoint(z, v, g, gp)}
+    for _ in range(warmup):
+        for f in ops.values():
+            f()
+    torch.cuda.synchronize()
+    ev = {k: [] for k in ops}
+    for _ in range(steps):
+        for k, f in ops.items():
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            f()
+            b.record()
+            ev[k].append((a, b))
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = {k: float(np.median([a.elapsed_time(b) for a, b in ev[k]])) for k in ev}
+    rr, yy, gg = r.cpu().numpy(), y.cpu().numpy(), g.cpu().numpy()
+    del ctx, z, dz, v, r, y, g
+    torch.cuda.empty_cache()
+    P3 = (mesh.p + 1) ** 3
+    extra = 80 * mesh.n_q + 4 * P3 * mesh.n_elem
+    alg = {"residual": 72 * mesh.n_nodes + 65 * mesh.n_q + extra,
+           "jacobian": 96 * mesh.n_nodes + 65 * mesh.n_q + extra,
+           "adjoint": 96 * mesh.n_nodes + 65 * mesh.n_q + extra}
+    errs = {}
+    try:
+        from oracle import pyoracle
+        pyoracle.build(force=False)
+        orc = pyoracle.Oracle.from_inputs(d)
+        errs["residual"] = whole_mesh_err(rr, orc.residual(d["z"]))
+        errs["jacobian"] = whole_mesh_err(yy, orc.jacobian(d["z"], d["dz"]))
+        errs["adjoint"] = whole_mesh_err(gg, orc.adjoint(d["z"], d["v_rand"])[0])
+        errs["nodes_compared"] = mesh.n_nodes
+    except Exception as exc:
+        errs["error"] = str(exc)
+    return {"config": f"{config} Q{mesh.p}, {mesh.n_elem} elements of the {mesh.box.nx}^3 lattice (cylindrical hole "
+                      f"of radius {hole} mm), each in one of the 24 cube orientations, nodes numbered by first "
+                      f"touch; {mesh.n_dof} DoFs, plastic matrix",
+            "ms_median": ms, "setup_ms": setup_ms,
+            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ms},
+            "alg_bytes_per_apply": alg,
+            "gbs_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 for k in ms},
+            "hbm_frac_alg": {k: alg[k] / (ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS for k in ms},
+            "rel_err_vs_oracle": errs}
 
 
 def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30,
@@ -495,6 +551,8 @@ def main():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--variant", default="base")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true",
+                    help="skip the whole-mesh oracle comparison of the headline workload (profiled runs)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-newton", action="store_true",
                     help="skip the Newton step (FGMRES + FP32 p-MG, and the CG variant) on --newton-config")
@@ -513,6 +571,8 @@ def main():
                     help="workload on which the applies on curved (mapped) Q3 elements are timed ('' = none)")
     ap.add_argument("--newton-curved-config", default="C5",
                     help="workload of the Newton step on the curved mesh (with --newton-all; '' = none)")
+    ap.add_argument("--table", default="C3",
+                    help="workload on which the applies on a mesh given by its element table are timed ('' = none)")
     ap.add_argument("--geometry-box", action="store_true",
                     help="also time the geometry leg's applies on the box mesh (the curved / box ratio)")
     args = ap.parse_args()
@@ -588,6 +648,8 @@ def main():
     # errors against the oracle on every node of the mesh (FP64 bar 1e-12, FP32 1e-5)
     errs = {}
     try:
+        if args.no_oracle:
+            raise RuntimeError("skipped (--no-oracle)")
         from oracle import pyoracle
         pyoracle.build(force=False)
         orc = pyoracle.Oracle.from_inputs(d)
@@ -699,7 +761,7 @@ def main():
         "rel_err_vs_oracle": errs,
     }
     newton = not args.no_newton
-    if args.secondary or newton or args.branches or args.geometry:
+    if args.secondary or newton or args.branches or args.geometry or args.table:
         del ctx, z, dz, v, r, y, gz, dz32, y32, b32, x32, ys
         torch.cuda.empty_cache()
     if args.branches:
@@ -709,6 +771,10 @@ def main():
     if args.geometry:
         out["geometry"] = geometry_leg(torch, I, pfmf, args.geometry, with_box=args.geometry_box)
         print(f"[bench] geometry {out['geometry']}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    if args.table:
+        out["table"] = table_leg(torch, I, pfmf, args.table)
+        print(f"[bench] table {out['table']}", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if args.secondary:
         out["secondary"] = secondary_leg(torch, I, pfmf, args.secondary)
