@@ -9,8 +9,8 @@ value = Jacobian-apply DoFs/s (FP64) = 4 n_nodes / median Jacobian-apply time.
 The headline's outputs are compared with the oracle on every node (rel-L2 and, per field,
 the largest entry error over the largest reference entry).
 Beside the headline the line carries side legs on other workloads: the third
-example's branches in parallel, curved (mapped) elements, the order-2 mesh and one
-Newton step on the Q4 box (FGMRES, and the conjugate-gradient variant beside it);
+example's branches in parallel, curved (mapped) elements, a mesh given by its
+element-to-node table (with a hole), the order-2 mesh and one Newton step on the Q4 box (FGMRES, and the conjugate-gradient variant beside it);
 with --newton-all also Newton steps with branches and on the curved mesh.
 Prints one JSON line.
 """
@@ -677,11 +677,12 @@ def main():
     achieved = bj / t_jac / 1e9
     counters = measured_counters(args.config + "/" + args.variant)
     traffic = counters.get("hbm_bytes_per_apply")
-    kname = {2: "pfmf::k_op64_q2<1, true, false, false> + pfmf::k_gather_bricks<double, 3>: one launch over all "
-                "bricks, then the node gather",
-             3: "pfmf::k_op64_q3<1, true, false, false, false> + pfmf::k_gather_bricks<double, 4>: one launch over all "
-                "bricks, then the node gather",
-             4: "pfmf::k_op64_q4<1, false, false>: 8 colour launches"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
+    kname = {2: "pfmf::k_op64_q2<1, true, false, false, false, false> + pfmf::k_gather_bricks<double, 3>: one "
+                "launch over all bricks, then the node gather",
+             3: "pfmf::k_op64_q3<1, true, false, false, false, false> + pfmf::k_gather_bricks<double, 4>: one "
+                "launch over all bricks, then the node gather",
+             4: "pfmf::k_op64_q4<1, false, false, false, true> + pfmf::k_gather_elems<double, 5>: one launch over "
+                "all elements, then the node gather"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(d, args.cpu_seconds)

@@ -250,16 +250,16 @@ pf_status pf_linearize(pf_ctx* ctx, const double* z, void* stream);
 pf_status pf_set_pmg_levels(pf_ctx* ctx, const int* orders, int n_levels);
 
 /* Context options (pf_set_option).
- * PF_OPT_SCATTER: how the matrix-core applies (FP64 residual, Jacobian and adjoint on
- * order-2 and order-3 meshes, FP32 level applies on order-3 meshes) add the element
+ * PF_OPT_SCATTER: how the FP64 residual, Jacobian and adjoint and the record applies
+ * (FP32 levels, stored FP64 Jacobian) on order-2, 3 and 4 meshes add the element
  * contributions into their output (the scatter-add E^T P^T of Section 4).
- * 1 = eight colour launches by brick parity that write the output directly;
- * 2 = one launch over all bricks that stores per-brick node sums in a context-owned
- * buffer (allocated on first use: 4 x 7^3 values per 2x2x2-element brick, FP64 and
- * FP32 separately), then a node gather; 0 = automatic (default): 2 while the FP64
- * buffer stays within PF_SCATTER_AUTO_BYTES, else 1. Both are deterministic and
- * differ only in the order of the final additions. Order-1 and order-4 meshes ignore
- * the option (order 4 launches one element per workgroup in 8 parity colours). */
+ * 1 = eight colour launches by brick (order 4: element) parity that write the output
+ * directly; 2 = the elements' sums stored in a context-owned buffer (allocated on first
+ * use; orders 2, 3: per 2x2x2-element brick, 4 x (2p+1)^3 values; order 4: per element,
+ * 4 x 125 values; FP64 and FP32 separately), then a node gather that adds them in a
+ * fixed order; 0 = automatic (default): 2 while the FP64 buffer stays within
+ * PF_SCATTER_AUTO_BYTES, else 1. Both are deterministic and differ only in the order of
+ * the final additions. Order-1 meshes ignore the option (8 colours). */
 #define PF_OPT_SCATTER 1
 #define PF_SCATTER_AUTO_BYTES (4LL << 30)
 /* PF_OPT_STORE_LIN64 (default 1): pf_linearize also stores the linearisation record

@@ -84,6 +84,21 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
 
 template <int MODE, bool VOCE, bool MB, bool GEO>
 pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
+  if (use_brick_buffer(c)) {
+    // element vectors in one launch, then the node gather
+    const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
+    if (!c->d_ebuf && hipMalloc(&c->d_ebuf, (size_t)n_elem * 4 * 125 * sizeof(double)) != hipSuccess)
+      return fail(PF_ENOMEM, "element-vector buffer: allocation failed");
+    a.evec = c->d_ebuf;
+    const int ng = xcd_grid_elems(c->mesh.nx, c->mesh.ny, c->mesh.nz);
+    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB, GEO, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tab);
+    HIPCHK(hipGetLastError());
+    const int n_rows = c->ny1 * c->nz1;
+    hipLaunchKernelGGL((k_gather_elems<double, 5>), dim3(std::min((n_rows + 3) / 4, 1 << 16)), dim3(NT), 0, s,
+                       (const double*)c->d_ebuf, a.m, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+  }
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;

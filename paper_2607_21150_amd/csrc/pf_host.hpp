@@ -101,12 +101,15 @@ struct pf_ctx {
   float* k32 = nullptr;
 };
 
-// PF_OPT_SCATTER: brick buffer unless colours were asked for, or the automatic choice
-// meets a buffer above PF_SCATTER_AUTO_BYTES; never inside an allocation-free call
+// PF_OPT_SCATTER: brick buffer (order 4: element vectors) unless colours were asked for,
+// or the automatic choice meets a buffer above PF_SCATTER_AUTO_BYTES; never inside an
+// allocation-free call
 inline bool use_brick_buffer(const pf_ctx* c) {
   if (c->colours_only) return false;
   if (c->scatter_mode != 0) return c->scatter_mode == 2;
-  return (int64_t)c->n_bricks * 4 * 343 * (int64_t)sizeof(double) <= PF_SCATTER_AUTO_BYTES;
+  const int64_t bytes = c->mesh.p == 4 ? (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz * 4 * 125 * 8
+                                       : (int64_t)c->n_bricks * 4 * 343 * 8;
+  return bytes <= PF_SCATTER_AUTO_BYTES;
 }
 
 // FP64 residual (MODE 0), Jacobian (1) or adjoint (2) over the context's mesh: every

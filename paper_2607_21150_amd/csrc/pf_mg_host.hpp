@@ -278,7 +278,29 @@ pf_status launch_a32_mfma(pf_ctx* c, A32Args a, hipStream_t s) {
 }
 
 template <typename V, int PC, bool MB, bool GEO>
-pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a, hipStream_t s) {
+pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a0, hipStream_t s) {
+  LinApplyArgs<V> a = a0;
+  if (use_brick_buffer(c)) {
+    // element vectors of the level (buffer sized for the fine level), then the node gather
+    V** buf;
+    if constexpr (sizeof(V) == 4) buf = &c->mg.ebuf32;
+    else buf = &c->d_ebuf;
+    const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
+    if (!*buf && hipMalloc((void**)buf, (size_t)n_elem * 4 * 125 * sizeof(V)) != hipSuccess)
+      return fail(PF_ENOMEM, "element-vector buffer: allocation failed");
+    a.ebuf = *buf;
+    const int ng = xcd_grid_elems(c->mesh.nx, c->mesh.ny, c->mesh.nz);
+    if constexpr (sizeof(V) == 4)
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB, GEO, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tabf);
+    else
+      hipLaunchKernelGGL((k_a32_q4<V, PC, MB, GEO, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tab);
+    HIPCHK(hipGetLastError());
+    const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
+    hipLaunchKernelGGL((k_gather_elems<V, PC>), dim3(std::min((n_rows + 3) / 4, 1 << 16)), dim3(NT), 0, s,
+                       (const V*)a.ebuf, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
+    HIPCHK(hipGetLastError());
+    return PF_OK;
+  }
   for (int col = 0; col < 8; ++col) {
     const int ng = xcd_grid(c->mesh.nx, c->mesh.ny, c->mesh.nz, col);
     if (ng == 0) continue;

@@ -1,6 +1,7 @@
 """Full-size parity: the workloads bench.py times, launched the way bench.py launches them
 (one context per workload, the automatic scatter-add: the brick buffer on Q2/Q3, element
-colours on Q4), against the oracle on every node of the mesh.
+vectors on Q4, each followed by its node gather), against the oracle on every node of the
+mesh.
 
 Each comparison checks two bars:
 * rel-L2 over the whole [4][n_nodes] vector: 1e-12 for the FP64 applies, 1e-5 for the FP32
@@ -93,10 +94,10 @@ def test_full_mesh(pf, oracle_lib, name, variant):
     print(f"  {name} {variant} (rel-L2, max entry): {out}", flush=True)
 
 
-@pytest.mark.parametrize("name", ["C2", "C3"])
+@pytest.mark.parametrize("name", ["C2", "C3", "C5"])
 def test_scatter_modes_agree_at_full_size(pf, name):
-    """The two scatter-adds at full size (where the automatic choice differs): the brick
-    buffer and the colour launches agree to rounding of the final additions."""
+    """The two scatter-adds at full size: the brick buffer (order 4: element vectors) with
+    its node gather and the colour launches agree to rounding of the final additions."""
     print(f"case {name} scatter modes", flush=True)
     d = I.make_inputs(name, "plastic")
     ctx = pf.Context.from_inputs(d)
