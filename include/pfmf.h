@@ -169,7 +169,9 @@ pf_status pf_sizes(const pf_ctx* ctx, int64_t* n_nodes, int64_t* n_q, int64_t* n
  * branches, and so does the linearisation: pf_linearize stores one record layer per
  * branch (the block's layer holds the switch and dL/dphi of the total psi^+), which the
  * FP32 levels, the V-cycle, pf_apply_jacobian_lin and pf_newton_step sum over; the
- * record grows to (1 + n_extra) layers. The call invalidates the linearisation.
+ * record grows to (1 + n_extra) layers. The call invalidates the linearisation and
+ * synchronises the device before it frees the previous branch tables (applies still in
+ * flight on any stream may read them), so it is not for use inside a stream capture.
  * The state commit with branches is pf_commit_state_branches.
  * Errors: PF_EINVAL for a bad kind or parameter (E > 0, -1 < nu < 0.5, eta_d > 0,
  * sigma0, H, visc, voce_beta >= 0, sigma_inf >= sigma0 with Voce), PF_EUNSUPPORTED at
@@ -182,8 +184,9 @@ pf_status pf_set_branches(pf_ctx* ctx, const pf_branch* branches, int n_extra, c
  * det J, 80 bytes per point, owned by the context, plus an FP32 copy of 40 bytes per point
  * for the FP32 levels) from which the applies take their gradients and weights; X itself
  * is not kept. X = NULL returns to
- * the box. Orders 2-4. The call invalidates the linearisation and synchronises the
- * stream. Everything else follows the geometry too: the state commit, the linearisation
+ * the box. Orders 2-4. The call invalidates the linearisation, synchronises the device
+ * before it frees the previous record (applies in flight may read it) and synchronises
+ * the stream after building the new one. Everything else follows the geometry too: the state commit, the linearisation
  * (records, FP32 levels evaluated at the fine points with the fine J^-1, their Jacobi
  * diagonals, the order-1 element matrices), pf_apply_jacobian_lin, the V-cycle and
  * pf_newton_step.

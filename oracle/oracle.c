@@ -270,6 +270,8 @@ static double log_divdiff(double bi_m1, double bj_m1) {
   return (double)(r / bj);
 }
 
+double or_log_divdiff(double bi_m1, double bj_m1) { return log_divdiff(bi_m1, bj_m1); }
+
 /* ------------------------------------------------------------------------ */
 /* Pointwise constitutive state: R1-R11.                                     */
 /* ------------------------------------------------------------------------ */

@@ -160,6 +160,9 @@ int or_commit_state_mb(const or_mesh* m, const or_phase* ph, int nph, const or_b
                        const double* z, double* state_new, double* xstate_new);
 
 /* Number of OpenMP threads the applies use (1 when built without OpenMP). */
+/* (ln b_i - ln b_j) / (b_i - b_j) for b = 1 + beta (the off-diagonal factor of the
+ * principal-direction tangent, Appendix B), finite as b_i -> b_j. */
+double or_log_divdiff(double bi_m1, double bj_m1);
 int or_num_threads(void);
 void or_set_num_threads(int n);  /* OpenMP threads of the element loops (timing only) */
 

@@ -100,6 +100,8 @@ def lib():
         for f in ("or_residual", "or_jacobian", "or_adjoint", "or_element_jacobian"):
             getattr(L, f).restype = C.c_int
         L.or_num_threads.restype = C.c_int
+        L.or_log_divdiff.argtypes = [C.c_double, C.c_double]
+        L.or_log_divdiff.restype = C.c_double
         L.or_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
@@ -360,6 +362,11 @@ class Oracle:
         gy = ey * m.p + a[None, :, None]
         gz = ez * m.p + a[:, None, None]
         return (gx + nx1 * (gy + ny1 * gz)).reshape(-1)
+
+
+def log_divdiff(bi_m1: float, bj_m1: float) -> float:
+    """(ln b_i - ln b_j) / (b_i - b_j) with b = 1 + beta: the oracle's off-diagonal tangent factor."""
+    return float(lib().or_log_divdiff(float(bi_m1), float(bj_m1)))
 
 
 def num_threads():
