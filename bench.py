@@ -28,6 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# What the paper states about its own runs (Section 5, computing environment): no per-apply
+# throughput is given, only the scale of the microstructure runs and their hardware.
+PAPER_CONTEXT = {
+    "per_apply_throughput": None,
+    "hardware": "AMD Instinct MI250X (gfx90a), 4 per node, each run as 2 logical GPUs; 64 EPYC cores and "
+                "512 GB host memory per node",
+    "largest_problem_dofs_approx": 2.0e7,
+    "time_steps_approx": 500,
+    "logical_gpus_max": 24,
+    "nodes_max": 3,
+    "allocation_hours": 12,
+    "derived_wall_s_per_step": 12 * 3600 / 500,
+    "elements": "quadratic tetrahedra, unstructured microstructure meshes",
+}
 HBM_PEAK_GBS = 8000.0
 FP64_VEC_PEAK_TFLOPS = 78.6
 CSRC = os.path.join(ROOT, "paper_2607_21150_amd", "csrc")
@@ -760,6 +774,7 @@ def main():
         "fp32_over_fp64_apply_speedup": ms_med["jacobian"] / ms_med["fp32_apply"],
         "fp32_over_stored_fp64_speedup": ms_med["jacobian_stored"] / ms_med["fp32_apply"],
         "rel_err_vs_oracle": errs,
+        "paper_context": PAPER_CONTEXT,
     }
     newton = not args.no_newton
     if args.secondary or newton or args.branches or args.geometry or args.table:
