@@ -46,8 +46,9 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
       hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = c->ny1 * c->nz1;
-    hipLaunchKernelGGL((k_gather_bricks<double, P>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
-                       (const double*)c->d_ebuf, a.m, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
+    hipLaunchKernelGGL((k_gather_ext<double, 2 * P - 1>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0,
+                       s, (const double*)c->d_ebuf, a.m.nbx, a.m.nby, a.m.nbz, c->nx1, c->ny1, n_rows, c->n_nodes,
+                       a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }
@@ -85,7 +86,8 @@ pf_status launch_op64_mfma(pf_ctx* c, OpArgs a, hipStream_t s) {
 template <int MODE, bool VOCE, bool MB, bool GEO>
 pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   if (use_brick_buffer(c)) {
-    // element vectors in one launch, then the node gather
+    // element vectors (extended node grid, one block per element) in one launch, then the
+    // node gather
     const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
     if (!c->d_ebuf && hipMalloc(&c->d_ebuf, (size_t)n_elem * 4 * 125 * sizeof(double)) != hipSuccess)
       return fail(PF_ENOMEM, "element-vector buffer: allocation failed");
@@ -94,8 +96,8 @@ pf_status launch_op64_q4_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, MB, GEO, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = c->ny1 * c->nz1;
-    hipLaunchKernelGGL((k_gather_elems<double, 5>), dim3(std::min((n_rows + 3) / 4, 1 << 16)), dim3(NT), 0, s,
-                       (const double*)c->d_ebuf, a.m, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
+    hipLaunchKernelGGL((k_gather_ext<double, 5>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const double*)c->d_ebuf, a.m.nx, a.m.ny, a.m.nz, c->nx1, c->ny1, n_rows, c->n_nodes, a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }
@@ -135,7 +137,7 @@ pf_status launch_op64_tab_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   HIPCHK(hipGetLastError());
   const int gb = (int)std::min<int64_t>((c->n_nodes + NT - 1) / NT, 1 << 16);
   hipLaunchKernelGGL(k_gather_csr, dim3(gb), dim3(NT), 0, s, (const double*)c->d_evec, (const int32_t*)c->d_csr_off,
-                     (const int32_t*)c->d_csr_ent, c->n_nodes, P * P * P, a.out);
+                     (const int32_t*)c->d_csr_ent, c->n_nodes, a.out);
   HIPCHK(hipGetLastError());
   return PF_OK;
 }

@@ -128,18 +128,21 @@ __global__ __launch_bounds__(NT) void k_geometry_tab(const double* __restrict__ 
 
 // Transpose of the table restriction (E^T P^T of Section 4) as a node-owner gather: node i
 // sums the element-vector entries listed for it in a CSR map, ent[off[i] .. off[i+1]), each
-// entry e 4 P3 + a (element e, local node a; the field adds f P3), in the map's fixed order
-// (by element, then local node): deterministic, no atomics. One thread per node.
+// entry (e P3 + a) 4 (element e, local node a; the 4 fields are contiguous, so one entry is
+// one 32-byte read), in the map's fixed order (by element, then local node):
+// deterministic, no atomics. One thread per node.
 static __global__ __launch_bounds__(NT) void k_gather_csr(const double* __restrict__ evec, const int32_t* __restrict__ off,
-                                                   const int32_t* __restrict__ ent, int64_t n_nodes, int P3,
+                                                   const int32_t* __restrict__ ent, int64_t n_nodes,
                                                    double* __restrict__ out) {
   for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < n_nodes; i += (int64_t)gridDim.x * NT) {
     const int k0 = off[i], k1 = off[i + 1];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = k0; k < k1; ++k) {
-      const int64_t b = ent[k];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) acc[f] += evec[b + f * P3];
+      const double4 v = *reinterpret_cast<const double4*>(evec + ent[k]);
+      acc[0] += v.x;
+      acc[1] += v.y;
+      acc[2] += v.z;
+      acc[3] += v.w;
     }
 #pragma unroll
     for (int f = 0; f < 4; ++f) out[f * n_nodes + i] = acc[f];

@@ -245,25 +245,42 @@ __device__ inline void store_brick4(const T* ev, const MeshDev& m, const BrickGe
   }
 }
 
-// Second half: every node sums the stored values of the (up to 8) bricks holding it
-// and stores the result. Along an axis, node i (brick size S = 2p nodes) sits at
-// extended position i + i / S of its own brick, and a node on a brick face (i % S == 0,
-// i > 0) also at the position just before, in the previous brick. One wave per node
-// row (blockIdx.y * 4 + wave, blockIdx.z = field), so the y and z cases are uniform;
-// lower bricks are added first along each axis.
-template <typename T, int P>
-__global__ __launch_bounds__(NT) void k_gather_bricks(const T* __restrict__ eb, MeshDev m, int nx1, int ny1,
-                                                      int n_rows, int64_t n_nodes, T* __restrict__ out) {
-  constexpr int p = P - 1, NB = 2 * P - 1, S = 2 * p;
+// Second half: every node sums the stored values of the (up to 8) blocks holding it
+// and stores the result. The buffer is an extended node grid [4][NZe][NYe][NXe] in
+// which each block (a brick of 2x2x2 elements, or one element) owns NB nodes per axis
+// and the nodes on a face between two blocks appear twice. Along an axis, node i
+// (S = NB - 1 nodes per block step) sits at extended position i + i / S of its own
+// block, and a node on a block face (i % S == 0, i > 0) also at the position just
+// before, in the previous block. One wave per node row (blockIdx.y * 4 + wave,
+// blockIdx.z = field); the wave first sums the row's (up to 4) extended rows at every
+// extended position (lane = position, so the loads are contiguous), then a face node
+// adds the previous position's sum, taken from the neighbouring lane. Lower blocks
+// are added first along each axis (deterministic).
+template <typename T>
+__device__ inline T lane_take(T v, int src);
+template <>
+__device__ inline double lane_take<double>(double v, int src) {
+  return lane_read(v, src);
+}
+template <>
+__device__ inline float lane_take<float>(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(NT) void k_gather_ext(const T* __restrict__ eb, int nbx, int nby, int nbz, int nx1,
+                                                   int ny1, int n_rows, int64_t n_nodes, T* __restrict__ out) {
+  constexpr int S = NB - 1;
   const int f = blockIdx.z, w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t NXe = (int64_t)m.nbx * NB, NYe = (int64_t)m.nby * NB, NZe = (int64_t)m.nbz * NB;
+  const int NXe = nbx * NB;
+  const int64_t NYe = (int64_t)nby * NB, NZe = (int64_t)nbz * NB;
   const T* ebf = eb + f * NZe * NYe * NXe;
   for (int r = blockIdx.y * 4 + w; r < n_rows; r += gridDim.y * 4) {
     const int iz = r / ny1, iy = r - iz * ny1;
-    const bool yo = iy / S < m.nby, yp = iy % S == 0 && iy >= S;
-    const bool zo = iz / S < m.nbz, zp = iz % S == 0 && iz >= S;
+    const bool yo = iy / S < nby, yp = iy % S == 0 && iy >= S;
+    const bool zo = iz / S < nbz, zp = iz % S == 0 && iz >= S;
     const int64_t gy = iy + iy / S, gz = iz + iz / S;
-    // extended rows: own / previous brick along z (index 0 / 1) and y (0 / 1)
+    // extended rows: own / previous block along z (index 0 / 1) and y (0 / 1)
     const T* rows[4];
     int nr = 0;
     if (zp && yp) rows[nr++] = ebf + ((gz - 1) * NYe + gy - 1) * NXe;
@@ -271,19 +288,30 @@ __global__ __launch_bounds__(NT) void k_gather_bricks(const T* __restrict__ eb, 
     if (zo && yp) rows[nr++] = ebf + (gz * NYe + gy - 1) * NXe;
     if (zo && yo) rows[nr++] = ebf + (gz * NYe + gy) * NXe;
     T* orow = out + f * n_nodes + (int64_t)r * nx1;
-#pragma unroll 4
-    for (int ix = l; ix < nx1; ix += 64) {
-      const int gx = ix + ix / S;
-      const bool xo = ix / S < m.nbx, xp = ix % S == 0 && ix >= S;
-      T acc = T(0);
+    for (int j0 = 0; j0 < NXe; j0 += 64) {
+      const int j = j0 + l;
+      const bool in = j < NXe;
+      T sv = T(0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (k < nr) {
-          if (xp) acc += rows[k][gx - 1];
-          if (xo) acc += rows[k][gx];
+      for (int k = 0; k < 4; ++k)
+        if (k < nr && in) sv += rows[k][j];
+      T prev = lane_take(sv, l > 0 ? l - 1 : 0);
+      const int b = j / NB, q = j - b * NB;
+      const bool face = q == 0 && j >= NB;
+      if (l == 0 && face) {  // the previous position belongs to the previous 64-lane chunk
+        prev = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < nr) prev += rows[k][j - 1];
+      }
+      if (in) {
+        const int ix = j - b;  // node of position j (q < NB - 1)
+        if (q < NB - 1) {
+          if (ix < nx1) orow[ix] = face ? prev + sv : sv;
+        } else if (ix == nx1 - 1) {  // last position of the last block: the row's end node
+          orow[ix] = sv;
         }
       }
-      orow[ix] = acc;
     }
   }
 }
@@ -481,7 +509,7 @@ __global__ __launch_bounds__(NT, 2) void k_op64_q3(OpArgs a, int colour, DevTabl
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         if (TAB)
-          a.evec[(e * 4 + f) * 64 + l] = r[f];
+          a.evec[(e * 64 + l) * 4 + f] = r[f];
         else
           ev[(slot * 4 + f) * 64 + l] = r[f];
       }
@@ -550,7 +578,7 @@ namespace pfmf {
 // restriction (with GEO): a group of 8 consecutive elements per workgroup (wave w: elements
 // w and w + 4), nodes from a.conn, element vectors straight to a.evec [n_elem][4][27].
 template <int MODE, bool BB, bool VOCE, bool MB, bool GEO, bool TAB = false>
-__global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
+__global__ __launch_bounds__(NT, (MB || GEO) ? 2 : 3) void k_op64_q2(OpArgs a, int colour,
                                                                               DevTables* __restrict__ tabs) {
   static_assert(!TAB || (GEO && !MB), "the table restriction runs on mapped elements without branches");
   __shared__ double ev[8 * 4 * 64];
@@ -785,7 +813,7 @@ __global__ __launch_bounds__(NT, (MODE == M_ADJ || MB || GEO) ? 2 : 3) void k_op
         if (nx_ < 3 && ny_ < 3 && nz_ < 3) {
           const int64_t eh = e0 + 4 * half;
 #pragma unroll
-          for (int f = 0; f < 4; ++f) a.evec[(eh * 4 + f) * 27 + nx_ + 3 * ny_ + 9 * nz_] = r[f];
+          for (int f = 0; f < 4; ++f) a.evec[(eh * 27 + nx_ + 3 * ny_ + 9 * nz_) * 4 + f] = r[f];
         }
       } else {
 #pragma unroll

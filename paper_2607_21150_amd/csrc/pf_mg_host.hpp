@@ -246,8 +246,9 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
       hipLaunchKernelGGL((k_a32_q2<V, PC, true, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
-    hipLaunchKernelGGL((k_gather_bricks<V, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
-                       (const V*)a.ebuf, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
+    hipLaunchKernelGGL((k_gather_ext<V, 2 * PC - 1>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const V*)a.ebuf, a.m.nbx, a.m.nby, a.m.nbz, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes,
+                       a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }
@@ -296,8 +297,8 @@ pf_status launch_lin_q4_v(pf_ctx* c, const LinApplyArgs<V>& a0, hipStream_t s) {
       hipLaunchKernelGGL((k_a32_q4<V, PC, MB, GEO, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
-    hipLaunchKernelGGL((k_gather_elems<V, PC>), dim3(std::min((n_rows + 3) / 4, 1 << 16)), dim3(NT), 0, s,
-                       (const V*)a.ebuf, a.m, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
+    hipLaunchKernelGGL((k_gather_ext<V, PC>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,
+                       (const V*)a.ebuf, a.m.nx, a.m.ny, a.m.nz, a.lev.nx1, a.lev.ny1, n_rows, a.lev.n_nodes, a.out);
     HIPCHK(hipGetLastError());
     return PF_OK;
   }

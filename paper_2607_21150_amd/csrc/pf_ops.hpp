@@ -39,7 +39,7 @@ struct OpArgs {
   int n_extra;
   const double* qd;     // mapped elements: per-point geometry [10][n_q] (null: the box)
   // table restriction (pf_setup_mesh_table): element e's local node a is global node
-  // conn[e * P^3 + a]; element vectors go to evec [n_elem][4][P^3], summed per node by
+  // conn[e * P^3 + a]; element vectors go to evec [n_elem][P^3][4], summed per node by
   // k_gather_csr; elements are taken in groups of 8 per workgroup
   const int32_t* conn;
   int64_t n_elem;

@@ -58,55 +58,18 @@ __device__ inline bool xcd_elem_all(const MeshDev& m, int id, ElemGeom& g) {
   return true;
 }
 
-// Store the element vector R[f][k][j][i] (NF fields of P^3 nodes) as element e's block of
-// the element-vector buffer ev [n_elem][NF][P^3].
+// Store the element vector R[f][k][j][i] (NF fields of P^3 nodes) into the extended node
+// grid ev [NF][nz P][ny P][nx P], in which every element owns its P nodes per axis (face
+// nodes appear once per element holding them); k_gather_ext<T, P> sums them per node.
+// Each row of P values is contiguous, and the next element along x (launched next on the
+// same XCD) writes the adjacent P values.
 template <typename T, int P, int NF>
-__device__ inline void store_elem(const T* R, int64_t e, T* __restrict__ ev) {
+__device__ inline void store_ext(const T* R, const MeshDev& m, const ElemGeom& g, T* __restrict__ ev) {
   constexpr int P3 = P * P * P;
-  for (int t = threadIdx.x; t < NF * P3; t += NT5) ev[e * (NF * P3) + t] = R[t];
-}
-
-// Node sums of the element vectors (the scatter-add E^T P^T of Section 4): along each axis
-// node i lies in element i / p at local i % p and, on an element face (i % p == 0, i > 0),
-// also in element i / p - 1 at local p; every node adds its (up to 8) entries, lower
-// elements first along z, y, x (deterministic, no atomics). One wave per node row
-// (row = iy + ny1 iz), four fields per node.
-template <typename T, int P>
-__global__ __launch_bounds__(NT) void k_gather_elems(const T* __restrict__ ev, MeshDev m, int nx1, int ny1,
-                                                     int n_rows, int64_t n_nodes, T* __restrict__ out) {
-  constexpr int p = P - 1, P3 = P * P * P;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int r = blockIdx.x * 4 + w; r < n_rows; r += gridDim.x * 4) {
-    const int iz = r / ny1, iy = r - iz * ny1;
-    int ez[2], lz[2], nzc = 0, ey[2], ly[2], nyc = 0;
-    if (iz % p == 0 && iz > 0) { ez[nzc] = iz / p - 1; lz[nzc++] = p; }
-    if (iz / p < m.nz) { ez[nzc] = iz / p; lz[nzc++] = iz % p; }
-    if (iy % p == 0 && iy > 0) { ey[nyc] = iy / p - 1; ly[nyc++] = p; }
-    if (iy / p < m.ny) { ey[nyc] = iy / p; ly[nyc++] = iy % p; }
-    for (int ix = l; ix < nx1; ix += 64) {
-      int ex[2], lx[2], nxc = 0;
-      if (ix % p == 0 && ix > 0) { ex[nxc] = ix / p - 1; lx[nxc++] = p; }
-      if (ix / p < m.nx) { ex[nxc] = ix / p; lx[nxc++] = ix % p; }
-      T acc[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        if (a >= nzc) break;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          if (b >= nyc) break;
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            if (c >= nxc) break;
-            const int64_t e = (int64_t)ex[c] + (int64_t)m.nx * (ey[b] + (int64_t)m.ny * ez[a]);
-            const T* src = ev + e * (4 * P3) + lx[c] + P * (ly[b] + P * lz[a]);
-#pragma unroll
-            for (int f = 0; f < 4; ++f) acc[f] += src[f * P3];
-          }
-        }
-      }
-#pragma unroll
-      for (int f = 0; f < 4; ++f) out[f * n_nodes + (int64_t)r * nx1 + ix] = acc[f];
-    }
+  const int64_t NXe = (int64_t)m.nx * P, NYe = (int64_t)m.ny * P, NZe = (int64_t)m.nz * P;
+  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
+    const int f = t / P3, n = t - f * P3, k = n / (P * P), j = (n / P) % P, i = n % P;
+    ev[((f * NZe + (int64_t)g.ez * P + k) * NYe + (int64_t)g.ey * P + j) * NXe + (int64_t)g.ex * P + i] = R[t];
   }
 }
 
@@ -320,8 +283,8 @@ template <int P, int Q> struct Q5Lds {
 
 // FP64 residual / Jacobian / adjoint on order-4 elements.
 // GEO: mapped elements (J^-1 and weight per point from a.qd). EV: all elements in one
-// launch, element vectors stored to a.evec (summed per node by k_gather_elems); otherwise
-// one colour, added into a.out by the colour rule.
+// launch, element vectors stored to the extended node grid a.evec (summed per node by
+// k_gather_ext); otherwise one colour, added into a.out by the colour rule.
 template <int MODE, bool VOCE, bool MB, bool GEO, bool EV = false>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   constexpr int P = 5, Q = 5, Q3 = 125;
@@ -467,7 +430,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   __syncthreads();
   sf5_bwd<double, DevTables, P, Q, 4>(bufB, bufA, tabs);
   if (EV)
-    store_elem<double, P, 4>(bufA, e, a.evec);
+    store_ext<double, P, 4>(bufA, a.m, g, a.evec);
   else
     scatter_elem<double, P, 4>(bufA, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);
   if (MODE == M_ADJ) {
@@ -505,8 +468,8 @@ template <typename V> struct TablesOf;
 template <> struct TablesOf<float> { using type = DevTablesF; };
 template <> struct TablesOf<double> { using type = DevTables; };
 
-// EV: all elements in one launch, the level's element vectors stored to a.ebuf
-// [n_elem][4][PC^3] (summed per node by k_gather_elems).
+// EV: all elements in one launch, the level's element vectors stored to the extended
+// node grid a.ebuf [4][nz PC][ny PC][nx PC] (summed per node by k_gather_ext).
 template <typename V, int PC, bool MB, bool GEO = false, bool EV = false>
 __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour,
                                                    const typename TablesOf<V>::type* __restrict__ tabs) {
@@ -600,7 +563,7 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
   __syncthreads();
   sf5_bwd<V, Tab, PC, Q, 4>(bufB, bufA, tabs);
   if (EV)
-    store_elem<V, PC, 4>(bufA, e, a.ebuf);
+    store_ext<V, PC, 4>(bufA, a.m, g, a.ebuf);
   else
     scatter_elem<V, PC, 4>(bufA, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
 }

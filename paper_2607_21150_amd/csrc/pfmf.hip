@@ -380,7 +380,7 @@ pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* con
   if (st0) return st0;
   const hipStream_t s = (hipStream_t)stream;
   // the table on the host: range check and the CSR map of its transpose (node -> entries
-  // e 4 P^3 + a in element order), built once here
+  // (e P^3 + a) 4 in element order), built once here
   std::vector<int32_t> h((size_t)mesh->n_elem * P3);
   {
     hipError_t e = hipMemcpyAsync(h.data(), conn, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -399,7 +399,7 @@ pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* con
     std::vector<int32_t> fill(off.begin(), off.end() - 1);
     for (size_t k = 0; k < h.size(); ++k) {
       const int64_t e = (int64_t)(k / P3), a = (int64_t)(k % P3);
-      ent[fill[h[k]]++] = (int32_t)(e * 4 * P3 + a);
+      ent[fill[h[k]]++] = (int32_t)((e * P3 + a) * 4);
     }
   }
   auto* c = new pf_ctx;
