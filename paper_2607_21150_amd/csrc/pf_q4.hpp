@@ -106,11 +106,21 @@ __device__ inline void scatter_elem(const T* R, const MeshDev& m, int nx1, int n
   }
 }
 
-// Forward: U[f][k][j][i] (P^3 per field) -> Qo[f][c][qz][qy][qx] (Q^3 per field and
-// component c = value, d/dxi_x, d/dxi_y, d/dxi_z). X holds 2 NF P^2 Q values, Y
-// (aliasing U) 3 NF Q^2 P. Starts after, and ends with, a barrier.
-template <typename T, typename Tab, int P, int Q, int NF>
+// Slot of component c (0 value, 1..3 d/dxi_x, d/dxi_y, d/dxi_z) of field f in the point
+// arrays Qo / Qi. CV (compact, four fields u_x, u_y, u_z, phi): the displacement fields
+// have no value slot (the operator reads only their gradients and tests them only against
+// gradients), so 13 arrays instead of 16; otherwise 4 f + c.
+template <bool CV>
+__device__ __forceinline__ constexpr int qslot(int f, int c) {
+  return CV ? (f < 3 ? 3 * f + c - 1 : 9 + c) : 4 * f + c;
+}
+
+// Forward: U[f][k][j][i] (P^3 per field) -> Qo[slot(f, c)][qz][qy][qx] (Q^3 per field and
+// component c = value, d/dxi_x, d/dxi_y, d/dxi_z; with CV no values for f < 3). X holds
+// 2 NF P^2 Q values, Y (aliasing U) 3 NF Q^2 P. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF, bool CV = false>
 __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb) {
+  static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
   constexpr int P2 = P * P, P3 = P2 * P, Q3 = Q * Q * Q;
   const int t = threadIdx.x;
   // x: thread (f, j, k); X[f][c][k][j][qx], c = B_x, D_x
@@ -180,20 +190,21 @@ __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb
         dx += bz * yx[k];
       }
       const int o = s + Q * Q * q;
-      XQ[(4 * f) * Q3 + o] = v;
-      XQ[(4 * f + 1) * Q3 + o] = dx;
-      XQ[(4 * f + 2) * Q3 + o] = dy;
-      XQ[(4 * f + 3) * Q3 + o] = dz;
+      if (!CV || f == 3) XQ[qslot<CV>(f, 0) * Q3 + o] = v;
+      XQ[qslot<CV>(f, 1) * Q3 + o] = dx;
+      XQ[qslot<CV>(f, 2) * Q3 + o] = dy;
+      XQ[qslot<CV>(f, 3) * Q3 + o] = dz;
     }
   }
   __syncthreads();
 }
 
-// Transposed: Qi[f][c][q] (c = value test, tests against d/dxi_x, d/dxi_y, d/dxi_z;
-// in XQ) -> R[f][k][j][i] (in ZR). Z (in ZR) holds 3 NF P Q^2 values, Y (in XQ)
-// 2 NF P^2 Q. Starts after, and ends with, a barrier.
-template <typename T, typename Tab, int P, int Q, int NF>
+// Transposed: Qi[slot(f, c)][q] (c = value test, tests against d/dxi_x, d/dxi_y,
+// d/dxi_z; in XQ; with CV no value tests for f < 3) -> R[f][k][j][i] (in ZR). Z (in ZR)
+// holds 3 NF P Q^2 values, Y (in XQ) 2 NF P^2 Q. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF, bool CV = false>
 __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb) {
+  static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
   const int t = threadIdx.x;
   // z^T: thread (f, qx, qy); Z[f][c][k][qy][qx], c = value chain, x tests, y tests
@@ -206,8 +217,9 @@ __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int o = s + Q2 * q;
-      const T f0 = XQ[(4 * f) * Q3 + o], fx = XQ[(4 * f + 1) * Q3 + o];
-      const T fy = XQ[(4 * f + 2) * Q3 + o], fz = XQ[(4 * f + 3) * Q3 + o];
+      const T f0 = (!CV || f == 3) ? XQ[qslot<CV>(f, 0) * Q3 + o] : T(0);
+      const T fx = XQ[qslot<CV>(f, 1) * Q3 + o];
+      const T fy = XQ[qslot<CV>(f, 2) * Q3 + o], fz = XQ[qslot<CV>(f, 3) * Q3 + o];
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         const T bz = (T)tb->B[P][Q][q][k];
@@ -273,11 +285,11 @@ __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb
   __syncthreads();
 }
 
-// LDS sizes (values) of the two buffers for up to 4 fields.
-template <int P, int Q> struct Q5Lds {
+// LDS sizes (values) of the two buffers for up to 4 fields (CV: the compact point arrays).
+template <int P, int Q, bool CV = false> struct Q5Lds {
   static constexpr int a0 = 4 * P * P * P, a1 = 12 * Q * Q * P;
   static constexpr int A = a0 > a1 ? a0 : a1;  // U / Y (forward), Z / R (backward)
-  static constexpr int b0 = 8 * P * P * Q, b1 = 16 * Q * Q * Q;
+  static constexpr int b0 = 8 * P * P * Q, b1 = (CV ? 13 : 16) * Q * Q * Q;
   static constexpr int B = b0 > b1 ? b0 : b1;  // X / Qo (forward), Qi / Y (backward)
 };
 
@@ -288,7 +300,9 @@ template <int P, int Q> struct Q5Lds {
 template <int MODE, bool VOCE, bool MB, bool GEO, bool EV = false>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
   constexpr int P = 5, Q = 5, Q3 = 125;
-  using L = Q5Lds<P, Q>;
+  // compact point arrays (13 of 125 values each): 25 KB of LDS per element instead of 28,
+  // so that six elements fit a CU's 160 KB (3 waves per SIMD, which the VGPRs allow)
+  using L = Q5Lds<P, Q, true>;
   __shared__ double bufA[L::A];
   __shared__ double bufB[L::B];
   __shared__ double red[2 * 3 * 8];
@@ -318,14 +332,14 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   }
   gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
   __syncthreads();
-  sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
+  sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
   double G[9], phi, gphi[3];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    const double dr[3] = {bufB[(4 * f + 1) * Q3 + ql], bufB[(4 * f + 2) * Q3 + ql], bufB[(4 * f + 3) * Q3 + ql]};
+    const double dr[3] = {bufB[qslot<true>(f, 1) * Q3 + ql], bufB[qslot<true>(f, 2) * Q3 + ql], bufB[qslot<true>(f, 3) * Q3 + ql]};
     ref_to_phys<GEO>(dr, ih, gA, f < 3 ? G + 3 * f : gphi);
   }
-  phi = bufB[12 * Q3 + ql];
+  phi = bufB[qslot<true>(3, 0) * Q3 + ql];
   double phin = 0.0;
   __syncthreads();
   if (MODE == M_RES) {
@@ -350,13 +364,13 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   if (MODE != M_RES) {
     gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
     __syncthreads();
-    sf5_fwd<double, DevTables, P, Q, 4>(bufA, bufB, tabs);
+    sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const double dr[3] = {bufB[(4 * f + 1) * Q3 + ql], bufB[(4 * f + 2) * Q3 + ql], bufB[(4 * f + 3) * Q3 + ql]};
+      const double dr[3] = {bufB[qslot<true>(f, 1) * Q3 + ql], bufB[qslot<true>(f, 2) * Q3 + ql], bufB[qslot<true>(f, 3) * Q3 + ql]};
       ref_to_phys<GEO>(dr, ih, gA, f < 3 ? W + 3 * f : gw);
     }
-    wphi = bufB[12 * Q3 + ql];
+    wphi = bufB[qslot<true>(3, 0) * Q3 + ql];
     __syncthreads();
   }
   const double kfg = a.fr.kf * mp.Gc;
@@ -415,20 +429,19 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     f0 = phib;
   }
   if (MB) bad |= pt && xbad;
-  // point coefficients into Qi[f][c][q] (bufB is free: every thread has read its values)
+  // point coefficients into Qi (bufB is free: every thread has read its values)
   if (pt) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
       double b[3];
       phys_to_ref<GEO>(f < 3 ? Fu + 3 * f : f1, ih, gA, b);
-      if (f < 3) bufB[(4 * f) * Q3 + ql] = 0.0;
 #pragma unroll
-      for (int K = 0; K < 3; ++K) bufB[(4 * f + 1 + K) * Q3 + ql] = b[K];
+      for (int K = 0; K < 3; ++K) bufB[qslot<true>(f, 1 + K) * Q3 + ql] = b[K];
     }
-    bufB[12 * Q3 + ql] = f0;
+    bufB[qslot<true>(3, 0) * Q3 + ql] = f0;
   }
   __syncthreads();
-  sf5_bwd<double, DevTables, P, Q, 4>(bufB, bufA, tabs);
+  sf5_bwd<double, DevTables, P, Q, 4, true>(bufB, bufA, tabs);
   if (EV)
     store_ext<double, P, 4>(bufA, a.m, g, a.evec);
   else
@@ -475,7 +488,7 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
                                                    const typename TablesOf<V>::type* __restrict__ tabs) {
   using Tab = typename TablesOf<V>::type;
   constexpr int PF = 5, Q = 5, Q3 = 125;
-  using L = Q5Lds<PF, Q>;
+  using L = Q5Lds<PF, Q, true>;  // compact point arrays for the direction (as k_op64_q4)
   __shared__ V bufA[L::A];
   __shared__ V bufB[L::B];
   ElemGeom g;
@@ -516,19 +529,19 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
   __syncthreads();
   gather_elem<V, V, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
   __syncthreads();
-  sf5_fwd<V, Tab, PC, Q, 4>(bufA, bufB, tabs);
+  sf5_fwd<V, Tab, PC, Q, 4, true>(bufA, bufB, tabs);
   V W[9], wphi, gw[3];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     V* out = f < 3 ? W + 3 * f : gw;
     if (GEO)
-      map_grad<V>((double)bufB[(4 * f + 1) * Q3 + ql], (double)bufB[(4 * f + 2) * Q3 + ql],
-                  (double)bufB[(4 * f + 3) * Q3 + ql], gA, out);
+      map_grad<V>((double)bufB[qslot<true>(f, 1) * Q3 + ql], (double)bufB[qslot<true>(f, 2) * Q3 + ql],
+                  (double)bufB[qslot<true>(f, 3) * Q3 + ql], gA, out);
     else
 #pragma unroll
-      for (int J = 0; J < 3; ++J) out[J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+      for (int J = 0; J < 3; ++J) out[J] = bufB[qslot<true>(f, 1 + J) * Q3 + ql] * ih[J];
   }
-  wphi = bufB[12 * Q3 + ql];
+  wphi = bufB[qslot<true>(3, 0) * Q3 + ql];
   __syncthreads();
   const int pidc = pid < a.nph ? pid : 0;
   const MatParams<V> mp = a.mats[pidc];
@@ -544,24 +557,21 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
 #pragma unroll
       for (int J = 0; J < 3; ++J) fl[J] = f < 3 ? (double)(wdet * Fu[3 * f + J]) : (double)(wdet * kfg * gw[J]);
       phys_to_ref<true>(fl, nullptr, gA, b);
-      if (f < 3) bufB[(4 * f) * Q3 + ql] = V(0);
 #pragma unroll
-      for (int K = 0; K < 3; ++K) bufB[(4 * f + 1 + K) * Q3 + ql] = (V)b[K];
+      for (int K = 0; K < 3; ++K) bufB[qslot<true>(f, 1 + K) * Q3 + ql] = (V)b[K];
     }
-    bufB[12 * Q3 + ql] = wdet * a.fr.s_phi * dL;
+    bufB[qslot<true>(3, 0) * Q3 + ql] = wdet * a.fr.s_phi * dL;
   } else if (pt) {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      bufB[(4 * f) * Q3 + ql] = V(0);
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
-      for (int J = 0; J < 3; ++J) bufB[(4 * f + 1 + J) * Q3 + ql] = wdet * Fu[3 * f + J] * ih[J];
-    }
-    bufB[12 * Q3 + ql] = wdet * a.fr.s_phi * dL;
+      for (int J = 0; J < 3; ++J) bufB[qslot<true>(f, 1 + J) * Q3 + ql] = wdet * Fu[3 * f + J] * ih[J];
+    bufB[qslot<true>(3, 0) * Q3 + ql] = wdet * a.fr.s_phi * dL;
 #pragma unroll
-    for (int J = 0; J < 3; ++J) bufB[(13 + J) * Q3 + ql] = wdet * kfg * gw[J] * ih[J];
+    for (int J = 0; J < 3; ++J) bufB[qslot<true>(3, 1 + J) * Q3 + ql] = wdet * kfg * gw[J] * ih[J];
   }
   __syncthreads();
-  sf5_bwd<V, Tab, PC, Q, 4>(bufB, bufA, tabs);
+  sf5_bwd<V, Tab, PC, Q, 4, true>(bufB, bufA, tabs);
   if (EV)
     store_ext<V, PC, 4>(bufA, a.m, g, a.ebuf);
   else
