@@ -475,12 +475,15 @@ def table_leg(torch, I, pfmf, config, steps=20, warmup=3, hole=0.15):
 
 
 def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_sweeps=32, restart=30,
-               geometry="box", with_cg=False):
+               geometry="box", with_cg=False, h_levels=False, h_coarse_sweeps=8):
     """One Newton step on a uniaxial-tension box: u_x = 0 on x = 0, u_y = 0 on y = 0, u_z = 0 on
     z = 0, u_z = e0 lz on z = lz; FGMRES(30) to 1e-8 with one FP32 V-cycle per iteration
     (levels p -> 2 -> 1 for p = 4, else p -> ... -> 1; Chebyshev(3); 32 sweeps on the order-1
-    level, assembled as a block stencil), FP64 Jacobian as the operator. geometry="curved":
-    the same on the curved mesh (planar boundary faces, so the same faces are constrained).
+    level, assembled as a block stencil), FP64 Jacobian as the operator. h_levels: below the
+    order-1 level the hierarchy continues on order-1 lattices halved per direction while the
+    element counts stay even (Galerkin stencils), with h_coarse_sweeps sweeps on the coarsest;
+    the step with the p-levels alone is then reported beside it. geometry="curved": the same
+    on the curved mesh (planar boundary faces, so the same faces are constrained).
     with_cg: the same step again from the same start with preconditioned conjugate gradients
     (the same V-cycle, at most 300 iterations), its outcome reported beside FGMRES."""
     t_gen = time.perf_counter()
@@ -497,7 +500,14 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
     z0[2, iz == 0] = 0.0
     z0[2, iz == nz1 - 1] = d["e0"] * mesh.lz
     ctx = pfmf.Context.from_inputs(d)
-    levels = [4, 2, 1] if mesh.p == 4 else list(range(mesh.p, 0, -1))
+    p_levels = [4, 2, 1] if mesh.p == 4 else list(range(mesh.p, 0, -1))
+    levels = list(p_levels)
+    if h_levels:
+        ne = [mesh.nx, mesh.ny, mesh.nz]
+        while len(levels) < 8 and all(n % 2 == 0 and n >= 2 for n in ne):
+            levels.append(1)
+            ne = [n // 2 for n in ne]
+        coarse_sweeps = h_coarse_sweeps
     ctx.set_pmg_levels(levels)
     ctx.set_dirichlet({"x0": ["ux"], "y0": ["uy"], "z0": ["uz"], "z1": ["uz"]})
     z = torch.as_tensor(z0).to("cuda", torch.float64)
@@ -539,6 +549,22 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
            "dofs_per_s": {k: mesh.n_dof / (ms[k] * 1e-3) for k in ("jacobian", "jacobian_stored", "fp32_apply")},
            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
            "fp32_over_stored_fp64_speedup": ms["jacobian_stored"] / ms["fp32_apply"]}
+    if levels != p_levels:
+        # the same step with the p-levels alone (32 Chebyshev sweeps on the order-1 stencil)
+        ctx.set_pmg_levels(p_levels)
+        zp = torch.as_tensor(z0).to("cuda", torch.float64)
+        ctx.linearize(zp)  # allocates the hierarchy outside the timed step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp = ctx.newton_step(zp, rtol=1e-8, restart=restart, max_iters=300, cheb_degree=cheb_degree,
+                             coarse_sweeps=32, raise_on_noconv=False)
+        t_p = time.perf_counter() - t0
+        print(f"[bench] newton step, p-levels {p_levels} only: {rp} in {t_p:.2f} s", file=sys.stderr, flush=True)
+        out["p_levels_only"] = {"levels": p_levels, "coarse_sweeps": 32, "time_to_solution_s": t_p,
+                                "fgmres_iterations": rp["iterations"], "converged": bool(rp["converged"]),
+                                "rel_res_true": rp["res_true"] / max(rp["res0"], 1e-300)}
+        ctx.set_pmg_levels(levels)
+        ctx.linearize(zp)
     if with_cg:
         zc = torch.as_tensor(z0).to("cuda", torch.float64)
         torch.cuda.synchronize()
@@ -797,7 +823,7 @@ def main():
         print(f"[bench] secondary {out['secondary']}", file=sys.stderr, flush=True)
     if newton:
         torch.cuda.empty_cache()
-        out["newton"] = newton_leg(torch, I, pfmf, args.newton_config, with_cg=True)
+        out["newton"] = newton_leg(torch, I, pfmf, args.newton_config, with_cg=True, h_levels=True)
     if newton and args.newton_all:
         if args.newton_branches_config:
             torch.cuda.empty_cache()

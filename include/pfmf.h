@@ -242,14 +242,21 @@ pf_status pf_apply_adjoint_noalloc(pf_ctx* ctx, const double* z, const double* v
  * factors are taken in FP64 and stored per point (and per branch, see pf_set_branches)
  * as an FP32 record of 15 values and a
  * flag byte (Appendices A-C evaluated once), with an FP32 mirror of u; assembles an
- * order-1 coarsest level into a block stencil; builds every level's point-Jacobi
+ * order-1 level into a block stencil and the Galerkin stencils of any coarser order-1
+ * lattices below it; builds every level's point-Jacobi
  * diagonal and Chebyshev bounds (power iteration on the device). Synchronises the
  * stream once. */
 pf_status pf_linearize(pf_ctx* ctx, const double* z, void* stream);
 
 /* Multigrid level orders, fine first: orders[0] = p > orders[1] > ... >= 1,
- * 2 <= n_levels <= 5 (n_levels = 0 restores the default p, p-1, ..., 1). Every level
- * is evaluated at the fine quadrature. Frees the hierarchy: call pf_linearize again. */
+ * 2 <= n_levels <= 8 (n_levels = 0 restores the default p, p-1, ..., 1). Every level
+ * is evaluated at the fine quadrature. After the first order 1 the list may repeat 1:
+ * each further 1 is the order-1 lattice with half the elements per direction (the
+ * element counts must be even), trilinear interpolation from it, and as its operator the
+ * Galerkin product P^T A P of the level above, formed by pf_linearize as a block stencil
+ * (a geometric coarse hierarchy below the p-levels, e.g. 4, 2, 1, 1, 1). PF_EINVAL for
+ * other lists or a lattice that cannot be halved. Frees the hierarchy: call pf_linearize
+ * again. */
 pf_status pf_set_pmg_levels(pf_ctx* ctx, const int* orders, int n_levels);
 
 /* Context options (pf_set_option).
@@ -345,8 +352,9 @@ pf_status pf_newton_step(pf_ctx* ctx, double* z, const pf_newton_opts* opts, pf_
  * order and node count of one level. */
 pf_status pf_level_info(const pf_ctx* ctx, int level, int* p, int64_t* n_nodes);
 
-/* y = J dz in FP32 on one level (level 0 = fine order p; level l has order p-l),
- * evaluated at the fine quadrature with the record of the last pf_linearize.
+/* y = J dz in FP32 on one level (level 0 = fine order p; the orders as set by
+ * pf_set_pmg_levels, default p - l), evaluated at the fine quadrature with the record of
+ * the last pf_linearize (a coarser order-1 lattice: its Galerkin stencil).
  * dz, y: device float[4][n_nodes(level)]. */
 pf_status pf_apply_jacobian_f32(pf_ctx* ctx, int level, const float* dz, float* y,
                                 void* stream);
@@ -362,8 +370,8 @@ pf_status pf_apply_jacobian_f32(pf_ctx* ctx, int level, const float* dz, float* 
 pf_status pf_apply_jacobian_lin(pf_ctx* ctx, const double* dz, double* y, void* stream);
 
 /* Level transfer: prolongation xf = P xc (coarse level l+1 -> level l, exact
- * interpolation of the coarse field at the fine nodes) and restriction rc = P^T rf.
- * Device float[4][n_nodes(level)]. */
+ * interpolation of the coarse field at the fine nodes; trilinear between order-1
+ * lattices) and restriction rc = P^T rf. Device float[4][n_nodes(level)]. */
 pf_status pf_prolong(pf_ctx* ctx, int level, const float* xc, float* xf, void* stream);
 pf_status pf_restrict(pf_ctx* ctx, int level, const float* rf, float* rc, void* stream);
 

@@ -265,4 +265,59 @@ __global__ __launch_bounds__(NT) void k_stencil_apply(const float* __restrict__ 
   }
 }
 
+// Galerkin product of a block stencil on a coarser order-1 lattice: Sc = P^T Sf P with P
+// the trilinear interpolation from the coarse lattice (every second fine node per
+// direction, fine n = 2 nc - 1 nodes) to the fine one; fine node 2I + a (a = -1, 0, 1)
+// takes weight 1 (a = 0) or 1/2 (|a| = 1) from coarse node I. Entry (O, f, g) of coarse
+// node I: sum over fine i = 2I + a and j = 2(I + O) + b with |j - i| <= 1 per direction
+// of w(a) w(b) Sf[j - i][f][g][i] (accumulated in double, fixed order: deterministic).
+// One thread per (offset, field pair, coarse node), nodes fastest.
+static __global__ __launch_bounds__(NT) void k_stencil_rap(const float* __restrict__ Sf, int fx1, int fy1, int fz1,
+                                                    float* __restrict__ Sc, int cx1, int cy1, int cz1) {
+  const int64_t nf = (int64_t)fx1 * fy1 * fz1, nc = (int64_t)cx1 * cy1 * cz1;
+  const int64_t n_all = 27 * 16 * nc;
+  const int fd[3] = {fx1, fy1, fz1}, cd[3] = {cx1, cy1, cz1};
+  for (int64_t t = blockIdx.x * (int64_t)NT + threadIdx.x; t < n_all; t += (int64_t)gridDim.x * NT) {
+    const int64_t I = t % nc;
+    const int rest = (int)(t / nc);
+    const int k = rest % 16, O = rest / 16;
+    const int Ic[3] = {(int)(I % cx1), (int)((I / cx1) % cy1), (int)(I / ((int64_t)cx1 * cy1))};
+    const int dO[3] = {O % 3 - 1, (O / 3) % 3 - 1, O / 9 - 1};
+    // per direction: the (fine i, offset o, weight) combinations
+    int ci[3][9], co[3][9], nco[3] = {0, 0, 0};
+    float cw[3][9];
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int J = Ic[d] + dO[d];
+      if (J < 0 || J >= cd[d]) inside = false;
+#pragma unroll
+      for (int a = -1; a <= 1; ++a) {
+        const int i = 2 * Ic[d] + a;
+        if (i < 0 || i >= fd[d]) continue;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+          const int j = 2 * J + b;
+          if (j < 0 || j >= fd[d] || j - i < -1 || j - i > 1) continue;
+          const int m = nco[d]++;
+          ci[d][m] = i;
+          co[d][m] = j - i;
+          cw[d][m] = (a == 0 ? 1.f : 0.5f) * (b == 0 ? 1.f : 0.5f);
+        }
+      }
+    }
+    double acc = 0.0;
+    if (inside) {
+      for (int mz = 0; mz < nco[2]; ++mz)
+        for (int my = 0; my < nco[1]; ++my)
+          for (int mx = 0; mx < nco[0]; ++mx) {
+            const int on = (co[0][mx] + 1) + 3 * (co[1][my] + 1) + 9 * (co[2][mz] + 1);
+            const int64_t i = ci[0][mx] + (int64_t)fx1 * (ci[1][my] + (int64_t)fy1 * ci[2][mz]);
+            acc += (double)(cw[0][mx] * cw[1][my] * cw[2][mz]) * (double)Sf[((int64_t)on * 16 + k) * nf + i];
+          }
+    }
+    Sc[((int64_t)O * 16 + k) * nc + I] = (float)acc;
+  }
+}
+
 }  // namespace pfmf

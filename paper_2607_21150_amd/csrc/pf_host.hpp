@@ -87,7 +87,7 @@ struct pf_ctx {
   int pnext = 0;
   MGState mg;
   // multigrid level orders (fine first); n_orders = 0 means p, p-1, ..., 1
-  int orders[5] = {0, 0, 0, 0, 0};
+  int orders[pfmf::MG_MAX_LEVELS] = {};
   int n_orders = 0;
   // Dirichlet faces (multigrid and Newton step)
   DirMask dir{{0, 0, 0, 0, 0, 0}};

@@ -4,7 +4,10 @@
 // Levels are orders p, p-1, ..., coarse_p on the same mesh. Every level is
 // evaluated at the fine Gauss points with the fine linearisation record, so a
 // coarse operator is the Galerkin product P^T A P of the fine one (the coarse
-// space is a subspace of the fine space). Kinematics (F, eigenframe, log strains)
+// space is a subspace of the fine space). Below an order-1 level the hierarchy may
+// continue on coarser order-1 lattices (every second node per direction, trilinear
+// interpolation), each operator the Galerkin product of the one above, formed once
+// per linearisation as a block stencil. Kinematics (F, eigenframe, log strains)
 // are recomputed in FP32 from FP32 mirrors of u and D at every apply; the yield,
 // split and history decisions and the return-mapping scalars come from the
 // record taken in FP64 by the linearisation.
@@ -30,10 +33,18 @@ struct LevelDev {
   int64_t n_nodes;
 };
 
+constexpr int MG_MAX_LEVELS = 8;
+
 struct MGLevel {
   int p = 0, P = 0;
+  // h: coarsening depth of an order-1 level (0: the mesh itself; h > 0: the order-1
+  // lattice with 2^h times fewer elements per direction, its operator the Galerkin
+  // product of the finer order-1 level's, stored as a block stencil S)
+  int h = 0;
+  int ne[3] = {0, 0, 0};  // elements per direction of this level's lattice
   int nx1 = 0, ny1 = 0, nz1 = 0;
   int64_t n_nodes = 0;
+  float* S = nullptr;  // h > 0: block stencil [27][4][4][n_nodes]
   float *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *b = nullptr;
   float *diag = nullptr, *dinv = nullptr;
   double lmax = 0.0;
@@ -48,13 +59,13 @@ struct MGLevel {
 
 struct MGState {
   int n_levels = 0;
-  MGLevel lv[5];
+  MGLevel lv[MG_MAX_LEVELS];
   float* z32 = nullptr;  // FP32 mirror of u on the fine level [3][n_nodes]
   RecordSoA rec{nullptr, nullptr};  // [rec_layers][REC_N][n_q] and flags [rec_layers][n_q]
   float* tmpA = nullptr;
   float* tmpB = nullptr;
   double* red = nullptr;  // reduction scratch
-  float* ebe = nullptr;    // element matrices of an order-1 coarsest level [n_elem][32][32]
+  float* ebe = nullptr;    // element matrices of the order-1 level on the mesh [n_elem][32][32]
   float* stencil = nullptr;  // the same level as a block stencil [27][4][4][n_nodes]
   float* ebuf32 = nullptr;   // brick-buffer scatter of the FP32 level applies
   double* rec64 = nullptr;   // stored FP64 linearisation [rec_layers][REC_N][n_q] (flags in rec.flags)
@@ -66,7 +77,7 @@ struct MGState {
 };
 
 inline void mg_free_level(MGLevel& L) {
-  float* fs[] = {L.x, L.r, L.d, L.t, L.b, L.diag, L.dinv};
+  float* fs[] = {L.x, L.r, L.d, L.t, L.b, L.diag, L.dinv, L.S};
   for (float* f : fs) (void)hipFree(f);
   for (int k = 0; k < 3; ++k) {
     (void)hipFree(L.pbase[k]);
@@ -78,7 +89,7 @@ inline void mg_free_level(MGLevel& L) {
 }
 
 inline void mg_free(MGState& mg) {
-  for (int l = 0; l < 5; ++l) mg_free_level(mg.lv[l]);
+  for (int l = 0; l < MG_MAX_LEVELS; ++l) mg_free_level(mg.lv[l]);
   (void)hipFree(mg.z32);
   (void)hipFree(mg.rec.rec);
   (void)hipFree(mg.rec.flags);

@@ -51,6 +51,33 @@ void transfer_rows_1d(int pf, int pc, int N, std::vector<int>& pbase, std::vecto
   }
 }
 
+// 1-D transfer rows from an order-1 lattice of Nf (even) elements to the one with Nf / 2:
+// fine node i takes coarse node i / 2 (even i, weight 1) or the mean of (i - 1) / 2 and
+// (i + 1) / 2 (odd i); restriction is the transpose (weights 1/2, 1, 1/2).
+void transfer_rows_h(int Nf, std::vector<int>& pbase, std::vector<float>& pw, std::vector<int>& rbase,
+                     std::vector<float>& rw) {
+  const int nf = Nf + 1, nc = Nf / 2 + 1;
+  pbase.assign(nf, 0);
+  pw.assign((size_t)nf * 2, 0.f);
+  for (int i = 0; i < nf; ++i) {
+    pbase[i] = i / 2;
+    if (i % 2 == 0) {
+      pw[(size_t)i * 2] = 1.f;
+    } else {
+      pw[(size_t)i * 2] = 0.5f;
+      pw[(size_t)i * 2 + 1] = 0.5f;
+    }
+  }
+  rbase.assign(nc, 0);
+  rw.assign((size_t)nc * 3, 0.f);
+  for (int J = 0; J < nc; ++J) {
+    rbase[J] = 2 * J - 1;
+    rw[(size_t)J * 3] = 0.5f;
+    rw[(size_t)J * 3 + 1] = 1.f;
+    rw[(size_t)J * 3 + 2] = 0.5f;
+  }
+}
+
 template <typename T>
 pf_status upload(T** dst, const std::vector<T>& v) {
   if (hipMalloc(dst, v.size() * sizeof(T)) != hipSuccess) return fail(PF_ENOMEM, "multigrid allocation failed");
@@ -64,7 +91,7 @@ pf_status mg_alloc(pf_ctx* c) {
   MGState& mg = c->mg;
   if (mg.n_levels > 0) return PF_OK;
   const int p = c->mesh.p;
-  int orders[5];
+  int orders[MG_MAX_LEVELS];
   int nl;
   if (c->n_orders > 0) {
     nl = c->n_orders;
@@ -91,19 +118,28 @@ pf_status mg_alloc_levels(pf_ctx* c, const int* orders, int nl) {
     MGLevel& L = mg.lv[l];
     L.p = orders[l];
     L.P = L.p + 1;
-    L.nx1 = L.p * N[0] + 1;
-    L.ny1 = L.p * N[1] + 1;
-    L.nz1 = L.p * N[2] + 1;
+    // a repeated order 1 coarsens the order-1 lattice by two per direction
+    L.h = (l > 0 && L.p == 1 && orders[l - 1] == 1) ? mg.lv[l - 1].h + 1 : 0;
+    for (int k = 0; k < 3; ++k) L.ne[k] = L.h > 0 ? mg.lv[l - 1].ne[k] / 2 : N[k];
+    L.nx1 = L.p * L.ne[0] + 1;
+    L.ny1 = L.p * L.ne[1] + 1;
+    L.nz1 = L.p * L.ne[2] + 1;
     L.n_nodes = (int64_t)L.nx1 * L.ny1 * L.nz1;
     const size_t nb = 4 * L.n_nodes * sizeof(float);
     float** bufs[] = {&L.x, &L.r, &L.d, &L.t, &L.b, &L.diag, &L.dinv};
     for (float** b : bufs)
       if (hipMalloc(b, nb) != hipSuccess) return fail(PF_ENOMEM, "multigrid level allocation failed");
+    if (L.h > 0 && hipMalloc(&L.S, (size_t)27 * 16 * L.n_nodes * sizeof(float)) != hipSuccess)
+      return fail(PF_ENOMEM, "coarse stencil: allocation failed");
     if (l + 1 < nl) {
+      const bool hnext = L.p == 1 && orders[l + 1] == 1;
       for (int k = 0; k < 3; ++k) {
         std::vector<int> pb, rb;
         std::vector<float> pw, rw;
-        transfer_rows_1d(L.p, orders[l + 1], N[k], pb, pw, rb, rw);
+        if (hnext)
+          transfer_rows_h(L.ne[k], pb, pw, rb, rw);
+        else
+          transfer_rows_1d(L.p, orders[l + 1], N[k], pb, pw, rb, rw);
         pf_status st;
         if ((st = upload(&L.pbase[k], pb)) || (st = upload(&L.pw[k], pw)) || (st = upload(&L.rbase[k], rb)) ||
             (st = upload(&L.rw[k], rw)))
@@ -111,12 +147,15 @@ pf_status mg_alloc_levels(pf_ctx* c, const int* orders, int nl) {
       }
     }
   }
-  if (mg.lv[nl - 1].p == 1) {
+  // the order-1 level on the mesh itself: element matrices and block stencil
+  for (int l = 0; l < nl; ++l) {
+    if (mg.lv[l].p != 1) continue;
     const int64_t n_elem = (int64_t)c->mesh.nx * c->mesh.ny * c->mesh.nz;
     if (hipMalloc(&mg.ebe, (size_t)n_elem * 1024 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&mg.stencil, (size_t)27 * 16 * mg.lv[nl - 1].n_nodes * sizeof(float)) != hipSuccess)
+        hipMalloc(&mg.stencil, (size_t)27 * 16 * mg.lv[l].n_nodes * sizeof(float)) != hipSuccess)
       return fail(PF_ENOMEM, "coarse element matrices: allocation failed");
-    mg.ebe_level = nl - 1;
+    mg.ebe_level = l;
+    break;
   }
   const size_t nfine = 4 * mg.lv[0].n_nodes * sizeof(float);
   if (hipMalloc(&mg.z32, 3 * c->n_nodes * sizeof(float)) != hipSuccess ||
@@ -382,18 +421,42 @@ pf_status ebe_assemble(pf_ctx* c, hipStream_t s) {
   return PF_OK;
 }
 
+// Block-stencil apply (MODE 0) or diagonal (MODE 1) of an order-1 level: the mesh's own
+// order-1 level (mg.stencil) or a coarser lattice (its own S).
 template <int MODE>
-pf_status ebe_apply(pf_ctx* c, const float* x, float* out, hipStream_t s) {
-  const MGLevel& L = c->mg.lv[c->mg.ebe_level];
+pf_status stencil_apply(pf_ctx* c, int level, const float* x, float* out, hipStream_t s) {
+  const MGLevel& L = c->mg.lv[level];
+  const float* S = L.h > 0 ? L.S : c->mg.stencil;
   const int nb = (int)std::min<int64_t>((L.n_nodes + NT - 1) / NT, 65536);
-  hipLaunchKernelGGL(k_stencil_apply<MODE>, dim3(nb, 4), dim3(NT), 0, s, c->mg.stencil, L.nx1, L.ny1, L.nz1,
-                     L.n_nodes, x, out);
+  hipLaunchKernelGGL(k_stencil_apply<MODE>, dim3(nb, 4), dim3(NT), 0, s, S, L.nx1, L.ny1, L.nz1, L.n_nodes, x, out);
   HIPCHK(hipGetLastError());
   return PF_OK;
 }
 
 template <int MODE>
+pf_status ebe_apply(pf_ctx* c, const float* x, float* out, hipStream_t s) {
+  return stencil_apply<MODE>(c, c->mg.ebe_level, x, out, s);
+}
+
+// Galerkin stencils of the coarser order-1 lattices, each from the level above it.
+pf_status build_h_levels(pf_ctx* c, hipStream_t s) {
+  MGState& mg = c->mg;
+  for (int l = 1; l < mg.n_levels; ++l) {
+    const MGLevel& L = mg.lv[l];
+    if (L.h == 0) continue;
+    const MGLevel& F = mg.lv[l - 1];
+    const float* Sf = F.h > 0 ? F.S : mg.stencil;
+    const int64_t nall = 27 * 16 * L.n_nodes;
+    const int nb = (int)std::min<int64_t>((nall + NT - 1) / NT, 65536);
+    hipLaunchKernelGGL(k_stencil_rap, dim3(nb), dim3(NT), 0, s, Sf, F.nx1, F.ny1, F.nz1, L.S, L.nx1, L.ny1, L.nz1);
+    HIPCHK(hipGetLastError());
+  }
+  return PF_OK;
+}
+
+template <int MODE>
 pf_status level_op_raw(pf_ctx* c, int level, const float* dz, float* out, hipStream_t s) {
+  if (c->mg.lv[level].h > 0) return stencil_apply<MODE>(c, level, dz, out, s);
   if (level == c->mg.ebe_level && c->mg.ebe) return ebe_apply<MODE>(c, dz, out, s);
   const A32Args a = a32_args(c, level, dz, out);
   const int PF = c->mg.lv[0].P, PC = c->mg.lv[level].P;
@@ -633,6 +696,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
   }
   if (st) return st;
   if (mg.ebe_level >= 0 && (st = ebe_assemble(c, s))) return st;
+  if ((st = build_h_levels(c, s))) return st;
   mg.linearized = true;
   mg.lin64_valid = c->store_lin64;
   // lambda_max(D^-1 A) per level by 15 power iterations, normalised on the device
@@ -660,7 +724,7 @@ pf_status pf_linearize(pf_ctx* c, const double* z, void* stream) {
     }
     HIPCHK(hipGetLastError());
   }
-  double lam[5];
+  double lam[MG_MAX_LEVELS];
   HIPCHK(hipMemcpyAsync(lam, nrm, mg.n_levels * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int l = 0; l < mg.n_levels; ++l) {
@@ -754,13 +818,26 @@ pf_status pf_set_pmg_levels(pf_ctx* c, const int* orders, int n_levels) {
   pf_status st = check_ctx(c);
   if (st) return st;
   if ((st = box_only(c, "pf_set_pmg_levels"))) return st;
-  if (n_levels < 0 || n_levels > 5) return fail(PF_EINVAL, "n_levels=%d outside 0..5", n_levels);
+  if (n_levels < 0 || n_levels > MG_MAX_LEVELS)
+    return fail(PF_EINVAL, "n_levels=%d outside 0..%d", n_levels, MG_MAX_LEVELS);
   if (n_levels > 0 && !orders) return fail(PF_EINVAL, "null orders");
   if (n_levels > 0) {
     if (orders[0] != c->mesh.p) return fail(PF_EINVAL, "the first level must be the mesh order %d", c->mesh.p);
     if (n_levels < 2) return fail(PF_EINVAL, "at least two levels");
-    for (int l = 1; l < n_levels; ++l)
-      if (!(orders[l] >= 1 && orders[l] < orders[l - 1])) return fail(PF_EINVAL, "orders must decrease to >= 1");
+    int ne[3] = {c->mesh.nx, c->mesh.ny, c->mesh.nz};
+    for (int l = 1; l < n_levels; ++l) {
+      if (orders[l] == 1 && orders[l - 1] == 1) {  // a coarser order-1 lattice
+        for (int k = 0; k < 3; ++k) {
+          if (ne[k] % 2 != 0 || ne[k] < 2)
+            return fail(PF_EINVAL, "level %d: an order-1 lattice of %d elements per direction cannot be halved", l,
+                        ne[k]);
+          ne[k] /= 2;
+        }
+        continue;
+      }
+      if (!(orders[l] >= 1 && orders[l] < orders[l - 1]))
+        return fail(PF_EINVAL, "orders must decrease to 1, then may repeat 1");
+    }
   }
   HIPCHK(hipDeviceSynchronize());
   mg_free(c->mg);

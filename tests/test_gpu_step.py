@@ -223,18 +223,20 @@ def test_newton_converges_on_small_mesh(pf, oracle_lib):
     assert hist[-1] < 0.1 * hist[-2]
 
 
-def test_newton_step_at_full_size_q4(pf):
+@pytest.mark.parametrize("levels,sweeps", [([4, 2, 1], 32), ([4, 2, 1, 1, 1, 1], 8)])
+def test_newton_step_at_full_size_q4(pf, levels, sweeps):
     """One Newton step on the Q4 40^3 box (16.7 M DoFs), as bench.py runs it: uniaxial faces,
-    FGMRES(30) with one FP32 V-cycle (levels 4 -> 2 -> 1) per iteration. The true linear
-    residual ||b - M J dz||, recomputed with the FP64 Jacobian apply, reaches 1e-8 of ||b||."""
-    print("case newton C5 full size", flush=True)
+    FGMRES(30) with one FP32 V-cycle per iteration, levels 4 -> 2 -> 1 (and below them the
+    order-1 lattices of 20, 10 and 5 elements per direction). The true linear residual
+    ||b - M J dz||, recomputed with the FP64 Jacobian apply, reaches 1e-8 of ||b||."""
+    print(f"case newton C5 full size levels {levels}", flush=True)
     d = I.make_inputs("C5", "base")
     z0, _ = constrained_start(d)
     ctx = pf.Context.from_inputs(d)
-    ctx.set_pmg_levels([4, 2, 1])
+    ctx.set_pmg_levels(levels)
     ctx.set_dirichlet(uniaxial_faces())
     z = dev(z0)
-    rep = ctx.newton_step(z, rtol=1e-8, restart=30, max_iters=300)
+    rep = ctx.newton_step(z, rtol=1e-8, restart=30, max_iters=300, coarse_sweeps=sweeps)
     ctx.check()
     print(rep, flush=True)
     assert rep["converged"] == 1 and rep["krylov"] == pf.PF_KRYLOV_FGMRES
