@@ -502,6 +502,7 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
     ctx = pfmf.Context.from_inputs(d)
     p_levels = [4, 2, 1] if mesh.p == 4 else list(range(mesh.p, 0, -1))
     levels = list(p_levels)
+    p_sweeps = coarse_sweeps
     if h_levels:
         ne = [mesh.nx, mesh.ny, mesh.nz]
         while len(levels) < 8 and all(n % 2 == 0 and n >= 2 for n in ne):
@@ -550,17 +551,17 @@ def newton_leg(torch, I, pfmf, config, variant="base", cheb_degree=3, coarse_swe
            "fp32_over_fp64_apply_speedup": ms["jacobian"] / ms["fp32_apply"],
            "fp32_over_stored_fp64_speedup": ms["jacobian_stored"] / ms["fp32_apply"]}
     if levels != p_levels:
-        # the same step with the p-levels alone (32 Chebyshev sweeps on the order-1 stencil)
+        # the same step with the p-levels alone (coarse_sweeps Chebyshev sweeps on the order-1 stencil)
         ctx.set_pmg_levels(p_levels)
         zp = torch.as_tensor(z0).to("cuda", torch.float64)
         ctx.linearize(zp)  # allocates the hierarchy outside the timed step
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rp = ctx.newton_step(zp, rtol=1e-8, restart=restart, max_iters=300, cheb_degree=cheb_degree,
-                             coarse_sweeps=32, raise_on_noconv=False)
+                             coarse_sweeps=p_sweeps, raise_on_noconv=False)
         t_p = time.perf_counter() - t0
         print(f"[bench] newton step, p-levels {p_levels} only: {rp} in {t_p:.2f} s", file=sys.stderr, flush=True)
-        out["p_levels_only"] = {"levels": p_levels, "coarse_sweeps": 32, "time_to_solution_s": t_p,
+        out["p_levels_only"] = {"levels": p_levels, "coarse_sweeps": p_sweeps, "time_to_solution_s": t_p,
                                 "fgmres_iterations": rp["iterations"], "converged": bool(rp["converged"]),
                                 "rel_res_true": rp["res_true"] / max(rp["res0"], 1e-300)}
         ctx.set_pmg_levels(levels)
@@ -829,13 +830,13 @@ def main():
             torch.cuda.empty_cache()
             # the third example's matrix needs a stronger smoother than the defaults
             out["newton_branches"] = newton_leg(torch, I, pfmf, args.newton_branches_config, "ex3", cheb_degree=12,
-                                                coarse_sweeps=64, restart=60)
+                                                coarse_sweeps=64, restart=60, h_levels=True)
         if args.newton_curved_config:
             torch.cuda.empty_cache()
             # the curved mesh, like the third example's matrix, needs a stronger smoother than the
             # defaults (which stall near 2e-7 of the initial residual at C5)
             out["newton_curved"] = newton_leg(torch, I, pfmf, args.newton_curved_config, geometry="curved",
-                                              cheb_degree=6, coarse_sweeps=64, restart=60)
+                                              cheb_degree=6, coarse_sweeps=64, restart=60, h_levels=True)
     print(json.dumps(out), flush=True)
 
 
