@@ -27,6 +27,43 @@ pf_status mdot(pf_ctx* c, const double* V, int64_t ld, int k, const double* w, i
   return PF_OK;
 }
 
+// The k block-partial rows of part summed on the host in block order.
+pf_status sum_partials(pf_ctx* c, int g, int k, hipStream_t s, double* out) {
+  std::vector<double> h((size_t)g * k);
+  HIPCHK(hipMemcpyAsync(h.data(), c->kpart, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int j = 0; j < k; ++j) {
+    double acc = 0.0;
+    for (int b = 0; b < g; ++b) acc += h[(size_t)j * g + b];
+    out[j] = acc;
+  }
+  return PF_OK;
+}
+
+// <V_j, w>, j < k <= GS_MAX, reading w once.
+pf_status mdot_multi(pf_ctx* c, const double* V, int64_t ld, int k, const double* w, int64_t n, hipStream_t s,
+                     double* out) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_mdot_multi, dim3(g), dim3(NT), 0, s, V, ld, k, w, n, c->kpart);
+  HIPCHK(hipGetLastError());
+  return sum_partials(c, g, k, s, out);
+}
+
+// w += sum_j coef[j] V_j (k <= GS_MAX) and, in the same pass, out = <V_j, w_new> (dots)
+// or out[0] = ||w_new||^2.
+pf_status gs_correct(pf_ctx* c, const double* V, int64_t ld, int k, const double* coef, double* w, int64_t n,
+                     bool dots, hipStream_t s, double* out) {
+  HIPCHK(hipMemcpyAsync(c->kcoef, coef, k * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));  // coef is host memory
+  const int g = vec_grid(n);
+  if (dots)
+    hipLaunchKernelGGL(k_maxpy_fused<true>, dim3(g), dim3(NT), 0, s, V, ld, k, c->kcoef, w, n, c->kpart);
+  else
+    hipLaunchKernelGGL(k_maxpy_fused<false>, dim3(g), dim3(NT), 0, s, V, ld, k, c->kcoef, w, n, c->kpart);
+  HIPCHK(hipGetLastError());
+  return sum_partials(c, g, dots ? k : 1, s, out);
+}
+
 // w += sum_j coef[j] V_j (coef copied from the host, k <= 64)
 pf_status maxpy(pf_ctx* c, const double* V, int64_t ld, int k, const double* coef, double* w, int64_t n,
                 hipStream_t s) {
@@ -226,26 +263,43 @@ pf_status pf_newton_step(pf_ctx* c, double* z, const pf_newton_opts* o, pf_newto
       // classical Gram-Schmidt with adaptive refinement (the GMRES variant of Section 5):
       // the first pass also returns ||w||^2 (Vn follows V_k in memory); a second pass runs
       // only when the first removed more than half of it, ||w1||^2 = ||w||^2 - sum h_j^2
-      // < ||w||^2 / 2, the point where orthogonality can be lost
-      if ((st = mdot(c, V, n, k + 2, Vn, n, s, h.data()))) return st;
+      // < ||w||^2 / 2, the point where orthogonality can be lost. With k + 2 <= GS_MAX
+      // every pass reads the basis once: the projections read w once, and each correction
+      // also yields the next pass's projections (refinement) or the new norm.
+      const bool fused = k + 2 <= GS_MAX;
+      if ((st = fused ? mdot_multi(c, V, n, k + 2, Vn, n, s, h.data()) : mdot(c, V, n, k + 2, Vn, n, s, h.data())))
+        return st;
       const double w0 = h[k + 1];
       double proj = 0.0;
       for (int j = 0; j <= k; ++j) {
         y[j] = -h[j];
         proj += h[j] * h[j];
       }
-      if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
-      if (!(w0 - proj > 0.5 * w0)) {
-        ++refinements;
-        if ((st = mdot(c, V, n, k + 1, Vn, n, s, h2.data()))) return st;
-        for (int j = 0; j <= k; ++j) {
-          y[j] = -h2[j];
-          h[j] += h2[j];
-        }
-        if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
-      }
+      const bool refine = !(w0 - proj > 0.5 * w0);
       double hn;
-      if ((st = mdot(c, Vn, n, 1, Vn, n, s, &hn))) return st;
+      if (fused) {
+        if (refine) {
+          ++refinements;
+          if ((st = gs_correct(c, V, n, k + 1, y.data(), Vn, n, true, s, h2.data()))) return st;
+          for (int j = 0; j <= k; ++j) {
+            y[j] = -h2[j];
+            h[j] += h2[j];
+          }
+        }
+        if ((st = gs_correct(c, V, n, k + 1, y.data(), Vn, n, false, s, &hn))) return st;
+      } else {
+        if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+        if (refine) {
+          ++refinements;
+          if ((st = mdot(c, V, n, k + 1, Vn, n, s, h2.data()))) return st;
+          for (int j = 0; j <= k; ++j) {
+            y[j] = -h2[j];
+            h[j] += h2[j];
+          }
+          if ((st = maxpy(c, V, n, k + 1, y.data(), Vn, n, s))) return st;
+        }
+        if ((st = mdot(c, Vn, n, 1, Vn, n, s, &hn))) return st;
+      }
       hn = std::sqrt(hn);
       h[k + 1] = hn;
       if (hn > 0.0) hipLaunchKernelGGL(k_daxpy, dim3(g), dim3(NT), 0, s, 1.0 / hn, Vn, Vn, n, 0);

@@ -117,6 +117,78 @@ static __global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int k, 
   }
 }
 
+// ---- Gram-Schmidt passes that read each basis vector once (k <= GS_MAX vectors) ----
+constexpr int GS_MAX = 32;
+
+// Sum each of the k per-thread values acc[0..k) over the block (wave butterflies, then
+// the 4 wave sums in wave order) and store block b's share as part[j * gridDim.x + b].
+template <int KM>
+__device__ __forceinline__ void block_partials(const double* acc, int k, double* __restrict__ part) {
+  __shared__ double red[(NT / 64) * KM];
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < KM; ++j) {
+    if (j < k) {  // uniform: the whole block takes the same branch
+      double v = acc[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (l == 0) red[wv * KM + j] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w * KM + threadIdx.x];
+    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// part: block shares of <V_j, w>, j = 0..k-1, with w read once (k <= GS_MAX).
+static __global__ __launch_bounds__(NT) void k_mdot_multi(const double* __restrict__ V, int64_t ld, int k,
+                                                   const double* __restrict__ w, int64_t n,
+                                                   double* __restrict__ part) {
+  double acc[GS_MAX];
+#pragma unroll
+  for (int j = 0; j < GS_MAX; ++j) acc[j] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int j = 0; j < GS_MAX; ++j)
+      if (j < k) acc[j] += V[(int64_t)j * ld + i] * wi;
+  }
+  block_partials<GS_MAX>(acc, k, part);
+}
+
+// One Gram-Schmidt correction and, in the same pass, the next one's projections or the
+// new norm: w += sum_j c[j] V_j (c in device memory), then
+//   DOTS: part = block shares of <V_j, w_new>, j < k (the refinement's projections);
+//   otherwise part = block shares of ||w_new||^2 (one value per block).
+template <bool DOTS>
+__global__ __launch_bounds__(NT) void k_maxpy_fused(const double* __restrict__ V, int64_t ld, int k,
+                                                    const double* __restrict__ c, double* __restrict__ w, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double cs[GS_MAX];
+  if ((int)threadIdx.x < k) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  double acc[DOTS ? GS_MAX : 1];
+#pragma unroll
+  for (int j = 0; j < (DOTS ? GS_MAX : 1); ++j) acc[j] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x = w[i];
+    for (int j = 0; j < k; ++j) x += cs[j] * V[(int64_t)j * ld + i];
+    w[i] = x;
+    if (DOTS) {
+#pragma unroll
+      for (int j = 0; j < GS_MAX; ++j)
+        if (j < k) acc[j] += V[(int64_t)j * ld + i] * x;
+    } else {
+      acc[0] += x * x;
+    }
+  }
+  block_partials<DOTS ? GS_MAX : 1>(acc, DOTS ? k : 1, part);
+}
+
 // y = a x (+ y when accumulate); x may be y
 static __global__ void k_daxpy(double a, const double* x, double* y, int64_t n, int accumulate) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
