@@ -130,7 +130,7 @@ pf_status pf_setup_mesh(const pf_mesh_desc* mesh, const pf_phase* phases, int n_
 
 /* Hexahedral mesh given by a table restriction (the general element restriction E and
  * P of Section 4's compact residual, eq:matrix-free-residual-compact, as on the paper's
- * unstructured meshes): n_elem elements of order p (2 or 3) over n_nodes nodes. */
+ * unstructured meshes): n_elem elements of order p (2, 3 or 4) over n_nodes nodes. */
 typedef struct { int p; int64_t n_elem, n_nodes; } pf_table_mesh_desc;
 
 /* Create a context on a mesh given by its element-to-node table. conn: device
@@ -151,7 +151,7 @@ typedef struct { int p; int64_t n_elem, n_nodes; } pf_table_mesh_desc;
  * pf_apply_adjoint_noalloc need the box lattice and return PF_EUNSUPPORTED on such a
  * context. Errors: PF_EINVAL for a node id outside 0..n_nodes-1, an inverted element
  * (det J <= 0), a phase id >= n_phases or sizes beyond 32-bit indices;
- * PF_EUNSUPPORTED for p other than 2, 3; PF_ENOMEM, PF_EHIP. */
+ * PF_EUNSUPPORTED for p other than 2, 3, 4; PF_ENOMEM, PF_EHIP. */
 pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* conn, const double* X,
                               const pf_phase* phases, int n_phases, const pf_fracture* fracture,
                               const uint8_t* qp_phase, const double* qp_state, const double* phi_n,

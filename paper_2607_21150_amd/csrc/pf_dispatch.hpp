@@ -130,7 +130,9 @@ pf_status launch_op64_q4(pf_ctx* c, OpArgs a, hipStream_t s) {
 template <int MODE, int P, bool VOCE>
 pf_status launch_op64_tab_v(pf_ctx* c, OpArgs a, hipStream_t s) {
   const int ng = xcd_grid_groups(c->n_groups);
-  if constexpr (P == 4)
+  if constexpr (P == 5)
+    hipLaunchKernelGGL((k_op64_q4<MODE, VOCE, false, true, false, true>), dim3(ng), dim3(NT5), 0, s, a, 0, c->d_tab);
+  else if constexpr (P == 4)
     hipLaunchKernelGGL((k_op64_q3<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
   else
     hipLaunchKernelGGL((k_op64_q2<MODE, false, VOCE, false, true, true>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
@@ -147,6 +149,8 @@ pf_status dispatch_op64(pf_ctx* c, OpArgs a, hipStream_t s) {
   if (c->table) {
     if (c->mesh.p == 2)
       return c->has_voce ? launch_op64_tab_v<MODE, 3, true>(c, a, s) : launch_op64_tab_v<MODE, 3, false>(c, a, s);
+    if (c->mesh.p == 4)
+      return c->has_voce ? launch_op64_tab_v<MODE, 5, true>(c, a, s) : launch_op64_tab_v<MODE, 5, false>(c, a, s);
     return c->has_voce ? launch_op64_tab_v<MODE, 4, true>(c, a, s) : launch_op64_tab_v<MODE, 4, false>(c, a, s);
   }
   switch (c->mesh.p) {

@@ -87,6 +87,29 @@ __device__ inline void gather_elem(const S* __restrict__ src, int64_t n_nodes, i
   }
 }
 
+// Table restriction: gather NF fields of the element's P^3 nodes, en = the element's row
+// of the element-to-node table (local lexicographic order), into U[f][n].
+template <typename T, typename S, int P, int NF>
+__device__ inline void gather_elem_tab(const S* __restrict__ src, int64_t n_nodes, const int32_t* __restrict__ en,
+                                       T* U) {
+  constexpr int P3 = P * P * P;
+  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
+    const int f = t / P3, n = t - f * P3;
+    U[t] = (T)src[f * n_nodes + en[n]];
+  }
+}
+
+// Table restriction: the element vector R[f][n] stored node-major, ev[(e P^3 + n) 4 + f]
+// (the four fields of one entry contiguous), summed per node by k_gather_csr.
+template <typename T, int P>
+__device__ inline void store_elem_tab(const T* R, int64_t e, T* __restrict__ ev) {
+  constexpr int P3 = P * P * P;
+  for (int t = threadIdx.x; t < 4 * P3; t += NT5) {
+    const int f = t / P3, n = t - f * P3;
+    ev[(e * P3 + n) * 4 + f] = R[t];
+  }
+}
+
 // Add the element vector R[f][k][j][i] into dst with the colour rule.
 template <typename T, int P, int NF>
 __device__ inline void scatter_elem(const T* R, const MeshDev& m, int nx1, int ny1, int64_t n_nodes,
@@ -296,9 +319,12 @@ template <int P, int Q, bool CV = false> struct Q5Lds {
 // FP64 residual / Jacobian / adjoint on order-4 elements.
 // GEO: mapped elements (J^-1 and weight per point from a.qd). EV: all elements in one
 // launch, element vectors stored to the extended node grid a.evec (summed per node by
-// k_gather_ext); otherwise one colour, added into a.out by the colour rule.
-template <int MODE, bool VOCE, bool MB, bool GEO, bool EV = false>
+// k_gather_ext); otherwise one colour, added into a.out by the colour rule. TAB (with
+// GEO): table restriction, element e = workgroup (XCD-aware order), nodes from a.conn,
+// the element vector stored node-major to a.evec (summed per node by k_gather_csr).
+template <int MODE, bool VOCE, bool MB, bool GEO, bool EV = false, bool TAB = false>
 __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTables* __restrict__ tabs) {
+  static_assert(!TAB || (GEO && !MB), "the table restriction runs on mapped elements without branches");
   constexpr int P = 5, Q = 5, Q3 = 125;
   // compact point arrays (13 of 125 values each): 25 KB of LDS per element instead of 28,
   // so that six elements fit a CU's 160 KB (3 waves per SIMD, which the VGPRs allow)
@@ -308,13 +334,21 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   __shared__ double red[2 * 3 * 8];
   __shared__ double mbs[MB ? 18 * NT5 : 1];  // branches in parallel: G and W (or Pb) per thread
   const Slot9 sG{mbs + threadIdx.x, NT5}, sW{mbs + 9 * NT5 + threadIdx.x, NT5};
-  ElemGeom g;
-  if (!(EV ? xcd_elem_all(a.m, blockIdx.x, g) : xcd_elem(a.m, colour, blockIdx.x, g))) return;  // padding (uniform)
+  ElemGeom g{0, 0, 0};
+  int64_t e;
+  if (TAB) {
+    const int id = xcd_group(a.n_groups, blockIdx.x);
+    if (id < 0) return;  // padding (uniform)
+    e = id;
+  } else {
+    if (!(EV ? xcd_elem_all(a.m, blockIdx.x, g) : xcd_elem(a.m, colour, blockIdx.x, g))) return;  // padding (uniform)
+    e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
+  }
+  const int32_t* en = TAB ? a.conn + e * (P * P * P) : nullptr;
   const int t = threadIdx.x;
   const bool pt = t < Q3;
   const int ql = pt ? t : 0;
   const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
-  const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
   const int64_t gq = e * Q3 + ql;
   // per-point state, issued before the gathers
   double st[8];
@@ -330,7 +364,10 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     for (int k = 0; k < 9; ++k) gA[k] = pt ? a.qd[k * a.n_q + gq] : 0.0;
     wdet = pt ? a.qd[9 * a.n_q + gq] : 0.0;
   }
-  gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
+  if (TAB)
+    gather_elem_tab<double, double, P, 4>(a.z, a.n_nodes, en, bufA);
+  else
+    gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
   __syncthreads();
   sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
   double G[9], phi, gphi[3];
@@ -343,7 +380,10 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   double phin = 0.0;
   __syncthreads();
   if (MODE == M_RES) {
-    gather_elem<double, double, P, 1>(a.phin, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    if (TAB)
+      gather_elem_tab<double, double, P, 1>(a.phin, a.n_nodes, en, bufA);
+    else
+      gather_elem<double, double, P, 1>(a.phin, a.n_nodes, a.nx1, a.ny1, g, bufA);
     __syncthreads();
     sf5_fwd<double, DevTables, P, Q, 1>(bufA, bufB, tabs);
     phin = bufB[ql];
@@ -362,7 +402,10 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   const bool bad_pid = pt && pid >= a.nph;  // an id outside the phase table raises the phase flag
   double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
   if (MODE != M_RES) {
-    gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    if (TAB)
+      gather_elem_tab<double, double, P, 4>(a.w, a.n_nodes, en, bufA);
+    else
+      gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
     __syncthreads();
     sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
 #pragma unroll
@@ -442,7 +485,9 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   }
   __syncthreads();
   sf5_bwd<double, DevTables, P, Q, 4, true>(bufB, bufA, tabs);
-  if (EV)
+  if (TAB)
+    store_elem_tab<double, P>(bufA, e, a.evec);
+  else if (EV)
     store_ext<double, P, 4>(bufA, a.m, g, a.evec);
   else
     scatter_elem<double, P, 4>(bufA, a.m, a.nx1, a.ny1, a.n_nodes, g, a.out);

@@ -371,7 +371,7 @@ pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* con
   if (!out) return fail(PF_EINVAL, "out is null");
   *out = nullptr;
   if (!mesh || !conn || !X || !phases || !fr || !qp_phase || !qp_state || !phi_n) return fail(PF_EINVAL, "null argument");
-  if (mesh->p != 2 && mesh->p != 3) return fail(PF_EUNSUPPORTED, "table restriction built for p = 2, 3 (p=%d)", mesh->p);
+  if (mesh->p < 2 || mesh->p > 4) return fail(PF_EUNSUPPORTED, "table restriction built for p = 2..4 (p=%d)", mesh->p);
   const int P = mesh->p + 1, P3 = P * P * P;
   if (mesh->n_elem < 1 || mesh->n_nodes < 1) return fail(PF_EINVAL, "empty mesh");
   if (mesh->n_nodes >= ((int64_t)1 << 31) - 1 || mesh->n_elem * 4 * P3 >= ((int64_t)1 << 31))
@@ -411,7 +411,8 @@ pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* con
   c->n_nodes = mesh->n_nodes;
   c->n_elem = mesh->n_elem;
   c->n_q = mesh->n_elem * P3;
-  c->n_groups = (int)((mesh->n_elem + 7) / 8);
+  // workgroups: 8 elements each on orders 2 and 3 (two per wave), one element on order 4
+  c->n_groups = mesh->p == 4 ? (int)mesh->n_elem : (int)((mesh->n_elem + 7) / 8);
   c->n_parts = c->n_groups;
   c->conn = conn;
   pf_status st = setup_common(c, phases, n_phases, fr, qp_phase, qp_state, phi_n, stream);
@@ -431,8 +432,11 @@ pf_status pf_setup_mesh_table(const pf_table_mesh_desc* mesh, const int32_t* con
     if (mesh->p == 2)
       hipLaunchKernelGGL((k_geometry_tab<3, 3>), grid, dim3(NT), 0, s, X, c->n_nodes, conn, c->n_q, c->d_tab, c->d_qd,
                          c->d_flag);
-    else
+    else if (mesh->p == 3)
       hipLaunchKernelGGL((k_geometry_tab<4, 4>), grid, dim3(NT), 0, s, X, c->n_nodes, conn, c->n_q, c->d_tab, c->d_qd,
+                         c->d_flag);
+    else
+      hipLaunchKernelGGL((k_geometry_tab<5, 5>), grid, dim3(NT), 0, s, X, c->n_nodes, conn, c->n_q, c->d_tab, c->d_qd,
                          c->d_flag);
     e = hipGetLastError();
   }

@@ -3,12 +3,12 @@ gather, element vectors, node-owner CSR gather.
 
 * Parity with the oracle (same table) on meshes with a cylindrical hole, every element in one
   of the 24 cube orientations, shuffled elements and randomly renumbered nodes: residual,
-  Jacobian, adjoint and parameter gradient, Q2 and Q3, several loadings; rel-L2 and per-field
-  max-entry bars 1e-12.
+  Jacobian, adjoint and parameter gradient, Q2, Q3 and Q4, several loadings; rel-L2 and
+  per-field max-entry bars 1e-12.
 * The lattice re-expressed as a table gives the box context's results after un-permuting.
 * Determinism, the dot-product identity, and the error paths.
-* Full size: the Q3 48^3 and Q2 32^3 workloads with a hole (bench.py's table workload), every
-  node against the oracle.
+* Full size: the Q2 32^3, Q3 48^3 (bench.py's table workload) and Q4 40^3 workloads with a
+  hole, every node against the oracle.
 """
 import numpy as np
 import pytest
@@ -53,7 +53,8 @@ def table_inputs(p, n, variant, hole=0.2, order="random", shuffle=True):
 
 
 @pytest.mark.parametrize("p,n,variant", [(2, 4, "plastic"), (2, 5, "base"), (2, 3, "compress"), (3, 3, "plastic"),
-                                         (3, 4, "base"), (3, 4, "voce"), (3, 5, "compress")])
+                                         (3, 4, "base"), (3, 4, "voce"), (3, 5, "compress"), (4, 2, "plastic"),
+                                         (4, 3, "base"), (4, 3, "voce")])
 def test_table_parity(pf, oracle_lib, p, n, variant):
     print(f"case table p={p} n={n} {variant}", flush=True)
     u = table_inputs(p, n, variant)
@@ -70,7 +71,7 @@ def test_table_parity(pf, oracle_lib, p, n, variant):
     assert np.abs(gp - gpref).max() <= 1e-11 * max(np.abs(gpref).max(), 1e-300), (gp, gpref)
 
 
-@pytest.mark.parametrize("p,n", [(2, 4), (3, 3)])
+@pytest.mark.parametrize("p,n", [(2, 4), (3, 3), (4, 2)])
 def test_lattice_as_a_table_matches_the_box(pf, p, n):
     """No hole: the table context reproduces the box context after un-permuting the nodes."""
     d = I.make_inputs("C1", "plastic", p=p, n=n)
@@ -127,14 +128,14 @@ def test_table_error_paths(pf):
         assert e.value.code == pf.PF_EUNSUPPORTED
     ctx.apply_residual(z)
     ctx.check()
-    d4 = I.make_inputs("C1", "base", p=4, n=2)
-    u4 = I.unstructured(d4)
+    d1 = I.make_inputs("C1", "base", p=1, n=3)
+    u1 = I.unstructured(d1)
     with pytest.raises(pf.PfError) as e:
-        pf.Context.from_inputs(u4)
+        pf.Context.from_inputs(u1)
     assert e.value.code == pf.PF_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("name", ["C2", "C3"])
+@pytest.mark.parametrize("name", ["C2", "C3", "C5"])
 def test_table_full_size(pf, oracle_lib, name):
     """bench.py's table workload: the lattice with a cylindrical hole of radius 0.15 mm, every
     element rotated, elements in lattice order, nodes numbered by first touch; every node
