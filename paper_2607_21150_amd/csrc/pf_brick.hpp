@@ -21,16 +21,20 @@ namespace pfmf {
 
 constexpr int NT = 256;  // threads per workgroup
 
-// 1-D tables per (P nodes, Q points): B[q][i], D[q][i], w[q] (index [P][Q]).
+// 1-D tables per (P nodes, Q points): B[q][i], D[q][i], w[q] (index [P][Q]); G[Q][q][m]
+// = derivative at Gauss point q of the Lagrange polynomial through the Q Gauss points that
+// is 1 at point m (collocated differentiation of values already at the points).
 struct DevTables {
   double B[6][6][5][5];
   double D[6][6][5][5];
   double w[6][5];
+  double G[6][5][5];
 };
 struct DevTablesF {
   float B[6][6][5][5];
   float D[6][6][5][5];
   float w[6][5];
+  float G[6][5][5];
 };
 
 struct BrickGeom {

@@ -10,10 +10,12 @@
 // row layout: a pass contracts one direction, and each thread owns one (field, row)
 // of the element, holds the row's P inputs in registers and produces all Q outputs
 // along it. Per field that is P (or Q) LDS reads per Q outputs, against P reads per
-// output when each thread owns one output. The passes run x, y, z forward and z, y,
-// x backward, ping-ponging two LDS buffers; the pointwise function then runs with one
-// thread per quadrature point (125 of the 128 threads). The 1-D tables are read with
-// compile-time indices, so they live in scalar registers.
+// output when each thread owns one output. The forward passes interpolate values only
+// (x, y, z), and the reference gradient is then formed from the point values with the
+// collocated Gauss-point derivative along x, y and z lines; the backward passes apply
+// the transposes in the opposite order, ping-ponging two LDS buffers. The pointwise
+// function runs with one thread per quadrature point (125 of the 128 threads). The 1-D
+// tables are read with compile-time indices, so they live in scalar registers.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -139,14 +141,22 @@ __device__ __forceinline__ constexpr int qslot(int f, int c) {
 }
 
 // Forward: U[f][k][j][i] (P^3 per field) -> Qo[slot(f, c)][qz][qy][qx] (Q^3 per field and
-// component c = value, d/dxi_x, d/dxi_y, d/dxi_z; with CV no values for f < 3). X holds
-// 2 NF P^2 Q values, Y (aliasing U) 3 NF Q^2 P. Starts after, and ends with, a barrier.
-template <typename T, typename Tab, int P, int Q, int NF, bool CV = false>
+// component c = value, d/dxi_x, d/dxi_y, d/dxi_z; with CV no values for f < 3). The nodal
+// values are interpolated to the points by x, y and z passes (B only), and the reference
+// derivatives are then taken from the point values along each line of points with the
+// Gauss-point differentiation matrix G, which is exact because the interpolant has degree
+// P - 1 <= Q - 1 along the line. Per (field, line) of the element a pass costs P Q (or
+// Q^2) multiply-adds, against carrying value and derivative chains through every pass.
+// LDS: X (in XQ) NF P^2 Q values; Y (in UY) NF Q^2 P, followed in UY by the point values
+// V (NF Q^3). GR = false: values only. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF, bool CV = false, bool GR = true>
 __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb) {
   static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
-  constexpr int P2 = P * P, P3 = P2 * P, Q3 = Q * Q * Q;
+  static_assert(GR || !CV, "the compact layout carries gradients");
+  constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+  T* VV = UY + NF * Q2 * P;
   const int t = threadIdx.x;
-  // x: thread (f, j, k); X[f][c][k][j][qx], c = B_x, D_x
+  // x: thread (f, j, k); X[f][k][j][qx]
   if (t < NF * P2) {
     const int f = t / P2, r = t - f * P2;
     T u[P];
@@ -154,154 +164,183 @@ __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb
     for (int i = 0; i < P; ++i) u[i] = UY[f * P3 + r * P + i];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T b = T(0), d = T(0);
+      T b = T(0);
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        b += (T)tb->B[P][Q][q][i] * u[i];
-        d += (T)tb->D[P][Q][q][i] * u[i];
-      }
-      XQ[(2 * f) * P2 * Q + r * Q + q] = b;
-      XQ[(2 * f + 1) * P2 * Q + r * Q + q] = d;
+      for (int i = 0; i < P; ++i) b += (T)tb->B[P][Q][q][i] * u[i];
+      XQ[f * P2 * Q + r * Q + q] = b;
     }
   }
   __syncthreads();
-  // y: thread (f, qx, k); Y[f][c][qy][qx][k], c = B_y B_x, D_y B_x, B_y D_x
+  // y: thread (f, qx, k); Y[f][qy][qx][k]
   if (t < NF * Q * P) {
     const int f = t / (Q * P), s = t - f * (Q * P);
     const int qx = s % Q, k = s / Q;
-    T xb[P], xd[P];
+    T x[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      xb[j] = XQ[(2 * f) * P2 * Q + (j + P * k) * Q + qx];
-      xd[j] = XQ[(2 * f + 1) * P2 * Q + (j + P * k) * Q + qx];
-    }
+    for (int j = 0; j < P; ++j) x[j] = XQ[f * P2 * Q + (j + P * k) * Q + qx];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T bb = T(0), db = T(0), bd = T(0);
+      T b = T(0);
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        bb += (T)tb->B[P][Q][q][j] * xb[j];
-        db += (T)tb->D[P][Q][q][j] * xb[j];
-        bd += (T)tb->B[P][Q][q][j] * xd[j];
-      }
-      const int o = (qx + Q * q) * P + k;
-      UY[(3 * f) * Q * Q * P + o] = bb;
-      UY[(3 * f + 1) * Q * Q * P + o] = db;
-      UY[(3 * f + 2) * Q * Q * P + o] = bd;
+      for (int j = 0; j < P; ++j) b += (T)tb->B[P][Q][q][j] * x[j];
+      UY[f * Q2 * P + (qx + Q * q) * P + k] = b;
     }
   }
   __syncthreads();
-  // z: thread (f, qx, qy); Qo[f][c][q]
-  if (t < NF * Q * Q) {
-    const int f = t / (Q * Q), s = t - f * (Q * Q);
-    T yb[P], yd[P], yx[P];
+  // z: thread (f, qx, qy); values V[f][qz][qy][qx], and d/dxi_z along the same line
+  if (t < NF * Q2) {
+    const int f = t / Q2, s = t - f * Q2;
+    T y[P], v[Q];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-      yb[k] = UY[(3 * f) * Q * Q * P + s * P + k];
-      yd[k] = UY[(3 * f + 1) * Q * Q * P + s * P + k];
-      yx[k] = UY[(3 * f + 2) * Q * Q * P + s * P + k];
-    }
+    for (int k = 0; k < P; ++k) y[k] = UY[f * Q2 * P + s * P + k];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T v = T(0), dz = T(0), dy = T(0), dx = T(0);
+      T b = T(0);
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        const T bz = (T)tb->B[P][Q][q][k];
-        v += bz * yb[k];
-        dz += (T)tb->D[P][Q][q][k] * yb[k];
-        dy += bz * yd[k];
-        dx += bz * yx[k];
+      for (int k = 0; k < P; ++k) b += (T)tb->B[P][Q][q][k] * y[k];
+      v[q] = b;
+      const int o = s + Q2 * q;
+      if (GR) VV[f * Q3 + o] = b;
+      if (!CV || f == 3) XQ[qslot<CV>(f, 0) * Q3 + o] = b;
+    }
+    if (GR) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        T d = T(0);
+#pragma unroll
+        for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
+        XQ[qslot<CV>(f, 3) * Q3 + s + Q2 * q] = d;
       }
-      const int o = s + Q * Q * q;
-      if (!CV || f == 3) XQ[qslot<CV>(f, 0) * Q3 + o] = v;
-      XQ[qslot<CV>(f, 1) * Q3 + o] = dx;
-      XQ[qslot<CV>(f, 2) * Q3 + o] = dy;
-      XQ[qslot<CV>(f, 3) * Q3 + o] = dz;
+    }
+  }
+  __syncthreads();
+  if (!GR) return;
+  // d/dxi_x along x lines: thread (f, qy, qz)
+  if (t < NF * Q2) {
+    const int f = t / Q2, s = t - f * Q2;
+    T v[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) v[m] = VV[f * Q3 + s * Q + m];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T d = T(0);
+#pragma unroll
+      for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
+      XQ[qslot<CV>(f, 1) * Q3 + s * Q + q] = d;
+    }
+  }
+  // d/dxi_y along y lines: thread (f, qx, qz)
+  if (t < NF * Q2) {
+    const int f = t / Q2, s = t - f * Q2;
+    const int base = f * Q3 + (s % Q) + Q2 * (s / Q);
+    T v[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) v[m] = VV[base + Q * m];
+    const int ob = qslot<CV>(f, 2) * Q3 + (s % Q) + Q2 * (s / Q);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T d = T(0);
+#pragma unroll
+      for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
+      XQ[ob + Q * q] = d;
     }
   }
   __syncthreads();
 }
 
 // Transposed: Qi[slot(f, c)][q] (c = value test, tests against d/dxi_x, d/dxi_y,
-// d/dxi_z; in XQ; with CV no value tests for f < 3) -> R[f][k][j][i] (in ZR). Z (in ZR)
-// holds 3 NF P Q^2 values, Y (in XQ) 2 NF P^2 Q. Starts after, and ends with, a barrier.
+// d/dxi_z; in XQ; with CV no value tests for f < 3) -> R[f][k][j][i] (in ZR). The
+// derivative tests are moved back onto the point values with G^T along x, y and z lines
+// and added to the value test (A[f][q] in ZR), which then goes through the transposed
+// interpolation passes z, y, x. Z (in ZR, after A) holds NF P Q^2 values, Y (in XQ) NF P^2 Q.
+// Starts after, and ends with, a barrier.
 template <typename T, typename Tab, int P, int Q, int NF, bool CV = false>
 __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb) {
   static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+  T* Z = ZR + NF * Q3;
   const int t = threadIdx.x;
-  // z^T: thread (f, qx, qy); Z[f][c][k][qy][qx], c = value chain, x tests, y tests
-  T z0[P], zx[P], zy[P];
-  const bool az = t < NF * Q2;
-  if (az) {
+  // x lines: thread (f, qy, qz); A = value test + G^T (x tests)
+  if (t < NF * Q2) {
     const int f = t / Q2, s = t - f * Q2;
+    T g[Q];
 #pragma unroll
-    for (int k = 0; k < P; ++k) z0[k] = zx[k] = zy[k] = T(0);
+    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 1) * Q3 + s * Q + m];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int o = s + Q2 * q;
-      const T f0 = (!CV || f == 3) ? XQ[qslot<CV>(f, 0) * Q3 + o] : T(0);
-      const T fx = XQ[qslot<CV>(f, 1) * Q3 + o];
-      const T fy = XQ[qslot<CV>(f, 2) * Q3 + o], fz = XQ[qslot<CV>(f, 3) * Q3 + o];
+      T a = (!CV || f == 3) ? XQ[qslot<CV>(f, 0) * Q3 + s * Q + q] : T(0);
 #pragma unroll
-      for (int k = 0; k < P; ++k) {
-        const T bz = (T)tb->B[P][Q][q][k];
-        z0[k] += bz * f0 + (T)tb->D[P][Q][q][k] * fz;
-        zx[k] += bz * fx;
-        zy[k] += bz * fy;
-      }
-    }
-  }
-  // Z aliases nothing that is still read: ZR is free until here
-  if (az) {
-    const int f = t / Q2, s = t - f * Q2;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      ZR[(3 * f) * P * Q2 + k * Q2 + s] = z0[k];
-      ZR[(3 * f + 1) * P * Q2 + k * Q2 + s] = zx[k];
-      ZR[(3 * f + 2) * P * Q2 + k * Q2 + s] = zy[k];
+      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
+      ZR[f * Q3 + s * Q + q] = a;
     }
   }
   __syncthreads();
-  // y^T: thread (f, qx, k); Y[f][c][k][j][qx], c = value chain, x tests
+  // y lines: thread (f, qx, qz); A += G^T (y tests)
+  if (t < NF * Q2) {
+    const int f = t / Q2, s = t - f * Q2;
+    const int o = (s % Q) + Q2 * (s / Q);
+    T g[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 2) * Q3 + o + Q * m];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T a = ZR[f * Q3 + o + Q * q];
+#pragma unroll
+      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
+      ZR[f * Q3 + o + Q * q] = a;
+    }
+  }
+  __syncthreads();
+  // z lines: thread (f, qx, qy); A + G^T (z tests), then the transposed z interpolation:
+  // Z[f][k][qy][qx]
+  if (t < NF * Q2) {
+    const int f = t / Q2, s = t - f * Q2;
+    T g[Q], c[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 3) * Q3 + s + Q2 * m];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      T a = ZR[f * Q3 + s + Q2 * q];
+#pragma unroll
+      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
+      c[q] = a;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      T z = T(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) z += (T)tb->B[P][Q][q][k] * c[q];
+      Z[f * P * Q2 + k * Q2 + s] = z;
+    }
+  }
+  __syncthreads();
+  // y^T: thread (f, qx, k); Y[f][k][j][qx]
   if (t < NF * Q * P) {
     const int f = t / (Q * P), s = t - f * (Q * P);
     const int qx = s % Q, k = s / Q;
-    T a0[P], ax[P];
+    T v[Q];
 #pragma unroll
-    for (int j = 0; j < P; ++j) a0[j] = ax[j] = T(0);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int o = k * Q2 + q * Q + qx;
-      const T v0 = ZR[(3 * f) * P * Q2 + o], vx = ZR[(3 * f + 1) * P * Q2 + o], vy = ZR[(3 * f + 2) * P * Q2 + o];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const T by = (T)tb->B[P][Q][q][j];
-        a0[j] += by * v0 + (T)tb->D[P][Q][q][j] * vy;
-        ax[j] += by * vx;
-      }
-    }
+    for (int q = 0; q < Q; ++q) v[q] = Z[f * P * Q2 + k * Q2 + q * Q + qx];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      XQ[(2 * f) * P2 * Q + (j + P * k) * Q + qx] = a0[j];
-      XQ[(2 * f + 1) * P2 * Q + (j + P * k) * Q + qx] = ax[j];
+      T a = T(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][j] * v[q];
+      XQ[f * P2 * Q + (j + P * k) * Q + qx] = a;
     }
   }
   __syncthreads();
   // x^T: thread (f, j, k); R[f][k][j][i]
   if (t < NF * P2) {
     const int f = t / P2, r = t - f * P2;
-    T y0[Q], yx[Q];
+    T y[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      y0[q] = XQ[(2 * f) * P2 * Q + r * Q + q];
-      yx[q] = XQ[(2 * f + 1) * P2 * Q + r * Q + q];
-    }
+    for (int q = 0; q < Q; ++q) y[q] = XQ[f * P2 * Q + r * Q + q];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       T a = T(0);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][i] * y0[q] + (T)tb->D[P][Q][q][i] * yx[q];
+      for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][i] * y[q];
       ZR[f * P3 + r * P + i] = a;
     }
   }
@@ -310,10 +349,10 @@ __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb
 
 // LDS sizes (values) of the two buffers for up to 4 fields (CV: the compact point arrays).
 template <int P, int Q, bool CV = false> struct Q5Lds {
-  static constexpr int a0 = 4 * P * P * P, a1 = 12 * Q * Q * P;
-  static constexpr int A = a0 > a1 ? a0 : a1;  // U / Y (forward), Z / R (backward)
-  static constexpr int b0 = 8 * P * P * Q, b1 = (CV ? 13 : 16) * Q * Q * Q;
-  static constexpr int B = b0 > b1 ? b0 : b1;  // X / Qo (forward), Qi / Y (backward)
+  static constexpr int a0 = 4 * P * P * P, a1 = 4 * Q * Q * P + 4 * Q * Q * Q;
+  static constexpr int A = a0 > a1 ? a0 : a1;  // U, then Y and V (forward); A and Z, then R (backward)
+  static constexpr int b0 = 4 * P * P * Q, b1 = (CV ? 13 : 16) * Q * Q * Q;
+  static constexpr int B = b0 > b1 ? b0 : b1;  // X, then the point arrays (forward); point arrays, then Y (backward)
 };
 
 // FP64 residual / Jacobian / adjoint on order-4 elements.
@@ -385,7 +424,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     else
       gather_elem<double, double, P, 1>(a.phin, a.n_nodes, a.nx1, a.ny1, g, bufA);
     __syncthreads();
-    sf5_fwd<double, DevTables, P, Q, 1>(bufA, bufB, tabs);
+    sf5_fwd<double, DevTables, P, Q, 1, false, false>(bufA, bufB, tabs);
     phin = bufB[ql];
     __syncthreads();
   }

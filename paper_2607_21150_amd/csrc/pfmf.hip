@@ -167,9 +167,15 @@ pf_status build_tables(pf_ctx* c) {
       std::vector<double> xq, wq, B, D;
       gauss_legendre(Q, xq, wq);
       lagrange_tables(xn, xq, B, D);
+      std::vector<double> Bg, Gg;
+      lagrange_tables(xq, xq, Bg, Gg);
       for (int q = 0; q < Q; ++q) {
         t->w[Q][q] = wq[q];
         tf->w[Q][q] = (float)wq[q];
+        for (int m = 0; m < Q; ++m) {
+          t->G[Q][q][m] = Gg[q * Q + m];
+          tf->G[Q][q][m] = (float)Gg[q * Q + m];
+        }
         for (int i = 0; i < P; ++i) {
           t->B[P][Q][q][i] = B[q * P + i];
           t->D[P][Q][q][i] = D[q * P + i];
