@@ -65,39 +65,46 @@ __device__ inline bool xcd_elem_all(const MeshDev& m, int id, ElemGeom& g) {
 // nodes appear once per element holding them); k_gather_ext<T, P> sums them per node.
 // Each row of P values is contiguous, and the next element along x (launched next on the
 // same XCD) writes the adjacent P values.
+// Thread n < P^3 owns the element's local node n = i + P (j + P k) in every gather and
+// store, so that its address is formed once for all fields.
 template <typename T, int P, int NF>
 __device__ inline void store_ext(const T* R, const MeshDev& m, const ElemGeom& g, T* __restrict__ ev) {
+  static_assert(P * P * P <= NT5, "one thread per element node");
   constexpr int P3 = P * P * P;
+  const int n = threadIdx.x;
+  if (n >= P3) return;
   const int64_t NXe = (int64_t)m.nx * P, NYe = (int64_t)m.ny * P, NZe = (int64_t)m.nz * P;
-  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
-    const int f = t / P3, n = t - f * P3, k = n / (P * P), j = (n / P) % P, i = n % P;
-    ev[((f * NZe + (int64_t)g.ez * P + k) * NYe + (int64_t)g.ey * P + j) * NXe + (int64_t)g.ex * P + i] = R[t];
-  }
+  const int i = n % P, j = (n / P) % P, k = n / (P * P);
+  T* d = ev + (((int64_t)g.ez * P + k) * NYe + (int64_t)g.ey * P + j) * NXe + (int64_t)g.ex * P + i;
+  const int64_t fs = NZe * NYe * NXe;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) d[f * fs] = R[f * P3 + n];
 }
 
-// Gather NF fields of the element's P^3 nodes (order P-1 lattice with nx1 x ny1
-// nodes per layer) into U[f][k][j][i].
-template <typename T, typename S, int P, int NF>
-__device__ inline void gather_elem(const S* __restrict__ src, int64_t n_nodes, int nx1, int ny1, const ElemGeom& g,
-                                   T* U) {
-  constexpr int p = P - 1, P3 = P * P * P;
-  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
-    const int f = t / P3, n = t - f * P3;
-    const int i = n % P, j = (n / P) % P, k = n / (P * P);
-    const int64_t gi = (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
-    U[t] = (T)src[f * n_nodes + gi];
-  }
+// Global node of the thread's local node on an order P-1 lattice with nx1 x ny1 nodes per
+// layer; -1 for threads beyond the P^3 nodes.
+template <int P>
+__device__ inline int64_t elem_node(int nx1, int ny1, const ElemGeom& g) {
+  static_assert(P * P * P <= NT5, "one thread per element node");
+  constexpr int p = P - 1;
+  const int n = threadIdx.x;
+  if (n >= P * P * P) return -1;
+  const int i = n % P, j = (n / P) % P, k = n / (P * P);
+  return (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
 }
 
-// Table restriction: gather NF fields of the element's P^3 nodes, en = the element's row
-// of the element-to-node table (local lexicographic order), into U[f][n].
+// Gather NF fields of the element's P^3 nodes into U[f][n]; gn = the thread's global node
+// (elem_node, or the element's row of the element-to-node table for the table restriction).
 template <typename T, typename S, int P, int NF>
-__device__ inline void gather_elem_tab(const S* __restrict__ src, int64_t n_nodes, const int32_t* __restrict__ en,
-                                       T* U) {
+__device__ inline void gather_nodes(const S* __restrict__ src, int64_t n_nodes, int64_t gn, T* U) {
   constexpr int P3 = P * P * P;
-  for (int t = threadIdx.x; t < NF * P3; t += NT5) {
-    const int f = t / P3, n = t - f * P3;
-    U[t] = (T)src[f * n_nodes + en[n]];
+  const int n = threadIdx.x;
+  if (n < P3) {
+    T v[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = (T)src[f * n_nodes + gn];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) U[f * P3 + n] = v[f];
   }
 }
 
@@ -105,11 +112,13 @@ __device__ inline void gather_elem_tab(const S* __restrict__ src, int64_t n_node
 // (the four fields of one entry contiguous), summed per node by k_gather_csr.
 template <typename T, int P>
 __device__ inline void store_elem_tab(const T* R, int64_t e, T* __restrict__ ev) {
+  static_assert(P * P * P <= NT5, "one thread per element node");
   constexpr int P3 = P * P * P;
-  for (int t = threadIdx.x; t < 4 * P3; t += NT5) {
-    const int f = t / P3, n = t - f * P3;
-    ev[(e * P3 + n) * 4 + f] = R[t];
-  }
+  const int n = threadIdx.x;
+  if (n >= P3) return;
+  T* d = ev + (e * P3 + n) * 4;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) d[f] = R[f * P3 + n];
 }
 
 // Add the element vector R[f][k][j][i] into dst with the colour rule.
@@ -383,8 +392,9 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     if (!(EV ? xcd_elem_all(a.m, blockIdx.x, g) : xcd_elem(a.m, colour, blockIdx.x, g))) return;  // padding (uniform)
     e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
   }
-  const int32_t* en = TAB ? a.conn + e * (P * P * P) : nullptr;
   const int t = threadIdx.x;
+  // the thread's element node (every gather below reads it)
+  const int64_t gn = TAB ? (t < P * P * P ? (int64_t)a.conn[e * (P * P * P) + t] : -1) : elem_node<P>(a.nx1, a.ny1, g);
   const bool pt = t < Q3;
   const int ql = pt ? t : 0;
   const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
@@ -403,10 +413,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
     for (int k = 0; k < 9; ++k) gA[k] = pt ? a.qd[k * a.n_q + gq] : 0.0;
     wdet = pt ? a.qd[9 * a.n_q + gq] : 0.0;
   }
-  if (TAB)
-    gather_elem_tab<double, double, P, 4>(a.z, a.n_nodes, en, bufA);
-  else
-    gather_elem<double, double, P, 4>(a.z, a.n_nodes, a.nx1, a.ny1, g, bufA);
+  gather_nodes<double, double, P, 4>(a.z, a.n_nodes, gn, bufA);
   __syncthreads();
   sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
   double G[9], phi, gphi[3];
@@ -419,10 +426,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   double phin = 0.0;
   __syncthreads();
   if (MODE == M_RES) {
-    if (TAB)
-      gather_elem_tab<double, double, P, 1>(a.phin, a.n_nodes, en, bufA);
-    else
-      gather_elem<double, double, P, 1>(a.phin, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    gather_nodes<double, double, P, 1>(a.phin, a.n_nodes, gn, bufA);
     __syncthreads();
     sf5_fwd<double, DevTables, P, Q, 1, false, false>(bufA, bufB, tabs);
     phin = bufB[ql];
@@ -441,10 +445,7 @@ __global__ __launch_bounds__(NT5, 2) void k_op64_q4(OpArgs a, int colour, DevTab
   const bool bad_pid = pt && pid >= a.nph;  // an id outside the phase table raises the phase flag
   double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
   if (MODE != M_RES) {
-    if (TAB)
-      gather_elem_tab<double, double, P, 4>(a.w, a.n_nodes, en, bufA);
-    else
-      gather_elem<double, double, P, 4>(a.w, a.n_nodes, a.nx1, a.ny1, g, bufA);
+    gather_nodes<double, double, P, 4>(a.w, a.n_nodes, gn, bufA);
     __syncthreads();
     sf5_fwd<double, DevTables, P, Q, 4, true>(bufA, bufB, tabs);
 #pragma unroll
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
     for (int k = 0; k < 9; ++k) gA[k] = pt ? a.qd[k * a.n_q + gq] : 0.0;
     wdet = pt ? (V)a.qd[9 * a.n_q + gq] : V(0);
   }
-  gather_elem<V, V, PF, 3>(a.z32, a.fine.n_nodes, a.fine.nx1, a.fine.ny1, g, bufA);
+  gather_nodes<V, V, PF, 3>(a.z32, a.fine.n_nodes, elem_node<PF>(a.fine.nx1, a.fine.ny1, g), bufA);
   __syncthreads();
   sf5_fwd<V, Tab, PF, Q, 3>(bufA, bufB, tabs);
   V G[9];
@@ -611,7 +612,7 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
       for (int J = 0; J < 3; ++J) G[3 * f + J] = bufB[(4 * f + 1 + J) * Q3 + ql] * ih[J];
   }
   __syncthreads();
-  gather_elem<V, V, PC, 4>(a.dz, a.lev.n_nodes, a.lev.nx1, a.lev.ny1, g, bufA);
+  gather_nodes<V, V, PC, 4>(a.dz, a.lev.n_nodes, elem_node<PC>(a.lev.nx1, a.lev.ny1, g), bufA);
   __syncthreads();
   sf5_fwd<V, Tab, PC, Q, 4, true>(bufA, bufB, tabs);
   V W[9], wphi, gw[3];
