@@ -11,6 +11,11 @@ inline int vec_grid(int64_t n) {
   return (int)(b < VEC_BLOCKS ? (b > 0 ? b : 1) : VEC_BLOCKS);
 }
 
+// Nodes of the six boundary faces of a lattice, each face counted in full (k_mask's range).
+inline int64_t face_nodes(int nx1, int ny1, int nz1) {
+  return 2 * ((int64_t)ny1 * nz1 + (int64_t)nx1 * nz1 + (int64_t)nx1 * ny1);
+}
+
 // 1-D transfer rows between orders pf (fine) and pc (coarse) on N elements.
 void transfer_rows_1d(int pf, int pc, int N, std::vector<int>& pbase, std::vector<float>& pw,
                       std::vector<int>& rbase, std::vector<float>& rw) {
@@ -188,14 +193,14 @@ pf_status ensure_records(pf_ctx* c) {
 pf_status mask_level(pf_ctx* c, int level, float* v, hipStream_t s) {
   if (!c->has_dir) return PF_OK;
   const MGLevel& L = c->mg.lv[level];
-  hipLaunchKernelGGL(k_mask<float>, dim3(vec_grid(L.n_nodes)), dim3(NT), 0, s, v, L.nx1, L.ny1, L.nz1, c->dir);
+  hipLaunchKernelGGL(k_mask<float>, dim3(vec_grid(face_nodes(L.nx1, L.ny1, L.nz1))), dim3(NT), 0, s, v, L.nx1, L.ny1, L.nz1, c->dir);
   HIPCHK(hipGetLastError());
   return PF_OK;
 }
 
 pf_status mask_fine64(pf_ctx* c, double* v, hipStream_t s) {
   if (!c->has_dir) return PF_OK;
-  hipLaunchKernelGGL(k_mask<double>, dim3(vec_grid(c->n_nodes)), dim3(NT), 0, s, v, c->nx1, c->ny1, c->nz1, c->dir);
+  hipLaunchKernelGGL(k_mask<double>, dim3(vec_grid(face_nodes(c->nx1, c->ny1, c->nz1))), dim3(NT), 0, s, v, c->nx1, c->ny1, c->nz1, c->dir);
   HIPCHK(hipGetLastError());
   return PF_OK;
 }

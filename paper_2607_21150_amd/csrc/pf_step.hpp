@@ -15,25 +15,35 @@ struct DirMask {
   uint32_t face[6];
 };
 
-__device__ inline uint32_t dir_fields(int64_t i, int nx1, int ny1, int nz1, const DirMask& d) {
-  const int ix = (int)(i % nx1), iy = (int)((i / nx1) % ny1), iz = (int)(i / ((int64_t)nx1 * ny1));
-  uint32_t f = 0;
-  if (ix == 0) f |= d.face[0];
-  if (ix == nx1 - 1) f |= d.face[1];
-  if (iy == 0) f |= d.face[2];
-  if (iy == ny1 - 1) f |= d.face[3];
-  if (iz == 0) f |= d.face[4];
-  if (iz == nz1 - 1) f |= d.face[5];
-  return f;
-}
-
-// v[f][i] = 0 for every constrained (node, field) of a [4][n] vector on a lattice.
+// v[f][i] = 0 for every constrained (node, field) of a [4][n] vector on a lattice. The
+// threads run over the nodes of the six boundary faces only (x = 0, x = max, y = 0, ...,
+// each face as its own range); a node on an edge or corner is zeroed once per face that
+// constrains it (the same zeros, so the result does not depend on the order).
 template <typename T>
 __global__ void k_mask(T* __restrict__ v, int nx1, int ny1, int nz1, DirMask d) {
   const int64_t n = (int64_t)nx1 * ny1 * nz1;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t f = dir_fields(i, nx1, ny1, nz1, d);
-    if (f == 0) continue;
+  const int64_t fx = (int64_t)ny1 * nz1, fy = (int64_t)nx1 * nz1, fz = (int64_t)nx1 * ny1;
+  const int64_t total = 2 * (fx + fy + fz);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = t, i;
+    int face;
+    if (r < 2 * fx) {
+      face = (int)(r / fx);
+      r -= face * fx;
+      const int64_t iy = r % ny1, iz = r / ny1;
+      i = (face ? nx1 - 1 : 0) + (int64_t)nx1 * (iy + (int64_t)ny1 * iz);
+    } else if ((r -= 2 * fx) < 2 * fy) {
+      face = 2 + (int)(r / fy);
+      r -= (face - 2) * fy;
+      const int64_t ix = r % nx1, iz = r / nx1;
+      i = ix + (int64_t)nx1 * ((face == 3 ? ny1 - 1 : 0) + (int64_t)ny1 * iz);
+    } else {
+      r -= 2 * fy;
+      face = 4 + (int)(r / fz);
+      r -= (face - 4) * fz;
+      i = r + (face == 5 ? (int64_t)(nz1 - 1) * fz : 0);
+    }
+    const uint32_t f = d.face[face];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       if ((f >> k) & 1u) v[k * n + i] = T(0);
