@@ -284,10 +284,17 @@ pf_status launch_lin_mfma_v(pf_ctx* c, LinApplyArgs<V> a, hipStream_t s) {
       return fail(PF_ENOMEM, "brick buffer: allocation failed");
     a.ebuf = *buf;
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
-    if constexpr (PF == 4)
+    if constexpr (PF == 4) {
       hipLaunchKernelGGL((k_a32_q3<V, PC, true, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
-    else
+    } else if constexpr (!MB && !GEO) {
+      // order 2 on box elements without branches: the row-layout kernel (no 3 -> 4 padding)
+      if constexpr (sizeof(V) == 4)
+        hipLaunchKernelGGL((k_a32_q2r<V, PC>), dim3(ng), dim3(NT), 0, s, a, c->d_tabf);
+      else
+        hipLaunchKernelGGL((k_a32_q2r<V, PC>), dim3(ng), dim3(NT), 0, s, a, c->d_tab);
+    } else {
       hipLaunchKernelGGL((k_a32_q2<V, PC, true, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    }
     HIPCHK(hipGetLastError());
     const int n_rows = (int)(a.lev.n_nodes / a.lev.nx1);
     hipLaunchKernelGGL((k_gather_ext<V, 2 * PC - 1>), dim3(1, std::min((n_rows + 3) / 4, 65535), 4), dim3(NT), 0, s,

@@ -25,6 +25,7 @@
 #include "pf_branch.hpp"
 #include "pf_geom.hpp"
 #include "pf_qf.hpp"
+#include "pf_mfma.hpp"
 
 namespace pfmf {
 
@@ -81,16 +82,21 @@ __device__ inline void store_ext(const T* R, const MeshDev& m, const ElemGeom& g
   for (int f = 0; f < NF; ++f) d[f * fs] = R[f * P3 + n];
 }
 
-// Global node of the thread's local node on an order P-1 lattice with nx1 x ny1 nodes per
-// layer; -1 for threads beyond the P^3 nodes.
+// Global node of local node n = i + P (j + P k) of element g on an order P-1 lattice with
+// nx1 x ny1 nodes per layer.
+template <int P>
+__device__ inline int64_t lattice_node(int nx1, int ny1, const ElemGeom& g, int n) {
+  constexpr int p = P - 1;
+  const int i = n % P, j = (n / P) % P, k = n / (P * P);
+  return (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
+}
+
+// Global node of the thread's local node; -1 for threads beyond the P^3 nodes.
 template <int P>
 __device__ inline int64_t elem_node(int nx1, int ny1, const ElemGeom& g) {
   static_assert(P * P * P <= NT5, "one thread per element node");
-  constexpr int p = P - 1;
   const int n = threadIdx.x;
-  if (n >= P * P * P) return -1;
-  const int i = n % P, j = (n / P) % P, k = n / (P * P);
-  return (int64_t)(g.ex * p + i) + (int64_t)nx1 * ((g.ey * p + j) + (int64_t)ny1 * (g.ez * p + k));
+  return n < P * P * P ? lattice_node<P>(nx1, ny1, g, n) : -1;
 }
 
 // Gather NF fields of the element's P^3 nodes into U[f][n]; gn = the thread's global node
@@ -149,6 +155,17 @@ __device__ __forceinline__ constexpr int qslot(int f, int c) {
   return CV ? (f < 3 ? 3 * f + c - 1 : 9 + c) : 4 * f + c;
 }
 
+// Runs f(task) for task = 0 .. NTASK-1 spread over the NTH threads of the workgroup (a
+// single guarded call when the workgroup has a thread per task).
+template <int NTASK, int NTH, typename F>
+__device__ __forceinline__ void for_tasks(F&& f) {
+  if constexpr (NTASK <= NTH) {
+    if ((int)threadIdx.x < NTASK) f((int)threadIdx.x);
+  } else {
+    for (int k = threadIdx.x; k < NTASK; k += NTH) f(k);
+  }
+}
+
 // Forward: U[f][k][j][i] (P^3 per field) -> Qo[slot(f, c)][qz][qy][qx] (Q^3 per field and
 // component c = value, d/dxi_x, d/dxi_y, d/dxi_z; with CV no values for f < 3). The nodal
 // values are interpolated to the points by x, y and z passes (B only), and the reference
@@ -157,51 +174,62 @@ __device__ __forceinline__ constexpr int qslot(int f, int c) {
 // P - 1 <= Q - 1 along the line. Per (field, line) of the element a pass costs P Q (or
 // Q^2) multiply-adds, against carrying value and derivative chains through every pass.
 // LDS: X (in XQ) NF P^2 Q values; Y (in UY) NF Q^2 P, followed in UY by the point values
-// V (NF Q^3). GR = false: values only. Starts after, and ends with, a barrier.
-template <typename T, typename Tab, int P, int Q, int NF, bool CV = false, bool GR = true>
-__device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb) {
+// V (NF Q^3). GR = false: values only. NE elements at once (element e's buffers at
+// UY + e la and XQ + e lb), their (field, line) tasks spread over the NTH threads. Starts
+// after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF, bool CV = false, bool GR = true, int NE = 1, int NTH = NT5>
+__device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb, int la = 0, int lb = 0) {
   static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
   static_assert(GR || !CV, "the compact layout carries gradients");
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
-  T* VV = UY + NF * Q2 * P;
-  const int t = threadIdx.x;
-  // x: thread (f, j, k); X[f][k][j][qx]
-  if (t < NF * P2) {
+  constexpr int VOFF = NF * Q2 * P;  // the point values V follow Y in UY
+  // x: task (f, j, k); X[f][k][j][qx]
+  for_tasks<NE * NF * P2, NTH>([&](int task) {
+    const int e = task / (NF * P2), t = task - e * (NF * P2);
+    const T* U = UY + e * la;
+    T* X = XQ + e * lb;
     const int f = t / P2, r = t - f * P2;
     T u[P];
 #pragma unroll
-    for (int i = 0; i < P; ++i) u[i] = UY[f * P3 + r * P + i];
+    for (int i = 0; i < P; ++i) u[i] = U[f * P3 + r * P + i];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T b = T(0);
 #pragma unroll
       for (int i = 0; i < P; ++i) b += (T)tb->B[P][Q][q][i] * u[i];
-      XQ[f * P2 * Q + r * Q + q] = b;
+      X[f * P2 * Q + r * Q + q] = b;
     }
-  }
+  });
   __syncthreads();
-  // y: thread (f, qx, k); Y[f][qy][qx][k]
-  if (t < NF * Q * P) {
+  // y: task (f, qx, k); Y[f][qy][qx][k]
+  for_tasks<NE * NF * Q * P, NTH>([&](int task) {
+    const int e = task / (NF * Q * P), t = task - e * (NF * Q * P);
+    const T* X = XQ + e * lb;
+    T* Y = UY + e * la;
     const int f = t / (Q * P), s = t - f * (Q * P);
     const int qx = s % Q, k = s / Q;
     T x[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) x[j] = XQ[f * P2 * Q + (j + P * k) * Q + qx];
+    for (int j = 0; j < P; ++j) x[j] = X[f * P2 * Q + (j + P * k) * Q + qx];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T b = T(0);
 #pragma unroll
       for (int j = 0; j < P; ++j) b += (T)tb->B[P][Q][q][j] * x[j];
-      UY[f * Q2 * P + (qx + Q * q) * P + k] = b;
+      Y[f * Q2 * P + (qx + Q * q) * P + k] = b;
     }
-  }
+  });
   __syncthreads();
-  // z: thread (f, qx, qy); values V[f][qz][qy][qx], and d/dxi_z along the same line
-  if (t < NF * Q2) {
+  // z: task (f, qx, qy); values V[f][qz][qy][qx], and d/dxi_z along the same line
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* Y = UY + e * la;
+    T* V = UY + e * la + VOFF;
+    T* O = XQ + e * lb;
     const int f = t / Q2, s = t - f * Q2;
     T y[P], v[Q];
 #pragma unroll
-    for (int k = 0; k < P; ++k) y[k] = UY[f * Q2 * P + s * P + k];
+    for (int k = 0; k < P; ++k) y[k] = Y[f * Q2 * P + s * P + k];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T b = T(0);
@@ -209,8 +237,8 @@ __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb
       for (int k = 0; k < P; ++k) b += (T)tb->B[P][Q][q][k] * y[k];
       v[q] = b;
       const int o = s + Q2 * q;
-      if (GR) VV[f * Q3 + o] = b;
-      if (!CV || f == 3) XQ[qslot<CV>(f, 0) * Q3 + o] = b;
+      if (GR) V[f * Q3 + o] = b;
+      if (!CV || f == 3) O[qslot<CV>(f, 0) * Q3 + o] = b;
     }
     if (GR) {
 #pragma unroll
@@ -218,42 +246,48 @@ __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb
         T d = T(0);
 #pragma unroll
         for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
-        XQ[qslot<CV>(f, 3) * Q3 + s + Q2 * q] = d;
+        O[qslot<CV>(f, 3) * Q3 + s + Q2 * q] = d;
       }
     }
-  }
+  });
   __syncthreads();
   if (!GR) return;
-  // d/dxi_x along x lines: thread (f, qy, qz)
-  if (t < NF * Q2) {
+  // d/dxi_x along x lines: task (f, qy, qz)
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* V = UY + e * la + VOFF;
+    T* O = XQ + e * lb;
     const int f = t / Q2, s = t - f * Q2;
     T v[Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) v[m] = VV[f * Q3 + s * Q + m];
+    for (int m = 0; m < Q; ++m) v[m] = V[f * Q3 + s * Q + m];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T d = T(0);
 #pragma unroll
       for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
-      XQ[qslot<CV>(f, 1) * Q3 + s * Q + q] = d;
+      O[qslot<CV>(f, 1) * Q3 + s * Q + q] = d;
     }
-  }
-  // d/dxi_y along y lines: thread (f, qx, qz)
-  if (t < NF * Q2) {
+  });
+  // d/dxi_y along y lines: task (f, qx, qz)
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* V = UY + e * la + VOFF;
+    T* O = XQ + e * lb;
     const int f = t / Q2, s = t - f * Q2;
     const int base = f * Q3 + (s % Q) + Q2 * (s / Q);
     T v[Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) v[m] = VV[base + Q * m];
+    for (int m = 0; m < Q; ++m) v[m] = V[base + Q * m];
     const int ob = qslot<CV>(f, 2) * Q3 + (s % Q) + Q2 * (s / Q);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       T d = T(0);
 #pragma unroll
       for (int m = 0; m < Q; ++m) d += (T)tb->G[Q][q][m] * v[m];
-      XQ[ob + Q * q] = d;
+      O[ob + Q * q] = d;
     }
-  }
+  });
   __syncthreads();
 }
 
@@ -262,57 +296,66 @@ __device__ __forceinline__ void sf5_fwd(T* UY, T* XQ, const Tab* __restrict__ tb
 // derivative tests are moved back onto the point values with G^T along x, y and z lines
 // and added to the value test (A[f][q] in ZR), which then goes through the transposed
 // interpolation passes z, y, x. Z (in ZR, after A) holds NF P Q^2 values, Y (in XQ) NF P^2 Q.
-// Starts after, and ends with, a barrier.
-template <typename T, typename Tab, int P, int Q, int NF, bool CV = false>
-__device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb) {
+// NE elements at once as in sf5_fwd. Starts after, and ends with, a barrier.
+template <typename T, typename Tab, int P, int Q, int NF, bool CV = false, int NE = 1, int NTH = NT5>
+__device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb, int lb = 0, int la = 0) {
   static_assert(!CV || NF == 4, "the compact layout is for the four operator fields");
   constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
-  T* Z = ZR + NF * Q3;
-  const int t = threadIdx.x;
-  // x lines: thread (f, qy, qz); A = value test + G^T (x tests)
-  if (t < NF * Q2) {
+  constexpr int ZOFF = NF * Q3;  // Z follows A in ZR
+  // x lines: task (f, qy, qz); A = value test + G^T (x tests)
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* I = XQ + e * lb;
+    T* A = ZR + e * la;
     const int f = t / Q2, s = t - f * Q2;
     T g[Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 1) * Q3 + s * Q + m];
+    for (int m = 0; m < Q; ++m) g[m] = I[qslot<CV>(f, 1) * Q3 + s * Q + m];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T a = (!CV || f == 3) ? XQ[qslot<CV>(f, 0) * Q3 + s * Q + q] : T(0);
+      T v = (!CV || f == 3) ? I[qslot<CV>(f, 0) * Q3 + s * Q + q] : T(0);
 #pragma unroll
-      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
-      ZR[f * Q3 + s * Q + q] = a;
+      for (int m = 0; m < Q; ++m) v += (T)tb->G[Q][m][q] * g[m];
+      A[f * Q3 + s * Q + q] = v;
     }
-  }
+  });
   __syncthreads();
-  // y lines: thread (f, qx, qz); A += G^T (y tests)
-  if (t < NF * Q2) {
+  // y lines: task (f, qx, qz); A += G^T (y tests)
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* I = XQ + e * lb;
+    T* A = ZR + e * la;
     const int f = t / Q2, s = t - f * Q2;
     const int o = (s % Q) + Q2 * (s / Q);
     T g[Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 2) * Q3 + o + Q * m];
+    for (int m = 0; m < Q; ++m) g[m] = I[qslot<CV>(f, 2) * Q3 + o + Q * m];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T a = ZR[f * Q3 + o + Q * q];
+      T v = A[f * Q3 + o + Q * q];
 #pragma unroll
-      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
-      ZR[f * Q3 + o + Q * q] = a;
+      for (int m = 0; m < Q; ++m) v += (T)tb->G[Q][m][q] * g[m];
+      A[f * Q3 + o + Q * q] = v;
     }
-  }
+  });
   __syncthreads();
-  // z lines: thread (f, qx, qy); A + G^T (z tests), then the transposed z interpolation:
+  // z lines: task (f, qx, qy); A + G^T (z tests), then the transposed z interpolation:
   // Z[f][k][qy][qx]
-  if (t < NF * Q2) {
+  for_tasks<NE * NF * Q2, NTH>([&](int task) {
+    const int e = task / (NF * Q2), t = task - e * (NF * Q2);
+    const T* I = XQ + e * lb;
+    const T* A = ZR + e * la;
+    T* Z = ZR + e * la + ZOFF;
     const int f = t / Q2, s = t - f * Q2;
     T g[Q], c[Q];
 #pragma unroll
-    for (int m = 0; m < Q; ++m) g[m] = XQ[qslot<CV>(f, 3) * Q3 + s + Q2 * m];
+    for (int m = 0; m < Q; ++m) g[m] = I[qslot<CV>(f, 3) * Q3 + s + Q2 * m];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      T a = ZR[f * Q3 + s + Q2 * q];
+      T v = A[f * Q3 + s + Q2 * q];
 #pragma unroll
-      for (int m = 0; m < Q; ++m) a += (T)tb->G[Q][m][q] * g[m];
-      c[q] = a;
+      for (int m = 0; m < Q; ++m) v += (T)tb->G[Q][m][q] * g[m];
+      c[q] = v;
     }
 #pragma unroll
     for (int k = 0; k < P; ++k) {
@@ -321,10 +364,13 @@ __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb
       for (int q = 0; q < Q; ++q) z += (T)tb->B[P][Q][q][k] * c[q];
       Z[f * P * Q2 + k * Q2 + s] = z;
     }
-  }
+  });
   __syncthreads();
-  // y^T: thread (f, qx, k); Y[f][k][j][qx]
-  if (t < NF * Q * P) {
+  // y^T: task (f, qx, k); Y[f][k][j][qx]
+  for_tasks<NE * NF * Q * P, NTH>([&](int task) {
+    const int e = task / (NF * Q * P), t = task - e * (NF * Q * P);
+    const T* Z = ZR + e * la + ZOFF;
+    T* Y = XQ + e * lb;
     const int f = t / (Q * P), s = t - f * (Q * P);
     const int qx = s % Q, k = s / Q;
     T v[Q];
@@ -335,24 +381,27 @@ __device__ __forceinline__ void sf5_bwd(T* XQ, T* ZR, const Tab* __restrict__ tb
       T a = T(0);
 #pragma unroll
       for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][j] * v[q];
-      XQ[f * P2 * Q + (j + P * k) * Q + qx] = a;
+      Y[f * P2 * Q + (j + P * k) * Q + qx] = a;
     }
-  }
+  });
   __syncthreads();
-  // x^T: thread (f, j, k); R[f][k][j][i]
-  if (t < NF * P2) {
+  // x^T: task (f, j, k); R[f][k][j][i]
+  for_tasks<NE * NF * P2, NTH>([&](int task) {
+    const int e = task / (NF * P2), t = task - e * (NF * P2);
+    const T* Y = XQ + e * lb;
+    T* R = ZR + e * la;
     const int f = t / P2, r = t - f * P2;
     T y[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) y[q] = XQ[f * P2 * Q + r * Q + q];
+    for (int q = 0; q < Q; ++q) y[q] = Y[f * P2 * Q + r * Q + q];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       T a = T(0);
 #pragma unroll
       for (int q = 0; q < Q; ++q) a += (T)tb->B[P][Q][q][i] * y[q];
-      ZR[f * P3 + r * P + i] = a;
+      R[f * P3 + r * P + i] = a;
     }
-  }
+  });
   __syncthreads();
 }
 
@@ -661,6 +710,109 @@ __global__ __launch_bounds__(NT5, 2) void k_a32_q4(LinApplyArgs<V> a, int colour
     store_ext<V, PC, 4>(bufA, a.m, g, a.ebuf);
   else
     scatter_elem<V, PC, 4>(bufA, a.m, a.lev.nx1, a.lev.ny1, a.lev.n_nodes, g, a.out);
+}
+
+
+// Linearised level apply on an order-2 fine mesh (3 nodes, 3 Gauss points per direction)
+// in row layout, without extra branches and on box elements: the k_a32_q4 scheme with a
+// brick of 2 x 2 x 2 elements per 256-thread workgroup. Each element has 32 threads for
+// the pointwise function (27 points) and its own LDS buffers, and the sum factorisation
+// tasks of the eight elements (a (field, line) each) are spread over the workgroup, so
+// that no contraction is padded from 3 to 4 points. The element vectors go to the brick
+// sums in the padded 4^3 lane layout (store_brick4), then k_gather_ext<V, 2 PC - 1>.
+template <typename V, int PC>
+__global__ __launch_bounds__(NT, 2) void k_a32_q2r(LinApplyArgs<V> a, const typename TablesOf<V>::type* __restrict__ tabs) {
+  using Tab = typename TablesOf<V>::type;
+  constexpr int PF = 3, Q = 3, Q3 = 27, NE = 8, PC3 = PC * PC * PC;
+  static_assert(PC <= PF && NE * 32 == NT, "eight elements of 32 threads");
+  using L = Q5Lds<PF, Q, true>;
+  __shared__ V bufA[NE * L::A];
+  __shared__ V bufB[NE * L::B];
+  __shared__ V ev[NE * 4 * 64];
+  const int brick = xcd_brick_all(a.m, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom bg = decode_brick_lin(a.m, brick);
+  const int t = threadIdx.x, slot = t >> 5, n = t & 31;
+  const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+  const bool ein = sx < bg.nex && sy < bg.ney && sz < bg.nez;  // the slot holds an element
+  const bool pt = ein && n < Q3;
+  const int ql = pt ? n : 0;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  const ElemGeom g{bg.ex0 + sx, bg.ey0 + sy, bg.ez0 + sz};
+  const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
+  const int64_t gq = e * Q3 + ql;
+  V* A = bufA + slot * L::A;
+  V* B = bufB + slot * L::B;
+  LinRecordT<V> rc;
+#pragma unroll
+  for (int k = 0; k < REC_N; ++k) rc.v[k] = pt ? a.rec.rec[k * a.n_q + gq] : V(0);
+  rc.flags = pt ? a.rec.flags[gq] : 0;
+  const int pid = pt ? a.phase[gq] : 0;
+  const V ih[3] = {(V)a.m.ih[0], (V)a.m.ih[1], (V)a.m.ih[2]};
+  const V wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * (V)a.m.jdet;
+  // the fine displacement mirror at the element's 27 nodes (thread n owns node n)
+  if (ein && n < PF * PF * PF) {
+    const int64_t gn = lattice_node<PF>(a.fine.nx1, a.fine.ny1, g, n);
+    V v[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) v[f] = a.z32[f * a.fine.n_nodes + gn];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) A[f * PF * PF * PF + n] = v[f];
+  }
+  __syncthreads();
+  sf5_fwd<V, Tab, PF, Q, 3, false, true, NE, NT>(bufA, bufB, tabs, L::A, L::B);
+  V G[9];
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) G[3 * f + J] = B[(4 * f + 1 + J) * Q3 + ql] * ih[J];
+  __syncthreads();
+  // the level direction at the element's PC^3 nodes
+  if (ein && n < PC3) {
+    const int64_t gn = lattice_node<PC>(a.lev.nx1, a.lev.ny1, g, n);
+    V v[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[f] = a.dz[f * a.lev.n_nodes + gn];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) A[f * PC3 + n] = v[f];
+  }
+  __syncthreads();
+  sf5_fwd<V, Tab, PC, Q, 4, true, true, NE, NT>(bufA, bufB, tabs, L::A, L::B);
+  V W[9], wphi, gw[3];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    V* out = f < 3 ? W + 3 * f : gw;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) out[J] = B[qslot<true>(f, 1 + J) * Q3 + ql] * ih[J];
+  }
+  wphi = B[qslot<true>(3, 0) * Q3 + ql];
+  __syncthreads();
+  const int pidc = pid < a.nph ? pid : 0;
+  const MatParams<V> mp = a.mats[pidc];
+  QPState<V> s;
+  qp_state_lin<V>(mp, G, rc, s);
+  V Fu[9], dL;
+  lin_tangent<V, false>(a.rec, a.n_q, a.xmats, a.n_extra, mp, s, pidc, gq, pt, G, W, wphi, Fu, dL);
+  const V kfg = a.fr.kf * mp.Gc;
+  if (pt) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) B[qslot<true>(f, 1 + J) * Q3 + ql] = wdet * Fu[3 * f + J] * ih[J];
+    B[qslot<true>(3, 0) * Q3 + ql] = wdet * a.fr.s_phi * dL;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) B[qslot<true>(3, 1 + J) * Q3 + ql] = wdet * kfg * gw[J] * ih[J];
+  }
+  __syncthreads();
+  sf5_bwd<V, Tab, PC, Q, 4, true, NE, NT>(bufB, bufA, tabs, L::B, L::A);
+  // element vectors into the padded lane layout of the brick sums (node a = i + 4 j + 16 k)
+  if (ein && n < PC3) {
+    const int i = n % PC, j = (n / PC) % PC, k = n / (PC * PC);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + i + 4 * j + 16 * k] = A[f * PC3 + n];
+  }
+  __syncthreads();
+  store_brick4<V, PC, 4>(ev, a.m, bg, a.ebuf);
 }
 
 }  // namespace pfmf
