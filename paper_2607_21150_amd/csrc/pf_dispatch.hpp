@@ -42,6 +42,8 @@ pf_status launch_op64_mfma_v(pf_ctx* c, OpArgs a, hipStream_t s) {
     const int ng = xcd_grid_all(c->nbx, c->nby, c->nbz);
     if constexpr (P == 4)
       hipLaunchKernelGGL((k_op64_q3<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
+    else if constexpr (!MB && !GEO)  // box elements without branches: row layout, no 3 -> 4 padding
+      hipLaunchKernelGGL((k_op64_q2r<MODE, VOCE>), dim3(ng), dim3(NT), 0, s, a, c->d_tab);
     else
       hipLaunchKernelGGL((k_op64_q2<MODE, true, VOCE, MB, GEO>), dim3(ng), dim3(NT), 0, s, a, 0, c->d_tab);
     HIPCHK(hipGetLastError());

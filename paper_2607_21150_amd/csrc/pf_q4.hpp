@@ -726,9 +726,10 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2r(LinApplyArgs<V> a, const type
   constexpr int PF = 3, Q = 3, Q3 = 27, NE = 8, PC3 = PC * PC * PC;
   static_assert(PC <= PF && NE * 32 == NT, "eight elements of 32 threads");
   using L = Q5Lds<PF, Q, true>;
+  static_assert(NE * 4 * 64 <= NE * L::B, "the element vectors reuse the point buffers");
   __shared__ V bufA[NE * L::A];
   __shared__ V bufB[NE * L::B];
-  __shared__ V ev[NE * 4 * 64];
+  V* ev = bufB;  // element vectors, once the transposed passes have left the point buffers
   const int brick = xcd_brick_all(a.m, blockIdx.x);
   if (brick < 0) return;  // padding workgroup (uniform)
   const BrickGeom bg = decode_brick_lin(a.m, brick);
@@ -813,6 +814,190 @@ __global__ __launch_bounds__(NT, 2) void k_a32_q2r(LinApplyArgs<V> a, const type
   }
   __syncthreads();
   store_brick4<V, PC, 4>(ev, a.m, bg, a.ebuf);
+}
+
+
+// FP64 residual / Jacobian / adjoint on order-2 box elements without extra branches, in
+// row layout: a brick of 2 x 2 x 2 elements per 256-thread workgroup, 32 threads per
+// element for the pointwise function (27 points), the eight elements' sum factorisation
+// tasks spread over the workgroup through LDS (no contraction padded from 3 to 4 points).
+// Brick sums to the brick buffer (store_brick4), then k_gather_ext<double, 5>; the
+// adjoint's per-phase parameter partials are summed per brick in a fixed order.
+template <int MODE, bool VOCE>
+__global__ __launch_bounds__(NT, 2) void k_op64_q2r(OpArgs a, DevTables* __restrict__ tabs) {
+  constexpr int P = 3, Q = 3, Q3 = 27, NE = 8;
+  static_assert(NE * 32 == NT, "eight elements of 32 threads");
+  using L = Q5Lds<P, Q, true>;
+  static_assert(NE * 4 * 64 <= NE * L::B, "the element vectors reuse the point buffers");
+  __shared__ double bufA[NE * L::A];
+  __shared__ double bufB[NE * L::B];
+  __shared__ double red[MODE == M_ADJ ? NT : 1];
+  double* ev = bufB;  // element vectors, once the transposed passes have left the point buffers
+  const int brick = xcd_brick_all(a.m, blockIdx.x);
+  if (brick < 0) return;  // padding workgroup (uniform)
+  const BrickGeom bg = decode_brick_lin(a.m, brick);
+  const int t = threadIdx.x, slot = t >> 5, n = t & 31, l = t & 63, wv = t >> 6;
+  const int sx = slot & 1, sy = (slot >> 1) & 1, sz = slot >> 2;
+  const bool ein = sx < bg.nex && sy < bg.ney && sz < bg.nez;  // the slot holds an element
+  const bool pt = ein && n < Q3;
+  const int ql = pt ? n : 0;
+  const int qx = ql % Q, qy = (ql / Q) % Q, qz = ql / (Q * Q);
+  const ElemGeom g{bg.ex0 + sx, bg.ey0 + sy, bg.ez0 + sz};
+  const int64_t e = (int64_t)g.ex + (int64_t)a.m.nx * (g.ey + (int64_t)a.m.ny * g.ez);
+  const int64_t gq = e * Q3 + ql;
+  const int64_t gn = (ein && n < Q3) ? lattice_node<P>(a.nx1, a.ny1, g, n) : -1;  // thread n owns node n
+  double* A = bufA + slot * L::A;
+  double* B = bufB + slot * L::B;
+  // per-point state, issued before the gathers
+  double st[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) st[k] = pt ? a.state[k * a.n_q + gq] : 0.0;
+  const int pid = pt ? a.phase[gq] : 0;
+  const double ih[3] = {a.m.ih[0], a.m.ih[1], a.m.ih[2]};
+  const double wdet = tabs->w[Q][qx] * tabs->w[Q][qy] * tabs->w[Q][qz] * a.m.jdet;
+  if (gn >= 0) {
+    double v[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) v[f] = a.z[f * a.n_nodes + gn];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) A[f * Q3 + n] = v[f];
+  }
+  __syncthreads();
+  sf5_fwd<double, DevTables, P, Q, 4, true, true, NE, NT>(bufA, bufB, tabs, L::A, L::B);
+  double G[9], phi, gphi[3];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) (f < 3 ? G + 3 * f : gphi)[J] = B[qslot<true>(f, 1 + J) * Q3 + ql] * ih[J];
+  phi = B[qslot<true>(3, 0) * Q3 + ql];
+  double phin = 0.0;
+  __syncthreads();
+  if (MODE == M_RES) {
+    if (gn >= 0) A[n] = a.phin[gn];
+    __syncthreads();
+    sf5_fwd<double, DevTables, P, Q, 1, false, false, NE, NT>(bufA, bufB, tabs, L::A, L::B);
+    phin = B[ql];
+    __syncthreads();
+  }
+  const bool bad_pid = pt && pid >= a.nph;  // an id outside the phase table raises the phase flag
+  const int pidc = pid < a.nph ? pid : 0;
+  const MatParams<double> mp = a.mats[pidc];
+  QPState<double> s;
+  qp_state<double, VOCE>(mp, a.fr, G, phi, phin, st, s);
+  const bool bad = pt && s.bad;
+  double W[9], wphi = 0.0, gw[3] = {0.0, 0.0, 0.0};
+  if (MODE != M_RES) {
+    if (gn >= 0) {
+      double v[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) v[f] = a.w[f * a.n_nodes + gn];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) A[f * Q3 + n] = v[f];
+    }
+    __syncthreads();
+    sf5_fwd<double, DevTables, P, Q, 4, true, true, NE, NT>(bufA, bufB, tabs, L::A, L::B);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) (f < 3 ? W + 3 * f : gw)[J] = B[qslot<true>(f, 1 + J) * Q3 + ql] * ih[J];
+    wphi = B[qslot<true>(3, 0) * Q3 + ql];
+    __syncthreads();
+  }
+  const double kfg = a.fr.kf * mp.Gc;
+  double Fu[9], f0, f1[3];
+  double gsum[3] = {0.0, 0.0, 0.0};
+  if (MODE == M_RES) {
+    piola<double>(s, Fu);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+    f0 = wdet * a.fr.s_phi * s.L;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gphi[J];
+  } else if (MODE == M_JAC) {
+    double dL;
+    qp_tangent<double>(mp, s, W, wphi, Fu, dL);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Fu[k] *= wdet;
+    f0 = wdet * a.fr.s_phi * dL;
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = wdet * kfg * gw[J];
+  } else {
+    double Pb[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Pb[k] = wdet * W[k];
+    const double f0b = wdet * wphi;
+    const double Lb = a.fr.s_phi * f0b;
+    double phib, Xd[3];
+    qp_tangent_T<double>(mp, s, Pb, Lb, Fu, phib, Xd);
+#pragma unroll
+    for (int J = 0; J < 3; ++J) f1[J] = kfg * wdet * gw[J];
+    const double alpha_p = (a.fr.at == 2) ? 2.0 * phi : 1.0;
+    gsum[0] = alpha_p * a.fr.inv_c0l0 * Lb + a.fr.kf * wdet * (gphi[0] * gw[0] + gphi[1] * gw[1] + gphi[2] * gw[2]);
+    if (s.plastic) {
+      const double ee = s.e[0] * s.e[0] + s.e[1] * s.e[1] + s.e[2] * s.e[2];
+      const double qv = 2.0 * mp.mu * sqrt(1.5 * ee);
+      const double w3q = 3.0 * mp.mu / qv;
+      const double xe = Xd[0] * s.e[0] + Xd[1] * s.e[1] + Xd[2] * s.e[2];
+      const double hterm = s.hactive ? Lb * s.gp * 2.0 * mp.mu * s.c * ee : 0.0;
+      const double base = s.g * 2.0 * mp.mu * xe + hterm;
+      gsum[1] = -w3q * s.ddg_s0 * base;
+      gsum[2] = -w3q * s.ddg_visc * base;
+    }
+    f0 = phib;
+    if (!pt) gsum[0] = gsum[1] = gsum[2] = 0.0;
+  }
+  // point coefficients into the point arrays (every thread has read its values)
+  if (pt) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int K = 0; K < 3; ++K) B[qslot<true>(f, 1 + K) * Q3 + ql] = (f < 3 ? Fu[3 * f + K] : f1[K]) * ih[K];
+    B[qslot<true>(3, 0) * Q3 + ql] = f0;
+  }
+  __syncthreads();
+  sf5_bwd<double, DevTables, P, Q, 4, true, NE, NT>(bufB, bufA, tabs, L::B, L::A);
+  // element vectors into the padded lane layout of the brick sums (node a = i + 4 j + 16 k)
+  if (gn >= 0) {
+    const int i = n % P, j = (n / P) % P, k = n / (P * P);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) ev[(slot * 4 + f) * 64 + i + 4 * j + 16 * k] = A[f * Q3 + n];
+  }
+  if (MODE == M_ADJ) {
+    // deterministic per-phase reduction: butterfly inside each wave, wave sums in order
+    const int nv = 3 * a.nph;
+    if (nv * (NT / 64) <= NT) {
+      for (int idx = 0; idx < nv; ++idx) {
+        const int ph = idx / 3, k = idx - 3 * ph;
+        double v = (pt && pid == ph) ? (k == 0 ? gsum[0] : (k == 1 ? gsum[1] : gsum[2])) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (l == 0) red[wv * nv + idx] = v;
+      }
+      __syncthreads();
+      if (t < nv) {
+        double r = red[t];
+        for (int w = 1; w < NT / 64; ++w) r += red[w * nv + t];
+        a.gpart[(int64_t)(a.brick_base + brick) * nv + t] = r;
+      }
+    } else {
+      for (int ph = 0; ph < a.nph; ++ph) {
+        for (int k = 0; k < 3; ++k) {
+          red[t] = (pt && pid == ph) ? (k == 0 ? gsum[0] : (k == 1 ? gsum[1] : gsum[2])) : 0.0;
+          __syncthreads();
+          for (int stp = NT / 2; stp > 0; stp >>= 1) {
+            if (t < stp) red[t] += red[t + stp];
+            __syncthreads();
+          }
+          if (t == 0) a.gpart[((int64_t)(a.brick_base + brick) * a.nph + ph) * 3 + k] = red[0];
+          __syncthreads();
+        }
+      }
+    }
+  }
+  __syncthreads();
+  store_brick4<double, P, 4>(ev, a.m, bg, a.ebuf);
+  if (bad) a.flag[0] = 1;
+  if (bad_pid) a.flag[1] = 1;
 }
 
 }  // namespace pfmf
