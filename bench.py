@@ -718,11 +718,11 @@ def main():
     achieved = bj / t_jac / 1e9
     counters = measured_counters(args.config + "/" + args.variant)
     traffic = counters.get("hbm_bytes_per_apply")
-    kname = {2: "pfmf::k_op64_q2<1, true, false, false, false, false> + pfmf::k_gather_ext<double, 5>: one "
+    kname = {2: "pfmf::k_op64_q2r<1, false> + pfmf::k_gather_ext<double, 5>: one "
                 "launch over all bricks, then the node gather",
              3: "pfmf::k_op64_q3<1, true, false, false, false, false> + pfmf::k_gather_ext<double, 7>: one "
                 "launch over all bricks, then the node gather",
-             4: "pfmf::k_op64_q4<1, false, false, false, true> + pfmf::k_gather_ext<double, 5>: one launch over "
+             4: "pfmf::k_op64_q4<1, false, false, false, true, false> + pfmf::k_gather_ext<double, 5>: one launch over "
                 "all elements, then the node gather"}.get(mesh.p, f"pfmf::k_op64<1, {mesh.p + 1}, {mesh.p + 1}>")
     cpu = None
     if not args.no_cpu:
