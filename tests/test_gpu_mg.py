@@ -71,7 +71,8 @@ def restrict_np(r, mesh_n, pf_order, pc_order):
 
 @pytest.mark.parametrize("name,variant,p,n", [("C1", "base", None, None), ("C1", "plastic", None, None),
                                               ("C1", "compress", None, None), ("C1", "plastic", 3, 3),
-                                              ("C2", "plastic", 2, 6), ("C1", "plastic", 4, 3),
+                                              ("C2", "plastic", 2, 6), ("C1", "plastic", 2, 5),
+                                              ("C1", "plastic", 4, 3),
                                               ("C1", "base", 4, 2), ("C1", "voce", 3, 3),
                                               ("C1", "ex3", None, None), ("C1", "ex3", 3, 3),
                                               ("C1", "ex3_compress", 3, 2), ("C1", "ex3", 4, 2)])
