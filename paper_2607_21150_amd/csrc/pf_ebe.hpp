@@ -67,8 +67,39 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
   __syncthreads();
   const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
   const float jdet = (float)a.m.jdet;
-  // NG thread groups per point share its 10 tangent directions (each recomputes G and
-  // the point state)
+  // the displacement gradient of each point, once, for the NG thread groups below: one
+  // task per (point, displacement field), spread over the workgroup. Gs lives in Tq,
+  // which the second contraction fills only after the tangents have been taken.
+  static_assert(Q3 * 9 <= QC * 10 * 32, "the point gradients fit the contraction buffer");
+  float (*Gs)[9] = reinterpret_cast<float (*)[9]>(&Tq[0][0][0]);
+  for (int task = t; task < 3 * Q3; task += NT) {
+    const int q = task % Q3, f = task / Q3;
+    const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
+    float g[3] = {0.f, 0.f, 0.f};
+    for (int n = 0; n < P3; ++n) {
+      const int ax = n % PF, ay = (n / PF) % PF, az = n / (PF * PF);
+      const float bx = Bf[qx * PF + ax], by = Bf[qy * PF + ay], bz = Bf[qz * PF + az];
+      const float u = ub[f * P3 + n];
+      g[0] += u * (Df[qx * PF + ax] * by * bz);
+      g[1] += u * (bx * Df[qy * PF + ay] * bz);
+      g[2] += u * (bx * by * Df[qz * PF + az]);
+    }
+    if (GEO) {  // reference derivatives to physical ones
+      const int64_t gq = e * Q3 + q;
+      double gA[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
+      map_grad<float>(g[0], g[1], g[2], gA, g);
+    } else {
+#pragma unroll
+      for (int J = 0; J < 3; ++J) g[J] *= ih[J];
+    }
+#pragma unroll
+    for (int J = 0; J < 3; ++J) Gs[q][3 * f + J] = g[J];
+  }
+  __syncthreads();
+  // NG thread groups per point share its 10 tangent directions (each recomputes the point
+  // state from the record)
   constexpr int NG = (NT / Q3) < 10 ? (NT / Q3) : 10;
   static_assert(NG >= 1, "a point per thread");
   if (t < NG * Q3) {
@@ -76,30 +107,8 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
     const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
     float G[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) G[k] = 0.f;
-    for (int n = 0; n < P3; ++n) {
-      const int ax = n % PF, ay = (n / PF) % PF, az = n / (PF * PF);
-      const float bx = Bf[qx * PF + ax], by = Bf[qy * PF + ay], bz = Bf[qz * PF + az];
-      // GEO: reference derivatives here, mapped below
-      const float gx = Df[qx * PF + ax] * by * bz * (GEO ? 1.f : ih[0]);
-      const float gy = bx * Df[qy * PF + ay] * bz * (GEO ? 1.f : ih[1]);
-      const float gz = bx * by * Df[qz * PF + az] * (GEO ? 1.f : ih[2]);
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const float u = ub[f * P3 + n];
-        G[3 * f + 0] += u * gx;
-        G[3 * f + 1] += u * gy;
-        G[3 * f + 2] += u * gz;
-      }
-    }
+    for (int k = 0; k < 9; ++k) G[k] = Gs[q][k];
     const int64_t gq = e * Q3 + q;
-    if (GEO) {
-      double gA[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
-#pragma unroll
-      for (int f = 0; f < 3; ++f) map_grad<float>(G[3 * f], G[3 * f + 1], G[3 * f + 2], gA, G + 3 * f);
-    }
     LinRecord rc;
 #pragma unroll
     for (int k = 0; k < REC_N; ++k) rc.v[k] = a.rec.rec[k * a.n_q + gq];
