@@ -68,34 +68,47 @@ __global__ __launch_bounds__(NT) void k_ebe_assemble(EbeArgs a, DevTablesF* __re
   const float ih[3] = {(float)a.m.ih[0], (float)a.m.ih[1], (float)a.m.ih[2]};
   const float jdet = (float)a.m.jdet;
   // the displacement gradient of each point, once, for the NG thread groups below: one
-  // task per (point, displacement field), spread over the workgroup. Gs lives in Tq,
-  // which the second contraction fills only after the tangents have been taken.
+  // task per (point, displacement field) when they fit the workgroup in one round, else
+  // one per point (the basis products then serve the three fields). Gs lives in Tq, which
+  // the second contraction fills only after the tangents have been taken.
   static_assert(Q3 * 9 <= QC * 10 * 32, "the point gradients fit the contraction buffer");
   float (*Gs)[9] = reinterpret_cast<float (*)[9]>(&Tq[0][0][0]);
-  for (int task = t; task < 3 * Q3; task += NT) {
-    const int q = task % Q3, f = task / Q3;
+  constexpr int NFT = 3 * Q3 <= NT ? 1 : 3;  // fields per task
+  for (int task = t; task < (3 / NFT) * Q3; task += NT) {
+    const int q = task % Q3, f0 = (task / Q3) * NFT;
     const int qx = q % Q, qy = (q / Q) % Q, qz = q / (Q * Q);
-    float g[3] = {0.f, 0.f, 0.f};
+    float g[NFT][3];
+#pragma unroll
+    for (int k = 0; k < NFT; ++k) g[k][0] = g[k][1] = g[k][2] = 0.f;
     for (int n = 0; n < P3; ++n) {
       const int ax = n % PF, ay = (n / PF) % PF, az = n / (PF * PF);
       const float bx = Bf[qx * PF + ax], by = Bf[qy * PF + ay], bz = Bf[qz * PF + az];
-      const float u = ub[f * P3 + n];
-      g[0] += u * (Df[qx * PF + ax] * by * bz);
-      g[1] += u * (bx * Df[qy * PF + ay] * bz);
-      g[2] += u * (bx * by * Df[qz * PF + az]);
+      const float dx = Df[qx * PF + ax] * by * bz, dy = bx * Df[qy * PF + ay] * bz, dz = bx * by * Df[qz * PF + az];
+#pragma unroll
+      for (int k = 0; k < NFT; ++k) {
+        const float u = ub[(f0 + k) * P3 + n];
+        g[k][0] += u * dx;
+        g[k][1] += u * dy;
+        g[k][2] += u * dz;
+      }
     }
-    if (GEO) {  // reference derivatives to physical ones
+    double gA[GEO ? 9 : 1];
+    if (GEO) {
       const int64_t gq = e * Q3 + q;
-      double gA[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) gA[k] = a.qd[k * a.n_q + gq];
-      map_grad<float>(g[0], g[1], g[2], gA, g);
-    } else {
-#pragma unroll
-      for (int J = 0; J < 3; ++J) g[J] *= ih[J];
     }
 #pragma unroll
-    for (int J = 0; J < 3; ++J) Gs[q][3 * f + J] = g[J];
+    for (int k = 0; k < NFT; ++k) {
+      if (GEO) {  // reference derivatives to physical ones
+        map_grad<float>(g[k][0], g[k][1], g[k][2], gA, g[k]);
+      } else {
+#pragma unroll
+        for (int J = 0; J < 3; ++J) g[k][J] *= ih[J];
+      }
+#pragma unroll
+      for (int J = 0; J < 3; ++J) Gs[q][3 * (f0 + k) + J] = g[k][J];
+    }
   }
   __syncthreads();
   // NG thread groups per point share its 10 tangent directions (each recomputes the point
